@@ -1,0 +1,202 @@
+"""Oracle for the paper's sparse x sparse ciphertext matmul (test infrastructure only).
+
+Algorithm 1 (CSR x CSC traversal with rotation-minimising alignment) and
+Algorithm 2 (per matched pair: EvalMult, Relinearize, Rescale, one-hot mask,
+Rescale, EvalRotate to the target slot, EvalAdd) are followed step by step for
+every matched pair, with no sharing of work between pairs.
+
+Readings where the paper is silent (listed in the design notes):
+  * loops run i in [0, m), j in [0, n); ``size`` in the target index is n;
+  * values of an operand longer than S = N/2 slots are packed into chunks of
+    S consecutive values; a position splits into (chunk, local slot);
+  * the result is packed row-major, chunked the same way, and each result
+    chunk starts as the all-zero ciphertext two levels below the top;
+  * rotations are cyclic over all S slots, a rotation by 0 is the identity,
+    the Relinearize after the plaintext mask multiply is the identity.
+"""
+from __future__ import annotations
+
+import multiprocessing as mp
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import ckks
+from .ckks import Ct, Keys, Params
+
+
+@dataclass
+class EncSparse:
+    """An encrypted sparse matrix: public pattern, encrypted values in slot chunks."""
+    rows: int
+    cols: int
+    indptr: np.ndarray
+    indices: np.ndarray
+    chunks: list
+
+
+def _encrypt_values(params: Params, keys: Keys, values: np.ndarray, seed: int, scale: float) -> list:
+    S = params.S
+    out = []
+    nchunks = max(1, -(-len(values) // S))
+    for c in range(nchunks):
+        z = values[c * S:(c + 1) * S]
+        m = ckks.encode(z, scale, params.N)
+        out.append(ckks.encrypt(params, keys, m, seed, c, scale))
+    return out
+
+
+def encrypt_csr(params: Params, keys: Keys, rows, cols, indptr, indices, values, seed: int) -> EncSparse:
+    """Left operand in CSR, values encoded at 2^log_delta."""
+    values = np.asarray(values, dtype=np.float64)
+    return EncSparse(rows, cols, np.asarray(indptr), np.asarray(indices),
+                     _encrypt_values(params, keys, values, seed, params.delta_a))
+
+
+def encrypt_csc(params: Params, keys: Keys, rows, cols, indptr, indices, values, seed: int) -> EncSparse:
+    """Right operand in CSC, values encoded at exactly q_top."""
+    values = np.asarray(values, dtype=np.float64)
+    return EncSparse(rows, cols, np.asarray(indptr), np.asarray(indices),
+                     _encrypt_values(params, keys, values, seed, params.delta_b))
+
+
+def matched_pairs(m: int, n: int, indptr_a, indices_a, indptr_b, indices_b) -> list:
+    """Algorithm 1's traversal: for every (row i, column j), merge the column ids of
+    row i of A with the row ids of column j of B; every equal id is one matched
+    pair (i, j, a_pos, b_pos), positions being indices into the value arrays."""
+    pairs = []
+    for i in range(m):
+        for j in range(n):
+            a_pos, a_end = int(indptr_a[i]), int(indptr_a[i + 1])
+            b_pos, b_end = int(indptr_b[j]), int(indptr_b[j + 1])
+            while a_pos < a_end and b_pos < b_end:
+                a_col, b_row = int(indices_a[a_pos]), int(indices_b[b_pos])
+                if a_col == b_row:
+                    pairs.append((i, j, a_pos, b_pos))
+                    a_pos += 1
+                    b_pos += 1
+                elif a_col < b_row:
+                    a_pos += 1
+                else:
+                    b_pos += 1
+    return pairs
+
+
+def alignment(params: Params, a_pos: int, b_pos: int):
+    """(chunk of A, chunk of B, rotation of A, rotation of B, min local position).
+    Only the operand whose value sits at the larger local slot is rotated, by the
+    difference; equal slots need no rotation."""
+    S = params.S
+    ca, la = divmod(a_pos, S)
+    cb, lb = divmod(b_pos, S)
+    if la < lb:
+        return ca, cb, 0, lb - la, la
+    if lb < la:
+        return ca, cb, la - lb, 0, lb
+    return ca, cb, 0, 0, la
+
+
+def target(params: Params, i: int, j: int, n: int, min_pos: int):
+    """(result chunk, rotation amount) moving slot min_pos to slot (i n + j) mod S."""
+    cr, lt = divmod(i * n + j, params.S)
+    return cr, (min_pos - lt) % params.S
+
+
+def pair_contribution(params: Params, keys: Keys, A: EncSparse, B: EncSparse, i: int, j: int, a_pos: int,
+                      b_pos: int) -> tuple:
+    ca, cb, ra, rb, mn = alignment(params, a_pos, b_pos)
+    vA, vB = A.chunks[ca], B.chunks[cb]
+    if rb:
+        vB = ckks.rotate(params, keys, vB, rb)
+    if ra:
+        vA = ckks.rotate(params, keys, vA, ra)
+    # Algorithm 2
+    d = ckks.mult_relin(params, keys, vA, vB)
+    d = ckks.rescale(params, d)
+    d = ckks.mul_plain(params, d, ckks.mask(params, mn), params.delta_mask)
+    d = ckks.rescale(params, d)
+    cr, rot = target(params, i, j, B.cols, mn)
+    d = ckks.rotate(params, keys, d, rot)
+    return cr, d
+
+
+def result_chunks(params: Params, m: int, n: int) -> int:
+    return max(1, -(-(m * n) // params.S))
+
+
+def _accumulate(params: Params, keys: Keys, A: EncSparse, B: EncSparse, pairs: list) -> list:
+    res = [None] * result_chunks(params, A.rows, B.cols)
+    for (i, j, a_pos, b_pos) in pairs:
+        cr, d = pair_contribution(params, keys, A, B, i, j, a_pos, b_pos)
+        res[cr] = d if res[cr] is None else ckks.add(params, res[cr], d)
+    return [None if r is None else r.data for r in res]
+
+
+_G = {}
+
+
+def _worker(idx):
+    g = _G
+    return _accumulate(g["params"], g["keys"], g["A"], g["B"], g["parts"][idx])
+
+
+def _keygen_worker(gval):
+    k = _G["keys"]
+    return gval, k.rot_key(gval)
+
+
+def rotation_elements(params: Params, A: EncSparse, B: EncSparse, pairs: list) -> set:
+    gs = set()
+    for (i, j, a_pos, b_pos) in pairs:
+        _, _, ra, rb, mn = alignment(params, a_pos, b_pos)
+        _, rt = target(params, i, j, B.cols, mn)
+        for r in (ra, rb, rt):
+            for step in ckks.rotation_steps(params, r):
+                gs.add(pow(5, step, 2 * params.N))
+    return gs
+
+
+def spmspm(params: Params, keys: Keys, A: EncSparse, B: EncSparse, workers: int = 1, pairs: list | None = None) -> list:
+    """Encrypted C = A B as a list of result-chunk ciphertexts (row-major slots).
+
+    ``pairs`` restricts the sum to a subset of matched pairs (default: all).
+    With workers > 1 the matched pairs are split across processes and the
+    partial results are added; addition mod q is exact, so the result does
+    not depend on the split."""
+    assert A.cols == B.rows
+    if pairs is None:
+        pairs = matched_pairs(A.rows, B.cols, A.indptr, A.indices, B.indptr, B.indices)
+    out_nl = params.n_q - 2
+    nres = result_chunks(params, A.rows, B.cols)
+    if workers <= 1 or len(pairs) < 2:
+        parts = [_accumulate(params, keys, A, B, pairs)]
+    else:
+        gs = sorted(rotation_elements(params, A, B, pairs) - set(keys._rot))
+        ctx = mp.get_context("fork")
+        _G.update(params=params, keys=keys, A=A, B=B)
+        if gs:
+            with ctx.Pool(workers) as pool:
+                for gval, key in pool.imap_unordered(_keygen_worker, gs):
+                    keys._rot[gval] = key
+        _G["parts"] = [pairs[w::workers] for w in range(workers)]
+        with ctx.Pool(workers) as pool:
+            parts = pool.map(_worker, range(workers))
+        _G.clear()
+    res = []
+    for c in range(nres):
+        acc = ckks.zero_ct(params, out_nl, params.delta_out)
+        for part in parts:
+            if part[c] is not None:
+                acc = ckks.add(params, acc, Ct(part[c], params.delta_out))
+        res.append(acc)
+    return res
+
+
+def decrypt_result(params: Params, keys: Keys, res: list, m: int, n: int) -> np.ndarray:
+    S = params.S
+    out = np.zeros(m * n)
+    for c, ct in enumerate(res):
+        lo, hi = c * S, min((c + 1) * S, m * n)
+        if hi > lo:
+            out[lo:hi] = ckks.decrypt_decode(params, keys, ct, np.arange(hi - lo))
+    return out.reshape(m, n)

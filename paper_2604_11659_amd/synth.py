@@ -1,0 +1,80 @@
+"""Seeded synthetic sparse operands (no CKKS arithmetic lives here).
+
+The paper evaluates on random square matrices at several sparsity levels
+(Section 4); the workloads below keep that recipe at the shapes of the
+benchmark configurations. Zeros are placed exactly: round(sparsity * size)
+positions chosen by a seeded permutation; values come from a seeded numpy
+PCG64 stream.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+def sparse_dense(rows: int, cols: int, sparsity: float, dist: str, seed_values: int, seed_mask: int,
+                 lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    rv = np.random.Generator(np.random.PCG64(seed_values))
+    if dist == "uniform":
+        vals = rv.uniform(lo, hi, size=(rows, cols))
+    elif dist == "halfnormal":
+        vals = np.abs(rv.standard_normal(size=(rows, cols)))
+    else:
+        raise ValueError(dist)
+    rm = np.random.Generator(np.random.PCG64(seed_mask))
+    nzero = int(round(sparsity * rows * cols))
+    perm = rm.permutation(rows * cols)
+    flat = vals.reshape(-1).copy()
+    flat[perm[:nzero]] = 0.0
+    return flat.reshape(rows, cols)
+
+
+def to_csr(d: np.ndarray):
+    """(indptr int32[rows+1], indices int32[nnz] column ids ascending per row, values f64[nnz])."""
+    rows, _ = d.shape
+    indptr = np.zeros(rows + 1, np.int32)
+    idx, val = [], []
+    for i in range(rows):
+        nz = np.nonzero(d[i])[0]
+        idx.extend(nz.tolist())
+        val.extend(d[i, nz].tolist())
+        indptr[i + 1] = len(idx)
+    return indptr, np.asarray(idx, np.int32), np.asarray(val, np.float64)
+
+
+def to_csc(d: np.ndarray):
+    """(indptr int32[cols+1], indices int32[nnz] row ids ascending per column, values f64[nnz])."""
+    return to_csr(np.ascontiguousarray(d.T))
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    log_n: int
+    n_q: int
+    n_p: int
+    alpha: int
+    rot_digits: int
+    m: int
+    k: int
+    n: int
+    sparsity_a: float
+    sparsity_b: float
+    dist_a: tuple
+    dist_b: tuple
+
+    def operands(self, seeds=(0, 1, 2, 3)):
+        a = sparse_dense(self.m, self.k, self.sparsity_a, self.dist_a[0], seeds[0], seeds[2], *self.dist_a[1:])
+        b = sparse_dense(self.k, self.n, self.sparsity_b, self.dist_b[0], seeds[1], seeds[3], *self.dist_b[1:])
+        return a, b
+
+
+WORKLOADS = {
+    # 16x16 x 16x16, 75% zeros each, N = 2^13, 4 x 50-bit Q primes, 1 x 60-bit P prime
+    "plain": Workload("plain", 13, 4, 1, 1, 1, 16, 16, 16, 0.75, 0.75, ("uniform", -1.0, 1.0), ("uniform", -1.0, 1.0)),
+    # DNN layer: W 128x128 (90% zeros, U[-0.1,0.1]) times X 128x64 (50% zeros, |N(0,1)|), N = 2^15
+    "dnn": Workload("dnn", 15, 10, 2, 2, 2, 128, 128, 64, 0.90, 0.50, ("uniform", -0.1, 0.1), ("halfnormal",)),
+    # 512x512 (95% zeros) times 512x512 (60% zeros), N = 2^16, 24 Q primes, 3 P primes
+    "large": Workload("large", 16, 24, 3, 3, 3, 512, 512, 512, 0.95, 0.60, ("uniform", -0.1, 0.1), ("halfnormal",)),
+}
