@@ -1,0 +1,183 @@
+/*
+ * fhe_spmspm.h - C-ABI of the MI355X (gfx950) library for sparse x sparse
+ * matrix multiplication on RNS-CKKS ciphertexts.
+ *
+ * The operation is the paper's CSR x CSC method: the left operand's values
+ * are packed row-major (CSR order) into ciphertext slots, the right
+ * operand's values column-major (CSC order); the sparsity pattern is public
+ * and only the values are encrypted (Section 3.2.1). Every matched pair of
+ * non-zeros found by the merge of Algorithm 1 is aligned by one rotation,
+ * multiplied, relinearised and rescaled, isolated with a one-hot plaintext
+ * mask, rescaled again, rotated to its row-major target slot and added to
+ * the result (Algorithm 2, Section 3.1).
+ *
+ * Conventions for every entry point
+ *   - Return value: FHE_OK (0) or a negative FHE_E* code; fhe_last_error()
+ *     then returns a message describing the failure (thread-local, valid
+ *     until the next call on the same thread).
+ *   - Host arrays passed in are read during the call only and stay owned by
+ *     the caller. Handles returned through out-pointers are owned by the
+ *     caller and released with the matching *_free call (NULL is accepted).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device work is enqueued on it; functions that return host data
+ *     synchronise that stream before returning.
+ *   - Device memory comes from the allocator registered with
+ *     fhe_set_allocator (default: hipMalloc / hipFree).
+ *   - Rotation by r is a LEFT rotation: slot t of the output holds slot
+ *     t + r (mod S) of the input, S = N/2 slots. It is applied as at most
+ *     rot_digits key-switched steps of the form r_t * 2^(b t), b =
+ *     ceil(log2 S / rot_digits) (a rotation by 0 is the identity).
+ *   - Coefficient-domain exports hold residues in [0, q_i), layout
+ *     [component][limb][coefficient], limb i modulo the i-th Q prime.
+ */
+#ifndef FHE_SPMSPM_H
+#define FHE_SPMSPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FHE_OK 0
+#define FHE_EINVAL (-1)  /* malformed argument (bad CSR/CSC, NULL, out-of-range value) */
+#define FHE_ESHAPE (-2)  /* incompatible shapes (A.cols != B.rows, buffer too small, level mismatch) */
+#define FHE_ELEVEL (-3)  /* not enough Q primes left for the operation (the method needs >= 3) */
+#define FHE_EKEY (-4)    /* a rotation key needed by the operation was not generated */
+#define FHE_ENOMEM (-5)  /* device allocation failed */
+#define FHE_EAGAIN (-6)  /* resource temporarily unavailable */
+#define FHE_EDEVICE (-7) /* HIP runtime error */
+
+typedef struct fhe_ctx fhe_ctx; /* parameters, device tables and evaluation keys (server side) */
+typedef struct fhe_sk fhe_sk;   /* secret key (client side) */
+typedef struct fhe_mat fhe_mat; /* encrypted matrix: public shape/pattern + ciphertext chunks */
+typedef struct fhe_ct fhe_ct;   /* a single ciphertext (operation-level interface) */
+
+/* RNS-CKKS parameter set (Section 2.1 describes CKKS; the paper fixes no values).
+ * Q primes: the n_q largest primes q < 2^q_bits with q = 1 (mod 2N), descending (q_0 > q_1 > ...).
+ * P primes: the n_p largest primes p < 2^p_bits with p = 1 (mod 2N), descending.
+ * Key switching is hybrid with `alpha` Q primes per digit. Scales: the CSR operand is encoded at
+ * 2^log_delta, the CSC operand at exactly q_(n_q-1), the one-hot mask at 2^mask_bits * q_(n_q-2);
+ * products of the method therefore end at scale exactly 2^(log_delta + mask_bits). */
+typedef struct fhe_params_desc {
+  int32_t log_n;      /* N = 2^log_n, 10 <= log_n <= 17 */
+  int32_t n_q;        /* number of Q primes, 3 <= n_q <= 64 */
+  int32_t q_bits;     /* bits of the Q primes, 30 <= q_bits <= 50 */
+  int32_t n_p;        /* number of special primes K, 1 <= n_p <= 8 */
+  int32_t p_bits;     /* bits of the special primes, q_bits < p_bits <= 61 */
+  int32_t alpha;      /* Q primes per key-switching digit, 1 <= alpha <= n_q */
+  int32_t rot_digits; /* D: key-switched steps per rotation, 1 <= D <= log2(N/2) */
+  int32_t log_delta;  /* scale of the CSR operand, 2^log_delta */
+  int32_t mask_bits;  /* s: mask scale 2^s * q_(n_q-2) */
+  int32_t device;     /* HIP device ordinal */
+} fhe_params_desc;
+
+/* Device allocator hooks: alloc(size, stream, user) returns device memory or NULL;
+ * free_(ptr, stream, user). Passing NULL for both restores hipMalloc/hipFree. Must be set before
+ * fhe_params_create; objects keep the hooks that were current when they were created. */
+typedef void* (*fhe_alloc_fn)(size_t size, void* stream, void* user);
+typedef void (*fhe_free_fn)(void* ptr, void* stream, void* user);
+int fhe_set_allocator(fhe_alloc_fn alloc, fhe_free_fn free_, void* user);
+
+/* Creates a context: prime chain, NTT tables, base-conversion and rescale constants and the
+ * transformed base mask, all resident on `desc->device`. Errors: FHE_EINVAL (desc out of range,
+ * not enough primes), FHE_ELEVEL (n_q < 3), FHE_ENOMEM, FHE_EDEVICE. */
+int fhe_params_create(const fhe_params_desc* desc, fhe_ctx** out);
+void fhe_ctx_free(fhe_ctx* ctx);
+
+/* Copies the moduli q_0..q_(n_q-1), p_0..p_(n_p-1) into out[cap]; returns their count (or < 0). */
+int fhe_ctx_primes(const fhe_ctx* ctx, uint64_t* out, size_t cap);
+
+/* Key generation (the paper's client holds the secret, Figure 1). Samples the ternary secret from
+ * `seed` and installs the relinearisation key (target s^2) into ctx. With rot_digits >= 2 it also
+ * installs every digit rotation key r_t * 2^(b t) (r_t in [1, 2^b)); with rot_digits == 1 rotation
+ * keys are generated on demand by fhe_keygen_rotations. Keys stay resident on the device
+ * (Section 3: ciphertexts and keys are uploaded once). Randomness: SplitMix64 streams keyed by
+ * (seed, object tag); this generator is reproducible, not cryptographically secure. */
+int fhe_keygen(fhe_ctx* ctx, uint64_t seed, void* stream, fhe_sk** sk_out);
+void fhe_sk_free(fhe_sk* sk);
+
+/* Installs the rotation keys needed to rotate left by each of amounts[0..n) (amounts are taken
+ * mod S; keys already present are skipped). Errors: FHE_EINVAL. */
+int fhe_keygen_rotations(fhe_ctx* ctx, const fhe_sk* sk, const int32_t* amounts, size_t n, void* stream);
+
+/* Encrypts a CSR matrix (left operand, Algorithm 1): indptr[rows+1], indices[nnz] (column ids,
+ * strictly ascending per row), values[nnz]. Values are packed in CSR order, S per ciphertext chunk,
+ * encoded at 2^log_delta and encrypted under the secret key at the top level with the SplitMix64
+ * stream `seed`. The pattern is kept in the handle as public metadata (Section 3.2.1).
+ * Errors: FHE_EINVAL (pattern malformed: indptr not non-decreasing from 0 to nnz, index out of
+ * range or not strictly ascending). */
+int fhe_encrypt_csr(fhe_ctx* ctx, const fhe_sk* sk, int32_t rows, int32_t cols, const int32_t* indptr,
+                    const int32_t* indices, const double* values, uint64_t seed, void* stream, fhe_mat** out);
+
+/* Encrypts a CSC matrix (right operand): indptr[cols+1], indices[nnz] (row ids, strictly ascending
+ * per column), values[nnz] in CSC order, encoded at exactly q_(n_q-1). Same errors as above. */
+int fhe_encrypt_csc(fhe_ctx* ctx, const fhe_sk* sk, int32_t rows, int32_t cols, const int32_t* indptr,
+                    const int32_t* indices, const double* values, uint64_t seed, void* stream, fhe_mat** out);
+
+/* C = A B (Algorithms 1 and 2). A: CSR handle (rows m, cols k); B: CSC handle (rows k, cols n).
+ * C is a dense encrypted m x n matrix packed row-major, S slots per chunk, two levels below the
+ * top, at scale 2^(log_delta + mask_bits). Its ciphertext limbs are bit-identical to performing
+ * every matched pair's operation sequence one by one, in any order. Errors: FHE_EINVAL (wrong
+ * handle kinds), FHE_ESHAPE (A.cols != B.rows), FHE_EKEY (a rotation key is missing). */
+int fhe_spmspm(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, void* stream, fhe_mat** C_out);
+
+/* As fhe_spmspm, restricted to the matched pairs with index in [pair_begin, pair_end) of
+ * Algorithm 1's traversal order (i-major, then j, then the merge). Used to check sampled
+ * contributions at full size. */
+int fhe_spmspm_pairs(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t pair_begin, int64_t pair_end,
+                     void* stream, fhe_mat** C_out);
+
+/* Plan statistics of A B without running it: counts[0] = matched pairs F, [1] = distinct products,
+ * [2] = alignment key switches, [3] = product relinearisations, [4] = target-rotation key switches,
+ * [5] = result chunks. Errors as fhe_spmspm. */
+int fhe_plan_stats(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t counts[6]);
+
+/* The distinct rotation step amounts the plan for A B uses (each < S); writes up to cap of them into
+ * out and the total into *n_out. Feed them to fhe_keygen_rotations when rot_digits == 1. */
+int fhe_plan_rotations(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int32_t* out, size_t cap, size_t* n_out);
+
+/* Decrypts and decodes a matrix handle into out[rows * cols] (row-major; for an encrypted CSR/CSC
+ * operand, out receives its values array in packing order instead, length nnz). Decryption uses the
+ * exact CRT of limbs q_0, q_1; decoding divides by the handle's scale. */
+int fhe_decrypt_decode(fhe_ctx* ctx, const fhe_sk* sk, const fhe_mat* M, void* stream, double* out, size_t cap);
+
+/* Shape of a matrix handle: kind (0 = CSR operand, 1 = CSC operand, 2 = dense result), rows, cols,
+ * number of ciphertext chunks, active Q limbs per chunk, scale. Any out-pointer may be NULL. */
+int fhe_mat_info(const fhe_mat* M, int32_t* kind, int32_t* rows, int32_t* cols, int32_t* chunks, int32_t* limbs,
+                 double* scale);
+
+/* Exports ciphertext chunk `chunk` of M in the coefficient domain into out[cap] (uint64,
+ * [2][limbs][N]). Errors: FHE_ESHAPE if cap is too small, FHE_EINVAL for a bad chunk index. */
+int fhe_mat_export(fhe_ctx* ctx, const fhe_mat* M, int32_t chunk, uint64_t* out, size_t cap, void* stream);
+void fhe_mat_free(fhe_mat* M);
+
+/* ---- Operation-level interface on single ciphertexts (the operations Algorithm 2 issues). ---- */
+
+/* Imports a ciphertext given in the coefficient domain: coeffs[ncomp][limbs][N], residues < q_i,
+ * ncomp in {2, 3}, 1 <= limbs <= n_q. */
+int fhe_ct_import(fhe_ctx* ctx, const uint64_t* coeffs, int32_t ncomp, int32_t limbs, double scale, void* stream,
+                  fhe_ct** out);
+/* Exports in the coefficient domain into out[cap] ([ncomp][limbs][N]). */
+int fhe_ct_export(fhe_ctx* ctx, const fhe_ct* ct, uint64_t* out, size_t cap, void* stream);
+int fhe_ct_info(const fhe_ct* ct, int32_t* ncomp, int32_t* limbs, double* scale);
+/* EvalRotate: left rotation by r (automorphism tau_(5^step) + hybrid key switch per step). */
+int fhe_ct_rotate(fhe_ctx* ctx, const fhe_ct* ct, int32_t r, void* stream, fhe_ct** out);
+/* EvalMult + Relinearize of two 2-component ciphertexts at the same level (scale multiplies). */
+int fhe_ct_mult_relin(fhe_ctx* ctx, const fhe_ct* a, const fhe_ct* b, void* stream, fhe_ct** out);
+/* Rescale: drops the last limb with nearest rounding (scale /= dropped prime). Needs >= 2 limbs. */
+int fhe_ct_rescale(fhe_ctx* ctx, const fhe_ct* ct, void* stream, fhe_ct** out);
+/* Plaintext multiply by the one-hot mask at `slot` (scale *= 2^mask_bits * q_(n_q-2)). */
+int fhe_ct_mask(fhe_ctx* ctx, const fhe_ct* ct, int32_t slot, void* stream, fhe_ct** out);
+/* EvalAdd of two ciphertexts of equal shape. */
+int fhe_ct_add(fhe_ctx* ctx, const fhe_ct* a, const fhe_ct* b, void* stream, fhe_ct** out);
+void fhe_ct_free(fhe_ct* ct);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* fhe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FHE_SPMSPM_H */

@@ -1,0 +1,122 @@
+// Internal types of the library: errors, device buffers, parameter set, context and handles.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "arith.h"
+#include "fhe_spmspm.h"
+
+namespace fhe {
+
+// Internal failures are thrown as Error and converted to return codes at the C boundary.
+struct Error {
+  int code;
+  std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string& msg);
+void hip_check(hipError_t e, const char* what, const char* file, int line);
+#define HIPCHECK(x) ::fhe::hip_check((x), #x, __FILE__, __LINE__)
+
+struct Allocator {
+  fhe_alloc_fn alloc = nullptr;
+  fhe_free_fn free_ = nullptr;
+  void* user = nullptr;
+};
+Allocator current_allocator();
+
+// Owning device buffer, allocated and released through the registered allocator.
+class DevBuf {
+ public:
+  DevBuf() = default;
+  DevBuf(size_t bytes, hipStream_t stream);
+  ~DevBuf() { reset(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept { *this = std::move(o); }
+  DevBuf& operator=(DevBuf&& o) noexcept;
+  void reset();
+  uint64_t* u64() const { return (uint64_t*)ptr_; }
+  void* get() const { return ptr_; }
+  size_t bytes() const { return bytes_; }
+
+ private:
+  void* ptr_ = nullptr;
+  size_t bytes_ = 0;
+  hipStream_t stream_ = nullptr;
+  Allocator al_;
+};
+
+// Copies a host vector into a new device buffer (synchronous with respect to the host).
+template <class T>
+DevBuf upload(const std::vector<T>& v, hipStream_t stream) {
+  DevBuf b(v.size() * sizeof(T) + 8, stream);
+  if (!v.empty()) HIPCHECK(hipMemcpyAsync(b.get(), v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, stream));
+  HIPCHECK(hipStreamSynchronize(stream));
+  return b;
+}
+
+struct Params {
+  fhe_params_desc d;
+  uint32_t N = 0, logN = 0, S = 0;
+  int nq = 0, np = 0, alpha = 1, rot_digits = 1, rot_bits = 0;
+  std::vector<uint64_t> moduli;  // q_0..q_{nq-1}, p_0..p_{np-1}
+  int nmod() const { return nq + np; }
+  int beta(int nl) const { return (nl + alpha - 1) / alpha; }
+  // NTT split: phase 1 transforms columns of 2^k1 elements, phase 2 rows of 2^(logN-k1).
+  uint32_t k1 = 0, logE = 0;
+};
+
+// Constant tables for one context (all in device memory).
+struct Tables {
+  DevBuf mods;     // ModInfo[nmod]
+  DevBuf tw;       // per modulus: fwd[N], fwd_shoup[N], inv[N], inv_shoup[N]
+  DevBuf modup;    // per (nl, digit): see modup_offset
+  DevBuf moddown;  // phat_inv[K][2], phat_mod_q[K][nq][2], pinv_mod_q[nq][2]
+  DevBuf rescale;  // ql_inv[l][i][2] = (q_l^-1 mod q_i, shoup), l < nq, i < l
+  DevBuf mask;     // NTT of the base mask on limbs 0..nq-2, Montgomery form: [nq-1][N]
+  std::vector<size_t> modup_offset;  // index nl (1..nq): offset (uint64 units) of the nl block
+  std::vector<int64_t> base_mask;    // coefficient-domain base mask (host copy)
+};
+
+struct SwitchKey {
+  DevBuf buf;  // [beta_top][2][nq+np][N], NTT domain, Montgomery form
+};
+
+}  // namespace fhe
+
+struct fhe_ctx {
+  fhe::Params p;
+  int device = 0;
+  fhe::Allocator al;
+  fhe::Tables t;
+  std::unique_ptr<fhe::SwitchKey> relin;
+  std::map<uint32_t, std::unique_ptr<fhe::SwitchKey>> rot;  // keyed by Galois element 5^r mod 2N
+};
+
+struct fhe_sk {
+  std::vector<int64_t> s;  // ternary secret, coefficient domain
+  fhe::DevBuf s_ntt;       // [nq+np][N], NTT domain (normal form)
+  uint64_t seed = 0;
+};
+
+struct fhe_ct {
+  int ncomp = 2, nl = 0;
+  double scale = 1.0;
+  fhe::DevBuf data;  // [ncomp][nl][N], NTT domain
+};
+
+struct fhe_mat {
+  int kind = 0;  // 0 CSR operand, 1 CSC operand, 2 dense result
+  int rows = 0, cols = 0;
+  std::vector<int32_t> indptr, indices;  // public pattern (operands)
+  int64_t nnz = 0;
+  int nl = 0, nchunks = 0;
+  double scale = 1.0;
+  fhe::DevBuf data;  // [nchunks][2][nl][N], NTT domain
+  uint64_t* chunk(int c, uint32_t N) const { return data.u64() + (size_t)c * 2 * nl * N; }
+};

@@ -1,0 +1,82 @@
+// Launchers of the gfx950 kernels. All pointers are device pointers; arrays of per-item pointers
+// (`const uint64_t* const*` etc.) live in device memory. Every launcher enqueues on `st`.
+#pragma once
+#include "common.h"
+
+namespace fhe {
+
+// A batch of limbs to transform: poly p, limb e is at base + p * poly_stride + e * N and uses
+// modulus index e (e < n_first) or p_base + (e - n_first) (e >= n_first).
+struct LimbBatch {
+  uint64_t* base;
+  uint32_t limbs;
+  uint32_t npoly;
+  uint64_t poly_stride;
+  uint32_t n_first;
+  uint32_t p_base;
+};
+
+// Negacyclic NTT, in place. Forward: coefficients -> evaluations at psi^(2 brv(i) + 1) (bit-reversed
+// order); inverse: back to coefficients (N^-1 included).
+void ntt_forward(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st);
+void ntt_inverse(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st);
+
+// dst[b] = tau_(galois[b]) (src[b]) in the NTT domain; src[b] is [ncomp][nl][N]; dst contiguous
+// [B][ncomp][nl][N].
+void automorph(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const uint64_t* const* src,
+               const uint32_t* galois, uint64_t* dst, hipStream_t st);
+
+// out (contiguous [B][3][nl][N]) = (a0 b0, a0 b1 + a1 b0, a1 b1) per item, NTT domain.
+void tensor(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* const* a, const uint64_t* const* b,
+            uint64_t* out, hipStream_t st);
+
+// Hybrid key switch of B polynomials at nl limbs (NTT domain). Input item b is `in + b * in_stride`
+// ([nl][N]) and is overwritten. keys[b]: switching key. add[2b + c] (may be NULL): [nl][N] added to
+// output component c. out[b]: [2][nl][N]. ws: keyswitch_ws_elems(ctx, B, nl) uint64 of workspace.
+size_t keyswitch_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t nl);
+void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, uint64_t* in, uint64_t in_stride,
+               const uint64_t* const* keys, const uint64_t* const* add, uint64_t* const* out, uint64_t* ws,
+               hipStream_t st);
+
+// Rescale of B ciphertexts [ncomp][nl][N] -> [ncomp][nl-1][N] (nearest rounding of the dropped limb).
+size_t rescale_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl);
+void rescale(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const uint64_t* const* in,
+             uint64_t* const* out, uint64_t* ws, hipStream_t st);
+
+// out[b] = in[b] * tau_(galois[b])(base mask) (one-hot mask), [2][nl][N], nl <= nq - 1.
+void mask_mul(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* const* in, const uint32_t* galois,
+              uint64_t* const* out, hipStream_t st);
+
+// result[seg[3s]] += sum of contrib[b] for b in [seg[3s+1], seg[3s+2]); [2][nl][N] each.
+void accumulate(const fhe_ctx* ctx, uint32_t nseg, uint32_t nl, const uint32_t* seg, const uint64_t* contrib,
+                uint64_t* result, hipStream_t st);
+
+// out[e][k] = v[k] mod modulus(e) for e < nlimbs (modulus index rule as in LimbBatch).
+void signed_to_limbs(const fhe_ctx* ctx, const int64_t* v, uint32_t nlimbs, uint32_t n_first, uint32_t p_base,
+                     uint64_t* out, hipStream_t st);
+
+// x -> x R mod q (Montgomery form) on [nlimbs][N], modulus index rule as above.
+void to_montgomery(const fhe_ctx* ctx, uint64_t* x, uint32_t nlimbs, uint32_t n_first, uint32_t p_base,
+                   hipStream_t st);
+
+// Switching-key digit on all nall limbs (NTT domain): b = e - a s + pfac_i s' (pfac_i = 0 outside the
+// digit); writes b and a in Montgomery form. pfac: [nall] (device).
+void keygen_digit(const fhe_ctx* ctx, uint32_t nall, const uint64_t* a, const uint64_t* s, const uint64_t* e,
+                  const uint64_t* sp, const uint64_t* pfac, uint64_t* bout, uint64_t* aout, hipStream_t st);
+
+// s2 = s * s pointwise on [nall][N] (NTT domain).
+void square(const fhe_ctx* ctx, uint32_t nall, const uint64_t* s, uint64_t* s2, hipStream_t st);
+
+// Encryption: c0 = em - a s, c1 = a on [nl][N] (NTT domain); ct = [2][nl][N].
+void encrypt_combine(const fhe_ctx* ctx, uint32_t nl, const uint64_t* a, const uint64_t* em, const uint64_t* s,
+                     uint64_t* ct, hipStream_t st);
+
+// m = c0 + c1 s on limbs [0, nlim) of ct [2][nl][N] (NTT domain) -> m [nlim][N].
+void decrypt_combine(const fhe_ctx* ctx, uint32_t nl, uint32_t nlim, const uint64_t* ct, const uint64_t* s,
+                     uint64_t* m, hipStream_t st);
+
+// out = a + b, elementwise mod q on [ncomp][nl][N].
+void add_ct(const fhe_ctx* ctx, uint32_t ncomp, uint32_t nl, const uint64_t* a, const uint64_t* b, uint64_t* out,
+            hipStream_t st);
+
+}  // namespace fhe

@@ -1,0 +1,329 @@
+// Planner and batched executor for the CSR x CSC ciphertext matmul.
+//
+// The planner walks Algorithm 1 (every row i of A against every column j of B, a two-pointer merge
+// of A's column ids and B's row ids) and records, for each match, the operand chunks, the alignment
+// rotation (only the operand holding the later slot is rotated, by the slot difference), the
+// isolated slot min_pos and the target rotation of Algorithm 2. Matched pairs that share
+// (chunk of A, chunk of B, alignment) share the aligned product EvalMult -> Relinearize -> Rescale
+// bit for bit, so the executor computes each such product once.
+//
+// The executor runs the per-pair sequence for many pairs at a time: each step (automorphism, key
+// switch, tensor, rescale, mask multiply, accumulation) is one batched launch over a group of
+// ciphertexts, which is what keeps 256 CUs busy with N = 2^13..2^17 limbs.
+#include "spmspm.h"
+
+#include <algorithm>
+#include <cstdlib>
+#include <functional>
+#include <unordered_map>
+
+namespace fhe {
+
+void check_pattern(int32_t outer, int32_t inner, const int32_t* indptr, const int32_t* indices) {
+  if (outer < 0 || inner < 0) fail(FHE_EINVAL, "negative matrix dimension");
+  if (!indptr) fail(FHE_EINVAL, "indptr is NULL");
+  if (indptr[0] != 0) fail(FHE_EINVAL, "indptr[0] must be 0");
+  for (int32_t r = 0; r < outer; ++r) {
+    if (indptr[r + 1] < indptr[r]) fail(FHE_EINVAL, "indptr must be non-decreasing");
+    for (int32_t k = indptr[r]; k < indptr[r + 1]; ++k) {
+      if (!indices) fail(FHE_EINVAL, "indices is NULL");
+      if (indices[k] < 0 || indices[k] >= inner) fail(FHE_EINVAL, "index out of range");
+      if (k > indptr[r] && indices[k] <= indices[k - 1]) fail(FHE_EINVAL, "indices must be strictly ascending");
+    }
+  }
+}
+
+Plan build_plan(const Params& p, const fhe_mat* A, const fhe_mat* B, int64_t begin, int64_t end) {
+  Plan plan;
+  const int64_t S = p.S;
+  const int m = A->rows, n = B->cols;
+  plan.nres = (int)std::max<int64_t>(1, ((int64_t)m * n + S - 1) / S);
+  std::unordered_map<uint64_t, int32_t> prod_id;
+  int64_t idx = 0;
+  for (int i = 0; i < m; ++i) {
+    const int32_t a_end = A->indptr[i + 1];
+    for (int j = 0; j < n; ++j) {
+      int32_t a_pos = A->indptr[i], b_pos = B->indptr[j];
+      const int32_t b_end = B->indptr[j + 1];
+      while (a_pos < a_end && b_pos < b_end) {
+        const int32_t a_col = A->indices[a_pos], b_row = B->indices[b_pos];
+        if (a_col == b_row) {
+          if (idx >= begin && idx < end) {
+            const int32_t ca = (int32_t)(a_pos / S), la = (int32_t)(a_pos % S);
+            const int32_t cb = (int32_t)(b_pos / S), lb = (int32_t)(b_pos % S);
+            const int32_t d = lb - la, mn = std::min(la, lb);
+            const uint64_t key = ((uint64_t)ca << 42) | ((uint64_t)cb << 21) | (uint64_t)(d + S);
+            auto it = prod_id.find(key);
+            int32_t pid;
+            if (it == prod_id.end()) {
+              pid = (int32_t)plan.prods.size();
+              prod_id.emplace(key, pid);
+              plan.prods.push_back(PlanProduct{ca, cb, d});
+            } else {
+              pid = it->second;
+            }
+            const int64_t t = (int64_t)i * n + j;
+            const int32_t cr = (int32_t)(t / S), lt = (int32_t)(t % S);
+            const uint32_t rot = (uint32_t)(((int64_t)mn - lt) % S + S) % S;
+            plan.pairs.push_back(PlanPair{pid, mn, cr, rot});
+          }
+          ++idx;
+          ++a_pos;
+          ++b_pos;
+        } else if (a_col < b_row) {
+          ++a_pos;
+        } else {
+          ++b_pos;
+        }
+      }
+    }
+  }
+  plan.matched = idx;
+  return plan;
+}
+
+void plan_counts(const Params& p, const Plan& plan, int64_t out[6]) {
+  int64_t align = 0, target = 0;
+  for (const auto& pr : plan.prods) align += (int64_t)rotation_steps(p, pr.d > 0 ? pr.d : -pr.d).size();
+  for (const auto& pa : plan.pairs) target += (int64_t)rotation_steps(p, pa.rot).size();
+  out[0] = (int64_t)plan.pairs.size();
+  out[1] = (int64_t)plan.prods.size();
+  out[2] = align;
+  out[3] = (int64_t)plan.prods.size();
+  out[4] = target;
+  out[5] = plan.nres;
+}
+
+namespace {
+
+struct Workspace {
+  uint64_t *align = nullptr, *rtmp = nullptr, *tens = nullptr, *pfull = nullptr, *prod = nullptr;
+  uint64_t *msk = nullptr, *cur = nullptr, *ksws = nullptr, *rsws = nullptr;
+};
+
+size_t workspace_budget_bytes() {
+  const char* e = getenv("FHE_WORKSPACE_MB");
+  size_t mb = e ? (size_t)atoll(e) : (size_t)24576;
+  if (mb < 64) mb = 64;
+  return mb << 20;
+}
+
+// One batched rotation step over `items`: src[b] -> out[b] rotated left by steps[b] (one key switch).
+void enqueue_rotation(fhe_ctx* ctx, ArgPack& ap, std::vector<std::function<void()>>& ops, uint32_t nl,
+                      const std::vector<const uint64_t*>& src, const std::vector<uint32_t>& steps,
+                      const std::vector<uint64_t*>& out, const Workspace& ws, hipStream_t st) {
+  const Params& p = ctx->p;
+  const uint32_t N = p.N, B = (uint32_t)src.size();
+  if (!B) return;
+  std::vector<uint32_t> gal(B);
+  std::vector<const uint64_t*> keys(B), add(2 * B);
+  for (uint32_t b = 0; b < B; ++b) {
+    gal[b] = galois_of_step(p, steps[b]);
+    keys[b] = rotation_key(ctx, steps[b])->buf.u64();
+    add[2 * b] = ws.rtmp + (size_t)b * 2 * nl * N;
+    add[2 * b + 1] = nullptr;
+  }
+  const size_t o_src = ap.push(src), o_g = ap.push(gal), o_k = ap.push(keys), o_a = ap.push(add), o_o = ap.push(out);
+  ops.push_back([=, &ap] {
+    automorph(ctx, B, 2, nl, ap.at<const uint64_t*>(o_src), ap.at<uint32_t>(o_g), ws.rtmp, st);
+    keyswitch(ctx, B, nl, ws.rtmp + (size_t)nl * N, (uint64_t)2 * nl * N, ap.at<const uint64_t*>(o_k),
+              ap.at<const uint64_t*>(o_a), ap.at<uint64_t*>(o_o), ws.ksws, st);
+  });
+}
+
+}  // namespace
+
+void execute_plan(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, const Plan& plan, hipStream_t st, fhe_mat* C) {
+  const Params& p = ctx->p;
+  const uint32_t N = p.N, nq = p.nq, nl1 = nq - 1, nl2 = nq - 2;
+  C->kind = 2;
+  C->rows = A->rows;
+  C->cols = B->cols;
+  C->nl = nl2;
+  C->nchunks = plan.nres;
+  C->scale = std::ldexp(1.0, p.d.log_delta + p.d.mask_bits);
+  const size_t chunk_elems = (size_t)2 * nl2 * N;
+  C->data = DevBuf((size_t)plan.nres * chunk_elems * 8, st);
+  HIPCHECK(hipMemsetAsync(C->data.get(), 0, (size_t)plan.nres * chunk_elems * 8, st));
+  if (plan.pairs.empty()) {
+    HIPCHECK(hipStreamSynchronize(st));
+    return;
+  }
+  for (const auto& pr : plan.prods) {
+    if (pr.ca >= A->nchunks || pr.cb >= B->nchunks) fail(FHE_EINVAL, "plan references a missing operand chunk");
+    if (pr.d != 0) (void)rotation_steps(p, pr.d > 0 ? pr.d : -pr.d);
+  }
+  if (!ctx->relin) fail(FHE_EKEY, "relinearisation key not generated");
+  for (const auto& pa : plan.pairs)
+    for (uint32_t s : rotation_steps(p, pa.rot)) (void)rotation_key(ctx, s);
+  for (const auto& pr : plan.prods)
+    for (uint32_t s : rotation_steps(p, pr.d > 0 ? pr.d : -pr.d)) (void)rotation_key(ctx, s);
+
+  // Pairs grouped by product (stable: traversal order inside a product).
+  const size_t nprod = plan.prods.size();
+  std::vector<size_t> first(nprod + 1, 0);
+  for (const auto& pa : plan.pairs) ++first[pa.prod + 1];
+  for (size_t i = 0; i < nprod; ++i) first[i + 1] += first[i];
+  std::vector<uint32_t> by_prod(plan.pairs.size());
+  {
+    std::vector<size_t> fill(first.begin(), first.end() - 1);
+    for (size_t k = 0; k < plan.pairs.size(); ++k) by_prod[fill[plan.pairs[k].prod]++] = (uint32_t)k;
+  }
+
+  // Batch sizes from the workspace budget.
+  const size_t e = 8ull * N;
+  const size_t per_prod = e * (2 * nq + 3 * nq + 2 * nq + 2 * nl1 + 2 * nq) +
+                          8 * (keyswitch_ws_elems(ctx, 1, nq) + rescale_ws_elems(ctx, 1, 2, nq));
+  const size_t per_pair = e * (2 * nl1 + 2 * nl2 + 2 * nl2) +
+                          8 * (keyswitch_ws_elems(ctx, 1, nl2) + rescale_ws_elems(ctx, 1, 2, nl1));
+  const size_t budget = workspace_budget_bytes();
+  size_t PB = std::max<size_t>(1, std::min<size_t>(nprod, (budget / 3) / per_prod));
+  size_t BB = std::max<size_t>(1, std::min<size_t>(plan.pairs.size(), (2 * budget / 3) / per_pair));
+  PB = std::min<size_t>(PB, 4096);
+  BB = std::min<size_t>(BB, 8192);
+
+  Workspace ws;
+  DevBuf wsbuf;
+  const size_t rt = std::max<size_t>(PB * 2 * nq, BB * 2 * nl2) * N;
+  const size_t sz_align = PB * 2 * nq * N, sz_tens = PB * 3 * nq * N, sz_pfull = PB * 2 * nq * N,
+               sz_prod = PB * 2 * nl1 * N, sz_msk = BB * 2 * nl1 * N, sz_cur = BB * 2 * nl2 * N;
+  const size_t sz_ks = std::max(keyswitch_ws_elems(ctx, (uint32_t)PB, nq), keyswitch_ws_elems(ctx, (uint32_t)BB, nl2));
+  const size_t sz_rs =
+      std::max(rescale_ws_elems(ctx, (uint32_t)PB, 2, nq), rescale_ws_elems(ctx, (uint32_t)BB, 2, nl1));
+  const size_t total = sz_align + rt + sz_tens + sz_pfull + sz_prod + sz_msk + sz_cur + sz_ks + sz_rs;
+  wsbuf = DevBuf(total * 8, st);
+  uint64_t* w = wsbuf.u64();
+  ws.align = w; w += sz_align;
+  ws.rtmp = w; w += rt;
+  ws.tens = w; w += sz_tens;
+  ws.pfull = w; w += sz_pfull;
+  ws.prod = w; w += sz_prod;
+  ws.msk = w; w += sz_msk;
+  ws.cur = w; w += sz_cur;
+  ws.ksws = w; w += sz_ks;
+  ws.rsws = w;
+
+  std::vector<std::unique_ptr<ArgPack>> packs;
+  for (size_t p0 = 0; p0 < nprod; p0 += PB) {
+    const size_t p1 = std::min(nprod, p0 + PB), npb = p1 - p0;
+    packs.emplace_back(new ArgPack());
+    ArgPack& ap = *packs.back();
+    std::vector<std::function<void()>> ops;
+
+    // (1) Alignment rotations (Algorithm 1): rotate the operand whose value sits at the later slot.
+    std::vector<const uint64_t*> cur_src(npb), opa(npb), opb(npb);
+    std::vector<std::vector<uint32_t>> steps(npb);
+    for (size_t k = 0; k < npb; ++k) {
+      const PlanProduct& pr = plan.prods[p0 + k];
+      opa[k] = A->chunk(pr.ca, N);
+      opb[k] = B->chunk(pr.cb, N);
+      cur_src[k] = pr.d > 0 ? opb[k] : opa[k];
+      steps[k] = rotation_steps(p, pr.d > 0 ? pr.d : -pr.d);
+      uint64_t* al = ws.align + k * 2 * nq * N;
+      if (pr.d > 0) opb[k] = al;
+      if (pr.d < 0) opa[k] = al;
+    }
+    for (int t = 0; t < p.rot_digits; ++t) {
+      std::vector<const uint64_t*> src;
+      std::vector<uint32_t> st_amt;
+      std::vector<uint64_t*> out;
+      const uint32_t b = p.rot_bits, mask = (1u << b) - 1;
+      for (size_t k = 0; k < npb; ++k) {
+        const PlanProduct& pr = plan.prods[p0 + k];
+        if (pr.d == 0) continue;
+        const uint32_t amt = (uint32_t)((pr.d > 0 ? pr.d : -pr.d) % (int32_t)p.S);
+        const uint32_t rt_ = (amt >> (b * t)) & mask;
+        if (!rt_) continue;
+        uint64_t* al = ws.align + k * 2 * nq * N;
+        src.push_back(cur_src[k]);
+        st_amt.push_back(rt_ << (b * t));
+        out.push_back(al);
+        cur_src[k] = al;
+      }
+      enqueue_rotation(ctx, ap, ops, nq, src, st_amt, out, ws, st);
+    }
+    // (2) EvalMult + Relinearize + Rescale (Algorithm 2, first three steps), once per product.
+    {
+      std::vector<const uint64_t*> keys(npb, ctx->relin->buf.u64()), add(2 * npb), pin(npb);
+      std::vector<uint64_t*> pout(npb), rout(npb);
+      for (size_t k = 0; k < npb; ++k) {
+        add[2 * k] = ws.tens + k * 3 * nq * N;
+        add[2 * k + 1] = ws.tens + k * 3 * nq * N + (size_t)nq * N;
+        pout[k] = ws.pfull + k * 2 * nq * N;
+        pin[k] = pout[k];
+        rout[k] = ws.prod + k * 2 * nl1 * N;
+      }
+      const size_t o_a = ap.push(opa), o_b = ap.push(opb), o_k = ap.push(keys), o_ad = ap.push(add),
+                   o_po = ap.push(pout), o_pi = ap.push(pin), o_ro = ap.push(rout);
+      const uint32_t Bn = (uint32_t)npb;
+      ops.push_back([=, &ap] {
+        tensor(ctx, Bn, nq, ap.at<const uint64_t*>(o_a), ap.at<const uint64_t*>(o_b), ws.tens, st);
+        keyswitch(ctx, Bn, nq, ws.tens + (size_t)2 * nq * N, (uint64_t)3 * nq * N, ap.at<const uint64_t*>(o_k),
+                  ap.at<const uint64_t*>(o_ad), ap.at<uint64_t*>(o_po), ws.ksws, st);
+        rescale(ctx, Bn, 2, nq, ap.at<const uint64_t*>(o_pi), ap.at<uint64_t*>(o_ro), ws.rsws, st);
+      });
+    }
+    // (3) Pairs of these products: mask, rescale, target rotation, accumulate.
+    std::vector<uint32_t> pairs(by_prod.begin() + first[p0], by_prod.begin() + first[p1]);
+    std::stable_sort(pairs.begin(), pairs.end(), [&](uint32_t x, uint32_t y) {
+      const PlanPair &a = plan.pairs[x], &b = plan.pairs[y];
+      if (a.chunk != b.chunk) return a.chunk < b.chunk;
+      return a.rot < b.rot;
+    });
+    for (size_t q0 = 0; q0 < pairs.size(); q0 += BB) {
+      const size_t q1 = std::min(pairs.size(), q0 + BB), nb = q1 - q0;
+      std::vector<const uint64_t*> min_(nb), rin(nb);
+      std::vector<uint32_t> mg(nb);
+      std::vector<uint64_t*> mout(nb), cur(nb);
+      for (size_t k = 0; k < nb; ++k) {
+        const PlanPair& pa = plan.pairs[pairs[q0 + k]];
+        min_[k] = ws.prod + (size_t)(pa.prod - p0) * 2 * nl1 * N;
+        mg[k] = mask_galois(p, pa.min_pos);
+        mout[k] = ws.msk + k * 2 * nl1 * N;
+        rin[k] = mout[k];
+        cur[k] = ws.cur + k * 2 * nl2 * N;
+      }
+      const size_t o_mi = ap.push(min_), o_mg = ap.push(mg), o_mo = ap.push(mout), o_ri = ap.push(rin),
+                   o_cu = ap.push(cur);
+      const uint32_t Bn = (uint32_t)nb;
+      ops.push_back([=, &ap] {
+        mask_mul(ctx, Bn, nl1, ap.at<const uint64_t*>(o_mi), ap.at<uint32_t>(o_mg), ap.at<uint64_t*>(o_mo), st);
+        rescale(ctx, Bn, 2, nl1, ap.at<const uint64_t*>(o_ri), ap.at<uint64_t*>(o_cu), ws.rsws, st);
+      });
+      for (int t = 0; t < p.rot_digits; ++t) {
+        std::vector<const uint64_t*> src;
+        std::vector<uint32_t> st_amt;
+        std::vector<uint64_t*> out;
+        const uint32_t b = p.rot_bits, mask = (1u << b) - 1;
+        for (size_t k = 0; k < nb; ++k) {
+          const uint32_t r = plan.pairs[pairs[q0 + k]].rot;
+          const uint32_t rt_ = (r >> (b * t)) & mask;
+          if (!rt_) continue;
+          src.push_back(cur[k]);
+          st_amt.push_back(rt_ << (b * t));
+          out.push_back(cur[k]);
+        }
+        enqueue_rotation(ctx, ap, ops, nl2, src, st_amt, out, ws, st);
+      }
+      std::vector<uint32_t> seg;
+      for (size_t k = 0; k < nb;) {
+        const int32_t ch = plan.pairs[pairs[q0 + k]].chunk;
+        size_t k2 = k;
+        while (k2 < nb && plan.pairs[pairs[q0 + k2]].chunk == ch) ++k2;
+        seg.push_back((uint32_t)ch);
+        seg.push_back((uint32_t)k);
+        seg.push_back((uint32_t)k2);
+        k = k2;
+      }
+      const size_t o_sg = ap.push(seg);
+      const uint32_t nseg = (uint32_t)(seg.size() / 3);
+      uint64_t* res = C->data.u64();
+      ops.push_back([=, &ap] { accumulate(ctx, nseg, nl2, ap.at<uint32_t>(o_sg), ws.cur, res, st); });
+    }
+    ap.upload(st);
+    for (auto& op : ops) op();
+  }
+  HIPCHECK(hipStreamSynchronize(st));
+}
+
+}  // namespace fhe

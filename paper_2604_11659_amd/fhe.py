@@ -1,0 +1,324 @@
+"""Python binding of libfhe_spmspm.so (ctypes; argument marshalling only).
+
+Every operation runs in the HIP library; this module converts numpy arrays and
+handles and raises ``FheError`` on a negative return code. Importing it fails
+loudly when the library has not been built (``python -m paper_2604_11659_amd.build``).
+
+Streams: calls take an optional ``stream`` (an int hipStream_t handle or a
+``torch.cuda.Stream``); by default torch's current stream is used when torch
+sees a GPU, else the HIP default stream. Device memory comes from torch's
+caching allocator when ``Context(..., allocator="torch")`` is requested,
+otherwise from hipMalloc.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfhe_spmspm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_11659_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+c_i32, c_i64, c_u64, c_sz, c_dbl, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t,
+                                          ctypes.c_double, ctypes.c_void_p)
+P_i32, P_i64, P_u64, P_dbl = (ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double))
+PP = ctypes.POINTER(ctypes.c_void_p)
+
+FHE_ERRORS = {-1: "EINVAL", -2: "ESHAPE", -3: "ELEVEL", -4: "EKEY", -5: "ENOMEM", -6: "EAGAIN", -7: "EDEVICE"}
+
+
+class fhe_params_desc(ctypes.Structure):
+    _fields_ = [("log_n", c_i32), ("n_q", c_i32), ("q_bits", c_i32), ("n_p", c_i32), ("p_bits", c_i32),
+                ("alpha", c_i32), ("rot_digits", c_i32), ("log_delta", c_i32), ("mask_bits", c_i32),
+                ("device", c_i32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(c_vp, c_sz, c_vp, c_vp)
+FREE_FN = ctypes.CFUNCTYPE(None, c_vp, c_vp, c_vp)
+
+_SIGS = {
+    "fhe_set_allocator": ([ALLOC_FN, FREE_FN, c_vp], c_i32),
+    "fhe_params_create": ([ctypes.POINTER(fhe_params_desc), PP], c_i32),
+    "fhe_ctx_free": ([c_vp], None),
+    "fhe_ctx_primes": ([c_vp, P_u64, c_sz], c_i32),
+    "fhe_keygen": ([c_vp, c_u64, c_vp, PP], c_i32),
+    "fhe_sk_free": ([c_vp], None),
+    "fhe_keygen_rotations": ([c_vp, c_vp, P_i32, c_sz, c_vp], c_i32),
+    "fhe_encrypt_csr": ([c_vp, c_vp, c_i32, c_i32, P_i32, P_i32, P_dbl, c_u64, c_vp, PP], c_i32),
+    "fhe_encrypt_csc": ([c_vp, c_vp, c_i32, c_i32, P_i32, P_i32, P_dbl, c_u64, c_vp, PP], c_i32),
+    "fhe_spmspm": ([c_vp, c_vp, c_vp, c_vp, PP], c_i32),
+    "fhe_spmspm_pairs": ([c_vp, c_vp, c_vp, c_i64, c_i64, c_vp, PP], c_i32),
+    "fhe_plan_stats": ([c_vp, c_vp, c_vp, P_i64], c_i32),
+    "fhe_plan_rotations": ([c_vp, c_vp, c_vp, P_i32, c_sz, ctypes.POINTER(c_sz)], c_i32),
+    "fhe_decrypt_decode": ([c_vp, c_vp, c_vp, c_vp, P_dbl, c_sz], c_i32),
+    "fhe_mat_info": ([c_vp, P_i32, P_i32, P_i32, P_i32, P_i32, P_dbl], c_i32),
+    "fhe_mat_export": ([c_vp, c_vp, c_i32, P_u64, c_sz, c_vp], c_i32),
+    "fhe_mat_free": ([c_vp], None),
+    "fhe_ct_import": ([c_vp, P_u64, c_i32, c_i32, c_dbl, c_vp, PP], c_i32),
+    "fhe_ct_export": ([c_vp, c_vp, P_u64, c_sz, c_vp], c_i32),
+    "fhe_ct_info": ([c_vp, P_i32, P_i32, P_dbl], c_i32),
+    "fhe_ct_rotate": ([c_vp, c_vp, c_i32, c_vp, PP], c_i32),
+    "fhe_ct_mult_relin": ([c_vp, c_vp, c_vp, c_vp, PP], c_i32),
+    "fhe_ct_rescale": ([c_vp, c_vp, c_vp, PP], c_i32),
+    "fhe_ct_mask": ([c_vp, c_vp, c_i32, c_vp, PP], c_i32),
+    "fhe_ct_add": ([c_vp, c_vp, c_vp, c_vp, PP], c_i32),
+    "fhe_ct_free": ([c_vp], None),
+    "fhe_last_error": ([], ctypes.c_char_p),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+class FheError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"FHE_{FHE_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc is not None and rc < 0:
+        raise FheError(rc, _lib.fhe_last_error().decode())
+    return rc
+
+
+def _stream(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:
+            pass
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+_TORCH_HOOKS = None
+
+
+def use_torch_allocator():
+    """Route the library's device allocations through torch's caching allocator."""
+    global _TORCH_HOOKS
+    import torch
+
+    def _alloc(size, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(size), stream=int(stream or 0))
+        except Exception:
+            return None
+
+    def _free(ptr, stream, user):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    _TORCH_HOOKS = (ALLOC_FN(_alloc), FREE_FN(_free))
+    _check(_lib.fhe_set_allocator(_TORCH_HOOKS[0], _TORCH_HOOKS[1], None))
+
+
+class _Handle:
+    _free_fn = None
+
+    def __init__(self, ptr, owner=None):
+        self._ptr = ptr
+        self._owner = owner
+
+    def close(self):
+        if self._ptr:
+            type(self)._free_fn(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SecretKey(_Handle):
+    _free_fn = staticmethod(_lib.fhe_sk_free)
+
+
+class Matrix(_Handle):
+    """Encrypted matrix handle (CSR operand, CSC operand or dense result)."""
+    _free_fn = staticmethod(_lib.fhe_mat_free)
+
+    def info(self):
+        kind, rows, cols, chunks, limbs = (c_i32() for _ in range(5))
+        scale = c_dbl()
+        _check(_lib.fhe_mat_info(self._ptr, ctypes.byref(kind), ctypes.byref(rows), ctypes.byref(cols),
+                                 ctypes.byref(chunks), ctypes.byref(limbs), ctypes.byref(scale)))
+        return dict(kind=kind.value, rows=rows.value, cols=cols.value, chunks=chunks.value, limbs=limbs.value,
+                    scale=scale.value)
+
+
+class Ciphertext(_Handle):
+    _free_fn = staticmethod(_lib.fhe_ct_free)
+
+    def info(self):
+        ncomp, limbs = c_i32(), c_i32()
+        scale = c_dbl()
+        _check(_lib.fhe_ct_info(self._ptr, ctypes.byref(ncomp), ctypes.byref(limbs), ctypes.byref(scale)))
+        return dict(ncomp=ncomp.value, limbs=limbs.value, scale=scale.value)
+
+
+@dataclass
+class PlanStats:
+    matched_pairs: int
+    products: int
+    align_keyswitches: int
+    relin_keyswitches: int
+    target_keyswitches: int
+    result_chunks: int
+
+    @property
+    def keyswitches(self) -> int:
+        return self.align_keyswitches + self.relin_keyswitches + self.target_keyswitches
+
+
+class Context(_Handle):
+    """Parameter set, device tables and evaluation keys on one GPU."""
+    _free_fn = staticmethod(_lib.fhe_ctx_free)
+
+    def __init__(self, log_n: int, n_q: int, n_p: int, alpha: int, rot_digits: int, q_bits: int = 50,
+                 p_bits: int = 60, log_delta: int = 40, mask_bits: int = 10, device: int = 0,
+                 allocator: str = "hip"):
+        if allocator == "torch":
+            use_torch_allocator()
+        d = fhe_params_desc(log_n, n_q, q_bits, n_p, p_bits, alpha, rot_digits, log_delta, mask_bits, device)
+        out = c_vp()
+        _check(_lib.fhe_params_create(ctypes.byref(d), ctypes.byref(out)))
+        super().__init__(out.value)
+        self.log_n, self.n_q, self.n_p, self.alpha, self.rot_digits = log_n, n_q, n_p, alpha, rot_digits
+        self.N = 1 << log_n
+        self.S = self.N // 2
+
+    @property
+    def primes(self):
+        n = _check(_lib.fhe_ctx_primes(self._ptr, None, 0))
+        out = np.zeros(n, np.uint64)
+        _check(_lib.fhe_ctx_primes(self._ptr, _ptr(out, c_u64), n))
+        return [int(x) for x in out]
+
+    def keygen(self, seed: int, stream=None) -> SecretKey:
+        out = c_vp()
+        _check(_lib.fhe_keygen(self._ptr, seed, _stream(stream), ctypes.byref(out)))
+        return SecretKey(out.value, self)
+
+    def keygen_rotations(self, sk: SecretKey, amounts, stream=None):
+        a = _arr(list(amounts), np.int32)
+        _check(_lib.fhe_keygen_rotations(self._ptr, sk._ptr, _ptr(a, c_i32), a.size, _stream(stream)))
+
+    def _encrypt(self, fn, sk, rows, cols, indptr, indices, values, seed, stream):
+        ip, ix, va = _arr(indptr, np.int32), _arr(indices, np.int32), _arr(values, np.float64)
+        out = c_vp()
+        _check(fn(self._ptr, sk._ptr, rows, cols, _ptr(ip, c_i32), _ptr(ix, c_i32), _ptr(va, c_dbl), seed,
+                  _stream(stream), ctypes.byref(out)))
+        return Matrix(out.value, self)
+
+    def encrypt_csr(self, sk, rows, cols, indptr, indices, values, seed, stream=None) -> Matrix:
+        return self._encrypt(_lib.fhe_encrypt_csr, sk, rows, cols, indptr, indices, values, seed, stream)
+
+    def encrypt_csc(self, sk, rows, cols, indptr, indices, values, seed, stream=None) -> Matrix:
+        return self._encrypt(_lib.fhe_encrypt_csc, sk, rows, cols, indptr, indices, values, seed, stream)
+
+    def spmspm(self, A: Matrix, B: Matrix, stream=None) -> Matrix:
+        out = c_vp()
+        _check(_lib.fhe_spmspm(self._ptr, A._ptr, B._ptr, _stream(stream), ctypes.byref(out)))
+        return Matrix(out.value, self)
+
+    def spmspm_pairs(self, A: Matrix, B: Matrix, begin: int, end: int, stream=None) -> Matrix:
+        out = c_vp()
+        _check(_lib.fhe_spmspm_pairs(self._ptr, A._ptr, B._ptr, begin, end, _stream(stream), ctypes.byref(out)))
+        return Matrix(out.value, self)
+
+    def plan_stats(self, A: Matrix, B: Matrix) -> PlanStats:
+        c = np.zeros(6, np.int64)
+        _check(_lib.fhe_plan_stats(self._ptr, A._ptr, B._ptr, _ptr(c, c_i64)))
+        return PlanStats(*[int(x) for x in c])
+
+    def plan_rotations(self, A: Matrix, B: Matrix):
+        n = c_sz()
+        _check(_lib.fhe_plan_rotations(self._ptr, A._ptr, B._ptr, None, 0, ctypes.byref(n)))
+        out = np.zeros(max(1, n.value), np.int32)
+        _check(_lib.fhe_plan_rotations(self._ptr, A._ptr, B._ptr, _ptr(out, c_i32), out.size, ctypes.byref(n)))
+        return [int(x) for x in out[: n.value]]
+
+    def decrypt_decode(self, sk: SecretKey, M: Matrix, stream=None) -> np.ndarray:
+        inf = M.info()
+        if inf["kind"] == 2:
+            shape, count = (inf["rows"], inf["cols"]), inf["rows"] * inf["cols"]
+        else:
+            count = None
+            shape = None
+        if count is None:
+            count = inf["chunks"] * self.S
+        out = np.zeros(max(1, count), np.float64)
+        _check(_lib.fhe_decrypt_decode(self._ptr, sk._ptr, M._ptr, _stream(stream), _ptr(out, c_dbl), out.size))
+        return out[:count].reshape(shape) if shape else out
+
+    def export(self, M: Matrix, chunk: int, stream=None) -> np.ndarray:
+        inf = M.info()
+        out = np.zeros((2, inf["limbs"], self.N), np.uint64)
+        _check(_lib.fhe_mat_export(self._ptr, M._ptr, chunk, _ptr(out, c_u64), out.size, _stream(stream)))
+        return out
+
+    # --- single-ciphertext operations -----------------------------------------------------------
+    def ct_import(self, coeffs: np.ndarray, scale: float, stream=None) -> Ciphertext:
+        a = _arr(coeffs, np.uint64)
+        assert a.ndim == 3 and a.shape[2] == self.N
+        out = c_vp()
+        _check(_lib.fhe_ct_import(self._ptr, _ptr(a, c_u64), a.shape[0], a.shape[1], scale, _stream(stream),
+                                  ctypes.byref(out)))
+        return Ciphertext(out.value, self)
+
+    def ct_export(self, ct: Ciphertext, stream=None) -> np.ndarray:
+        inf = ct.info()
+        out = np.zeros((inf["ncomp"], inf["limbs"], self.N), np.uint64)
+        _check(_lib.fhe_ct_export(self._ptr, ct._ptr, _ptr(out, c_u64), out.size, _stream(stream)))
+        return out
+
+    def _ct1(self, fn, *args, stream=None):
+        out = c_vp()
+        _check(fn(self._ptr, *args, _stream(stream), ctypes.byref(out)))
+        return Ciphertext(out.value, self)
+
+    def ct_rotate(self, ct: Ciphertext, r: int, stream=None) -> Ciphertext:
+        return self._ct1(_lib.fhe_ct_rotate, ct._ptr, r, stream=stream)
+
+    def ct_mult_relin(self, a: Ciphertext, b: Ciphertext, stream=None) -> Ciphertext:
+        return self._ct1(_lib.fhe_ct_mult_relin, a._ptr, b._ptr, stream=stream)
+
+    def ct_rescale(self, ct: Ciphertext, stream=None) -> Ciphertext:
+        return self._ct1(_lib.fhe_ct_rescale, ct._ptr, stream=stream)
+
+    def ct_mask(self, ct: Ciphertext, slot: int, stream=None) -> Ciphertext:
+        return self._ct1(_lib.fhe_ct_mask, ct._ptr, slot, stream=stream)
+
+    def ct_add(self, a: Ciphertext, b: Ciphertext, stream=None) -> Ciphertext:
+        return self._ct1(_lib.fhe_ct_add, a._ptr, b._ptr, stream=stream)

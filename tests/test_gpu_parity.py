@@ -1,0 +1,180 @@
+"""GPU parity: the HIP library against the CPU oracle, bit-exact in the coefficient domain.
+
+Each test prints the case it runs (flushed) before touching the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ckks, spmspm
+from paper_2604_11659_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+# (log_n, n_q, n_p, alpha, rot_digits): a small set with two-prime digits, two special primes and
+# two-step rotations, and the single-prime-digit set of the 16x16 workload at a smaller ring.
+OP_PARAMS = [(12, 5, 2, 2, 2), (11, 4, 1, 1, 1)]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fhe():
+    from paper_2604_11659_amd import fhe as f
+    return f
+
+
+_CACHE = {}
+
+
+def _setup(fhe, prm):
+    if prm not in _CACHE:
+        log_n, n_q, n_p, alpha, D = prm
+        _say(f"[setup] params {prm}")
+        op = ckks.Params(log_n=log_n, n_q=n_q, n_p=n_p, alpha=alpha, rot_digits=D)
+        ctx = fhe.Context(log_n, n_q, n_p, alpha, D)
+        okeys = ckks.Keys(op, 42)
+        sk = ctx.keygen(42)
+        _CACHE[prm] = (op, okeys, ctx, sk)
+    return _CACHE[prm]
+
+
+def _rand_ct(op, nl, seed, ncomp=2):
+    rng = np.random.default_rng(seed)
+    return np.stack([np.stack([rng.integers(0, op.q[i], op.N, dtype=np.uint64) for i in range(nl)])
+                     for _ in range(ncomp)])
+
+
+@pytest.mark.parametrize("prm", OP_PARAMS)
+def test_primes_match(fhe, prm):
+    op, _, ctx, _ = _setup(fhe, prm)
+    assert ctx.primes == list(op.q) + list(op.p)
+
+
+@pytest.mark.parametrize("prm", OP_PARAMS)
+def test_ntt_roundtrip_and_add(fhe, prm):
+    op, _, ctx, _ = _setup(fhe, prm)
+    _say(f"[ntt/add] {prm}")
+    a, b = _rand_ct(op, op.n_q, 1), _rand_ct(op, op.n_q, 2)
+    ca, cb = ctx.ct_import(a, 1.0), ctx.ct_import(b, 1.0)
+    assert (ctx.ct_export(ca) == a).all()
+    got = ctx.ct_export(ctx.ct_add(ca, cb))
+    ref = ckks.add(op, ckks.Ct(a, 1.0), ckks.Ct(b, 1.0)).data
+    assert (got == ref).all()
+
+
+@pytest.mark.parametrize("prm", OP_PARAMS)
+@pytest.mark.parametrize("ncomp", [2, 3])
+def test_rescale_parity(fhe, prm, ncomp):
+    op, _, ctx, _ = _setup(fhe, prm)
+    for nl in range(2, op.n_q + 1):
+        _say(f"[rescale] {prm} ncomp={ncomp} nl={nl}")
+        a = _rand_ct(op, nl, 10 + nl, ncomp)
+        got = ctx.ct_export(ctx.ct_rescale(ctx.ct_import(a, 1.0)))
+        ref = ckks.rescale(op, ckks.Ct(a, 1.0)).data
+        assert (got == ref).all(), f"nl={nl}"
+
+
+@pytest.mark.parametrize("prm", OP_PARAMS)
+def test_mult_relin_parity(fhe, prm):
+    op, okeys, ctx, _ = _setup(fhe, prm)
+    for nl in sorted({op.n_q, 2, op.n_q - 1}):
+        _say(f"[mult_relin] {prm} nl={nl}")
+        a, b = _rand_ct(op, nl, 20 + nl), _rand_ct(op, nl, 30 + nl)
+        got = ctx.ct_export(ctx.ct_mult_relin(ctx.ct_import(a, 1.0), ctx.ct_import(b, 1.0)))
+        ref = ckks.mult_relin(op, okeys, ckks.Ct(a, 1.0), ckks.Ct(b, 1.0)).data
+        assert (got == ref).all(), f"nl={nl}"
+
+
+@pytest.mark.parametrize("prm", OP_PARAMS)
+def test_rotate_parity(fhe, prm):
+    op, okeys, ctx, sk = _setup(fhe, prm)
+    amounts = [1, 5, op.S - 1, 3 * (1 << op.rot_step_bits()) + 7, 0]
+    if op.rot_digits == 1:
+        ctx.keygen_rotations(sk, amounts)
+    for nl in sorted({op.n_q, op.n_q - 2}):
+        a = _rand_ct(op, nl, 40 + nl)
+        ca = ctx.ct_import(a, 1.0)
+        for r in amounts:
+            _say(f"[rotate] {prm} nl={nl} r={r}")
+            got = ctx.ct_export(ctx.ct_rotate(ca, r))
+            ref = ckks.rotate(op, okeys, ckks.Ct(a, 1.0), r).data
+            assert (got == ref).all(), f"nl={nl} r={r}"
+
+
+@pytest.mark.parametrize("prm", OP_PARAMS)
+def test_mask_parity(fhe, prm):
+    op, _, ctx, _ = _setup(fhe, prm)
+    nl = op.n_q - 1
+    a = _rand_ct(op, nl, 50)
+    ca = ctx.ct_import(a, 1.0)
+    for slot in [0, 1, 77, op.S - 1]:
+        _say(f"[mask] {prm} slot={slot}")
+        got = ctx.ct_export(ctx.ct_mask(ca, slot))
+        ref = ckks.mul_plain(op, ckks.Ct(a, 1.0), ckks.mask(op, slot), op.delta_mask).data
+        assert (got == ref).all(), f"slot={slot}"
+
+
+@pytest.mark.parametrize("prm", OP_PARAMS)
+def test_encryption_parity(fhe, prm):
+    """Encoding, sampling and encryption reproduce the oracle's ciphertexts bit for bit."""
+    op, okeys, ctx, sk = _setup(fhe, prm)
+    _say(f"[encrypt] {prm}")
+    a = synth.sparse_dense(6, 9, 0.5, "uniform", 5, 6)
+    ip, ix, va = synth.to_csr(a)
+    A = ctx.encrypt_csr(sk, 6, 9, ip, ix, va, seed=43)
+    OA = spmspm.encrypt_csr(op, okeys, 6, 9, ip, ix, va, seed=43)
+    assert (ctx.export(A, 0) == OA.chunks[0].data).all()
+    b = synth.sparse_dense(9, 4, 0.5, "halfnormal", 7, 8)
+    ip, ix, vb = synth.to_csc(b)
+    B = ctx.encrypt_csc(sk, 9, 4, ip, ix, vb, seed=44)
+    OB = spmspm.encrypt_csc(op, okeys, 9, 4, ip, ix, vb, seed=44)
+    assert (ctx.export(B, 0) == OB.chunks[0].data).all()
+    dec = ctx.decrypt_decode(sk, A)[: len(va)]
+    assert np.abs(dec - va).max() < 1e-6
+
+
+def _matmul_case(fhe, prm, m, k, n, sp_a, sp_b, seeds, workers=1):
+    op, okeys, ctx, sk = _setup(fhe, prm)
+    a = synth.sparse_dense(m, k, sp_a, "uniform", seeds[0], seeds[2])
+    b = synth.sparse_dense(k, n, sp_b, "uniform", seeds[1], seeds[3])
+    ipa, ixa, va = synth.to_csr(a)
+    ipb, ixb, vb = synth.to_csc(b)
+    A = ctx.encrypt_csr(sk, m, k, ipa, ixa, va, seed=43)
+    B = ctx.encrypt_csc(sk, k, n, ipb, ixb, vb, seed=44)
+    if op.rot_digits == 1:
+        ctx.keygen_rotations(sk, ctx.plan_rotations(A, B))
+    _say(f"[spmspm] {prm} {m}x{k}x{n} gpu")
+    C = ctx.spmspm(A, B)
+    OA = spmspm.encrypt_csr(op, okeys, m, k, ipa, ixa, va, seed=43)
+    OB = spmspm.encrypt_csc(op, okeys, k, n, ipb, ixb, vb, seed=44)
+    _say(f"[spmspm] {prm} {m}x{k}x{n} oracle")
+    ref = spmspm.spmspm(op, okeys, OA, OB, workers=workers)
+    for c, rct in enumerate(ref):
+        assert (ctx.export(C, c) == rct.data).all(), f"chunk {c}"
+    dec = ctx.decrypt_decode(sk, C)
+    assert np.abs(dec - a @ b).max() < 1e-5
+    return ctx, A, B
+
+
+def test_spmspm_parity_small(fhe):
+    _matmul_case(fhe, OP_PARAMS[0], 5, 6, 7, 0.5, 0.5, (0, 1, 2, 3))
+
+
+def test_spmspm_parity_single_digit(fhe):
+    _matmul_case(fhe, OP_PARAMS[1], 6, 5, 4, 0.4, 0.6, (4, 5, 6, 7))
+
+
+def test_spmspm_full_sparsity_is_zero(fhe):
+    op, _, ctx, sk = _setup(fhe, OP_PARAMS[0])
+    z = np.zeros((4, 4))
+    ip, ix, v = synth.to_csr(z)
+    A = ctx.encrypt_csr(sk, 4, 4, ip, ix, v, seed=43)
+    B = ctx.encrypt_csc(sk, 4, 4, ip, ix, v, seed=44)
+    C = ctx.spmspm(A, B)
+    assert (ctx.export(C, 0) == 0).all()
+    assert (ctx.decrypt_decode(sk, C) == 0).all()
