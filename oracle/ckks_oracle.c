@@ -485,8 +485,11 @@ void or_modup(const uint64_t* d, uint64_t nl, uint64_t lo, uint64_t hi, const ui
 }
 
 /* ModDown of one polynomial u over (q_0..q_{nl-1}, p_0..p_{nk-1}) to q_0..q_{nl-1}:
- * z_k = [u_{p_k} (P/p_k)^-1]_{p_k}; conv_i = sum_k z_k (P/p_k mod q_i) mod q_i;
- * out_i = (u_{q_i} - conv_i) P^-1 mod q_i. ext_moduli: [nl + nk]; u: [nl+nk][N]; out: [nl][N]. */
+ * z_k = [u_{p_k} (P/p_k)^-1]_{p_k}, taken as the centred representative (z_k - p_k when
+ * z_k > (p_k - 1)/2); conv_i = sum_k z_k (P/p_k mod q_i) mod q_i; out_i = (u_{q_i} - conv_i) P^-1 mod q_i.
+ * Centring makes the rounding error of the division by P zero-mean; with [0, p_k) representatives it
+ * has mean (K-1)/2 per coefficient, which adds the same slot pattern at every key switch.
+ * ext_moduli: [nl + nk]; u: [nl+nk][N]; out: [nl][N]. */
 void or_moddown(const uint64_t* u, uint64_t nl, const uint64_t* ext_moduli, uint64_t nk, uint64_t N, uint64_t* out) {
   const uint64_t* pm = ext_moduli + nl;
   uint64_t* z = (uint64_t*)malloc(nk * N * 8);
@@ -509,7 +512,9 @@ void or_moddown(const uint64_t* u, uint64_t nl, const uint64_t* ext_moduli, uint
         uint64_t phat_q = 1; /* (P / p_kk) mod q_i */
         for (uint64_t k2 = 0; k2 < nk; ++k2)
           if (k2 != kk) phat_q = or_mulmod(phat_q, pm[k2] % qi, qi);
-        conv = or_addmod(conv, or_mulmod(z[kk * N + k] % qi, phat_q, qi), qi);
+        uint64_t pk = pm[kk], zk = z[kk * N + k];
+        int64_t zc = (zk > (pk - 1) / 2) ? (int64_t)zk - (int64_t)pk : (int64_t)zk;
+        conv = or_addmod(conv, or_mulmod(from_signed(zc, qi), phat_q, qi), qi);
       }
       out[i * N + k] = or_mulmod(or_submod(u[i * N + k], conv, qi), pinv, qi);
     }

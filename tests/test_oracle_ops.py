@@ -44,7 +44,8 @@ def test_modup_is_crt_lift_plus_small_multiple(alpha, nl, j):
 
 @pytest.mark.parametrize("nl,nk", [(4, 1), (6, 2), (5, 3)])
 def test_moddown_is_division_by_p_up_to_k(nl, nk):
-    """out * P = U - Z (mod Q P) with 0 <= Z < K P, i.e. out = floor-ish(U / P) off by < K."""
+    """out * P = U - Z (mod Q P) with Z = U (mod P) and |Z| < K P / 2 (centred conversion): out is U / P
+    rounded with an error below K / 2 + 1 / 2; with one special prime it is the nearest integer."""
     params = ckks.Params(log_n=5, n_q=6, n_p=nk, alpha=1, rot_digits=1)
     N = params.N
     rng = np.random.default_rng(nl * 7 + nk)
@@ -61,8 +62,9 @@ def test_moddown_is_division_by_p_up_to_k(nl, nk):
     for k in range(N):
         U, _ = crt([u[e, k] for e in range(nl + nk)], [int(m) for m in ext_mod])
         W, _ = crt([out[i, k] for i in range(nl)], list(params.q[:nl]))
-        Z = (U - W * Pp) % (Ql * Pp)
-        assert 0 <= Z < nk * Pp
+        Z = centered((U - W * Pp) % (Ql * Pp), Ql * Pp)
+        assert 2 * abs(Z) < nk * Pp
+        assert (Z - U) % Pp == 0
 
 
 @pytest.mark.parametrize("nl", [2, 3, 5])
@@ -103,6 +105,10 @@ def test_tensor_ring_identity():
 
 
 def _ks_error(params, keys, d, u, sprime_signed):
+    return max(abs(e) for e in _ks_errors(params, keys, d, u, sprime_signed))
+
+
+def _ks_errors(params, keys, d, u, sprime_signed):
     """Centred CRT of u0 + u1 s - d s' over the active Q limbs (Python schoolbook)."""
     nl = d.shape[0]
     N = params.N
@@ -118,7 +124,7 @@ def _ks_error(params, keys, d, u, sprime_signed):
     for k in range(N):
         x, M = crt([rows[i][k] for i in range(nl)], list(params.q[:nl]))
         errs.append(centered(x, M))
-    return max(abs(e) for e in errs)
+    return errs
 
 
 @pytest.mark.parametrize("alpha,n_q,n_p,nl", [(1, 4, 1, 4), (1, 4, 1, 2), (2, 6, 2, 6), (2, 6, 2, 5), (3, 6, 3, 4)])
@@ -138,6 +144,30 @@ def test_keyswitch_decrypts_to_target_secret(alpha, n_q, n_p, nl):
     assert _ks_error(params, keys, d, u, ckks.automorph_signed(keys.s, g)) <= bound
     # and a wrong target is far off (the pin has teeth)
     assert _ks_error(params, keys, d, u, s2) > 2 ** 60
+
+
+@pytest.mark.parametrize("alpha,n_q,n_p", [(1, 4, 1), (2, 6, 2), (3, 6, 3)])
+def test_keyswitch_error_is_zero_mean(alpha, n_q, n_p):
+    """The key-switch error e = u0 + u1 s - d s' has no systematic part. A ModDown rounding error v with
+    mean mu per coefficient would add -mu (1 + 1 * s) (1 = the all-ones polynomial, * the negacyclic
+    product); the projection of e on that direction must stay within a few standard deviations."""
+    params = ckks.Params(log_n=8, n_q=n_q, n_p=n_p, alpha=alpha, rot_digits=1)
+    keys = ckks.Keys(params, 42)
+    N = params.N
+    g = pow(5, 7, 2 * N)
+    target = ckks.automorph_signed(keys.s, g)
+    bias = [1 + x for x in negacyclic_mul([1] * N, list(keys.s))]
+    norm = sum(x * x for x in bias) ** 0.5
+    proj, sq, cnt, trials = 0.0, 0, 0, 6
+    for trial in range(trials):
+        d = _rand_limbs(np.random.default_rng(100 + trial), params.q, N)
+        u = ckks.keyswitch(params, d, keys.rot_key(g))
+        errs = _ks_errors(params, keys, d, u, target)
+        proj += sum(e * b for e, b in zip(errs, bias)) / norm
+        sq += sum(e * e for e in errs)
+        cnt += len(errs)
+    std = (sq / cnt) ** 0.5
+    assert abs(proj) < 6 * std * trials ** 0.5, (proj, std)
 
 
 @pytest.fixture(scope="module")
