@@ -61,7 +61,7 @@ typedef struct fhe_ct fhe_ct;   /* a single ciphertext (operation-level interfac
  * 2^log_delta, the CSC operand at exactly q_(n_q-1), the one-hot mask at 2^mask_bits * q_(n_q-2);
  * products of the method therefore end at scale exactly 2^(log_delta + mask_bits). */
 typedef struct fhe_params_desc {
-  int32_t log_n;      /* N = 2^log_n, 10 <= log_n <= 17 */
+  int32_t log_n;      /* N = 2^log_n, 12 <= log_n <= 17 */
   int32_t n_q;        /* number of Q primes, 3 <= n_q <= 64 */
   int32_t q_bits;     /* bits of the Q primes, 30 <= q_bits <= 50 */
   int32_t n_p;        /* number of special primes K, 1 <= n_p <= 8 */
@@ -129,10 +129,24 @@ int fhe_spmspm(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, void* stream, f
 int fhe_spmspm_pairs(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t pair_begin, int64_t pair_end,
                      void* stream, fhe_mat** C_out);
 
+/* Batched form: C_out[i] = A[i] B[i] for i < cnt, run as one stream of batched launches. The plans
+ * of all matmuls are merged (products and matched pairs of every matmul share the same launches, and
+ * pairs that use the same rotation keys are processed together), so many small or uneven matmuls
+ * fill the GPU where one at a time would not. Each result is bit-identical to fhe_spmspm on the same
+ * operands. On error no result handle is returned (all C_out[i] are NULL). */
+int fhe_spmspm_batch(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B, void* stream,
+                     fhe_mat** C_out);
+
 /* Plan statistics of A B without running it: counts[0] = matched pairs F, [1] = distinct products,
  * [2] = alignment key switches, [3] = product relinearisations, [4] = target-rotation key switches,
  * [5] = result chunks. Errors as fhe_spmspm. */
 int fhe_plan_stats(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t counts[6]);
+
+/* Host-only planning from the public patterns (no context, no device): the same counts as
+ * fhe_plan_stats for A (m x k, CSR pattern) times B (k x n, CSC pattern) at ring dimension 2^log_n
+ * with rot_digits rotation steps. Errors: FHE_EINVAL (malformed pattern or parameters). */
+int fhe_plan_pattern(int32_t log_n, int32_t rot_digits, int32_t m, int32_t k, int32_t n, const int32_t* indptr_a,
+                     const int32_t* indices_a, const int32_t* indptr_b, const int32_t* indices_b, int64_t counts[6]);
 
 /* The distinct rotation step amounts the plan for A B uses (each < S); writes up to cap of them into
  * out and the total into *n_out. Feed them to fhe_keygen_rotations when rot_digits == 1. */
@@ -173,6 +187,54 @@ int fhe_ct_mask(fhe_ctx* ctx, const fhe_ct* ct, int32_t slot, void* stream, fhe_
 /* EvalAdd of two ciphertexts of equal shape. */
 int fhe_ct_add(fhe_ctx* ctx, const fhe_ct* a, const fhe_ct* b, void* stream, fhe_ct** out);
 void fhe_ct_free(fhe_ct* ct);
+
+/* ---- Request loop with continuous batching. ---- */
+
+typedef struct fhe_server fhe_server;
+
+/* Starts a serving loop on ctx (a worker thread with its own HIP stream). Requests are admitted while
+ * fewer than max_inflight are running and the sum of their result buffers stays within hbm_budget
+ * bytes (operands and keys are already resident). Each scheduling step runs the next
+ * slice_products products (with all their matched pairs) of every admitted request as one merged
+ * launch stream, so a request that arrives while others run joins the next step. At most max_queue
+ * requests wait for admission. Errors: FHE_EINVAL, FHE_EDEVICE. */
+int fhe_server_create(fhe_ctx* ctx, size_t hbm_budget, int32_t max_inflight, int32_t slice_products,
+                      int32_t max_queue, fhe_server** out);
+
+/* Queues C = A B (A: CSR handle, B: CSC handle; both must stay alive until the request is polled).
+ * Returns a ticket. Errors: FHE_EAGAIN (queue full), FHE_EINVAL, FHE_ESHAPE. */
+int fhe_server_submit(fhe_server* s, const fhe_mat* A, const fhe_mat* B, uint64_t* ticket);
+
+/* Waits up to wait_ms for the ticket. FHE_OK: *C_out receives the result (bit-identical to
+ * fhe_spmspm on the same operands) and *latency_s the submit-to-completion time; the ticket is
+ * retired. FHE_EAGAIN: not finished yet. Other codes: the request failed (FHE_ENOMEM if its result
+ * exceeds the whole budget, FHE_EKEY for a missing rotation key) and the ticket is retired. */
+int fhe_server_poll(fhe_server* s, uint64_t ticket, int32_t wait_ms, fhe_mat** C_out, double* latency_s);
+
+/* Latency percentiles (seconds) over completed requests, and the completed / in-flight / queued counts. */
+int fhe_server_stats(fhe_server* s, double* p50_s, double* p99_s, int64_t* completed, int64_t* inflight,
+                     int64_t* queued);
+
+/* Drains queued and running requests, stops the worker and frees the server. */
+void fhe_server_free(fhe_server* s);
+
+/* ---- Measurement hooks (not part of the method). ---- */
+
+/* Per-kernel device timing. fhe_profile_enable(1) clears earlier records and starts bracketing every
+ * kernel launch of this library with two HIP events on the launch stream; fhe_profile_enable(0) stops
+ * recording (records are kept until the next enable). Process-wide. */
+int fhe_profile_enable(int on);
+
+typedef struct fhe_kernel_stat {
+  char name[32];        /* kernel name, e.g. "ks_inner", "ntt_fwd_p1" */
+  int64_t launches;     /* recorded launches */
+  double total_ms;      /* sum of event-measured durations */
+  double bytes;         /* sum of the launches' algorithmic HBM bytes (reads + writes the kernel must do) */
+} fhe_kernel_stat;
+
+/* Aggregates the records per kernel name into out[cap] (synchronises on the recorded events);
+ * returns the number of distinct kernels (entries beyond cap are not written). */
+int fhe_profile_read(fhe_kernel_stat* out, size_t cap);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* fhe_last_error(void);

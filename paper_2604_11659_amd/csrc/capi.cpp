@@ -164,10 +164,34 @@ int fhe_spmspm_pairs(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t p
     check_operands(A, B);
     if (pair_begin < 0 || pair_end < pair_begin) fail(FHE_EINVAL, "bad pair range");
     set_dev(ctx);
-    Plan plan = build_plan(ctx->p, A, B, pair_begin, pair_end);
     std::unique_ptr<fhe_mat> C(new fhe_mat());
-    execute_plan(ctx, A, B, plan, as_stream(stream), C.get());
+    std::vector<Job> jobs(1);
+    jobs[0] = Job{A, B, build_plan(ctx->p, A, B, pair_begin, pair_end), C.get()};
+    execute_jobs(ctx, jobs, as_stream(stream));
     *C_out = C.release();
+  });
+}
+
+int fhe_spmspm_batch(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B, void* stream,
+                     fhe_mat** C_out) {
+  return guarded([&] {
+    need(ctx, "ctx");
+    need(C_out, "C_out");
+    if (cnt) {
+      need(A, "A");
+      need(B, "B");
+    }
+    for (size_t i = 0; i < cnt; ++i) C_out[i] = nullptr;
+    for (size_t i = 0; i < cnt; ++i) check_operands(A[i], B[i]);
+    set_dev(ctx);
+    std::vector<std::unique_ptr<fhe_mat>> Cs(cnt);
+    std::vector<Job> jobs(cnt);
+    for (size_t i = 0; i < cnt; ++i) {
+      Cs[i].reset(new fhe_mat());
+      jobs[i] = Job{A[i], B[i], build_plan(ctx->p, A[i], B[i], 0, INT64_MAX), Cs[i].get()};
+    }
+    execute_jobs(ctx, jobs, as_stream(stream));
+    for (size_t i = 0; i < cnt; ++i) C_out[i] = Cs[i].release();
   });
 }
 
@@ -182,6 +206,35 @@ int fhe_plan_stats(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t cou
     check_operands(A, B);
     Plan plan = build_plan(ctx->p, A, B, 0, INT64_MAX);
     plan_counts(ctx->p, plan, counts);
+  });
+}
+
+int fhe_plan_pattern(int32_t log_n, int32_t rot_digits, int32_t m, int32_t k, int32_t n, const int32_t* indptr_a,
+                     const int32_t* indices_a, const int32_t* indptr_b, const int32_t* indices_b, int64_t counts[6]) {
+  return guarded([&] {
+    need(counts, "counts");
+    if (log_n < 2 || log_n > 20 || rot_digits < 1 || rot_digits > log_n - 1) fail(FHE_EINVAL, "bad log_n / rot_digits");
+    check_pattern(m, k, indptr_a, indices_a);
+    check_pattern(n, k, indptr_b, indices_b);
+    Params p;
+    p.logN = (uint32_t)log_n;
+    p.N = 1u << log_n;
+    p.S = p.N / 2;
+    p.rot_digits = rot_digits;
+    p.rot_bits = (int)((p.logN - 1 + rot_digits - 1) / rot_digits);
+    fhe_mat A, B;
+    A.kind = 0;
+    A.rows = m;
+    A.cols = k;
+    A.indptr.assign(indptr_a, indptr_a + m + 1);
+    A.indices.assign(indices_a, indices_a + indptr_a[m]);
+    B.kind = 1;
+    B.rows = k;
+    B.cols = n;
+    B.indptr.assign(indptr_b, indptr_b + n + 1);
+    B.indices.assign(indices_b, indices_b + indptr_b[n]);
+    Plan plan = build_plan(p, &A, &B, 0, INT64_MAX);
+    plan_counts(p, plan, counts);
   });
 }
 
@@ -405,6 +458,26 @@ int fhe_ct_add(fhe_ctx* ctx, const fhe_ct* a, const fhe_ct* b, void* stream, fhe
 }
 
 void fhe_ct_free(fhe_ct* ct) { delete ct; }
+
+int fhe_profile_enable(int on) {
+  return guarded([&] { prof_enable(on != 0); });
+}
+
+int fhe_profile_read(fhe_kernel_stat* out, size_t cap) {
+  int n = 0;
+  int rc = guarded([&] {
+    auto rows = prof_summary();
+    n = (int)rows.size();
+    for (size_t i = 0; i < rows.size() && out && i < cap; ++i) {
+      memset(&out[i], 0, sizeof(out[i]));
+      strncpy(out[i].name, std::get<0>(rows[i]).c_str(), sizeof(out[i].name) - 1);
+      out[i].launches = std::get<1>(rows[i]);
+      out[i].total_ms = std::get<2>(rows[i]);
+      out[i].bytes = std::get<3>(rows[i]);
+    }
+  });
+  return rc ? rc : n;
+}
 
 const char* fhe_last_error(void) { return g_err.c_str(); }
 

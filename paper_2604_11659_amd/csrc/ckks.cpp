@@ -46,7 +46,7 @@ void sync(hipStream_t st) { HIPCHECK(hipStreamSynchronize(st)); }
 void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
   Params& p = ctx->p;
   p.d = *d;
-  if (d->log_n < 10 || d->log_n > 17) fail(FHE_EINVAL, "log_n must be in [10, 17]");
+  if (d->log_n < 12 || d->log_n > 17) fail(FHE_EINVAL, "log_n must be in [12, 17]");
   if (d->n_q < 3) fail(FHE_ELEVEL, "the method needs at least 3 Q primes (two rescales)");
   if (d->n_q > 64) fail(FHE_EINVAL, "n_q must be <= 64");
   if (d->q_bits < 30 || d->q_bits > 50) fail(FHE_EINVAL, "q_bits must be in [30, 50]");
@@ -68,7 +68,6 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
   p.rot_digits = d->rot_digits;
   p.rot_bits = (int)((p.logN - 1 + p.rot_digits - 1) / p.rot_digits);
   p.k1 = p.logN / 2;
-  p.logE = p.logN < 12 ? p.logN : 12;
   const uint64_t m = 2ull * p.N;
   std::vector<uint64_t> qs = primes_below(d->q_bits, p.nq, m);
   if ((int)qs.size() != p.nq) fail(FHE_EINVAL, "not enough Q primes of the requested size");
@@ -83,6 +82,7 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
   // Per-modulus constants and NTT twiddles.
   std::vector<ModInfo> mi(nmod);
   std::vector<uint64_t> tw((size_t)nmod * 4 * N);
+  std::vector<double> twf((size_t)nmod * 4 * N);
   for (int i = 0; i < nmod; ++i) {
     const uint64_t q = p.moduli[i];
     ModInfo& x = mi[i];
@@ -108,10 +108,17 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
       f[N + k] = shoup_prep(pp[rk], q);
       f[2 * N + k] = pi[rk];
       f[3 * N + k] = shoup_prep(pi[rk], q);
+      // FP64 twiddles (used for q < 2^50): w and fl(w / q).
+      double* ff = twf.data() + (size_t)i * 4 * N;
+      ff[k] = (double)pp[rk];
+      ff[N + k] = (double)pp[rk] / (double)q;
+      ff[2 * N + k] = (double)pi[rk];
+      ff[3 * N + k] = (double)pi[rk] / (double)q;
     }
   }
   ctx->t.mods = upload(mi, st);
   ctx->t.tw = upload(tw, st);
+  ctx->t.twf = upload(twf, st);
 
   // ModUp constants per level.
   const int K = p.np;
@@ -146,7 +153,7 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
   ctx->t.modup = upload(mu, st);
 
   // ModDown constants.
-  std::vector<uint64_t> md(2 * K + 2 * (size_t)K * p.nq + 2 * (size_t)p.nq, 0);
+  std::vector<uint64_t> md(2 * K + 2 * (size_t)K * p.nq + 3 * (size_t)p.nq, 0);
   for (int kk = 0; kk < K; ++kk) {
     const uint64_t pk = p.moduli[p.nq + kk];
     uint64_t ph = 1;
@@ -171,6 +178,7 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
     const uint64_t inv = invmod_host(P, qi);
     md[2 * K + 2 * (size_t)K * p.nq + 2 * i] = inv;
     md[2 * K + 2 * (size_t)K * p.nq + 2 * i + 1] = shoup_prep(inv, qi);
+    md[2 * K + 2 * (size_t)K * p.nq + 2 * (size_t)p.nq + i] = P;
   }
   ctx->t.moddown = upload(md, st);
 

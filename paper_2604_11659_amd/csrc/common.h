@@ -5,7 +5,9 @@
 
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "arith.h"
@@ -28,6 +30,12 @@ struct Allocator {
   void* user = nullptr;
 };
 Allocator current_allocator();
+
+// Per-kernel device timing (HIP events around tracked launches); see runtime.cpp.
+int prof_begin(const char* name, hipStream_t st);
+void prof_end(int tok, hipStream_t st, double algorithmic_bytes);
+void prof_enable(bool on);
+std::vector<std::tuple<std::string, int64_t, double, double>> prof_summary();
 
 // Owning device buffer, allocated and released through the registered allocator.
 class DevBuf {
@@ -68,15 +76,16 @@ struct Params {
   int nmod() const { return nq + np; }
   int beta(int nl) const { return (nl + alpha - 1) / alpha; }
   // NTT split: phase 1 transforms columns of 2^k1 elements, phase 2 rows of 2^(logN-k1).
-  uint32_t k1 = 0, logE = 0;
+  uint32_t k1 = 0;
 };
 
 // Constant tables for one context (all in device memory).
 struct Tables {
   DevBuf mods;     // ModInfo[nmod]
   DevBuf tw;       // per modulus: fwd[N], fwd_shoup[N], inv[N], inv_shoup[N]
+  DevBuf twf;      // per modulus (as double): fwd[N], fwd / q [N], inv[N], inv / q [N]
   DevBuf modup;    // per (nl, digit): see modup_offset
-  DevBuf moddown;  // phat_inv[K][2], phat_mod_q[K][nq][2], pinv_mod_q[nq][2]
+  DevBuf moddown;  // phat_inv[K][2], phat_mod_q[K][nq][2], pinv_mod_q[nq][2], p_mod_q[nq]
   DevBuf rescale;  // ql_inv[l][i][2] = (q_l^-1 mod q_i, shoup), l < nq, i < l
   DevBuf mask;     // NTT of the base mask on limbs 0..nq-2, Montgomery form: [nq-1][N]
   std::vector<size_t> modup_offset;  // index nl (1..nq): offset (uint64 units) of the nl block
@@ -96,6 +105,8 @@ struct fhe_ctx {
   fhe::Tables t;
   std::unique_ptr<fhe::SwitchKey> relin;
   std::map<uint32_t, std::unique_ptr<fhe::SwitchKey>> rot;  // keyed by Galois element 5^r mod 2N
+  std::mutex exec_mu;    // one matmul execution at a time per context (shared scratch)
+  fhe::DevBuf ws_cache;  // executor scratch, grown on demand
 };
 
 struct fhe_sk {

@@ -7,6 +7,10 @@ namespace fhe {
 
 // A batch of limbs to transform: poly p, limb e is at base + p * poly_stride + e * N and uses
 // modulus index e (e < n_first) or p_base + (e - n_first) (e >= n_first).
+// Optional: `src` (with src_stride per poly) is where the first phase reads from (out of place);
+// a "hole" skips a key-switch digit's own limbs in compacted ModUp rows: with hole_items > 0, poly p
+// belongs to digit j = hole_j0 + p / hole_items and rows e >= j * hole_alpha (and < n_first) map to
+// modulus e + hole_len.
 struct LimbBatch {
   uint64_t* base;
   uint32_t limbs;
@@ -14,6 +18,9 @@ struct LimbBatch {
   uint64_t poly_stride;
   uint32_t n_first;
   uint32_t p_base;
+  const uint64_t* src = nullptr;
+  uint64_t src_stride = 0;
+  uint32_t hole_items = 0, hole_alpha = 0, hole_len = 0, hole_j0 = 0;
 };
 
 // Negacyclic NTT, in place. Forward: coefficients -> evaluations at psi^(2 brv(i) + 1) (bit-reversed
@@ -31,10 +38,10 @@ void tensor(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* const* 
             uint64_t* out, hipStream_t st);
 
 // Hybrid key switch of B polynomials at nl limbs (NTT domain). Input item b is `in + b * in_stride`
-// ([nl][N]) and is overwritten. keys[b]: switching key. add[2b + c] (may be NULL): [nl][N] added to
+// ([nl][N]); it is read, not modified. keys[b]: switching key. add[2b + c] (may be NULL): [nl][N] added to
 // output component c. out[b]: [2][nl][N]. ws: keyswitch_ws_elems(ctx, B, nl) uint64 of workspace.
 size_t keyswitch_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t nl);
-void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, uint64_t* in, uint64_t in_stride,
+void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, uint64_t in_stride,
                const uint64_t* const* keys, const uint64_t* const* add, uint64_t* const* out, uint64_t* ws,
                hipStream_t st);
 
@@ -47,9 +54,12 @@ void rescale(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const 
 void mask_mul(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* const* in, const uint32_t* galois,
               uint64_t* const* out, hipStream_t st);
 
-// result[seg[3s]] += sum of contrib[b] for b in [seg[3s+1], seg[3s+2]); [2][nl][N] each.
-void accumulate(const fhe_ctx* ctx, uint32_t nseg, uint32_t nl, const uint32_t* seg, const uint64_t* contrib,
-                uint64_t* result, hipStream_t st);
+// results[seg[3s]] += sum of contrib[b] for b in [seg[3s+1], seg[3s+2]); [2][nl][N] each; `results` is
+// a device array of result-chunk pointers. ncontrib (the number of contributions the segments cover)
+// only sizes the launch's traffic figure for the kernel timer.
+void accumulate(const fhe_ctx* ctx, uint32_t nseg, uint32_t ncontrib, uint32_t nl, const uint32_t* seg,
+                const uint64_t* contrib,
+                uint64_t* const* results, hipStream_t st);
 
 // out[e][k] = v[k] mod modulus(e) for e < nlimbs (modulus index rule as in LimbBatch).
 void signed_to_limbs(const fhe_ctx* ctx, const int64_t* v, uint32_t nlimbs, uint32_t n_first, uint32_t p_base,

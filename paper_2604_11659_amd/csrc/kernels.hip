@@ -2,6 +2,8 @@
 // (ModUp fast base conversion, key inner product, ModDown), rescale, one-hot mask multiply and
 // accumulation. Residues are uint64 in [0, q), limb-major ([..][limb][coefficient]) so that a
 // wavefront reads 64 consecutive coefficients of one limb (512 contiguous bytes).
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace fhe {
@@ -14,8 +16,13 @@ constexpr int kMaxK = 8;
 
 __device__ __forceinline__ uint32_t brev_bits(uint32_t x, uint32_t bits) { return __brev(x) >> (32 - bits); }
 
-__device__ __forceinline__ uint32_t mod_index(const LimbBatch& lb, uint32_t e) {
-  return e < lb.n_first ? e : lb.p_base + (e - lb.n_first);
+__device__ __forceinline__ uint32_t mod_index(const LimbBatch& lb, uint32_t poly, uint32_t e) {
+  if (e >= lb.n_first) return lb.p_base + (e - lb.n_first);
+  if (lb.hole_items) {
+    const uint32_t j = lb.hole_j0 + poly / lb.hole_items;
+    if (e >= j * lb.hole_alpha) e += lb.hole_len;
+  }
+  return e;
 }
 
 // Index k' such that the NTT-domain value of tau_g(a) at position k is a[k'] (bit-reversed order:
@@ -35,141 +42,325 @@ inline uint32_t grid_for(uint64_t total) {
 
 // ------------------------------------------------------------------------------------------------
 // NTT. Cooley-Tukey (forward) / Gentleman-Sande (inverse) with the 2N-th root psi merged into the
-// twiddles: stage s uses w = psi_rev[2^s + floor(j / 2t)], t = N / 2^(s+1). Stages 0..k1-1 (t >= N2)
-// pair elements in the same column of the N1 x N2 view (stride N2); phase 1 loads 2^logC adjacent
-// columns per workgroup into LDS. Stages k1..logN-1 act inside contiguous rows; phase 2 loads a
-// contiguous tile of rows. Each workgroup moves one 2^logE-element tile through LDS per phase.
+// twiddles: stage s pairs j and j + t (t = N / 2^(s+1)) with w = psi_rev[2^s + floor(j / 2t)].
+// A limb is viewed as an N1 x N2 matrix (N1 = 2^k1 rows of N2 = 2^(logN-k1)). Phase 1 runs stages
+// 0..k1-1 (pairs inside a column, stride N2); phase 2 runs stages k1..logN-1 (pairs inside a row).
+// Each workgroup moves a 4096-element tile (several columns, resp. several contiguous rows) through
+// LDS; inside a phase, stages are done in rounds of up to four: every thread gathers 16 elements
+// whose row/column index differs only in the round's 4 bits, runs the 4 stages in registers and
+// scatters back, so LDS is crossed once per 4 stages instead of once per stage. LDS rows are padded
+// by one element per 16 to keep 64-bit accesses of a wavefront on distinct banks.
+// Arithmetic: Q primes (< 2^50) use an exact FP64-FMA multiply (quotient from the product with
+// w/q, remainder recovered exactly with two FMAs, one conditional correction); the special primes
+// (< 2^61) use integer Shoup multiplication. Both return the same residue in [0, q).
 // ------------------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kThreads) void k_ntt_fwd_p1(LimbBatch lb, const ModInfo* __restrict__ mods,
-                                                        const uint64_t* __restrict__ tw, uint32_t logN,
-                                                        uint32_t k1, uint32_t logE) {
+constexpr uint32_t kNttLogE = 12;
+constexpr uint32_t kNttE = 1u << kNttLogE;
+constexpr uint32_t kNttLdsElems = kNttE + (kNttE >> 4);
+
+__device__ __forceinline__ uint32_t pad_idx(uint32_t i) { return i + (i >> 4); }
+
+// Integer arithmetic (special primes up to 61 bits): residues in [0, q) everywhere.
+struct IntArith {
+  typedef uint64_t T;
+  typedef uint64_t W;
+  uint64_t q;
+  __device__ __forceinline__ void init(uint64_t qq) { q = qq; }
+  __device__ __forceinline__ uint64_t lds_in(uint64_t x) const { return x; }   // global -> LDS word
+  __device__ __forceinline__ uint64_t lds_out(uint64_t x) const { return x; }  // LDS word -> [0, q)
+  __device__ __forceinline__ T ld(uint64_t x) const { return x; }
+  __device__ __forceinline__ uint64_t st(T x) const { return x; }
+  __device__ __forceinline__ void round_end(T&) const {}
+  __device__ __forceinline__ void ct(T& a, T& b, W w, W wx) const {
+    const T v = shoup_mul(b, w, wx, q);
+    b = sub_mod(a, v, q);
+    a = add_mod(a, v, q);
+  }
+  __device__ __forceinline__ void gs(T& a, T& b, W w, W wx) const {
+    const T u = a, v = b;
+    a = add_mod(u, v, q);
+    b = shoup_mul(sub_mod(u, v, q), w, wx, q);
+  }
+};
+
+// FP64 arithmetic for q < 2^50 on signed residues (doubles holding integers), lazily reduced.
+//   mulc(a, w): c = rint(a * fl(w/q)); a*w = h + l exactly (FMA); r = (h - c q) + l, both steps exact.
+//     For |a| <= 5q the quotient is within 1.5 of a w / q, so |r| <= 1.5 q and every intermediate
+//     stays below 2^53 in magnitude (exactly representable).
+//   red(x) = x - q rint(x / q) returns the representative in [-q/2 - 1, q/2 + 1].
+// Forward butterflies leave sums unreduced inside a round of at most four stages (|x| <= 5q from an
+// input in [0, q)); inverse butterflies reduce the sum branch every stage. Every round ends with
+// red(), and values leave LDS as [0, q) integers.
+struct FpArith {
+  typedef double T;
+  typedef double W;
+  double q, qinv;
+  __device__ __forceinline__ void init(uint64_t qq) {
+    q = (double)qq;
+    qinv = 1.0 / q;
+  }
+  __device__ __forceinline__ uint64_t lds_in(uint64_t x) const { return __double_as_longlong((double)x); }
+  __device__ __forceinline__ uint64_t lds_out(uint64_t bits) const {
+    const double x = __longlong_as_double((long long)bits);
+    return (uint64_t)(x < 0.0 ? x + q : x);
+  }
+  __device__ __forceinline__ T ld(uint64_t bits) const { return __longlong_as_double((long long)bits); }
+  __device__ __forceinline__ uint64_t st(T x) const { return (uint64_t)__double_as_longlong(x); }
+  __device__ __forceinline__ T red(T x) const { return __fma_rn(-rint(x * qinv), q, x); }
+  __device__ __forceinline__ T mulc(T a, W w, W wq) const {
+    const double c = rint(a * wq);
+    const double h = a * w;
+    const double l = __fma_rn(a, w, -h);
+    return __fma_rn(-c, q, h) + l;
+  }
+  __device__ __forceinline__ void round_end(T& x) const { x = red(x); }
+  __device__ __forceinline__ void ct(T& a, T& b, W w, W wq) const {
+    const T t = mulc(b, w, wq);
+    b = a - t;
+    a = a + t;
+  }
+  __device__ __forceinline__ void gs(T& a, T& b, W w, W wq) const {
+    const T d = a - b;
+    a = red(a + b);
+    b = mulc(d, w, wq);
+  }
+};
+
+// One round: bits [lo, lo + M) of the in-phase index x, with NT threads holding EPT elements each
+// (NT * EPT = tile size). k = bits of x, logC = log2(sub-transforms per tile), sbase = global index of
+// the phase's first stage, j0 = global index of the tile's first element.
+// Thread group g holds x = (xh << (lo + M)) | (i << lo) | xl for i in [0, 2^M). At the stage on bit
+// b = lo + bl the twiddle index 2^s + floor(j / 2^(b+1)) depends on i only through i >> (bl + 1), so
+// each of the 2^(M - bl - 1) twiddles of the stage is loaded once and shared by 2^bl butterflies.
+template <int M, bool kInv, int kPhase, class A, int EPT, int NT>
+__device__ __forceinline__ void ntt_round(uint64_t* lds, const A& ar, const typename A::W* w,
+                                          const typename A::W* wx, uint32_t lo, uint32_t k, uint32_t logC,
+                                          uint32_t sbase, uint64_t j0) {
+  constexpr uint32_t GM = 1u << M, G = EPT >> M;
+  typename A::T r[EPT];
+  uint32_t xh[G], xl[G], cc[G];
+#pragma unroll
+  for (uint32_t u = 0; u < G; ++u) {
+    const uint32_t gid = u * NT + threadIdx.x;
+    if (kPhase == 1) {
+      cc[u] = gid & ((1u << logC) - 1);
+      const uint32_t rest = gid >> logC;
+      xl[u] = rest & ((1u << lo) - 1);
+      xh[u] = rest >> lo;
+    } else {
+      xl[u] = gid & ((1u << lo) - 1);
+      const uint32_t rest = gid >> lo, nh = k - lo - M;
+      xh[u] = rest & ((1u << nh) - 1);
+      cc[u] = rest >> nh;
+    }
+    const uint32_t xb = (xh[u] << (lo + M)) | xl[u];
+#pragma unroll
+    for (uint32_t i = 0; i < GM; ++i) {
+      const uint32_t x = xb | (i << lo);
+      const uint32_t li = kPhase == 1 ? (x << logC) + cc[u] : (cc[u] << k) + x;
+      r[u * GM + i] = ar.ld(lds[pad_idx(li)]);
+    }
+  }
+#pragma unroll
+  for (uint32_t sb = 0; sb < M; ++sb) {
+    const uint32_t bl = kInv ? sb : (M - 1 - sb);
+    const uint32_t b = lo + bl;
+    const uint32_t s = sbase + (k - 1 - b);
+#pragma unroll
+    for (uint32_t u = 0; u < G; ++u) {
+      uint32_t base = (1u << s) + (xh[u] << (M - bl - 1));
+      if (kPhase == 2) base += (uint32_t)(j0 >> (b + 1)) + (cc[u] << (k - b - 1));
+#pragma unroll
+      for (uint32_t t = 0; t < (1u << (M - bl - 1)); ++t) {
+        const typename A::W W = w[base + t], Wx = wx[base + t];
+#pragma unroll
+        for (uint32_t low = 0; low < (1u << bl); ++low) {
+          const uint32_t i = (t << (bl + 1)) | low, i2 = i | (1u << bl);
+          if (kInv) ar.gs(r[u * GM + i], r[u * GM + i2], W, Wx);
+          else ar.ct(r[u * GM + i], r[u * GM + i2], W, Wx);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (uint32_t u = 0; u < G; ++u) {
+    const uint32_t xb = (xh[u] << (lo + M)) | xl[u];
+#pragma unroll
+    for (uint32_t i = 0; i < GM; ++i) {
+      const uint32_t x = xb | (i << lo);
+      const uint32_t li = kPhase == 1 ? (x << logC) + cc[u] : (cc[u] << k) + x;
+      ar.round_end(r[u * GM + i]);
+      lds[pad_idx(li)] = ar.st(r[u * GM + i]);
+    }
+  }
+}
+
+template <bool kInv, int kPhase, class A, int EPT, int NT>
+__device__ __forceinline__ void ntt_rounds(uint64_t* lds, const A& ar, const typename A::W* w,
+                                           const typename A::W* wx, uint32_t k, uint32_t logC, uint32_t sbase,
+                                           uint64_t j0) {
+  // Rounds of MB = log2(EPT) bits. Forward: chunks from the top ([k-MB, k), [k-2MB, k-MB), ...,
+  // [0, rem)); inverse: the same chunks in reverse order.
+  constexpr uint32_t MB = EPT == 16 ? 4 : (EPT == 8 ? 3 : 2);
+  const uint32_t nr = (k + MB - 1) / MB;
+  for (uint32_t rr = 0; rr < nr; ++rr) {
+    const uint32_t rf = kInv ? nr - 1 - rr : rr;
+    const uint32_t hi = k - MB * rf;
+    const uint32_t lo = hi >= MB ? hi - MB : 0;
+    switch (hi - lo) {
+      case 4:
+        if constexpr (MB >= 4) ntt_round<4, kInv, kPhase, A, EPT, NT>(lds, ar, w, wx, lo, k, logC, sbase, j0);
+        break;
+      case 3:
+        if constexpr (MB >= 3) ntt_round<3, kInv, kPhase, A, EPT, NT>(lds, ar, w, wx, lo, k, logC, sbase, j0);
+        break;
+      case 2: ntt_round<2, kInv, kPhase, A, EPT, NT>(lds, ar, w, wx, lo, k, logC, sbase, j0); break;
+      default: ntt_round<1, kInv, kPhase, A, EPT, NT>(lds, ar, w, wx, lo, k, logC, sbase, j0); break;
+    }
+    __syncthreads();
+  }
+}
+
+template <bool kInv, int kPhase, class A>
+__global__ __launch_bounds__(kThreads) void k_ntt(LimbBatch lb, const ModInfo* __restrict__ mods,
+                                                 const typename A::W* __restrict__ tw, uint32_t logN, uint32_t k1,
+                                                 bool from_src) {
   extern __shared__ uint64_t lds[];
-  const uint32_t N = 1u << logN, k2 = logN - k1, E = 1u << logE, logC = logE - k1, C = 1u << logC;
-  const uint32_t tiles = N >> logE;
+  const uint32_t N = 1u << logN, tiles = N >> kNttLogE;
   const uint32_t limb = blockIdx.x / tiles, tile = blockIdx.x - limb * tiles;
   const uint32_t poly = limb / lb.limbs, e = limb - poly * lb.limbs;
   uint64_t* a = lb.base + (uint64_t)poly * lb.poly_stride + (uint64_t)e * N;
-  const uint32_t mi = mod_index(lb, e);
-  const uint64_t q = mods[mi].q;
-  const uint64_t* w = tw + (uint64_t)mi * 4 * N;
-  const uint64_t* wp = w + N;
-  const uint32_t y0 = tile << logC;
-  for (uint32_t idx = threadIdx.x; idx < E; idx += kThreads)
-    lds[idx] = a[((uint64_t)(idx >> logC) << k2) + y0 + (idx & (C - 1))];
-  __syncthreads();
-  for (uint32_t s = 0; s < k1; ++s) {
-    const uint32_t logt = k1 - 1 - s;  // column distance 2^logt
-    for (uint32_t b = threadIdx.x; b < E / 2; b += kThreads) {
-      const uint32_t c = b & (C - 1), h = b >> logC;
-      const uint32_t x = ((h >> logt) << (logt + 1)) + (h & ((1u << logt) - 1));
-      const uint32_t wi = (1u << s) + (x >> (logt + 1));
-      const uint32_t i0 = (x << logC) + c, i1 = i0 + (1u << (logt + logC));
-      const uint64_t U = lds[i0];
-      const uint64_t V = shoup_mul(lds[i1], w[wi], wp[wi], q);
-      lds[i0] = add_mod(U, V, q);
-      lds[i1] = sub_mod(U, V, q);
-    }
-    __syncthreads();
+  const uint64_t* in = from_src ? lb.src + (uint64_t)poly * lb.src_stride + (uint64_t)e * N : a;
+  const uint32_t mi = mod_index(lb, poly, e);
+  const ModInfo m = mods[mi];
+  A ar;
+  ar.init(m.q);
+  const uint32_t k = kPhase == 1 ? k1 : logN - k1, k2 = logN - k1;
+  const uint32_t logC = kNttLogE - k, C = 1u << logC;
+  const uint64_t j0 = (uint64_t)tile * kNttE;
+  for (uint32_t idx = threadIdx.x; idx < kNttE; idx += kThreads) {
+    const uint64_t g = kPhase == 1 ? ((uint64_t)(idx >> logC) << k2) + ((uint64_t)tile << logC) + (idx & (C - 1))
+                                   : j0 + idx;
+    lds[pad_idx(idx)] = ar.lds_in(in[g]);
   }
-  for (uint32_t idx = threadIdx.x; idx < E; idx += kThreads)
-    a[((uint64_t)(idx >> logC) << k2) + y0 + (idx & (C - 1))] = lds[idx];
+  __syncthreads();
+  const uint64_t toff = (uint64_t)mi * 4 * N + (kInv ? 2 * (uint64_t)N : 0);
+  ntt_rounds<kInv, kPhase, A, 16, kThreads>(lds, ar, tw + toff, tw + toff + N, k, logC, kPhase == 1 ? 0 : k1, j0);
+  for (uint32_t idx = threadIdx.x; idx < kNttE; idx += kThreads) {
+    const uint64_t g = kPhase == 1 ? ((uint64_t)(idx >> logC) << k2) + ((uint64_t)tile << logC) + (idx & (C - 1))
+                                   : j0 + idx;
+    uint64_t v = ar.lds_out(lds[pad_idx(idx)]);
+    if (kInv && kPhase == 1) v = shoup_mul(v, m.n_inv, m.n_inv_shoup, m.q);
+    a[g] = v;
+  }
 }
 
-__global__ __launch_bounds__(kThreads) void k_ntt_fwd_p2(LimbBatch lb, const ModInfo* __restrict__ mods,
-                                                        const uint64_t* __restrict__ tw, uint32_t logN,
-                                                        uint32_t k1, uint32_t logE) {
+// Row phase of the forward NTT of the ModUp digits fused with the key inner product.
+// Workgroup (item b, extended limb e, tile), 512 threads holding 8 elements each: for every digit
+// j, the digit's row for limb e (column phase already applied) goes through the row stages in LDS
+// and is multiplied by the key tile; for the digit that contains e the NTT-domain input is used
+// directly. Only u = sum_j ext_j * key_j (both components) is written, so the transformed digits
+// never return to HBM.
+constexpr int kInnerThreads = 512;
+template <class A>
+__global__ __launch_bounds__(kInnerThreads) void k_ntt_p2_inner(
+    uint32_t B, uint32_t nl, uint32_t K, uint32_t nq, uint32_t alpha, uint32_t R, uint32_t e0, uint32_t ne,
+    uint32_t logN, uint32_t k1, const ModInfo* __restrict__ mods, const typename A::W* __restrict__ tw,
+    const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __restrict__ ext,
+    const uint64_t* const* __restrict__ keys, uint64_t* __restrict__ u) {
   extern __shared__ uint64_t lds[];
-  const uint32_t N = 1u << logN, E = 1u << logE;
-  const uint32_t tiles = N >> logE;
-  const uint32_t limb = blockIdx.x / tiles, tile = blockIdx.x - limb * tiles;
-  const uint32_t poly = limb / lb.limbs, e = limb - poly * lb.limbs;
-  uint64_t* a = lb.base + (uint64_t)poly * lb.poly_stride + (uint64_t)e * N + (uint64_t)tile * E;
-  const uint32_t mi = mod_index(lb, e);
-  const uint64_t q = mods[mi].q;
-  const uint64_t* w = tw + (uint64_t)mi * 4 * N;
-  const uint64_t* wp = w + N;
-  const uint32_t j0 = tile * E;
-  for (uint32_t idx = threadIdx.x; idx < E; idx += kThreads) lds[idx] = a[idx];
-  __syncthreads();
-  for (uint32_t s = k1; s < logN; ++s) {
-    const uint32_t logt = logN - 1 - s;
-    for (uint32_t b = threadIdx.x; b < E / 2; b += kThreads) {
-      const uint32_t j = ((b >> logt) << (logt + 1)) + (b & ((1u << logt) - 1));
-      const uint32_t wi = (1u << s) + ((j0 + j) >> (logt + 1));
-      const uint64_t U = lds[j];
-      const uint64_t V = shoup_mul(lds[j + (1u << logt)], w[wi], wp[wi], q);
-      lds[j] = add_mod(U, V, q);
-      lds[j + (1u << logt)] = sub_mod(U, V, q);
+  constexpr uint32_t kPer = kNttE / kInnerThreads;
+  const uint32_t N = 1u << logN, tiles = N >> kNttLogE;
+  const uint32_t tile = blockIdx.x % tiles, be = blockIdx.x / tiles;
+  const uint32_t e = e0 + be % ne, b = be / ne;
+  const uint32_t next = nl + K, beta = (nl + alpha - 1) / alpha, nall = nq + K;
+  const uint32_t mi = e < nl ? e : nq + (e - nl);
+  const ModInfo m = mods[mi];
+  const uint64_t j0 = (uint64_t)tile * kNttE;
+  const uint32_t k = logN - k1, logC = kNttLogE - k;
+  const uint64_t* key = keys[b];
+  A ar;
+  ar.init(m.q);
+  const typename A::W* w = tw + (uint64_t)mi * 4 * N;
+  uint64_t acc0[kPer], acc1[kPer];
+#pragma unroll
+  for (uint32_t r = 0; r < kPer; ++r) acc0[r] = acc1[r] = 0;
+  for (uint32_t j = 0; j < beta; ++j) {
+    const uint32_t lo = j * alpha, cnt = min(alpha, nl - lo);
+    const uint64_t* kb = key + ((uint64_t)(j * 2 + 0) * nall + mi) * N + j0;
+    const uint64_t* ka = key + ((uint64_t)(j * 2 + 1) * nall + mi) * N + j0;
+    if (e >= lo && e < lo + cnt) {
+      const uint64_t* x = in + (uint64_t)b * in_stride + (uint64_t)e * N + j0;
+#pragma unroll
+      for (uint32_t r = 0; r < kPer; ++r) {
+        const uint32_t idx = threadIdx.x + r * kInnerThreads;
+        const uint64_t xv = x[idx];
+        acc0[r] = add_mod(acc0[r], mont_mul(xv, kb[idx], m.q, m.qinv), m.q);
+        acc1[r] = add_mod(acc1[r], mont_mul(xv, ka[idx], m.q, m.qinv), m.q);
+      }
+    } else {
+      const uint32_t row = e < lo ? e : e - cnt;
+      const uint64_t* src = ext + (((uint64_t)j * B + b) * R + row) * N + j0;
+      for (uint32_t idx = threadIdx.x; idx < kNttE; idx += kInnerThreads) lds[pad_idx(idx)] = ar.lds_in(src[idx]);
+      __syncthreads();
+      ntt_rounds<false, 2, A, 8, kInnerThreads>(lds, ar, w, w + N, k, logC, k1, j0);
+#pragma unroll
+      for (uint32_t r = 0; r < kPer; ++r) {
+        const uint32_t idx = threadIdx.x + r * kInnerThreads;
+        const uint64_t xv = ar.lds_out(lds[pad_idx(idx)]);
+        acc0[r] = add_mod(acc0[r], mont_mul(xv, kb[idx], m.q, m.qinv), m.q);
+        acc1[r] = add_mod(acc1[r], mont_mul(xv, ka[idx], m.q, m.qinv), m.q);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  for (uint32_t idx = threadIdx.x; idx < E; idx += kThreads) a[idx] = lds[idx];
+  uint64_t* u0 = u + ((uint64_t)(b * 2 + 0) * next + e) * N + j0;
+  uint64_t* u1 = u + ((uint64_t)(b * 2 + 1) * next + e) * N + j0;
+#pragma unroll
+  for (uint32_t r = 0; r < kPer; ++r) {
+    const uint32_t idx = threadIdx.x + r * kInnerThreads;
+    u0[idx] = acc0[r];
+    u1[idx] = acc1[r];
+  }
 }
 
-__global__ __launch_bounds__(kThreads) void k_ntt_inv_p2(LimbBatch lb, const ModInfo* __restrict__ mods,
-                                                        const uint64_t* __restrict__ tw, uint32_t logN,
-                                                        uint32_t k1, uint32_t logE) {
+// Row phase of the forward NTT of the ModDown conversion fused with the final combine:
+// out[b][c][i] = add[2b+c][i] + (u[b][c][i] - NTT(conv)[b][c][i]) P^-1 (NTT domain).
+// Workgroup (poly bc = 2b + c, limb i, tile); conv has had its column phase.
+template <class A>
+__global__ __launch_bounds__(kThreads) void k_ntt_p2_combine(uint32_t nl, uint32_t K, uint32_t nq, uint32_t logN,
+                                                            uint32_t k1, const ModInfo* __restrict__ mods,
+                                                            const typename A::W* __restrict__ tw,
+                                                            const uint64_t* __restrict__ tab,
+                                                            const uint64_t* __restrict__ u,
+                                                            const uint64_t* __restrict__ conv,
+                                                            const uint64_t* const* __restrict__ add,
+                                                            uint64_t* const* __restrict__ out) {
   extern __shared__ uint64_t lds[];
-  const uint32_t N = 1u << logN, E = 1u << logE;
-  const uint32_t tiles = N >> logE;
-  const uint32_t limb = blockIdx.x / tiles, tile = blockIdx.x - limb * tiles;
-  const uint32_t poly = limb / lb.limbs, e = limb - poly * lb.limbs;
-  uint64_t* a = lb.base + (uint64_t)poly * lb.poly_stride + (uint64_t)e * N + (uint64_t)tile * E;
-  const uint32_t mi = mod_index(lb, e);
-  const uint64_t q = mods[mi].q;
-  const uint64_t* w = tw + (uint64_t)mi * 4 * N + 2 * (uint64_t)N;
-  const uint64_t* wp = w + N;
-  const uint32_t j0 = tile * E;
-  for (uint32_t idx = threadIdx.x; idx < E; idx += kThreads) lds[idx] = a[idx];
+  const uint32_t N = 1u << logN, tiles = N >> kNttLogE, next = nl + K;
+  const uint32_t tile = blockIdx.x % tiles, li = blockIdx.x / tiles;
+  const uint32_t i = li % nl, bc = li / nl, b = bc >> 1, c = bc & 1;
+  const ModInfo m = mods[i];
+  A ar;
+  ar.init(m.q);
+  const uint64_t j0 = (uint64_t)tile * kNttE;
+  const uint32_t k = logN - k1, logC = kNttLogE - k;
+  const uint64_t* src = conv + ((uint64_t)bc * nl + i) * N + j0;
+  for (uint32_t idx = threadIdx.x; idx < kNttE; idx += kThreads) lds[pad_idx(idx)] = ar.lds_in(src[idx]);
   __syncthreads();
-  for (int s = (int)logN - 1; s >= (int)k1; --s) {
-    const uint32_t logt = logN - 1 - s;
-    for (uint32_t b = threadIdx.x; b < E / 2; b += kThreads) {
-      const uint32_t j = ((b >> logt) << (logt + 1)) + (b & ((1u << logt) - 1));
-      const uint32_t wi = (1u << s) + ((j0 + j) >> (logt + 1));
-      const uint64_t U = lds[j], V = lds[j + (1u << logt)];
-      lds[j] = add_mod(U, V, q);
-      lds[j + (1u << logt)] = shoup_mul(sub_mod(U, V, q), w[wi], wp[wi], q);
-    }
-    __syncthreads();
+  const typename A::W* w = tw + (uint64_t)i * 4 * N;
+  ntt_rounds<false, 2, A, 16, kThreads>(lds, ar, w, w + N, k, logC, k1, j0);
+  const uint64_t* pinv = tab + 2 * K + 2 * (uint64_t)K * nq + 2 * i;
+  const uint64_t* uu = u + ((uint64_t)bc * next + i) * N + j0;
+  const uint64_t* ad = add[bc];
+  if (ad) ad += (uint64_t)i * N + j0;
+  uint64_t* o = out[b] + ((uint64_t)c * nl + i) * N + j0;
+  for (uint32_t idx = threadIdx.x; idx < kNttE; idx += kThreads) {
+    uint64_t v = shoup_mul(sub_mod(uu[idx], ar.lds_out(lds[pad_idx(idx)]), m.q), pinv[0], pinv[1], m.q);
+    if (ad) v = add_mod(v, ad[idx], m.q);
+    o[idx] = v;
   }
-  for (uint32_t idx = threadIdx.x; idx < E; idx += kThreads) a[idx] = lds[idx];
-}
-
-__global__ __launch_bounds__(kThreads) void k_ntt_inv_p1(LimbBatch lb, const ModInfo* __restrict__ mods,
-                                                        const uint64_t* __restrict__ tw, uint32_t logN,
-                                                        uint32_t k1, uint32_t logE) {
-  extern __shared__ uint64_t lds[];
-  const uint32_t N = 1u << logN, k2 = logN - k1, E = 1u << logE, logC = logE - k1, C = 1u << logC;
-  const uint32_t tiles = N >> logE;
-  const uint32_t limb = blockIdx.x / tiles, tile = blockIdx.x - limb * tiles;
-  const uint32_t poly = limb / lb.limbs, e = limb - poly * lb.limbs;
-  uint64_t* a = lb.base + (uint64_t)poly * lb.poly_stride + (uint64_t)e * N;
-  const uint32_t mi = mod_index(lb, e);
-  const uint64_t q = mods[mi].q;
-  const uint64_t ninv = mods[mi].n_inv, ninvp = mods[mi].n_inv_shoup;
-  const uint64_t* w = tw + (uint64_t)mi * 4 * N + 2 * (uint64_t)N;
-  const uint64_t* wp = w + N;
-  const uint32_t y0 = tile << logC;
-  for (uint32_t idx = threadIdx.x; idx < E; idx += kThreads)
-    lds[idx] = a[((uint64_t)(idx >> logC) << k2) + y0 + (idx & (C - 1))];
-  __syncthreads();
-  for (int s = (int)k1 - 1; s >= 0; --s) {
-    const uint32_t logt = k1 - 1 - s;
-    for (uint32_t b = threadIdx.x; b < E / 2; b += kThreads) {
-      const uint32_t c = b & (C - 1), h = b >> logC;
-      const uint32_t x = ((h >> logt) << (logt + 1)) + (h & ((1u << logt) - 1));
-      const uint32_t wi = (1u << s) + (x >> (logt + 1));
-      const uint32_t i0 = (x << logC) + c, i1 = i0 + (1u << (logt + logC));
-      const uint64_t U = lds[i0], V = lds[i1];
-      lds[i0] = add_mod(U, V, q);
-      lds[i1] = shoup_mul(sub_mod(U, V, q), w[wi], wp[wi], q);
-    }
-    __syncthreads();
-  }
-  for (uint32_t idx = threadIdx.x; idx < E; idx += kThreads)
-    a[((uint64_t)(idx >> logC) << k2) + y0 + (idx & (C - 1))] = shoup_mul(lds[idx], ninv, ninvp, q);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -214,77 +405,46 @@ __global__ __launch_bounds__(kThreads) void k_tensor(uint32_t B, uint32_t nl, ui
   }
 }
 
-// ModUp (coefficient domain): for item b, digit j, coefficient k.
+// ModUp (coefficient domain): for item b, digit j, coefficient k. Only the limbs outside the digit are
+// produced (the digit's own limbs are the input itself): compacted rows, row r -> extended-basis limb
+// e = r (r < lo) or r + cnt, laid out [digit][item][row (stride R)][N].
 // tab block of digit j: [alpha][2] (Dhat_i^-1 mod q_i, shoup) then [alpha][next][2] (Dhat_i mod t_e, shoup).
 __global__ __launch_bounds__(kThreads) void k_modup(uint32_t B, uint32_t nl, uint32_t K, uint32_t nq, uint32_t alpha,
-                                                   uint32_t logN, const ModInfo* __restrict__ mods,
-                                                   const uint64_t* __restrict__ tab, const uint64_t* __restrict__ din,
-                                                   uint64_t in_stride, uint64_t* __restrict__ ext) {
+                                                   uint32_t R, uint32_t logN, const ModInfo* __restrict__ mods,
+                                                   const uint64_t* __restrict__ tab, const uint64_t* __restrict__ dcoef,
+                                                   uint64_t* __restrict__ ext) {
   const uint32_t N = 1u << logN;
   const uint32_t beta = (nl + alpha - 1) / alpha, next = nl + K;
   const uint64_t total = (uint64_t)B * beta << logN;
   for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < total; t += (uint64_t)gridDim.x * kThreads) {
     const uint32_t k = (uint32_t)t & (N - 1);
     const uint64_t r = t >> logN;
-    const uint32_t j = (uint32_t)(r % beta), b = (uint32_t)(r / beta);
+    const uint32_t b = (uint32_t)(r % B), j = (uint32_t)(r / B);
     const uint32_t lo = j * alpha, cnt = min(alpha, nl - lo);
     const uint64_t* blk = tab + (uint64_t)j * (2 * alpha + 2 * alpha * next);
-    const uint64_t* d = din + (uint64_t)b * in_stride;
-    uint64_t dv[kMaxAlpha], y[kMaxAlpha];
-    for (uint32_t i = 0; i < cnt; ++i) {
-      dv[i] = d[(uint64_t)(lo + i) * N + k];
-      y[i] = shoup_mul(dv[i], blk[2 * i], blk[2 * i + 1], mods[lo + i].q);
-    }
-    uint64_t* o = ext + (uint64_t)(b * beta + j) * next * N + k;
-    for (uint32_t e = 0; e < next; ++e) {
-      uint64_t v;
-      if (e >= lo && e < lo + cnt) {
-        v = dv[e - lo];
-      } else {
-        const uint64_t tq = mods[e < nl ? e : nq + (e - nl)].q;
-        const uint64_t* mrow = blk + 2 * alpha + 2 * (uint64_t)e;
-        v = 0;
-        for (uint32_t i = 0; i < cnt; ++i) {
-          const uint64_t* c = mrow + (uint64_t)i * 2 * next;
-          v = add_mod(v, shoup_mul(y[i], c[0], c[1], tq), tq);
-        }
+    const uint64_t* d = dcoef + (uint64_t)b * nl * N;
+    uint64_t y[kMaxAlpha];
+    for (uint32_t i = 0; i < cnt; ++i)
+      y[i] = shoup_mul(d[(uint64_t)(lo + i) * N + k], blk[2 * i], blk[2 * i + 1], mods[lo + i].q);
+    uint64_t* o = ext + ((uint64_t)j * B + b) * R * N + k;
+    for (uint32_t row = 0; row < next - cnt; ++row) {
+      const uint32_t e = row < lo ? row : row + cnt;
+      const uint64_t tq = mods[e < nl ? e : nq + (e - nl)].q;
+      const uint64_t* mrow = blk + 2 * alpha + 2 * (uint64_t)e;
+      uint64_t v = 0;
+      for (uint32_t i = 0; i < cnt; ++i) {
+        const uint64_t* c = mrow + (uint64_t)i * 2 * next;
+        v = add_mod(v, shoup_mul(y[i], c[0], c[1], tq), tq);
       }
-      o[(uint64_t)e * N] = v;
+      o[(uint64_t)row * N] = v;
     }
   }
 }
 
-// u[b][c][e] = sum_j ext[b][j][e] * key[b][j][c][limb(e)] (key in Montgomery form).
-__global__ __launch_bounds__(kThreads) void k_ks_inner(uint32_t B, uint32_t nl, uint32_t K, uint32_t nq,
-                                                      uint32_t alpha, uint32_t logN, const ModInfo* __restrict__ mods,
-                                                      const uint64_t* __restrict__ ext,
-                                                      const uint64_t* const* __restrict__ keys,
-                                                      uint64_t* __restrict__ u) {
-  const uint32_t N = 1u << logN;
-  const uint32_t beta = (nl + alpha - 1) / alpha, next = nl + K, nall = nq + K;
-  const uint64_t total = (uint64_t)B * next << logN;
-  for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < total; t += (uint64_t)gridDim.x * kThreads) {
-    const uint32_t k = (uint32_t)t & (N - 1);
-    const uint64_t r = t >> logN;
-    const uint32_t e = (uint32_t)(r % next), b = (uint32_t)(r / next);
-    const uint32_t mi = e < nl ? e : nq + (e - nl);
-    const ModInfo m = mods[mi];
-    const uint64_t* key = keys[b];
-    uint64_t acc0 = 0, acc1 = 0;
-    for (uint32_t j = 0; j < beta; ++j) {
-      const uint64_t x = ext[((uint64_t)(b * beta + j) * next + e) * N + k];
-      const uint64_t k0 = key[((uint64_t)(j * 2 + 0) * nall + mi) * N + k];
-      const uint64_t k1 = key[((uint64_t)(j * 2 + 1) * nall + mi) * N + k];
-      acc0 = add_mod(acc0, mont_mul(x, k0, m.q, m.qinv), m.q);
-      acc1 = add_mod(acc1, mont_mul(x, k1, m.q, m.qinv), m.q);
-    }
-    u[((uint64_t)(b * 2 + 0) * next + e) * N + k] = acc0;
-    u[((uint64_t)(b * 2 + 1) * next + e) * N + k] = acc1;
-  }
-}
-
-// ModDown base conversion P -> Q_l (coefficient domain). tab: [K][2] ((P/p_k)^-1 mod p_k),
-// [K][nq][2] ((P/p_k) mod q_i), [nq][2] (P^-1 mod q_i).
+// ModDown base conversion P -> Q_l (coefficient domain) with centred representatives:
+// z_k = [u_(p_k) (P/p_k)^-1]_(p_k) is used as z_k - p_k when z_k > (p_k - 1)/2, so the rounding error of
+// the division by P is zero-mean. Since p_k (P/p_k) = P, each centred term subtracts P mod q_i.
+// tab: [K][2] ((P/p_k)^-1 mod p_k), [K][nq][2] ((P/p_k) mod q_i), [nq][2] (P^-1 mod q_i), [nq] (P mod q_i).
 __global__ __launch_bounds__(kThreads) void k_moddown_conv(uint32_t B, uint32_t nl, uint32_t K, uint32_t nq,
                                                           uint32_t logN, const ModInfo* __restrict__ mods,
                                                           const uint64_t* __restrict__ tab,
@@ -296,9 +456,14 @@ __global__ __launch_bounds__(kThreads) void k_moddown_conv(uint32_t B, uint32_t 
     const uint32_t k = (uint32_t)t & (N - 1);
     const uint32_t bc = (uint32_t)(t >> logN);
     uint64_t z[kMaxK];
-    for (uint32_t kk = 0; kk < K; ++kk)
-      z[kk] = shoup_mul(u[((uint64_t)bc * next + nl + kk) * N + k], tab[2 * kk], tab[2 * kk + 1], mods[nq + kk].q);
+    uint32_t nneg = 0;
+    for (uint32_t kk = 0; kk < K; ++kk) {
+      const uint64_t pk = mods[nq + kk].q;
+      z[kk] = shoup_mul(u[((uint64_t)bc * next + nl + kk) * N + k], tab[2 * kk], tab[2 * kk + 1], pk);
+      nneg += z[kk] > (pk - 1) / 2 ? 1u : 0u;
+    }
     const uint64_t* pq = tab + 2 * K;
+    const uint64_t* pmod = tab + 2 * K + 2 * (uint64_t)K * nq + 2 * nq;
     for (uint32_t i = 0; i < nl; ++i) {
       const uint64_t q = mods[i].q;
       uint64_t acc = 0;
@@ -306,33 +471,9 @@ __global__ __launch_bounds__(kThreads) void k_moddown_conv(uint32_t B, uint32_t 
         const uint64_t* c = pq + 2 * ((uint64_t)kk * nq + i);
         acc = add_mod(acc, shoup_mul(z[kk], c[0], c[1], q), q);
       }
+      for (uint32_t n = 0; n < nneg; ++n) acc = sub_mod(acc, pmod[i], q);
       conv[((uint64_t)bc * nl + i) * N + k] = acc;
     }
-  }
-}
-
-// out[b][c][i] = add[2b+c][i] + (u[b][c][i] - conv[b][c][i]) P^-1 (NTT domain).
-__global__ __launch_bounds__(kThreads) void k_ks_combine(uint32_t B, uint32_t nl, uint32_t K, uint32_t nq,
-                                                        uint32_t logN, const ModInfo* __restrict__ mods,
-                                                        const uint64_t* __restrict__ tab,
-                                                        const uint64_t* __restrict__ u,
-                                                        const uint64_t* __restrict__ conv,
-                                                        const uint64_t* const* __restrict__ add,
-                                                        uint64_t* const* __restrict__ out) {
-  const uint32_t N = 1u << logN, next = nl + K;
-  const uint64_t* pinv = tab + 2 * K + 2 * (uint64_t)K * nq;
-  const uint64_t total = (uint64_t)B * 2 * nl << logN;
-  for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < total; t += (uint64_t)gridDim.x * kThreads) {
-    const uint32_t k = (uint32_t)t & (N - 1);
-    const uint64_t r = t >> logN;
-    const uint32_t i = (uint32_t)(r % nl);
-    const uint32_t bc = (uint32_t)(r / nl), b = bc >> 1, c = bc & 1;
-    const uint64_t q = mods[i].q;
-    uint64_t v = sub_mod(u[((uint64_t)bc * next + i) * N + k], conv[((uint64_t)bc * nl + i) * N + k], q);
-    v = shoup_mul(v, pinv[2 * i], pinv[2 * i + 1], q);
-    const uint64_t* ad = add[bc];
-    if (ad) v = add_mod(v, ad[(uint64_t)i * N + k], q);
-    out[b][((uint64_t)c * nl + i) * N + k] = v;
   }
 }
 
@@ -411,8 +552,7 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(uint32_t nseg, uint32_t
                                                         const ModInfo* __restrict__ mods,
                                                         const uint32_t* __restrict__ seg,
                                                         const uint64_t* __restrict__ contrib,
-                                                        uint64_t* __restrict__ result) {
-  const uint32_t N = 1u << logN;
+                                                        uint64_t* const* __restrict__ results) {
   const uint64_t per = (uint64_t)2 * nl << logN;
   const uint64_t total = (uint64_t)nseg * per;
   for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < total; t += (uint64_t)gridDim.x * kThreads) {
@@ -420,10 +560,11 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(uint32_t nseg, uint32_t
     const uint64_t off = t - (uint64_t)s * per;
     const uint32_t i = (uint32_t)((off >> logN) % nl);
     const uint64_t q = mods[i].q;
-    const uint32_t chunk = seg[3 * s], b0 = seg[3 * s + 1], b1 = seg[3 * s + 2];
-    uint64_t acc = result[(uint64_t)chunk * per + off];
+    const uint32_t b0 = seg[3 * s + 1], b1 = seg[3 * s + 2];
+    uint64_t* res = results[seg[3 * s]];
+    uint64_t acc = res[off];
     for (uint32_t b = b0; b < b1; ++b) acc = add_mod(acc, contrib[(uint64_t)b * per + off], q);
-    result[(uint64_t)chunk * per + off] = acc;
+    res[off] = acc;
   }
 }
 
@@ -535,100 +676,195 @@ static void check_launch(const char* what) {
   if (e != hipSuccess) fail(FHE_EDEVICE, std::string("kernel launch failed (") + what + "): " + hipGetErrorString(e));
 }
 
+// Launch with optional event timing; `bytes` is the kernel's algorithmic HBM traffic for this launch.
+#define FHE_LAUNCH_T(name, bytes, kern, grid, threads, lds, st, ...)            \
+  do {                                                                           \
+    const int tok_ = prof_begin(name, st);                                       \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, __VA_ARGS__);  \
+    prof_end(tok_, st, (double)(bytes));                                         \
+    check_launch(name);                                                          \
+  } while (0)
+#define FHE_LAUNCH(name, bytes, kern, grid, lds, st, ...) \
+  FHE_LAUNCH_T(name, bytes, kern, grid, kThreads, lds, st, __VA_ARGS__)
+
 static void check_batch(const fhe_ctx* ctx, const LimbBatch& lb) {
   const Params& p = ctx->p;
-  if (lb.limbs == 0 || lb.npoly == 0) return;
   uint32_t last = lb.limbs - 1;
   uint32_t mi = last < lb.n_first ? last : lb.p_base + (last - lb.n_first);
   uint32_t mi0 = 0 < lb.n_first ? 0 : lb.p_base;
   if (mi >= (uint32_t)p.nmod() || mi0 >= (uint32_t)p.nmod()) fail(FHE_EINVAL, "NTT batch modulus index out of range");
 }
 
+static uint32_t ntt_blocks(const fhe_ctx* ctx, const LimbBatch& lb) {
+  const uint64_t blocks = (uint64_t)(ctx->p.N >> kNttLogE) * lb.limbs * lb.npoly;
+  if (blocks >= (1ull << 31)) fail(FHE_EINVAL, "NTT batch too large");
+  return (uint32_t)blocks;
+}
+
+// Launches one phase of the transform over a batch. Limbs [0, n_first) use moduli 0.., the others
+// p_base..; each part runs the kernel for its moduli class (FP64 for Q primes, integer for P primes).
+// Launches one phase of the transform over a batch, split into runs of limbs whose moduli are all Q
+// primes (FP64 kernel) or all special primes (integer kernel):
+//   rows [0, qa)             -> moduli 0.. (with the digit hole, if any), Q primes;
+//   rows [qa, min(n_first))  -> moduli qa.., special primes (batches that index the whole chain);
+//   rows [n_first, limbs)    -> moduli p_base.., Q or special primes.
+template <bool kInv, int kPhase>
+static void ntt_phase(const fhe_ctx* ctx, const LimbBatch& lb, const char* name_q, const char* name_p, bool from_src,
+                      hipStream_t st) {
+  const Params& p = ctx->p;
+  const size_t lds = kNttLdsElems * sizeof(uint64_t);
+  const uint32_t nq = (uint32_t)p.nq;
+  const double* twf = (const double*)ctx->t.twf.get();
+  const uint32_t nf = std::min(lb.n_first, lb.limbs);
+  const uint32_t qa = lb.hole_items ? nf : std::min(nf, nq);
+  struct Run {
+    uint32_t lo, hi;
+    bool q;
+  };
+  Run runs[3] = {{0, qa, true}, {qa, nf, false}, {nf, lb.limbs, lb.p_base + (lb.limbs - nf) <= nq}};
+  if (nf < lb.limbs && !runs[2].q && lb.p_base < nq) fail(FHE_EINVAL, "NTT batch mixes Q and P moduli in its tail");
+  for (int part = 0; part < 3; ++part) {
+    const Run& r = runs[part];
+    if (r.hi <= r.lo) continue;
+    LimbBatch sub = lb;
+    sub.base = lb.base + (uint64_t)r.lo * p.N;
+    if (sub.src) sub.src = lb.src + (uint64_t)r.lo * p.N;
+    sub.limbs = r.hi - r.lo;
+    if (part == 0) {
+      sub.n_first = sub.limbs;
+    } else {
+      sub.n_first = 0;
+      sub.hole_items = 0;
+      sub.p_base = part == 1 ? r.lo : lb.p_base;
+    }
+    const uint32_t blocks = ntt_blocks(ctx, sub);
+    const double bytes = 16.0 * p.N * sub.limbs * sub.npoly;
+    if (r.q)
+      FHE_LAUNCH(name_q, bytes, (k_ntt<kInv, kPhase, FpArith>), blocks, lds, st, sub, mods_of(ctx), twf, p.logN, p.k1,
+                 from_src);
+    else
+      FHE_LAUNCH(name_p, bytes, (k_ntt<kInv, kPhase, IntArith>), blocks, lds, st, sub, mods_of(ctx), ctx->t.tw.u64(),
+                 p.logN, p.k1, from_src);
+  }
+}
+
+static void check_holes(const fhe_ctx* ctx, const LimbBatch& lb) {
+  if (lb.hole_items && lb.n_first + lb.hole_len > (uint32_t)ctx->p.nq)
+    fail(FHE_EINVAL, "NTT batch digit rows exceed the Q chain");
+}
+
+static void ntt_forward_cols(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st) {
+  if (lb.limbs == 0 || lb.npoly == 0) return;
+  check_batch(ctx, lb);
+  check_holes(ctx, lb);
+  ntt_phase<false, 1>(ctx, lb, "ntt_fwd_p1_q", "ntt_fwd_p1_p", lb.src != nullptr, st);
+}
+
 void ntt_forward(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st) {
   if (lb.limbs == 0 || lb.npoly == 0) return;
   check_batch(ctx, lb);
-  const Params& p = ctx->p;
-  const uint32_t tiles = p.N >> p.logE;
-  const uint64_t blocks = (uint64_t)tiles * lb.limbs * lb.npoly;
-  if (blocks >= (1ull << 31)) fail(FHE_EINVAL, "NTT batch too large");
-  const size_t lds = ((size_t)1 << p.logE) * sizeof(uint64_t);
-  hipLaunchKernelGGL(k_ntt_fwd_p1, dim3((uint32_t)blocks), dim3(kThreads), lds, st, lb, mods_of(ctx), ctx->t.tw.u64(),
-                     p.logN, p.k1, p.logE);
-  hipLaunchKernelGGL(k_ntt_fwd_p2, dim3((uint32_t)blocks), dim3(kThreads), lds, st, lb, mods_of(ctx), ctx->t.tw.u64(),
-                     p.logN, p.k1, p.logE);
-  check_launch("ntt_forward");
+  check_holes(ctx, lb);
+  ntt_phase<false, 1>(ctx, lb, "ntt_fwd_p1_q", "ntt_fwd_p1_p", lb.src != nullptr, st);
+  ntt_phase<false, 2>(ctx, lb, "ntt_fwd_p2_q", "ntt_fwd_p2_p", false, st);
 }
 
 void ntt_inverse(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st) {
   if (lb.limbs == 0 || lb.npoly == 0) return;
   check_batch(ctx, lb);
-  const Params& p = ctx->p;
-  const uint32_t tiles = p.N >> p.logE;
-  const uint64_t blocks = (uint64_t)tiles * lb.limbs * lb.npoly;
-  if (blocks >= (1ull << 31)) fail(FHE_EINVAL, "NTT batch too large");
-  const size_t lds = ((size_t)1 << p.logE) * sizeof(uint64_t);
-  hipLaunchKernelGGL(k_ntt_inv_p2, dim3((uint32_t)blocks), dim3(kThreads), lds, st, lb, mods_of(ctx), ctx->t.tw.u64(),
-                     p.logN, p.k1, p.logE);
-  hipLaunchKernelGGL(k_ntt_inv_p1, dim3((uint32_t)blocks), dim3(kThreads), lds, st, lb, mods_of(ctx), ctx->t.tw.u64(),
-                     p.logN, p.k1, p.logE);
-  check_launch("ntt_inverse");
+  check_holes(ctx, lb);
+  ntt_phase<true, 2>(ctx, lb, "ntt_inv_p2_q", "ntt_inv_p2_p", lb.src != nullptr, st);
+  ntt_phase<true, 1>(ctx, lb, "ntt_inv_p1_q", "ntt_inv_p1_p", false, st);
 }
 
 void automorph(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const uint64_t* const* src,
                const uint32_t* galois, uint64_t* dst, hipStream_t st) {
   if (!B) return;
-  hipLaunchKernelGGL(k_automorph, dim3(grid_for((uint64_t)B << ctx->p.logN)), dim3(kThreads), 0, st, B, ncomp, nl,
-                     ctx->p.logN, src, galois, dst);
-  check_launch("automorph");
+  const double bytes = 16.0 * B * ncomp * nl * ctx->p.N;
+  FHE_LAUNCH("automorph", bytes, k_automorph, grid_for((uint64_t)B << ctx->p.logN), 0, st, B, ncomp, nl, ctx->p.logN,
+             src, galois, dst);
 }
 
 void tensor(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* const* a, const uint64_t* const* b,
             uint64_t* out, hipStream_t st) {
   if (!B) return;
-  hipLaunchKernelGGL(k_tensor, dim3(grid_for((uint64_t)B * nl << ctx->p.logN)), dim3(kThreads), 0, st, B, nl,
-                     ctx->p.logN, mods_of(ctx), a, b, out);
-  check_launch("tensor");
+  const double bytes = 8.0 * 7 * B * nl * ctx->p.N;
+  FHE_LAUNCH("tensor", bytes, k_tensor, grid_for((uint64_t)B * nl << ctx->p.logN), 0, st, B, nl, ctx->p.logN,
+             mods_of(ctx), a, b, out);
+}
+
+// Rows per digit in the compacted ModUp buffer: next - (size of the last, possibly truncated, digit).
+static uint32_t modup_rows(const Params& p, uint32_t nl) {
+  const uint32_t beta = p.beta(nl), cnt_last = nl - (beta - 1) * p.alpha;
+  return nl + p.np - cnt_last;
 }
 
 size_t keyswitch_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t nl) {
   const Params& p = ctx->p;
-  const size_t N = p.N, next = nl + p.np, beta = p.beta(nl);
-  return (size_t)B * N * (beta * next + 2 * next + 2 * nl);
+  const size_t N = p.N, next = nl + p.np, beta = p.beta(nl), R = modup_rows(p, nl);
+  return (size_t)B * N * (nl + beta * R + 2 * next + 2 * nl);
 }
 
-void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, uint64_t* in, uint64_t in_stride,
+void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, uint64_t in_stride,
                const uint64_t* const* keys, const uint64_t* const* add, uint64_t* const* out, uint64_t* ws,
                hipStream_t st) {
   if (!B) return;
   const Params& p = ctx->p;
   if (p.alpha > kMaxAlpha || p.np > kMaxK) fail(FHE_EINVAL, "alpha or n_p above kernel limits");
   if (nl < 1 || nl > (uint32_t)p.nq) fail(FHE_ESHAPE, "key switch level out of range");
-  const uint32_t N = p.N, K = p.np, next = nl + K, beta = p.beta(nl);
-  uint64_t* ext = ws;                                   // [B][beta][next][N]
-  uint64_t* u = ext + (size_t)B * beta * next * N;      // [B][2][next][N]
+  const uint32_t N = p.N, K = p.np, next = nl + K, beta = p.beta(nl), alpha = p.alpha;
+  const uint32_t R = modup_rows(p, nl), cnt_last = nl - (beta - 1) * alpha;
+  const uint32_t beta_full = cnt_last == alpha ? beta : beta - 1;
+  const double e8 = 8.0 * N * B;
+  uint64_t* dcoef = ws;                                 // [B][nl][N]
+  uint64_t* ext = dcoef + (size_t)B * nl * N;           // [beta][B][R][N]
+  uint64_t* u = ext + (size_t)beta * B * R * N;         // [B][2][next][N]
   uint64_t* conv = u + (size_t)B * 2 * next * N;        // [B][2][nl][N]
-  // 1. INTT of the input (in place).
-  ntt_inverse(ctx, LimbBatch{in, nl, B, in_stride, nl, 0}, st);
-  // 2. ModUp per digit, all limbs of the extended basis.
-  hipLaunchKernelGGL(k_modup, dim3(grid_for((uint64_t)B * beta * N)), dim3(kThreads), 0, st, B, nl, K, (uint32_t)p.nq,
-                     (uint32_t)p.alpha, p.logN, mods_of(ctx), ctx->t.modup.u64() + ctx->t.modup_offset[nl], in, in_stride,
-                     ext);
-  check_launch("modup");
-  // 3. NTT of the extended digits.
-  ntt_forward(ctx, LimbBatch{ext, next, B * beta, (uint64_t)next * N, nl, (uint32_t)p.nq}, st);
-  // 4. Inner product with the key.
-  hipLaunchKernelGGL(k_ks_inner, dim3(grid_for((uint64_t)B * next * N)), dim3(kThreads), 0, st, B, nl, K,
-                     (uint32_t)p.nq, (uint32_t)p.alpha, p.logN, mods_of(ctx), ext, keys, u);
-  check_launch("ks_inner");
-  // 5. ModDown: INTT of the P limbs, conversion to Q_l, NTT, combine.
+  // 1. INTT of the input into dcoef (the NTT-domain input is kept for the digits' own limbs).
+  LimbBatch lb_in{dcoef, nl, B, (uint64_t)nl * N, nl, 0};
+  lb_in.src = in;
+  lb_in.src_stride = in_stride;
+  ntt_inverse(ctx, lb_in, st);
+  // 2. ModUp: the limbs outside each digit.
+  FHE_LAUNCH("modup", e8 * (nl + beta * (next - alpha)), k_modup, grid_for((uint64_t)B * beta * N), 0, st, B, nl, K,
+             (uint32_t)p.nq, alpha, R, p.logN, mods_of(ctx), ctx->t.modup.u64() + ctx->t.modup_offset[nl], dcoef,
+             ext);
+  // 3. Column phase of the NTT of the extended rows (full digits, then a truncated last digit).
+  if (beta_full) {
+    LimbBatch lb{ext, next - alpha, beta_full * B, (uint64_t)R * N, nl - alpha, (uint32_t)p.nq};
+    lb.hole_items = B;
+    lb.hole_alpha = alpha;
+    lb.hole_len = alpha;
+    lb.hole_j0 = 0;
+    ntt_forward_cols(ctx, lb, st);
+  }
+  if (beta_full < beta) {
+    LimbBatch lb{ext + (size_t)beta_full * B * R * N, next - cnt_last, B, (uint64_t)R * N, nl - cnt_last,
+                 (uint32_t)p.nq};
+    lb.hole_items = B;
+    lb.hole_alpha = alpha;
+    lb.hole_len = cnt_last;
+    lb.hole_j0 = beta_full;
+    ntt_forward_cols(ctx, lb, st);
+  }
+  // 4. Row phase fused with the key inner product (Q limbs on the FP64 path, P limbs on the integer path).
+  const size_t lds = kNttLdsElems * sizeof(uint64_t);
+  const uint32_t tiles = N >> kNttLogE;
+  if ((uint64_t)B * next * tiles >= (1ull << 31)) fail(FHE_EINVAL, "key-switch batch too large");
+  const double* twf = (const double*)ctx->t.twf.get();
+  // per extended limb: beta digit words (input or ModUp row), 2 beta key words, 2 output words
+  const double ib = 8.0 * N * (double)B * (3.0 * beta + 2.0);
+  FHE_LAUNCH_T("ntt_p2_inner_q", ib * nl, k_ntt_p2_inner<FpArith>, (uint64_t)B * nl * tiles, kInnerThreads, lds, st, B, nl, K,
+             (uint32_t)p.nq, alpha, R, 0u, nl, p.logN, p.k1, mods_of(ctx), twf, in, in_stride, ext, keys, u);
+  FHE_LAUNCH_T("ntt_p2_inner_p", ib * K, k_ntt_p2_inner<IntArith>, (uint64_t)B * K * tiles, kInnerThreads, lds, st, B, nl, K,
+             (uint32_t)p.nq, alpha, R, nl, K, p.logN, p.k1, mods_of(ctx), ctx->t.tw.u64(), in, in_stride, ext, keys,
+             u);
+  // 5. ModDown: INTT of the P limbs, conversion to Q_l, column phase, row phase fused with the combine.
   ntt_inverse(ctx, LimbBatch{u + (size_t)nl * N, K, 2 * B, (uint64_t)next * N, 0, (uint32_t)p.nq}, st);
-  hipLaunchKernelGGL(k_moddown_conv, dim3(grid_for((uint64_t)B * 2 * N)), dim3(kThreads), 0, st, B, nl, K,
-                     (uint32_t)p.nq, p.logN, mods_of(ctx), ctx->t.moddown.u64(), u, conv);
-  check_launch("moddown_conv");
-  ntt_forward(ctx, LimbBatch{conv, nl, 2 * B, (uint64_t)nl * N, nl, 0}, st);
-  hipLaunchKernelGGL(k_ks_combine, dim3(grid_for((uint64_t)B * 2 * nl * N)), dim3(kThreads), 0, st, B, nl, K,
-                     (uint32_t)p.nq, p.logN, mods_of(ctx), ctx->t.moddown.u64(), u, conv, add, out);
-  check_launch("ks_combine");
+  FHE_LAUNCH("moddown_conv", e8 * 2 * (K + nl), k_moddown_conv, grid_for((uint64_t)B * 2 * N), 0, st, B, nl, K,
+             (uint32_t)p.nq, p.logN, mods_of(ctx), ctx->t.moddown.u64(), u, conv);
+  ntt_forward_cols(ctx, LimbBatch{conv, nl, 2 * B, (uint64_t)nl * N, nl, 0}, st);
+  FHE_LAUNCH("ntt_p2_combine", e8 * 2 * nl * 3.5, k_ntt_p2_combine<FpArith>, (uint64_t)2 * B * nl * tiles, lds, st, nl,
+             K, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.moddown.u64(), u, conv, add, out);
 }
 
 size_t rescale_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl) {
@@ -641,84 +877,75 @@ void rescale(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const 
   const Params& p = ctx->p;
   if (nl < 2 || nl > (uint32_t)p.nq) fail(FHE_ELEVEL, "rescale needs at least two limbs");
   const uint32_t N = p.N, BC = B * ncomp;
+  const double e8 = 8.0 * N * BC;
   uint64_t* tmp = ws;                       // [BC][N]
   uint64_t* w = ws + (size_t)BC * N;        // [BC][nl-1][N]
-  hipLaunchKernelGGL(k_copy_last, dim3(grid_for((uint64_t)BC * N)), dim3(kThreads), 0, st, B, ncomp, nl, p.logN, in,
-                     tmp);
-  check_launch("copy_last");
+  FHE_LAUNCH("copy_last", e8 * 2, k_copy_last, grid_for((uint64_t)BC * N), 0, st, B, ncomp, nl, p.logN, in, tmp);
   ntt_inverse(ctx, LimbBatch{tmp, 1, BC, N, 0, nl - 1}, st);
-  hipLaunchKernelGGL(k_rescale_bcast, dim3(grid_for((uint64_t)BC * (nl - 1) * N)), dim3(kThreads), 0, st, BC, nl,
-                     p.logN, mods_of(ctx), tmp, w);
-  check_launch("rescale_bcast");
+  FHE_LAUNCH("rescale_bcast", e8 * nl, k_rescale_bcast, grid_for((uint64_t)BC * (nl - 1) * N), 0, st, BC, nl, p.logN,
+             mods_of(ctx), tmp, w);
   ntt_forward(ctx, LimbBatch{w, nl - 1, BC, (uint64_t)(nl - 1) * N, nl - 1, 0}, st);
-  hipLaunchKernelGGL(k_rescale_combine, dim3(grid_for((uint64_t)BC * (nl - 1) * N)), dim3(kThreads), 0, st, B, ncomp,
-                     nl, (uint32_t)p.nq, p.logN, mods_of(ctx), ctx->t.rescale.u64(), in, w, out);
-  check_launch("rescale_combine");
+  FHE_LAUNCH("rescale_combine", e8 * 3 * (nl - 1), k_rescale_combine, grid_for((uint64_t)BC * (nl - 1) * N), 0, st, B,
+             ncomp, nl, (uint32_t)p.nq, p.logN, mods_of(ctx), ctx->t.rescale.u64(), in, w, out);
 }
 
 void mask_mul(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* const* in, const uint32_t* galois,
               uint64_t* const* out, hipStream_t st) {
   if (!B) return;
   if (nl > (uint32_t)ctx->p.nq - 1) fail(FHE_ESHAPE, "mask multiply above level top-1");
-  hipLaunchKernelGGL(k_mask_mul, dim3(grid_for((uint64_t)B << ctx->p.logN)), dim3(kThreads), 0, st, B, nl,
-                     ctx->p.logN, mods_of(ctx), ctx->t.mask.u64(), in, galois, out);
-  check_launch("mask_mul");
+  const double bytes = 8.0 * ctx->p.N * nl * (4.0 * B + 1);
+  FHE_LAUNCH("mask_mul", bytes, k_mask_mul, grid_for((uint64_t)B << ctx->p.logN), 0, st, B, nl, ctx->p.logN,
+             mods_of(ctx), ctx->t.mask.u64(), in, galois, out);
 }
 
-void accumulate(const fhe_ctx* ctx, uint32_t nseg, uint32_t nl, const uint32_t* seg, const uint64_t* contrib,
-                uint64_t* result, hipStream_t st) {
+void accumulate(const fhe_ctx* ctx, uint32_t nseg, uint32_t ncontrib, uint32_t nl, const uint32_t* seg,
+                const uint64_t* contrib, uint64_t* const* results, hipStream_t st) {
   if (!nseg) return;
-  hipLaunchKernelGGL(k_accumulate, dim3(grid_for((uint64_t)nseg * 2 * nl << ctx->p.logN)), dim3(kThreads), 0, st, nseg,
-                     nl, ctx->p.logN, mods_of(ctx), seg, contrib, result);
-  check_launch("accumulate");
+  // every contribution read once, every touched result chunk read and written once
+  const double bytes = 8.0 * 2 * nl * ctx->p.N * ((double)ncontrib + 2.0 * nseg);
+  FHE_LAUNCH("accumulate", bytes, k_accumulate, grid_for((uint64_t)nseg * 2 * nl << ctx->p.logN), 0, st, nseg, nl,
+             ctx->p.logN, mods_of(ctx), seg, contrib, results);
 }
 
 void signed_to_limbs(const fhe_ctx* ctx, const int64_t* v, uint32_t nlimbs, uint32_t n_first, uint32_t p_base,
                      uint64_t* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_signed_to_limbs, dim3(grid_for((uint64_t)nlimbs << ctx->p.logN)), dim3(kThreads), 0, st, v,
-                     nlimbs, n_first, p_base, ctx->p.logN, mods_of(ctx), out);
-  check_launch("signed_to_limbs");
+  FHE_LAUNCH("signed_to_limbs", 0.0, k_signed_to_limbs, grid_for((uint64_t)nlimbs << ctx->p.logN), 0, st, v, nlimbs,
+             n_first, p_base, ctx->p.logN, mods_of(ctx), out);
 }
 
 void to_montgomery(const fhe_ctx* ctx, uint64_t* x, uint32_t nlimbs, uint32_t n_first, uint32_t p_base,
                    hipStream_t st) {
-  hipLaunchKernelGGL(k_to_mont, dim3(grid_for((uint64_t)nlimbs << ctx->p.logN)), dim3(kThreads), 0, st, x, nlimbs,
-                     n_first, p_base, ctx->p.logN, mods_of(ctx));
-  check_launch("to_montgomery");
+  FHE_LAUNCH("to_montgomery", 0.0, k_to_mont, grid_for((uint64_t)nlimbs << ctx->p.logN), 0, st, x, nlimbs, n_first,
+             p_base, ctx->p.logN, mods_of(ctx));
 }
 
 void keygen_digit(const fhe_ctx* ctx, uint32_t nall, const uint64_t* a, const uint64_t* s, const uint64_t* e,
                   const uint64_t* sp, const uint64_t* pfac, uint64_t* bout, uint64_t* aout, hipStream_t st) {
-  hipLaunchKernelGGL(k_keygen_digit, dim3(grid_for((uint64_t)nall << ctx->p.logN)), dim3(kThreads), 0, st, nall,
-                     ctx->p.logN, mods_of(ctx), a, s, e, sp, pfac, bout, aout);
-  check_launch("keygen_digit");
+  FHE_LAUNCH("keygen_digit", 0.0, k_keygen_digit, grid_for((uint64_t)nall << ctx->p.logN), 0, st, nall, ctx->p.logN,
+             mods_of(ctx), a, s, e, sp, pfac, bout, aout);
 }
 
 void square(const fhe_ctx* ctx, uint32_t nall, const uint64_t* s, uint64_t* s2, hipStream_t st) {
-  hipLaunchKernelGGL(k_square, dim3(grid_for((uint64_t)nall << ctx->p.logN)), dim3(kThreads), 0, st, nall,
-                     ctx->p.logN, mods_of(ctx), s, s2);
-  check_launch("square");
+  FHE_LAUNCH("square", 0.0, k_square, grid_for((uint64_t)nall << ctx->p.logN), 0, st, nall, ctx->p.logN, mods_of(ctx),
+             s, s2);
 }
 
 void encrypt_combine(const fhe_ctx* ctx, uint32_t nl, const uint64_t* a, const uint64_t* em, const uint64_t* s,
                      uint64_t* ct, hipStream_t st) {
-  hipLaunchKernelGGL(k_encrypt_combine, dim3(grid_for((uint64_t)nl << ctx->p.logN)), dim3(kThreads), 0, st, nl,
-                     ctx->p.logN, mods_of(ctx), a, em, s, ct);
-  check_launch("encrypt_combine");
+  FHE_LAUNCH("encrypt_combine", 0.0, k_encrypt_combine, grid_for((uint64_t)nl << ctx->p.logN), 0, st, nl, ctx->p.logN,
+             mods_of(ctx), a, em, s, ct);
 }
 
 void decrypt_combine(const fhe_ctx* ctx, uint32_t nl, uint32_t nlim, const uint64_t* ct, const uint64_t* s,
                      uint64_t* m, hipStream_t st) {
-  hipLaunchKernelGGL(k_decrypt_combine, dim3(grid_for((uint64_t)nlim << ctx->p.logN)), dim3(kThreads), 0, st, nl, nlim,
-                     ctx->p.logN, mods_of(ctx), ct, s, m);
-  check_launch("decrypt_combine");
+  FHE_LAUNCH("decrypt_combine", 0.0, k_decrypt_combine, grid_for((uint64_t)nlim << ctx->p.logN), 0, st, nl, nlim,
+             ctx->p.logN, mods_of(ctx), ct, s, m);
 }
 
 void add_ct(const fhe_ctx* ctx, uint32_t ncomp, uint32_t nl, const uint64_t* a, const uint64_t* b, uint64_t* out,
             hipStream_t st) {
-  hipLaunchKernelGGL(k_add, dim3(grid_for((uint64_t)ncomp * nl << ctx->p.logN)), dim3(kThreads), 0, st, ncomp, nl,
-                     ctx->p.logN, mods_of(ctx), a, b, out);
-  check_launch("add");
+  FHE_LAUNCH("add", 24.0 * ncomp * nl * ctx->p.N, k_add, grid_for((uint64_t)ncomp * nl << ctx->p.logN), 0, st, ncomp,
+             nl, ctx->p.logN, mods_of(ctx), a, b, out);
 }
 
 }  // namespace fhe

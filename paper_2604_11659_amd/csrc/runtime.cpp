@@ -1,5 +1,7 @@
 // Errors, the device allocator hook and owning device buffers.
+#include <map>
 #include <mutex>
+#include <tuple>
 
 #include "common.h"
 
@@ -64,6 +66,94 @@ void DevBuf::reset() {
   }
   ptr_ = nullptr;
   bytes_ = 0;
+}
+
+}  // namespace fhe
+
+// ------------------------------------------------------------------------------------------------
+// Per-kernel timing with HIP events (off by default). Each tracked launch is bracketed by two events
+// recorded on the launch stream, so a query reports device time per kernel, not host time.
+// ------------------------------------------------------------------------------------------------
+namespace fhe {
+
+namespace {
+struct TimerRec {
+  const char* name;
+  hipEvent_t a, b;
+  double bytes;
+};
+struct KernelTimer {
+  std::mutex mu;
+  bool on = false;
+  std::vector<TimerRec> recs;
+  std::vector<hipEvent_t> pool;
+};
+KernelTimer& timer() {
+  static KernelTimer* t = new KernelTimer();
+  return *t;
+}
+hipEvent_t take_event(KernelTimer& t) {
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHECK(hipEventCreate(&e));
+  return e;
+}
+}  // namespace
+
+int prof_begin(const char* name, hipStream_t st) {
+  KernelTimer& t = timer();
+  std::lock_guard<std::mutex> lk(t.mu);
+  if (!t.on) return -1;
+  TimerRec r{name, take_event(t), take_event(t), 0.0};
+  HIPCHECK(hipEventRecord(r.a, st));
+  t.recs.push_back(r);
+  return (int)t.recs.size() - 1;
+}
+
+void prof_end(int tok, hipStream_t st, double bytes) {
+  if (tok < 0) return;
+  KernelTimer& t = timer();
+  std::lock_guard<std::mutex> lk(t.mu);
+  if (tok >= (int)t.recs.size()) return;
+  t.recs[tok].bytes = bytes;
+  HIPCHECK(hipEventRecord(t.recs[tok].b, st));
+}
+
+void prof_enable(bool on) {
+  KernelTimer& t = timer();
+  std::lock_guard<std::mutex> lk(t.mu);
+  if (on) {  // a new measurement starts: recycle the events of the previous one
+    for (auto& r : t.recs) {
+      (void)hipEventSynchronize(r.b);
+      t.pool.push_back(r.a);
+      t.pool.push_back(r.b);
+    }
+    t.recs.clear();
+  }
+  t.on = on;
+}
+
+// Aggregates the records: name -> (launches, total ms, algorithmic bytes).
+std::vector<std::tuple<std::string, int64_t, double, double>> prof_summary() {
+  KernelTimer& t = timer();
+  std::lock_guard<std::mutex> lk(t.mu);
+  std::map<std::string, std::tuple<int64_t, double, double>> agg;
+  for (auto& r : t.recs) {
+    HIPCHECK(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, r.a, r.b));
+    auto& x = agg[r.name];
+    std::get<0>(x) += 1;
+    std::get<1>(x) += ms;
+    std::get<2>(x) += r.bytes;
+  }
+  std::vector<std::tuple<std::string, int64_t, double, double>> out;
+  for (auto& kv : agg) out.emplace_back(kv.first, std::get<0>(kv.second), std::get<1>(kv.second), std::get<2>(kv.second));
+  return out;
 }
 
 }  // namespace fhe

@@ -133,42 +133,83 @@ void enqueue_rotation(fhe_ctx* ctx, ArgPack& ap, std::vector<std::function<void(
 
 }  // namespace
 
-void execute_plan(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, const Plan& plan, hipStream_t st, fhe_mat* C) {
+void index_plan(Plan& plan) {
+  const size_t nprod = plan.prods.size();
+  plan.first.assign(nprod + 1, 0);
+  for (const auto& pa : plan.pairs) ++plan.first[pa.prod + 1];
+  for (size_t i = 0; i < nprod; ++i) plan.first[i + 1] += plan.first[i];
+  plan.by_prod.assign(plan.pairs.size(), 0);
+  std::vector<size_t> fill(plan.first.begin(), plan.first.end() - 1);
+  for (size_t k = 0; k < plan.pairs.size(); ++k) plan.by_prod[fill[plan.pairs[k].prod]++] = (uint32_t)k;
+}
+
+void prepare_result(fhe_ctx* ctx, Job& J, hipStream_t st) {
+  const Params& p = ctx->p;
+  const uint32_t N = p.N, nl2 = p.nq - 2;
+  const size_t chunk_elems = (size_t)2 * nl2 * N;
+  if (J.plan.first.size() != J.plan.prods.size() + 1) index_plan(J.plan);
+  for (const auto& pr : J.plan.prods)
+    if (pr.ca >= J.A->nchunks || pr.cb >= J.B->nchunks) fail(FHE_EINVAL, "plan references a missing operand chunk");
+  if (!J.plan.pairs.empty() && !ctx->relin) fail(FHE_EKEY, "relinearisation key not generated");
+  for (const auto& pa : J.plan.pairs)
+    for (uint32_t s : rotation_steps(p, pa.rot)) (void)rotation_key(ctx, s);
+  for (const auto& pr : J.plan.prods)
+    for (uint32_t s : rotation_steps(p, pr.d > 0 ? pr.d : -pr.d)) (void)rotation_key(ctx, s);
+  fhe_mat* C = J.C;
+  C->kind = 2;
+  C->rows = J.A->rows;
+  C->cols = J.B->cols;
+  C->nl = nl2;
+  C->nchunks = J.plan.nres;
+  C->scale = std::ldexp(1.0, p.d.log_delta + p.d.mask_bits);
+  C->data = DevBuf((size_t)J.plan.nres * chunk_elems * 8, st);
+  HIPCHECK(hipMemsetAsync(C->data.get(), 0, (size_t)J.plan.nres * chunk_elems * 8, st));
+}
+
+void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st) {
+  std::vector<Slice> slices;
+  for (auto& J : jobs) {
+    prepare_result(ctx, J, st);
+    slices.push_back(Slice{&J, 0, (int32_t)J.plan.prods.size()});
+  }
+  execute_slices(ctx, slices, st);
+}
+
+void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st) {
   const Params& p = ctx->p;
   const uint32_t N = p.N, nq = p.nq, nl1 = nq - 1, nl2 = nq - 2;
-  C->kind = 2;
-  C->rows = A->rows;
-  C->cols = B->cols;
-  C->nl = nl2;
-  C->nchunks = plan.nres;
-  C->scale = std::ldexp(1.0, p.d.log_delta + p.d.mask_bits);
-  const size_t chunk_elems = (size_t)2 * nl2 * N;
-  C->data = DevBuf((size_t)plan.nres * chunk_elems * 8, st);
-  HIPCHECK(hipMemsetAsync(C->data.get(), 0, (size_t)plan.nres * chunk_elems * 8, st));
+  std::lock_guard<std::mutex> exec_lock(ctx->exec_mu);
+  // Merge the slices: products [lo, hi) of each job and their pairs, with result-chunk pointers.
+  Plan plan;
+  std::vector<uint64_t*> result_ptr;
+  std::vector<const Job*> job_of;
+  for (auto& sl : slices) {
+    const Job& J = *sl.job;
+    const int32_t jid = (int32_t)job_of.size();
+    job_of.push_back(&J);
+    const int32_t prod0 = (int32_t)plan.prods.size(), chunk0 = (int32_t)result_ptr.size();
+    for (int c = 0; c < J.plan.nres; ++c) result_ptr.push_back(J.C->chunk(c, N));
+    for (int32_t pi = sl.lo; pi < sl.hi; ++pi) {
+      PlanProduct pr = J.plan.prods[pi];
+      pr.job = jid;
+      plan.prods.push_back(pr);
+      for (size_t k = J.plan.first[pi]; k < J.plan.first[pi + 1]; ++k) {
+        PlanPair pa = J.plan.pairs[J.plan.by_prod[k]];
+        pa.prod = prod0 + (pi - sl.lo);
+        pa.chunk += chunk0;
+        plan.pairs.push_back(pa);
+      }
+    }
+  }
   if (plan.pairs.empty()) {
     HIPCHECK(hipStreamSynchronize(st));
     return;
   }
-  for (const auto& pr : plan.prods) {
-    if (pr.ca >= A->nchunks || pr.cb >= B->nchunks) fail(FHE_EINVAL, "plan references a missing operand chunk");
-    if (pr.d != 0) (void)rotation_steps(p, pr.d > 0 ? pr.d : -pr.d);
-  }
-  if (!ctx->relin) fail(FHE_EKEY, "relinearisation key not generated");
-  for (const auto& pa : plan.pairs)
-    for (uint32_t s : rotation_steps(p, pa.rot)) (void)rotation_key(ctx, s);
-  for (const auto& pr : plan.prods)
-    for (uint32_t s : rotation_steps(p, pr.d > 0 ? pr.d : -pr.d)) (void)rotation_key(ctx, s);
-
-  // Pairs grouped by product (stable: traversal order inside a product).
+  DevBuf result_dev = upload(result_ptr, st);
+  index_plan(plan);
   const size_t nprod = plan.prods.size();
-  std::vector<size_t> first(nprod + 1, 0);
-  for (const auto& pa : plan.pairs) ++first[pa.prod + 1];
-  for (size_t i = 0; i < nprod; ++i) first[i + 1] += first[i];
-  std::vector<uint32_t> by_prod(plan.pairs.size());
-  {
-    std::vector<size_t> fill(first.begin(), first.end() - 1);
-    for (size_t k = 0; k < plan.pairs.size(); ++k) by_prod[fill[plan.pairs[k].prod]++] = (uint32_t)k;
-  }
+  const std::vector<size_t>& first = plan.first;
+  const std::vector<uint32_t>& by_prod = plan.by_prod;
 
   // Batch sizes from the workspace budget.
   const size_t e = 8ull * N;
@@ -183,7 +224,6 @@ void execute_plan(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, const Plan& 
   BB = std::min<size_t>(BB, 8192);
 
   Workspace ws;
-  DevBuf wsbuf;
   const size_t rt = std::max<size_t>(PB * 2 * nq, BB * 2 * nl2) * N;
   const size_t sz_align = PB * 2 * nq * N, sz_tens = PB * 3 * nq * N, sz_pfull = PB * 2 * nq * N,
                sz_prod = PB * 2 * nl1 * N, sz_msk = BB * 2 * nl1 * N, sz_cur = BB * 2 * nl2 * N;
@@ -191,8 +231,11 @@ void execute_plan(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, const Plan& 
   const size_t sz_rs =
       std::max(rescale_ws_elems(ctx, (uint32_t)PB, 2, nq), rescale_ws_elems(ctx, (uint32_t)BB, 2, nl1));
   const size_t total = sz_align + rt + sz_tens + sz_pfull + sz_prod + sz_msk + sz_cur + sz_ks + sz_rs;
-  wsbuf = DevBuf(total * 8, st);
-  uint64_t* w = wsbuf.u64();
+  if (ctx->ws_cache.bytes() < total * 8) {  // grow-only scratch kept by the context between calls
+    ctx->ws_cache.reset();
+    ctx->ws_cache = DevBuf(total * 8, st);
+  }
+  uint64_t* w = ctx->ws_cache.u64();
   ws.align = w; w += sz_align;
   ws.rtmp = w; w += rt;
   ws.tens = w; w += sz_tens;
@@ -215,8 +258,8 @@ void execute_plan(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, const Plan& 
     std::vector<std::vector<uint32_t>> steps(npb);
     for (size_t k = 0; k < npb; ++k) {
       const PlanProduct& pr = plan.prods[p0 + k];
-      opa[k] = A->chunk(pr.ca, N);
-      opb[k] = B->chunk(pr.cb, N);
+      opa[k] = job_of[pr.job]->A->chunk(pr.ca, N);
+      opb[k] = job_of[pr.job]->B->chunk(pr.cb, N);
       cur_src[k] = pr.d > 0 ? opb[k] : opa[k];
       steps[k] = rotation_steps(p, pr.d > 0 ? pr.d : -pr.d);
       uint64_t* al = ws.align + k * 2 * nq * N;
@@ -317,8 +360,9 @@ void execute_plan(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, const Plan& 
       }
       const size_t o_sg = ap.push(seg);
       const uint32_t nseg = (uint32_t)(seg.size() / 3);
-      uint64_t* res = C->data.u64();
-      ops.push_back([=, &ap] { accumulate(ctx, nseg, nl2, ap.at<uint32_t>(o_sg), ws.cur, res, st); });
+      uint64_t* const* res = (uint64_t* const*)result_dev.get();
+      const uint32_t ncontrib = (uint32_t)nb;
+      ops.push_back([=, &ap] { accumulate(ctx, nseg, ncontrib, nl2, ap.at<uint32_t>(o_sg), ws.cur, res, st); });
     }
     ap.upload(st);
     for (auto& op : ops) op();

@@ -8,6 +8,7 @@ namespace fhe {
 // when d > 0, A by -d when d < 0). Every matched pair with the same triple shares the product.
 struct PlanProduct {
   int32_t ca, cb, d;
+  int32_t job = 0;  // which matmul of a batch the operands belong to
 };
 
 // One matched pair after alignment: its product, the slot min_pos isolated by the mask, the result
@@ -15,7 +16,7 @@ struct PlanProduct {
 struct PlanPair {
   int32_t prod;
   int32_t min_pos;
-  int32_t chunk;
+  int32_t chunk;  // result chunk (for a merged batch plan: index into all jobs' result chunks)
   uint32_t rot;
 };
 
@@ -24,7 +25,12 @@ struct Plan {
   std::vector<PlanPair> pairs;
   int nres = 1;           // result chunks
   int64_t matched = 0;    // matched pairs of the full traversal
+  // pairs grouped by product: pairs[by_prod[first[i] .. first[i+1])] belong to product i
+  std::vector<size_t> first;
+  std::vector<uint32_t> by_prod;
 };
+
+void index_plan(Plan& plan);
 
 // Validates a CSR/CSC pattern (indptr non-decreasing from 0 to nnz, indices in range and strictly
 // ascending per row/column).
@@ -33,8 +39,28 @@ void check_pattern(int32_t outer, int32_t inner, const int32_t* indptr, const in
 // Algorithm 1 over A (CSR) and B (CSC), keeping the pairs with traversal index in [begin, end).
 Plan build_plan(const Params& p, const fhe_mat* A, const fhe_mat* B, int64_t begin, int64_t end);
 
-// Executes the plan; C receives the dense result chunks (two levels below the top).
-void execute_plan(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, const Plan& plan, hipStream_t st, fhe_mat* C);
+// One matmul of a batch: operands, its plan, its result handle.
+struct Job {
+  const fhe_mat* A;
+  const fhe_mat* B;
+  Plan plan;
+  fhe_mat* C;
+};
+
+// Executes one or many matmuls as a single stream of batched launches: the products and pairs of all
+// jobs are merged, so small matmuls share launches and pairs with equal rotation keys sit together.
+// Each job's C receives its dense result chunks (two levels below the top).
+void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st);
+
+// Resumable execution: prepare_result validates keys/operands and zeroes C; execute_slices runs the
+// products [lo, hi) of several prepared jobs (and all their pairs) as one merged launch stream,
+// accumulating into each job's C. Synchronises `st` before returning. Serialised per context.
+struct Slice {
+  Job* job;
+  int32_t lo, hi;
+};
+void prepare_result(fhe_ctx* ctx, Job& J, hipStream_t st);
+void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st);
 
 // Counts of key-switch work in the plan: [F, products, align KS, relin KS, target KS, result chunks].
 void plan_counts(const Params& p, const Plan& plan, int64_t out[6]);

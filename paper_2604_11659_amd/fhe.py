@@ -41,6 +41,10 @@ class fhe_params_desc(ctypes.Structure):
                 ("device", c_i32)]
 
 
+class fhe_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", c_i64), ("total_ms", c_dbl), ("bytes", c_dbl)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(c_vp, c_sz, c_vp, c_vp)
 FREE_FN = ctypes.CFUNCTYPE(None, c_vp, c_vp, c_vp)
 
@@ -56,7 +60,9 @@ _SIGS = {
     "fhe_encrypt_csc": ([c_vp, c_vp, c_i32, c_i32, P_i32, P_i32, P_dbl, c_u64, c_vp, PP], c_i32),
     "fhe_spmspm": ([c_vp, c_vp, c_vp, c_vp, PP], c_i32),
     "fhe_spmspm_pairs": ([c_vp, c_vp, c_vp, c_i64, c_i64, c_vp, PP], c_i32),
+    "fhe_spmspm_batch": ([c_vp, c_sz, PP, PP, c_vp, PP], c_i32),
     "fhe_plan_stats": ([c_vp, c_vp, c_vp, P_i64], c_i32),
+    "fhe_plan_pattern": ([c_i32, c_i32, c_i32, c_i32, c_i32, P_i32, P_i32, P_i32, P_i32, P_i64], c_i32),
     "fhe_plan_rotations": ([c_vp, c_vp, c_vp, P_i32, c_sz, ctypes.POINTER(c_sz)], c_i32),
     "fhe_decrypt_decode": ([c_vp, c_vp, c_vp, c_vp, P_dbl, c_sz], c_i32),
     "fhe_mat_info": ([c_vp, P_i32, P_i32, P_i32, P_i32, P_i32, P_dbl], c_i32),
@@ -71,6 +77,13 @@ _SIGS = {
     "fhe_ct_mask": ([c_vp, c_vp, c_i32, c_vp, PP], c_i32),
     "fhe_ct_add": ([c_vp, c_vp, c_vp, c_vp, PP], c_i32),
     "fhe_ct_free": ([c_vp], None),
+    "fhe_server_create": ([c_vp, c_sz, c_i32, c_i32, c_i32, PP], c_i32),
+    "fhe_server_submit": ([c_vp, c_vp, c_vp, ctypes.POINTER(c_u64)], c_i32),
+    "fhe_server_poll": ([c_vp, c_u64, c_i32, PP, P_dbl], c_i32),
+    "fhe_server_stats": ([c_vp, P_dbl, P_dbl, P_i64, P_i64, P_i64], c_i32),
+    "fhe_server_free": ([c_vp], None),
+    "fhe_profile_enable": ([ctypes.c_int], c_i32),
+    "fhe_profile_read": ([ctypes.POINTER(fhe_kernel_stat), c_sz], c_i32),
     "fhe_last_error": ([], ctypes.c_char_p),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -115,6 +128,20 @@ def _arr(a, dtype):
 
 def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def profile_enable(on: bool = True):
+    """Start (clearing earlier records) or stop per-kernel HIP-event timing."""
+    _check(_lib.fhe_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{kernel: dict(launches, total_ms, bytes)} for the records since the last profile_enable(True)."""
+    n = _check(_lib.fhe_profile_read(None, 0))
+    arr = (fhe_kernel_stat * max(1, n))()
+    _check(_lib.fhe_profile_read(arr, n))
+    return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms, bytes=arr[i].bytes)
+            for i in range(n)}
 
 
 _TORCH_HOOKS = None
@@ -201,6 +228,16 @@ class PlanStats:
         return self.align_keyswitches + self.relin_keyswitches + self.target_keyswitches
 
 
+def plan_pattern(log_n: int, rot_digits: int, m: int, k: int, n: int, csr_a, csc_b) -> "PlanStats":
+    """Host-only plan statistics from the public patterns (csr_a = (indptr, indices) of A, csc_b of B)."""
+    ipa, ixa = _arr(csr_a[0], np.int32), _arr(csr_a[1], np.int32)
+    ipb, ixb = _arr(csc_b[0], np.int32), _arr(csc_b[1], np.int32)
+    c = np.zeros(6, np.int64)
+    _check(_lib.fhe_plan_pattern(log_n, rot_digits, m, k, n, _ptr(ipa, c_i32), _ptr(ixa, c_i32), _ptr(ipb, c_i32),
+                                 _ptr(ixb, c_i32), _ptr(c, c_i64)))
+    return PlanStats(*[int(x) for x in c])
+
+
 class Context(_Handle):
     """Parameter set, device tables and evaluation keys on one GPU."""
     _free_fn = staticmethod(_lib.fhe_ctx_free)
@@ -251,6 +288,17 @@ class Context(_Handle):
         out = c_vp()
         _check(_lib.fhe_spmspm(self._ptr, A._ptr, B._ptr, _stream(stream), ctypes.byref(out)))
         return Matrix(out.value, self)
+
+    def spmspm_batch(self, As, Bs, stream=None) -> list:
+        """[A_i B_i] in one merged launch stream (bit-identical to one-at-a-time spmspm)."""
+        n = len(As)
+        assert len(Bs) == n
+        pa = (c_vp * max(1, n))(*[a._ptr for a in As])
+        pb = (c_vp * max(1, n))(*[b._ptr for b in Bs])
+        out = (c_vp * max(1, n))()
+        _check(_lib.fhe_spmspm_batch(self._ptr, n, ctypes.cast(pa, PP), ctypes.cast(pb, PP), _stream(stream),
+                                     ctypes.cast(out, PP)))
+        return [Matrix(out[i], self) for i in range(n)]
 
     def spmspm_pairs(self, A: Matrix, B: Matrix, begin: int, end: int, stream=None) -> Matrix:
         out = c_vp()
@@ -322,3 +370,41 @@ class Context(_Handle):
 
     def ct_add(self, a: Ciphertext, b: Ciphertext, stream=None) -> Ciphertext:
         return self._ct1(_lib.fhe_ct_add, a._ptr, b._ptr, stream=stream)
+
+
+class Server(_Handle):
+    """Continuous-batching request loop on a Context (worker thread + own HIP stream)."""
+    _free_fn = staticmethod(_lib.fhe_server_free)
+
+    def __init__(self, ctx: Context, hbm_budget: int, max_inflight: int = 8, slice_products: int = 64,
+                 max_queue: int = 1024):
+        out = c_vp()
+        _check(_lib.fhe_server_create(ctx._ptr, hbm_budget, max_inflight, slice_products, max_queue,
+                                      ctypes.byref(out)))
+        super().__init__(out.value, ctx)
+        self._keep = {}
+
+    def submit(self, A: Matrix, B: Matrix) -> int:
+        t = c_u64()
+        _check(_lib.fhe_server_submit(self._ptr, A._ptr, B._ptr, ctypes.byref(t)))
+        self._keep[t.value] = (A, B)  # operands must outlive the request
+        return t.value
+
+    def poll(self, ticket: int, wait_ms: int = 0):
+        """(Matrix, latency_s) when done, None while running; raises FheError if the request failed."""
+        out = c_vp()
+        lat = c_dbl()
+        rc = _lib.fhe_server_poll(self._ptr, ticket, wait_ms, ctypes.byref(out), ctypes.byref(lat))
+        if rc == -6:
+            return None
+        self._keep.pop(ticket, None)
+        if rc < 0:
+            raise FheError(rc, "request failed")
+        return Matrix(out.value, self._owner), lat.value
+
+    def stats(self) -> dict:
+        p50, p99 = c_dbl(), c_dbl()
+        done, infl, qd = c_i64(), c_i64(), c_i64()
+        _check(_lib.fhe_server_stats(self._ptr, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(done),
+                                     ctypes.byref(infl), ctypes.byref(qd)))
+        return dict(p50_s=p50.value, p99_s=p99.value, completed=done.value, inflight=infl.value, queued=qd.value)

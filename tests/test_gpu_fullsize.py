@@ -1,0 +1,80 @@
+"""GPU parity at the benchmark workloads' full sizes.
+
+* 16x16 x 16x16 (75% zeros each), N = 2^13: every result limb bit-exact against the oracle.
+* DNN layer 128x128 (90% zeros) x 128x64 (50% zeros), N = 2^15: the full product decrypts to the FP64
+  matmul within 1e-5 (max-abs); sampled pair ranges (start, middle, end of Algorithm 1's traversal)
+  run through the same executor and are bit-exact against the oracle on the same pairs.
+The oracle runs in 8 forked CPU workers (they never touch the GPU).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ckks, spmspm
+from paper_2604_11659_amd import synth
+
+pytestmark = pytest.mark.gpu
+WORKERS = 8
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _prepare(w):
+    from paper_2604_11659_amd import fhe
+    a, b = w.operands()
+    ipa, ixa, va = synth.to_csr(a)
+    ipb, ixb, vb = synth.to_csc(b)
+    ctx = fhe.Context(w.log_n, w.n_q, w.n_p, w.alpha, w.rot_digits)
+    sk = ctx.keygen(42)
+    A = ctx.encrypt_csr(sk, w.m, w.k, ipa, ixa, va, seed=43)
+    B = ctx.encrypt_csc(sk, w.k, w.n, ipb, ixb, vb, seed=44)
+    if w.rot_digits == 1:
+        ctx.keygen_rotations(sk, ctx.plan_rotations(A, B))
+    op = ckks.Params(log_n=w.log_n, n_q=w.n_q, n_p=w.n_p, alpha=w.alpha, rot_digits=w.rot_digits)
+    keys = ckks.Keys(op, 42)
+    OA = spmspm.encrypt_csr(op, keys, w.m, w.k, ipa, ixa, va, seed=43)
+    OB = spmspm.encrypt_csc(op, keys, w.k, w.n, ipb, ixb, vb, seed=44)
+    return a, b, ctx, sk, A, B, op, keys, OA, OB
+
+
+@pytest.mark.timeout(900)
+def test_plain_16x16_full_bit_exact():
+    w = synth.WORKLOADS["plain"]
+    _say("[full] plain 16x16 N=2^13 setup")
+    a, b, ctx, sk, A, B, op, keys, OA, OB = _prepare(w)
+    st = ctx.plan_stats(A, B)
+    _say(f"[full] plain gpu spmspm, {st}")
+    C = ctx.spmspm(A, B)
+    _say("[full] plain oracle")
+    ref = spmspm.spmspm(op, keys, OA, OB, workers=WORKERS)
+    assert len(ref) == st.result_chunks == 1
+    assert (ctx.export(C, 0) == ref[0].data).all()
+    err = np.abs(ctx.decrypt_decode(sk, C) - a @ b).max()
+    assert err < 1e-5
+    _say(f"[full] plain ok, max-abs error {err:.3e}")
+
+
+@pytest.mark.timeout(1200)
+def test_dnn_layer_full_fp64_and_sampled_bit_exact():
+    w = synth.WORKLOADS["dnn"]
+    _say("[full] dnn setup")
+    a, b, ctx, sk, A, B, op, keys, OA, OB = _prepare(w)
+    st = ctx.plan_stats(A, B)
+    _say(f"[full] dnn gpu spmspm, {st}")
+    C = ctx.spmspm(A, B)
+    err = np.abs(ctx.decrypt_decode(sk, C) - a @ b).max()
+    _say(f"[full] dnn max-abs error {err:.3e}")
+    assert err < 1e-5
+    F = st.matched_pairs
+    pairs = spmspm.matched_pairs(w.m, w.n, OA.indptr, OA.indices, OB.indptr, OB.indices)
+    assert len(pairs) == F
+    for lo, hi in [(0, 3), (F // 2, F // 2 + 3), (F - 3, F)]:
+        _say(f"[full] dnn pairs [{lo}, {hi}) gpu")
+        Cs = ctx.spmspm_pairs(A, B, lo, hi)
+        _say(f"[full] dnn pairs [{lo}, {hi}) oracle")
+        ref = spmspm.spmspm(op, keys, OA, OB, workers=WORKERS, pairs=pairs[lo:hi])
+        assert (ctx.export(Cs, 0) == ref[0].data).all(), (lo, hi)

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 # (log_n, n_q, n_p, alpha, rot_digits): a small set with two-prime digits, two special primes and
 # two-step rotations, and the single-prime-digit set of the 16x16 workload at a smaller ring.
-OP_PARAMS = [(12, 5, 2, 2, 2), (11, 4, 1, 1, 1)]
+OP_PARAMS = [(12, 5, 2, 2, 2), (13, 4, 1, 1, 1)]
 
 
 def _say(msg):
@@ -167,6 +167,54 @@ def test_spmspm_parity_small(fhe):
 
 def test_spmspm_parity_single_digit(fhe):
     _matmul_case(fhe, OP_PARAMS[1], 6, 5, 4, 0.4, 0.6, (4, 5, 6, 7))
+
+
+@pytest.mark.parametrize("log_n", [14, 15, 16, 17])
+def test_ring_size_sweep(fhe, log_n):
+    """Every supported ring size (two-phase NTT with 2-3 register rounds per phase, FP64 and integer
+    arithmetic): mult + relinearise and one rotation bit-exact against the oracle."""
+    prm = (log_n, 3, 1, 1, 1)
+    op, okeys, ctx, sk = _setup(fhe, prm)
+    _say(f"[sweep] {prm}")
+    a, b = _rand_ct(op, 3, 60 + log_n), _rand_ct(op, 3, 70 + log_n)
+    ca, cb = ctx.ct_import(a, 1.0), ctx.ct_import(b, 1.0)
+    assert (ctx.ct_export(ca) == a).all()
+    got = ctx.ct_export(ctx.ct_mult_relin(ca, cb))
+    assert (got == ckks.mult_relin(op, okeys, ckks.Ct(a, 1.0), ckks.Ct(b, 1.0)).data).all()
+    r = op.S // 3 + 1
+    ctx.keygen_rotations(sk, [r])
+    got = ctx.ct_export(ctx.ct_rotate(ca, r))
+    assert (got == ckks.rotate(op, okeys, ckks.Ct(a, 1.0), r).data).all()
+
+
+def test_spmspm_batch_matches_individual_and_oracle(fhe):
+    """Uneven matmuls merged into one launch stream give bit-identical results to one-at-a-time runs."""
+    op, okeys, ctx, sk = _setup(fhe, OP_PARAMS[0])
+    shapes = [(3, 4, 5, 0.5, 0.5), (6, 6, 2, 0.3, 0.7), (1, 5, 1, 0.0, 0.0), (4, 4, 4, 1.0, 0.2), (5, 3, 6, 0.6, 0.4)]
+    As, Bs, dense = [], [], []
+    for t, (m, k, n, sa, sb) in enumerate(shapes):
+        a = synth.sparse_dense(m, k, sa, "uniform", 100 + t, 200 + t)
+        b = synth.sparse_dense(k, n, sb, "uniform", 300 + t, 400 + t)
+        As.append(ctx.encrypt_csr(sk, m, k, *synth.to_csr(a), seed=43 + 10 * t))
+        Bs.append(ctx.encrypt_csc(sk, k, n, *synth.to_csc(b), seed=44 + 10 * t))
+        dense.append((a, b))
+    _say("[batch] merged")
+    Cb = ctx.spmspm_batch(As, Bs)
+    for t in range(len(shapes)):
+        _say(f"[batch] single {t}")
+        Ci = ctx.spmspm(As[t], Bs[t])
+        info = Ci.info()
+        for c in range(info["chunks"]):
+            assert (ctx.export(Cb[t], c) == ctx.export(Ci, c)).all(), (t, c)
+        a, b = dense[t]
+        assert np.abs(ctx.decrypt_decode(sk, Cb[t]) - a @ b).max() < 1e-5
+    # one of them against the oracle as well
+    a, b = dense[0]
+    m, k, n = shapes[0][:3]
+    OA = spmspm.encrypt_csr(op, okeys, m, k, *synth.to_csr(a), seed=43)
+    OB = spmspm.encrypt_csc(op, okeys, k, n, *synth.to_csc(b), seed=44)
+    ref = spmspm.spmspm(op, okeys, OA, OB)
+    assert (ctx.export(Cb[0], 0) == ref[0].data).all()
 
 
 def test_spmspm_full_sparsity_is_zero(fhe):
