@@ -79,11 +79,177 @@ def roofline(prof: dict) -> tuple[dict, dict]:
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     r = prof[dom]
     achieved = r["bytes"] / (r["total_ms"] * 1e6)
+    # HBM bytes per launch from the committed counter runs, only if taken on the current kernel source
+    from paper_2604_11659_amd import profiling
+    t = profiling.load_traffic(os.path.join(ROOT, "profiles"), dom)
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": round(t["bytes_per_launch"]) if t else None,
+            "traffic_source": t["file"] if t else None,
             "avg_launch_us": kernels[dom]["avg_us"],
             "algo_bytes_per_launch": r["bytes"] / r["launches"]}
     return roof, kernels
+
+
+def run_batch(args) -> dict:
+    """Batched vs plain form of the batching workload on a bounded prefix of every matmul's plan.
+
+    The full workload (64 matmuls, about 2e7 matched pairs at N = 2^16) takes hours; here every matmul
+    runs its first `--batch-cap` matched pairs (all of them when it has fewer), once as one
+    fhe_spmspm_batch_pairs call and once as one fhe_spmspm_pairs call per matmul, on the same
+    ciphertexts and keys. SpMSpM/s is projected as measured pairs/s divided by the mean F of the full
+    matmuls."""
+    import torch
+    from paper_2604_11659_amd import fhe
+    w = synth.BATCH_WORKLOADS[args.workload]
+    specs = w.specs()
+    t0 = time.perf_counter()
+    ctx = fhe.Context(w.log_n, w.n_q, w.n_p, w.alpha, w.rot_digits)
+    sk = ctx.keygen(42)
+    As, Bs, F = [], [], []
+    for i, sp in enumerate(specs):
+        a, b = w.operands(i, sp)
+        n = sp[0]
+        As.append(ctx.encrypt_csr(sk, n, n, *synth.to_csr(a), seed=10_000 + i))
+        Bs.append(ctx.encrypt_csc(sk, n, n, *synth.to_csc(b), seed=20_000 + i))
+        F.append(ctx.plan_stats(As[-1], Bs[-1]).matched_pairs)
+    setup_s = time.perf_counter() - t0
+    ranges = [(0, min(f, args.batch_cap)) for f in F]
+    pairs = sum(hi for _, hi in ranges)
+    log(f"setup {setup_s:.1f} s; {len(specs)} matmuls, F total {sum(F)}, prefix pairs {pairs}")
+    # warm-up on a small prefix (workspace allocation, code objects)
+    for C in ctx.spmspm_batch(As[:2], Bs[:2], pair_ranges=[(0, min(8, f)) for f in F[:2]]):
+        C.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Cb = ctx.spmspm_batch(As, Bs, pair_ranges=ranges)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"batched: {t_batch:.2f} s")
+    t0 = time.perf_counter()
+    Cp = [ctx.spmspm_pairs(A, B, lo, hi) for A, B, (lo, hi) in zip(As, Bs, ranges)]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    log(f"plain: {t_plain:.2f} s")
+    same = all((ctx.export(x, c) == ctx.export(y, c)).all()
+               for x, y in list(zip(Cb, Cp))[:: max(1, len(Cb) // 8)] for c in range(x.info()["chunks"]))
+    mean_f = sum(F) / len(F)
+    pb, pp = pairs / t_batch, pairs / t_plain
+    return {
+        "metric": METRIC, "value": round(pb / mean_f, 8), "unit": "SpMSpM/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(1000 * t_batch, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": (f"{w.name}: {w.count} square matmuls, n from {list(w.sizes)}, per-operand sparsity "
+                                f"U[{w.sparsity[0]}, {w.sparsity[1]}], values U[-1,1]; CKKS N=2^{w.log_n}, "
+                                f"{w.n_q} x 50-bit Q + {w.n_p} x 60-bit P primes, alpha={w.alpha}, rotation "
+                                f"digits={w.rot_digits}"),
+                   "prefix_pairs_per_matmul": args.batch_cap, "pairs_run": pairs, "full_pairs": sum(F),
+                   "parallelism": "single GPU"},
+        "projected": True,
+        "batched": {"pairs_per_s": round(pb, 1), "spmspm_per_s_projected": pb / mean_f, "s": round(t_batch, 3)},
+        "plain": {"pairs_per_s": round(pp, 1), "spmspm_per_s_projected": pp / mean_f, "s": round(t_plain, 3)},
+        "batched_over_plain": round(t_plain / t_batch, 3),
+        "results_bit_identical": bool(same), "setup_s": round(setup_s, 1),
+    }
+
+
+SERVE_PARAMS = [(16, 24, 3, 3, 3), (17, 35, 3, 3, 4)]  # (log_n, n_q, n_p, alpha, rotation digits)
+
+
+def run_serve(args) -> dict:
+    """Request loop under Poisson arrivals: one server (worker thread + stream) per parameter set.
+
+    Requests alternate between the parameter sets (a 50/50 mix), have square sizes from
+    `--serve-sizes` and per-operand sparsity U[0.70, 0.95], values U[-1, 1]; operands are encrypted
+    and keys generated before the clock starts (resident). Phase 1 offers load at `--serve-load` of the
+    capacity measured from requests run alone and reports p50/p99 latency and throughput; phase 2
+    offers `--serve-rate` requests/s for `--serve-overload-s` seconds and reports how many were
+    admitted, completed and left queued when the window closed."""
+    import torch
+    from paper_2604_11659_amd import fhe
+    sizes = [int(x) for x in args.serve_sizes.split(",")]
+    params = SERVE_PARAMS[: 2 if args.serve_mix else 1]
+    t0 = time.perf_counter()
+    ctxs = [fhe.Context(*p) for p in params]
+    sks = [c.keygen(42) for c in ctxs]
+    log(f"keys for {len(ctxs)} parameter sets in {time.perf_counter() - t0:.1f} s")
+    rng = np.random.Generator(np.random.PCG64(5))
+
+    def make(i):
+        ci = i % len(ctxs)
+        n = int(rng.choice(sizes))
+        sa, sb = (float(x) for x in rng.uniform(0.70, 0.95, size=2))
+        a = synth.sparse_dense(n, n, sa, "uniform", 7000 + 4 * i, 7002 + 4 * i)
+        b = synth.sparse_dense(n, n, sb, "uniform", 7001 + 4 * i, 7003 + 4 * i)
+        A = ctxs[ci].encrypt_csr(sks[ci], n, n, *synth.to_csr(a), seed=30_000 + i)
+        B = ctxs[ci].encrypt_csc(sks[ci], n, n, *synth.to_csc(b), seed=40_000 + i)
+        return ci, A, B, a @ b
+
+    # capacity: a few requests of each parameter set alone
+    svc = []
+    for i in range(2 * len(ctxs)):
+        ci, A, B, _ = make(i)
+        ctxs[ci].spmspm(A, B).close()  # first call per context allocates its workspace
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctxs[ci].spmspm(A, B).close()
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t)
+    t_req = float(np.mean(svc))
+    lam = args.serve_load / t_req
+    log(f"mean service time alone {t_req:.3f} s -> offered rate {lam:.3f} req/s")
+
+    def run_window(rate, window_s, seed, drain):
+        arrivals = synth.poisson_arrivals(rate, window_s, seed)
+        reqs = [make(1000 * seed + i) for i in range(len(arrivals))]
+        srvs = [fhe.Server(c, hbm_budget=args.serve_budget_gb << 30, max_inflight=8, slice_products=32,
+                           max_queue=4096) for c in ctxs]
+        tickets = []
+        torch.cuda.synchronize()
+        start = time.perf_counter()
+        for t_arr, (ci, A, B, ref) in zip(arrivals, reqs):
+            dt = start + t_arr - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append((ci, srvs[ci].submit(A, B), ref))
+        at_close = [s.stats() for s in srvs]
+        lat, errs = [], []
+        if drain:
+            for ci, tk, ref in tickets:
+                C, l = srvs[ci].poll(tk, wait_ms=600_000)
+                lat.append(l)
+                if len(errs) < 4:
+                    errs.append(float(np.abs(ctxs[ci].decrypt_decode(sks[ci], C) - ref).max()))
+                C.close()
+        elapsed = time.perf_counter() - start
+        st = [s.stats() for s in srvs]
+        for s in srvs:
+            s.close()
+        return arrivals, lat, errs, elapsed, at_close, st
+
+    arr, lat, errs, el, _, st = run_window(lam, args.serve_window_s, 6, True)
+    steady = {"offered_req_per_s": round(lam, 4), "requests": len(arr), "completed": len(lat),
+              "throughput_req_per_s": round(len(lat) / el, 4),
+              "p50_s": round(float(np.percentile(lat, 50)), 4) if lat else None,
+              "p99_s": round(float(np.percentile(lat, 99)), 4) if lat else None,
+              "server_p50_p99_s": [(round(x["p50_s"], 4), round(x["p99_s"], 4)) for x in st],
+              "max_abs_err_sampled": max(errs) if errs else None}
+    log(f"steady: {steady}")
+    arr2, _, _, el2, at_close, _ = run_window(args.serve_rate, args.serve_overload_s, 7, False)
+    over = {"offered_req_per_s": args.serve_rate, "window_s": args.serve_overload_s, "arrived": len(arr2),
+            "completed_in_window": sum(x["completed"] for x in at_close),
+            "in_flight_at_close": sum(x["inflight"] for x in at_close),
+            "queued_at_close": sum(x["queued"] for x in at_close), "wall_incl_inflight_drain_s": round(el2, 2)}
+    log(f"overload: {over}")
+    return {
+        "metric": "encrypted SpMSpM serving latency p50/p99 (s) under Poisson arrivals", "value": steady["p99_s"],
+        "unit": "s (p99)", "n_gpus": 1, "higher_is_better": False, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": (f"serve: Poisson arrivals, square sizes {sizes}, per-operand sparsity U[0.70, 0.95], "
+                                f"values U[-1,1], parameter sets (log_n, n_q, n_p, alpha, digits) {params} "
+                                f"alternating; keys and operands resident"),
+                   "capacity_req_per_s_alone": round(1.0 / t_req, 4)},
+        "steady": steady, "overload": over,
+    }
 
 
 def main():
@@ -91,7 +257,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dnn", choices=sorted(synth.WORKLOADS))
+    ap.add_argument("--workload", default="dnn", choices=sorted(synth.WORKLOADS) + sorted(synth.BATCH_WORKLOADS))
+    ap.add_argument("--batch-cap", type=int, default=256, help="batching workload: matched pairs run per matmul")
+    ap.add_argument("--serve", action="store_true", help="run the request-loop benchmark instead")
+    ap.add_argument("--serve-mix", type=int, default=1, help="1: N=2^16 and N=2^17 parameter sets, 0: N=2^16 only")
+    ap.add_argument("--serve-sizes", default="16,32")
+    ap.add_argument("--serve-load", type=float, default=0.7, help="offered load as a fraction of capacity")
+    ap.add_argument("--serve-window-s", type=float, default=40.0)
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="overload phase arrival rate (req/s)")
+    ap.add_argument("--serve-overload-s", type=float, default=3.0)
+    ap.add_argument("--serve-budget-gb", type=int, default=16)
     ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle pairs to time (0 = skip, -1 = one per core)")
     ap.add_argument("--kernels-out", default=None, help="write per-kernel timings (JSON) here")
     ap.add_argument("--copy-calibrate", action="store_true",
@@ -102,6 +277,12 @@ def main():
               "matched pairs is a design note, not built.", file=sys.stderr)
         sys.exit(2)
 
+    if args.serve:
+        print(json.dumps(run_serve(args)), flush=True)
+        return
+    if args.workload in synth.BATCH_WORKLOADS:
+        print(json.dumps(run_batch(args)), flush=True)
+        return
     w = synth.WORKLOADS[args.workload]
     a, b = w.operands()
     ref = a @ b
@@ -113,13 +294,15 @@ def main():
     import torch
     from paper_2604_11659_amd import fhe
     if args.copy_calibrate:
-        # A plain copy kernel of known size: 2^27 uint64 words (1 GiB) read and 1 GiB written.
+        # Plain copy-like kernels of known size: 2^27 int64 words (1 GiB) read and 1 GiB written, once
+        # as a device-to-device copy and once as an elementwise kernel (bitwise not).
         src = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
+        torch.bitwise_not(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-        log("copy calibration done (1 GiB read + 1 GiB written)")
+        log("copy calibration done (1 GiB read + 1 GiB written, twice)")
     ipa, ixa, va = synth.to_csr(a)
     ipb, ixb, vb = synth.to_csc(b)
     t0 = time.perf_counter()

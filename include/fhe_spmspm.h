@@ -137,6 +137,12 @@ int fhe_spmspm_pairs(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t p
 int fhe_spmspm_batch(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B, void* stream,
                      fhe_mat** C_out);
 
+/* Batched form restricted per matmul to the matched pairs with traversal index in
+ * [pair_begin[i], pair_end[i]) (as fhe_spmspm_pairs); both arrays are host arrays of cnt entries,
+ * or both NULL for the full matmuls. Used to measure a bounded prefix of very large batches. */
+int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B,
+                           const int64_t* pair_begin, const int64_t* pair_end, void* stream, fhe_mat** C_out);
+
 /* Plan statistics of A B without running it: counts[0] = matched pairs F, [1] = distinct products,
  * [2] = alignment key switches, [3] = product relinearisations, [4] = target-rotation key switches,
  * [5] = result chunks. Errors as fhe_spmspm. */
@@ -215,7 +221,8 @@ int fhe_server_poll(fhe_server* s, uint64_t ticket, int32_t wait_ms, fhe_mat** C
 int fhe_server_stats(fhe_server* s, double* p50_s, double* p99_s, int64_t* completed, int64_t* inflight,
                      int64_t* queued);
 
-/* Drains queued and running requests, stops the worker and frees the server. */
+/* Cancels the requests still waiting for admission, lets the admitted ones run to the end, stops the
+ * worker and frees the server (result handles not yet polled are released with it). */
 void fhe_server_free(fhe_server* s);
 
 /* ---- Measurement hooks (not part of the method). ---- */

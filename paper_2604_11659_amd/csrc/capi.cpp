@@ -172,8 +172,8 @@ int fhe_spmspm_pairs(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t p
   });
 }
 
-int fhe_spmspm_batch(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B, void* stream,
-                     fhe_mat** C_out) {
+int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B,
+                           const int64_t* pair_begin, const int64_t* pair_end, void* stream, fhe_mat** C_out) {
   return guarded([&] {
     need(ctx, "ctx");
     need(C_out, "C_out");
@@ -182,17 +182,27 @@ int fhe_spmspm_batch(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fh
       need(B, "B");
     }
     for (size_t i = 0; i < cnt; ++i) C_out[i] = nullptr;
-    for (size_t i = 0; i < cnt; ++i) check_operands(A[i], B[i]);
+    if ((pair_begin == nullptr) != (pair_end == nullptr)) fail(FHE_EINVAL, "pair_begin and pair_end go together");
+    for (size_t i = 0; i < cnt; ++i) {
+      check_operands(A[i], B[i]);
+      if (pair_begin && (pair_begin[i] < 0 || pair_end[i] < pair_begin[i])) fail(FHE_EINVAL, "bad pair range");
+    }
     set_dev(ctx);
     std::vector<std::unique_ptr<fhe_mat>> Cs(cnt);
     std::vector<Job> jobs(cnt);
     for (size_t i = 0; i < cnt; ++i) {
       Cs[i].reset(new fhe_mat());
-      jobs[i] = Job{A[i], B[i], build_plan(ctx->p, A[i], B[i], 0, INT64_MAX), Cs[i].get()};
+      const int64_t lo = pair_begin ? pair_begin[i] : 0, hi = pair_end ? pair_end[i] : INT64_MAX;
+      jobs[i] = Job{A[i], B[i], build_plan(ctx->p, A[i], B[i], lo, hi), Cs[i].get()};
     }
     execute_jobs(ctx, jobs, as_stream(stream));
     for (size_t i = 0; i < cnt; ++i) C_out[i] = Cs[i].release();
   });
+}
+
+int fhe_spmspm_batch(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B, void* stream,
+                     fhe_mat** C_out) {
+  return fhe_spmspm_batch_pairs(ctx, cnt, A, B, nullptr, nullptr, stream, C_out);
 }
 
 int fhe_spmspm(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, void* stream, fhe_mat** C_out) {

@@ -104,16 +104,17 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
     }
     for (uint32_t k = 0; k < N; ++k) {
       const uint32_t rk = bitrev(k, p.logN);
-      f[k] = pp[rk];
-      f[N + k] = shoup_prep(pp[rk], q);
-      f[2 * N + k] = pi[rk];
-      f[3 * N + k] = shoup_prep(pi[rk], q);
+      // (twiddle, companion) pairs interleaved so one 16-byte load fetches both
+      f[2 * k] = pp[rk];
+      f[2 * k + 1] = shoup_prep(pp[rk], q);
+      f[2 * N + 2 * k] = pi[rk];
+      f[2 * N + 2 * k + 1] = shoup_prep(pi[rk], q);
       // FP64 twiddles (used for q < 2^50): w and fl(w / q).
       double* ff = twf.data() + (size_t)i * 4 * N;
-      ff[k] = (double)pp[rk];
-      ff[N + k] = (double)pp[rk] / (double)q;
-      ff[2 * N + k] = (double)pi[rk];
-      ff[3 * N + k] = (double)pi[rk] / (double)q;
+      ff[2 * k] = (double)pp[rk];
+      ff[2 * k + 1] = (double)pp[rk] / (double)q;
+      ff[2 * N + 2 * k] = (double)pi[rk];
+      ff[2 * N + 2 * k + 1] = (double)pi[rk] / (double)q;
     }
   }
   ctx->t.mods = upload(mi, st);

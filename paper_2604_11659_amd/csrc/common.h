@@ -82,8 +82,8 @@ struct Params {
 // Constant tables for one context (all in device memory).
 struct Tables {
   DevBuf mods;     // ModInfo[nmod]
-  DevBuf tw;       // per modulus: fwd[N], fwd_shoup[N], inv[N], inv_shoup[N]
-  DevBuf twf;      // per modulus (as double): fwd[N], fwd / q [N], inv[N], inv / q [N]
+  DevBuf tw;       // per modulus: fwd[N][2] (w, shoup), inv[N][2] (w, shoup)
+  DevBuf twf;      // per modulus (as double): fwd[N][2] (w, w / q), inv[N][2] (w, w / q)
   DevBuf modup;    // per (nl, digit): see modup_offset
   DevBuf moddown;  // phat_inv[K][2], phat_mod_q[K][nq][2], pinv_mod_q[nq][2], p_mod_q[nq]
   DevBuf rescale;  // ql_inv[l][i][2] = (q_l^-1 mod q_i, shoup), l < nq, i < l
@@ -93,7 +93,7 @@ struct Tables {
 };
 
 struct SwitchKey {
-  DevBuf buf;  // [beta_top][2][nq+np][N], NTT domain, Montgomery form
+  DevBuf buf;  // [beta_top][2][nq+np][N], NTT domain; Q limbs as doubles' bits, P limbs in Montgomery form
 };
 
 }  // namespace fhe

@@ -70,7 +70,8 @@ void to_montgomery(const fhe_ctx* ctx, uint64_t* x, uint32_t nlimbs, uint32_t n_
                    hipStream_t st);
 
 // Switching-key digit on all nall limbs (NTT domain): b = e - a s + pfac_i s' (pfac_i = 0 outside the
-// digit); writes b and a in Montgomery form. pfac: [nall] (device).
+// digit). Writes b and a as the doubles' bits of the residues on Q primes (FP64 key product) and in
+// Montgomery form on special primes. pfac: [nall] (device).
 void keygen_digit(const fhe_ctx* ctx, uint32_t nall, const uint64_t* a, const uint64_t* s, const uint64_t* e,
                   const uint64_t* sp, const uint64_t* pfac, uint64_t* bout, uint64_t* aout, hipStream_t st);
 

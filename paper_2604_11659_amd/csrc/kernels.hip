@@ -3,6 +3,7 @@
 // accumulation. Residues are uint64 in [0, q), limb-major ([..][limb][coefficient]) so that a
 // wavefront reads 64 consecutive coefficients of one limb (512 contiguous bytes).
 #include <algorithm>
+#include <cstdlib>
 
 #include "kernels.h"
 
@@ -61,16 +62,29 @@ constexpr uint32_t kNttLdsElems = kNttE + (kNttE >> 4);
 
 __device__ __forceinline__ uint32_t pad_idx(uint32_t i) { return i + (i >> 4); }
 
+// A copy of x the compiler cannot see through: index arithmetic derived from it is recomputed
+// where it is used instead of being kept live (in registers) across the transform rounds.
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 // Integer arithmetic (special primes up to 61 bits): residues in [0, q) everywhere.
+// Key-switching key words are in Montgomery form (x R mod q, R = 2^64).
 struct IntArith {
   typedef uint64_t T;
   typedef uint64_t W;
-  uint64_t q;
-  __device__ __forceinline__ void init(uint64_t qq) { q = qq; }
+  typedef uint64_t Acc;
+  uint64_t q, qinv;
+  __device__ __forceinline__ void init(const ModInfo& m) {
+    q = m.q;
+    qinv = m.qinv;
+  }
   __device__ __forceinline__ uint64_t lds_in(uint64_t x) const { return x; }   // global -> LDS word
   __device__ __forceinline__ uint64_t lds_out(uint64_t x) const { return x; }  // LDS word -> [0, q)
   __device__ __forceinline__ T ld(uint64_t x) const { return x; }
   __device__ __forceinline__ uint64_t st(T x) const { return x; }
+  __device__ __forceinline__ T from_u64(uint64_t x) const { return x; }
   __device__ __forceinline__ void round_end(T&) const {}
   __device__ __forceinline__ void ct(T& a, T& b, W w, W wx) const {
     const T v = shoup_mul(b, w, wx, q);
@@ -82,22 +96,31 @@ struct IntArith {
     a = add_mod(u, v, q);
     b = shoup_mul(sub_mod(u, v, q), w, wx, q);
   }
+  // Key inner product: acc + x * key (key word in Montgomery form), in [0, q).
+  __device__ __forceinline__ Acc kacc(Acc acc, T x, uint64_t kw) const {
+    return add_mod(acc, mont_mul(x, kw, q, qinv), q);
+  }
+  __device__ __forceinline__ void kred(Acc&) const {}
+  __device__ __forceinline__ uint64_t kfinal(Acc acc) const { return acc; }
 };
 
 // FP64 arithmetic for q < 2^50 on signed residues (doubles holding integers), lazily reduced.
-//   mulc(a, w): c = rint(a * fl(w/q)); a*w = h + l exactly (FMA); r = (h - c q) + l, both steps exact.
-//     For |a| <= 5q the quotient is within 1.5 of a w / q, so |r| <= 1.5 q and every intermediate
-//     stays below 2^53 in magnitude (exactly representable).
-//   red(x) = x - q rint(x / q) returns the representative in [-q/2 - 1, q/2 + 1].
-// Forward butterflies leave sums unreduced inside a round of at most four stages (|x| <= 5q from an
-// input in [0, q)); inverse butterflies reduce the sum branch every stage. Every round ends with
-// red(), and values leave LDS as [0, q) integers.
+//   mulc(a, w) (twiddle w in [0, q), wq = fl(w / q)): c = rint(a wq); a w = h + l exactly (FMA);
+//     r = (h - c q) + l, both steps exact. The quotient estimate is off by at most 0.5 + |a| / 4q,
+//     so |r| <= (0.5 + |a| / 4q) q, and every intermediate is an integer below 2^53 in magnitude.
+//   red(x) = x - q rint(x / q) lies within [-q/2 - 2, q/2 + 2].
+// Forward butterflies leave sums unreduced inside a round of at most four stages: from |x| <= q the
+// magnitudes grow to at most 1.75q, 2.7q, 3.9q, 5.4q (< 2^53). Inverse butterflies reduce the sum
+// branch every stage (|x| <= q throughout). Every round ends with red(); LDS holds the doubles'
+// bits between rounds, and values leave LDS as [0, q) integers.
+// Key-switching key words are the doubles' bits of plain residues in [0, q).
 struct FpArith {
   typedef double T;
   typedef double W;
+  typedef double Acc;
   double q, qinv;
-  __device__ __forceinline__ void init(uint64_t qq) {
-    q = (double)qq;
+  __device__ __forceinline__ void init(const ModInfo& m) {
+    q = (double)m.q;
     qinv = 1.0 / q;
   }
   __device__ __forceinline__ uint64_t lds_in(uint64_t x) const { return __double_as_longlong((double)x); }
@@ -107,6 +130,7 @@ struct FpArith {
   }
   __device__ __forceinline__ T ld(uint64_t bits) const { return __longlong_as_double((long long)bits); }
   __device__ __forceinline__ uint64_t st(T x) const { return (uint64_t)__double_as_longlong(x); }
+  __device__ __forceinline__ T from_u64(uint64_t x) const { return (double)x; }
   __device__ __forceinline__ T red(T x) const { return __fma_rn(-rint(x * qinv), q, x); }
   __device__ __forceinline__ T mulc(T a, W w, W wq) const {
     const double c = rint(a * wq);
@@ -125,6 +149,21 @@ struct FpArith {
     a = red(a + b);
     b = mulc(d, w, wq);
   }
+  // Key inner product: acc + x * k with |x| < q and k in [0, q). The quotient of h = fl(x k) by q is
+  // estimated from fl(h / q) to within 0.875, so each term has |r| <= 0.875q; the sum is reduced every
+  // four digits (kred), which keeps it below 4q + q/2 + 2 < 2^53.
+  __device__ __forceinline__ Acc kacc(Acc acc, T x, uint64_t kw) const {
+    const double k = __longlong_as_double((long long)kw);
+    const double h = x * k;
+    const double l = __fma_rn(x, k, -h);
+    const double c = rint(h * qinv);
+    return acc + (__fma_rn(-c, q, h) + l);
+  }
+  __device__ __forceinline__ void kred(Acc& acc) const { acc = red(acc); }
+  __device__ __forceinline__ uint64_t kfinal(Acc acc) const {
+    const double x = red(acc);
+    return (uint64_t)(x < 0.0 ? x + q : x);
+  }
 };
 
 // One round: bits [lo, lo + M) of the in-phase index x, with NT threads holding EPT elements each
@@ -134,9 +173,8 @@ struct FpArith {
 // b = lo + bl the twiddle index 2^s + floor(j / 2^(b+1)) depends on i only through i >> (bl + 1), so
 // each of the 2^(M - bl - 1) twiddles of the stage is loaded once and shared by 2^bl butterflies.
 template <int M, bool kInv, int kPhase, class A, int EPT, int NT>
-__device__ __forceinline__ void ntt_round(uint64_t* lds, const A& ar, const typename A::W* w,
-                                          const typename A::W* wx, uint32_t lo, uint32_t k, uint32_t logC,
-                                          uint32_t sbase, uint64_t j0) {
+__device__ __forceinline__ void ntt_round(uint64_t* lds, const A& ar, const typename A::W* tw2, uint32_t lo,
+                                          uint32_t k, uint32_t logC, uint32_t sbase, uint64_t j0) {
   constexpr uint32_t GM = 1u << M, G = EPT >> M;
   typename A::T r[EPT];
   uint32_t xh[G], xl[G], cc[G];
@@ -173,7 +211,7 @@ __device__ __forceinline__ void ntt_round(uint64_t* lds, const A& ar, const type
       if (kPhase == 2) base += (uint32_t)(j0 >> (b + 1)) + (cc[u] << (k - b - 1));
 #pragma unroll
       for (uint32_t t = 0; t < (1u << (M - bl - 1)); ++t) {
-        const typename A::W W = w[base + t], Wx = wx[base + t];
+        const typename A::W W = tw2[2 * (base + t)], Wx = tw2[2 * (base + t) + 1];
 #pragma unroll
         for (uint32_t low = 0; low < (1u << bl); ++low) {
           const uint32_t i = (t << (bl + 1)) | low, i2 = i | (1u << bl);
@@ -197,9 +235,8 @@ __device__ __forceinline__ void ntt_round(uint64_t* lds, const A& ar, const type
 }
 
 template <bool kInv, int kPhase, class A, int EPT, int NT>
-__device__ __forceinline__ void ntt_rounds(uint64_t* lds, const A& ar, const typename A::W* w,
-                                           const typename A::W* wx, uint32_t k, uint32_t logC, uint32_t sbase,
-                                           uint64_t j0) {
+__device__ __forceinline__ void ntt_rounds(uint64_t* lds, const A& ar, const typename A::W* tw2, uint32_t k,
+                                           uint32_t logC, uint32_t sbase, uint64_t j0) {
   // Rounds of MB = log2(EPT) bits. Forward: chunks from the top ([k-MB, k), [k-2MB, k-MB), ...,
   // [0, rem)); inverse: the same chunks in reverse order.
   constexpr uint32_t MB = EPT == 16 ? 4 : (EPT == 8 ? 3 : 2);
@@ -210,13 +247,13 @@ __device__ __forceinline__ void ntt_rounds(uint64_t* lds, const A& ar, const typ
     const uint32_t lo = hi >= MB ? hi - MB : 0;
     switch (hi - lo) {
       case 4:
-        if constexpr (MB >= 4) ntt_round<4, kInv, kPhase, A, EPT, NT>(lds, ar, w, wx, lo, k, logC, sbase, j0);
+        if constexpr (MB >= 4) ntt_round<4, kInv, kPhase, A, EPT, NT>(lds, ar, tw2, lo, k, logC, sbase, j0);
         break;
       case 3:
-        if constexpr (MB >= 3) ntt_round<3, kInv, kPhase, A, EPT, NT>(lds, ar, w, wx, lo, k, logC, sbase, j0);
+        if constexpr (MB >= 3) ntt_round<3, kInv, kPhase, A, EPT, NT>(lds, ar, tw2, lo, k, logC, sbase, j0);
         break;
-      case 2: ntt_round<2, kInv, kPhase, A, EPT, NT>(lds, ar, w, wx, lo, k, logC, sbase, j0); break;
-      default: ntt_round<1, kInv, kPhase, A, EPT, NT>(lds, ar, w, wx, lo, k, logC, sbase, j0); break;
+      case 2: ntt_round<2, kInv, kPhase, A, EPT, NT>(lds, ar, tw2, lo, k, logC, sbase, j0); break;
+      default: ntt_round<1, kInv, kPhase, A, EPT, NT>(lds, ar, tw2, lo, k, logC, sbase, j0); break;
     }
     __syncthreads();
   }
@@ -235,21 +272,24 @@ __global__ __launch_bounds__(kThreads) void k_ntt(LimbBatch lb, const ModInfo* _
   const uint32_t mi = mod_index(lb, poly, e);
   const ModInfo m = mods[mi];
   A ar;
-  ar.init(m.q);
+  ar.init(m);
   const uint32_t k = kPhase == 1 ? k1 : logN - k1, k2 = logN - k1;
   const uint32_t logC = kNttLogE - k, C = 1u << logC;
   const uint64_t j0 = (uint64_t)tile * kNttE;
-  for (uint32_t idx = threadIdx.x; idx < kNttE; idx += kThreads) {
-    const uint64_t g = kPhase == 1 ? ((uint64_t)(idx >> logC) << k2) + ((uint64_t)tile << logC) + (idx & (C - 1))
-                                   : j0 + idx;
+#pragma unroll
+  for (uint32_t r_ = 0; r_ < kNttE / kThreads; ++r_) {
+    const uint32_t idx = threadIdx.x + r_ * kThreads;
+    const uint32_t g = kPhase == 1 ? ((idx >> logC) << k2) + (tile << logC) + (idx & (C - 1)) : (uint32_t)j0 + idx;
     lds[pad_idx(idx)] = ar.lds_in(in[g]);
   }
   __syncthreads();
   const uint64_t toff = (uint64_t)mi * 4 * N + (kInv ? 2 * (uint64_t)N : 0);
-  ntt_rounds<kInv, kPhase, A, 16, kThreads>(lds, ar, tw + toff, tw + toff + N, k, logC, kPhase == 1 ? 0 : k1, j0);
-  for (uint32_t idx = threadIdx.x; idx < kNttE; idx += kThreads) {
-    const uint64_t g = kPhase == 1 ? ((uint64_t)(idx >> logC) << k2) + ((uint64_t)tile << logC) + (idx & (C - 1))
-                                   : j0 + idx;
+  ntt_rounds<kInv, kPhase, A, 16, kThreads>(lds, ar, tw + toff, k, logC, kPhase == 1 ? 0 : k1, j0);
+  const uint32_t tid = opaque(threadIdx.x);
+#pragma unroll
+  for (uint32_t r_ = 0; r_ < kNttE / kThreads; ++r_) {
+    const uint32_t idx = tid + r_ * kThreads;
+    const uint32_t g = kPhase == 1 ? ((idx >> logC) << k2) + (tile << logC) + (idx & (C - 1)) : (uint32_t)j0 + idx;
     uint64_t v = ar.lds_out(lds[pad_idx(idx)]);
     if (kInv && kPhase == 1) v = shoup_mul(v, m.n_inv, m.n_inv_shoup, m.q);
     a[g] = v;
@@ -264,7 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_ntt(LimbBatch lb, const ModInfo* _
 // never return to HBM.
 constexpr int kInnerThreads = 512;
 template <class A>
-__global__ __launch_bounds__(kInnerThreads) void k_ntt_p2_inner(
+__device__ __forceinline__ void ntt_p2_inner_body(
     uint32_t B, uint32_t nl, uint32_t K, uint32_t nq, uint32_t alpha, uint32_t R, uint32_t e0, uint32_t ne,
     uint32_t logN, uint32_t k1, const ModInfo* __restrict__ mods, const typename A::W* __restrict__ tw,
     const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __restrict__ ext,
@@ -281,9 +321,9 @@ __global__ __launch_bounds__(kInnerThreads) void k_ntt_p2_inner(
   const uint32_t k = logN - k1, logC = kNttLogE - k;
   const uint64_t* key = keys[b];
   A ar;
-  ar.init(m.q);
+  ar.init(m);
   const typename A::W* w = tw + (uint64_t)mi * 4 * N;
-  uint64_t acc0[kPer], acc1[kPer];
+  typename A::Acc acc0[kPer], acc1[kPer];
 #pragma unroll
   for (uint32_t r = 0; r < kPer; ++r) acc0[r] = acc1[r] = 0;
   for (uint32_t j = 0; j < beta; ++j) {
@@ -295,24 +335,36 @@ __global__ __launch_bounds__(kInnerThreads) void k_ntt_p2_inner(
 #pragma unroll
       for (uint32_t r = 0; r < kPer; ++r) {
         const uint32_t idx = threadIdx.x + r * kInnerThreads;
-        const uint64_t xv = x[idx];
-        acc0[r] = add_mod(acc0[r], mont_mul(xv, kb[idx], m.q, m.qinv), m.q);
-        acc1[r] = add_mod(acc1[r], mont_mul(xv, ka[idx], m.q, m.qinv), m.q);
+        const typename A::T xv = ar.from_u64(x[idx]);
+        acc0[r] = ar.kacc(acc0[r], xv, kb[idx]);
+        acc1[r] = ar.kacc(acc1[r], xv, ka[idx]);
       }
     } else {
       const uint32_t row = e < lo ? e : e - cnt;
       const uint64_t* src = ext + (((uint64_t)j * B + b) * R + row) * N + j0;
-      for (uint32_t idx = threadIdx.x; idx < kNttE; idx += kInnerThreads) lds[pad_idx(idx)] = ar.lds_in(src[idx]);
-      __syncthreads();
-      ntt_rounds<false, 2, A, 8, kInnerThreads>(lds, ar, w, w + N, k, logC, k1, j0);
-#pragma unroll
-      for (uint32_t r = 0; r < kPer; ++r) {
-        const uint32_t idx = threadIdx.x + r * kInnerThreads;
-        const uint64_t xv = ar.lds_out(lds[pad_idx(idx)]);
-        acc0[r] = add_mod(acc0[r], mont_mul(xv, kb[idx], m.q, m.qinv), m.q);
-        acc1[r] = add_mod(acc1[r], mont_mul(xv, ka[idx], m.q, m.qinv), m.q);
+    #pragma unroll
+      for (uint32_t r_ = 0; r_ < kNttE / kInnerThreads; ++r_) {
+        const uint32_t idx = threadIdx.x + r_ * kInnerThreads;
+        lds[pad_idx(idx)] = ar.lds_in(src[idx]);
       }
       __syncthreads();
+      ntt_rounds<false, 2, A, 8, kInnerThreads>(lds, ar, w, k, logC, k1, j0);
+      const uint32_t tid = opaque(threadIdx.x);
+#pragma unroll
+      for (uint32_t r = 0; r < kPer; ++r) {
+        const uint32_t idx = tid + r * kInnerThreads;
+        const typename A::T xv = ar.ld(lds[pad_idx(idx)]);
+        acc0[r] = ar.kacc(acc0[r], xv, kb[idx]);
+        acc1[r] = ar.kacc(acc1[r], xv, ka[idx]);
+      }
+      __syncthreads();
+    }
+    if ((j & 3) == 3) {
+#pragma unroll
+      for (uint32_t r = 0; r < kPer; ++r) {
+        ar.kred(acc0[r]);
+        ar.kred(acc1[r]);
+      }
     }
   }
   uint64_t* u0 = u + ((uint64_t)(b * 2 + 0) * next + e) * N + j0;
@@ -320,10 +372,28 @@ __global__ __launch_bounds__(kInnerThreads) void k_ntt_p2_inner(
 #pragma unroll
   for (uint32_t r = 0; r < kPer; ++r) {
     const uint32_t idx = threadIdx.x + r * kInnerThreads;
-    u0[idx] = acc0[r];
-    u1[idx] = acc1[r];
+    u0[idx] = ar.kfinal(acc0[r]);
+    u1[idx] = ar.kfinal(acc1[r]);
   }
 }
+
+#define FHE_P2_INNER_ARGS                                                                                  \
+  uint32_t B, uint32_t nl, uint32_t K, uint32_t nq, uint32_t alpha, uint32_t R, uint32_t e0, uint32_t ne,   \
+      uint32_t logN, uint32_t k1, const ModInfo *__restrict__ mods, const typename A::W *__restrict__ tw,   \
+      const uint64_t *__restrict__ in, uint64_t in_stride, const uint64_t *__restrict__ ext,                \
+      const uint64_t *const *__restrict__ keys, uint64_t *__restrict__ u
+// Two register budgets: one 512-thread workgroup per CU at the compiler's natural register count, or
+// two per CU (at most 128 VGPRs, a few spilled).
+template <class A>
+__global__ __launch_bounds__(kInnerThreads) void k_ntt_p2_inner(FHE_P2_INNER_ARGS) {
+  ntt_p2_inner_body<A>(B, nl, K, nq, alpha, R, e0, ne, logN, k1, mods, tw, in, in_stride, ext, keys, u);
+}
+template <class A>
+__global__ __launch_bounds__(kInnerThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_ntt_p2_inner_occ2(
+    FHE_P2_INNER_ARGS) {
+  ntt_p2_inner_body<A>(B, nl, K, nq, alpha, R, e0, ne, logN, k1, mods, tw, in, in_stride, ext, keys, u);
+}
+#undef FHE_P2_INNER_ARGS
 
 // Row phase of the forward NTT of the ModDown conversion fused with the final combine:
 // out[b][c][i] = add[2b+c][i] + (u[b][c][i] - NTT(conv)[b][c][i]) P^-1 (NTT domain).
@@ -343,20 +413,27 @@ __global__ __launch_bounds__(kThreads) void k_ntt_p2_combine(uint32_t nl, uint32
   const uint32_t i = li % nl, bc = li / nl, b = bc >> 1, c = bc & 1;
   const ModInfo m = mods[i];
   A ar;
-  ar.init(m.q);
+  ar.init(m);
   const uint64_t j0 = (uint64_t)tile * kNttE;
   const uint32_t k = logN - k1, logC = kNttLogE - k;
   const uint64_t* src = conv + ((uint64_t)bc * nl + i) * N + j0;
-  for (uint32_t idx = threadIdx.x; idx < kNttE; idx += kThreads) lds[pad_idx(idx)] = ar.lds_in(src[idx]);
+#pragma unroll
+  for (uint32_t r_ = 0; r_ < kNttE / kThreads; ++r_) {
+    const uint32_t idx = threadIdx.x + r_ * kThreads;
+    lds[pad_idx(idx)] = ar.lds_in(src[idx]);
+  }
   __syncthreads();
   const typename A::W* w = tw + (uint64_t)i * 4 * N;
-  ntt_rounds<false, 2, A, 16, kThreads>(lds, ar, w, w + N, k, logC, k1, j0);
+  ntt_rounds<false, 2, A, 16, kThreads>(lds, ar, w, k, logC, k1, j0);
   const uint64_t* pinv = tab + 2 * K + 2 * (uint64_t)K * nq + 2 * i;
   const uint64_t* uu = u + ((uint64_t)bc * next + i) * N + j0;
   const uint64_t* ad = add[bc];
   if (ad) ad += (uint64_t)i * N + j0;
   uint64_t* o = out[b] + ((uint64_t)c * nl + i) * N + j0;
-  for (uint32_t idx = threadIdx.x; idx < kNttE; idx += kThreads) {
+  const uint32_t tid = opaque(threadIdx.x);
+#pragma unroll
+  for (uint32_t r_ = 0; r_ < kNttE / kThreads; ++r_) {
+    const uint32_t idx = tid + r_ * kThreads;
     uint64_t v = shoup_mul(sub_mod(uu[idx], ar.lds_out(lds[pad_idx(idx)]), m.q), pinv[0], pinv[1], m.q);
     if (ad) v = add_mod(v, ad[idx], m.q);
     o[idx] = v;
@@ -473,6 +550,171 @@ __global__ __launch_bounds__(kThreads) void k_moddown_conv(uint32_t B, uint32_t 
       }
       for (uint32_t n = 0; n < nneg; ++n) acc = sub_mod(acc, pmod[i], q);
       conv[((uint64_t)bc * nl + i) * N + k] = acc;
+    }
+  }
+}
+
+// Column-phase tiles of 2^LOG_E elements: 2^k1 rows (stride 2^(logN - k1)) by C = 2^(LOG_E - k1)
+// adjacent columns; `col_index` maps a tile slot to its coefficient index.
+__device__ __forceinline__ uint32_t col_index(uint32_t idx, uint32_t logC, uint32_t k2, uint32_t tile) {
+  return ((idx >> logC) << k2) + (tile << logC) + (idx & ((1u << logC) - 1));
+}
+
+// ModUp fused with the column phases around it. Workgroup (digit j, item b, tile): the digit's limbs
+// (row phase of the inverse NTT already applied, in dc2 [B][nl][N]) go through the inverse column
+// phase in LDS and are scaled to y_i = d_i Dhat_i^-1 mod q_i (N^-1 folded in); then for every limb
+// outside the digit the converted row sum_i y_i (Dhat_i mod t) mod t is formed in LDS, goes through the
+// forward column phase of its modulus and is written to ext (layout as k_modup). The coefficient-
+// domain digits and converted rows never reach HBM.
+// LDS: one padded work tile plus alpha tiles of y.
+template <int LOG_E, int NT>
+__global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint32_t K, uint32_t nq, uint32_t alpha,
+                                                  uint32_t R, uint32_t logN, uint32_t k1,
+                                                  const ModInfo* __restrict__ mods, const double* __restrict__ twf,
+                                                  const uint64_t* __restrict__ twi, const uint64_t* __restrict__ tab,
+                                                  const uint64_t* __restrict__ dc2, uint64_t* __restrict__ ext) {
+  constexpr uint32_t E = 1u << LOG_E, EPT = E / NT, EP = E + (E >> 4);
+  extern __shared__ uint64_t lds[];
+  uint64_t* work = lds;
+  uint64_t* ys = lds + EP;
+  const uint32_t N = 1u << logN, tiles = N >> LOG_E;
+  const uint32_t tile = blockIdx.x % tiles, rest = blockIdx.x / tiles;
+  const uint32_t b = rest % B, j = rest / B;
+  const uint32_t next = nl + K, lo = j * alpha, cnt = min(alpha, nl - lo);
+  const uint32_t k2 = logN - k1, logC = LOG_E - k1;
+  const uint64_t* blk = tab + (uint64_t)j * (2 * alpha + 2 * alpha * next);
+  for (uint32_t i = 0; i < cnt; ++i) {
+    const ModInfo m = mods[lo + i];
+    FpArith ar;
+    ar.init(m);
+    const uint64_t* src = dc2 + ((uint64_t)b * nl + lo + i) * N;
+  #pragma unroll
+    for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
+      const uint32_t idx = threadIdx.x + r_ * NT;
+      work[pad_idx(idx)] = ar.lds_in(src[col_index(idx, logC, k2, tile)]);
+    }
+    __syncthreads();
+    const double* w = twf + (uint64_t)(lo + i) * 4 * N + 2 * (uint64_t)N;
+    ntt_rounds<true, 1, FpArith, EPT, NT>(work, ar, w, k1, logC, 0, 0);
+    const double c = (double)shoup_mul(m.n_inv, blk[2 * i], blk[2 * i + 1], m.q);
+    const double cq = c / ar.q;
+  #pragma unroll
+    for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
+      const uint32_t idx = threadIdx.x + r_ * NT;
+      const double y = ar.mulc(ar.ld(work[pad_idx(idx)]), c, cq);
+      ys[(uint64_t)i * E + idx] = (uint64_t)(y < 0.0 ? y + ar.q : y);
+    }
+    // the next limb's loads write only this thread's own slots: no barrier needed here
+  }
+  uint64_t* out = ext + ((uint64_t)j * B + b) * R * N;
+  for (uint32_t row = 0; row < next - cnt; ++row) {
+    const uint32_t e = row < lo ? row : row + cnt;
+    const uint32_t mi = e < nl ? e : nq + (e - nl);
+    const ModInfo m = mods[mi];
+    const uint64_t* mrow = blk + 2 * alpha + 2 * (uint64_t)e;
+    const bool fp = e < nl;
+  #pragma unroll
+    for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
+      const uint32_t idx = threadIdx.x + r_ * NT;
+      uint64_t v = 0;
+      for (uint32_t i = 0; i < cnt; ++i) {
+        const uint64_t* cc = mrow + (uint64_t)i * 2 * next;
+        v = add_mod(v, shoup_mul(ys[(uint64_t)i * E + idx], cc[0], cc[1], m.q), m.q);
+      }
+      work[pad_idx(idx)] = fp ? (uint64_t)__double_as_longlong((double)v) : v;
+    }
+    __syncthreads();
+    uint64_t* o = out + (uint64_t)row * N;
+    if (fp) {
+      FpArith ar;
+      ar.init(m);
+      const double* w = twf + (uint64_t)mi * 4 * N;
+      ntt_rounds<false, 1, FpArith, EPT, NT>(work, ar, w, k1, logC, 0, 0);
+    #pragma unroll
+      for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
+        const uint32_t idx = threadIdx.x + r_ * NT;
+        o[col_index(idx, logC, k2, tile)] = ar.lds_out(work[pad_idx(idx)]);
+      }
+    } else {
+      IntArith ar;
+      ar.init(m);
+      const uint64_t* w = twi + (uint64_t)mi * 4 * N;
+      ntt_rounds<false, 1, IntArith, EPT, NT>(work, ar, w, k1, logC, 0, 0);
+    #pragma unroll
+      for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
+        const uint32_t idx = threadIdx.x + r_ * NT;
+        o[col_index(idx, logC, k2, tile)] = work[pad_idx(idx)];
+      }
+    }
+    // the next row's sums write only this thread's own slots: no barrier needed here
+  }
+}
+
+// ModDown conversion fused with the column phases around it. Workgroup (item b, component c, tile):
+// the K special-prime limbs of u (row phase of the inverse NTT already applied) go through the inverse
+// column phase in LDS and are scaled to z_k = [u_(p_k) (P/p_k)^-1]_(p_k) (N^-1 applied first), taken
+// as centred representatives as in k_moddown_conv; every Q limb's conversion is formed in LDS, goes
+// through the forward column phase and is written to conv [B][2][nl][N].
+template <int LOG_E, int NT>
+__global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, uint32_t nq, uint32_t logN, uint32_t k1,
+                                                    const ModInfo* __restrict__ mods, const double* __restrict__ twf,
+                                                    const uint64_t* __restrict__ twi, const uint64_t* __restrict__ tab,
+                                                    const uint64_t* __restrict__ u, uint64_t* __restrict__ conv) {
+  constexpr uint32_t E = 1u << LOG_E, EPT = E / NT, EP = E + (E >> 4);
+  extern __shared__ uint64_t lds[];
+  uint64_t* work = lds;
+  uint64_t* zs = lds + EP;
+  const uint32_t N = 1u << logN, tiles = N >> LOG_E;
+  const uint32_t tile = blockIdx.x % tiles, bc = blockIdx.x / tiles;
+  const uint32_t next = nl + K, k2 = logN - k1, logC = LOG_E - k1;
+  for (uint32_t kk = 0; kk < K; ++kk) {
+    const ModInfo m = mods[nq + kk];
+    IntArith ar;
+    ar.init(m);
+    const uint64_t* src = u + ((uint64_t)bc * next + nl + kk) * N;
+  #pragma unroll
+    for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
+      const uint32_t idx = threadIdx.x + r_ * NT;
+      work[pad_idx(idx)] = src[col_index(idx, logC, k2, tile)];
+    }
+    __syncthreads();
+    const uint64_t* w = twi + (uint64_t)(nq + kk) * 4 * N + 2 * (uint64_t)N;
+    ntt_rounds<true, 1, IntArith, EPT, NT>(work, ar, w, k1, logC, 0, 0);
+  #pragma unroll
+    for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
+      const uint32_t idx = threadIdx.x + r_ * NT;
+      const uint64_t x = shoup_mul(work[pad_idx(idx)], m.n_inv, m.n_inv_shoup, m.q);
+      zs[(uint64_t)kk * E + idx] = shoup_mul(x, tab[2 * kk], tab[2 * kk + 1], m.q);
+    }
+  }
+  const uint64_t* pq = tab + 2 * K;
+  const uint64_t* pmod = tab + 2 * K + 2 * (uint64_t)K * nq + 2 * nq;
+  for (uint32_t i = 0; i < nl; ++i) {
+    const ModInfo m = mods[i];
+  #pragma unroll
+    for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
+      const uint32_t idx = threadIdx.x + r_ * NT;
+      uint64_t acc = 0;
+      uint32_t nneg = 0;
+      for (uint32_t kk = 0; kk < K; ++kk) {
+        const uint64_t z = zs[(uint64_t)kk * E + idx];
+        const uint64_t* cc = pq + 2 * ((uint64_t)kk * nq + i);
+        acc = add_mod(acc, shoup_mul(z, cc[0], cc[1], m.q), m.q);
+        nneg += z > (mods[nq + kk].q - 1) / 2 ? 1u : 0u;
+      }
+      for (uint32_t n = 0; n < nneg; ++n) acc = sub_mod(acc, pmod[i], m.q);
+      work[pad_idx(idx)] = (uint64_t)__double_as_longlong((double)acc);
+    }
+    __syncthreads();
+    FpArith ar;
+    ar.init(m);
+    const double* w = twf + (uint64_t)i * 4 * N;
+    ntt_rounds<false, 1, FpArith, EPT, NT>(work, ar, w, k1, logC, 0, 0);
+    uint64_t* o = conv + ((uint64_t)bc * nl + i) * N;
+  #pragma unroll
+    for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
+      const uint32_t idx = threadIdx.x + r_ * NT;
+      o[col_index(idx, logC, k2, tile)] = ar.lds_out(work[pad_idx(idx)]);
     }
   }
 }
@@ -594,7 +836,7 @@ __global__ __launch_bounds__(kThreads) void k_to_mont(uint64_t* __restrict__ x, 
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_keygen_digit(uint32_t nall, uint32_t logN,
+__global__ __launch_bounds__(kThreads) void k_keygen_digit(uint32_t nall, uint32_t nq, uint32_t logN,
                                                           const ModInfo* __restrict__ mods,
                                                           const uint64_t* __restrict__ a,
                                                           const uint64_t* __restrict__ s,
@@ -610,8 +852,13 @@ __global__ __launch_bounds__(kThreads) void k_keygen_digit(uint32_t nall, uint32
     uint64_t b = sub_mod(e[t], as, m.q);
     const uint64_t f = pfac[li];
     if (f) b = add_mod(b, mont_mul(mont_mul(f, sp[t], m.q, m.qinv), m.r2, m.q, m.qinv), m.q);
-    bout[t] = mont_mul(b, m.r2, m.q, m.qinv);
-    aout[t] = mont_mul(a[t], m.r2, m.q, m.qinv);
+    if (li < nq) {  // Q primes: the doubles' bits of the plain residues (FP64 key product)
+      bout[t] = (uint64_t)__double_as_longlong((double)b);
+      aout[t] = (uint64_t)__double_as_longlong((double)a[t]);
+    } else {  // special primes: Montgomery form (integer key product)
+      bout[t] = mont_mul(b, m.r2, m.q, m.qinv);
+      aout[t] = mont_mul(a[t], m.r2, m.q, m.qinv);
+    }
   }
 }
 
@@ -695,6 +942,16 @@ static void check_batch(const fhe_ctx* ctx, const LimbBatch& lb) {
   if (mi >= (uint32_t)p.nmod() || mi0 >= (uint32_t)p.nmod()) fail(FHE_EINVAL, "NTT batch modulus index out of range");
 }
 
+// Register budget of the fused inner-product kernel on Q limbs: FHE_INNER_OCC=2 selects the variant
+// that fits two workgroups per CU.
+static bool inner_occ2() {
+  static const bool v = [] {
+    const char* e = std::getenv("FHE_INNER_OCC");
+    return e && std::atoi(e) == 2;
+  }();
+  return v;
+}
+
 static uint32_t ntt_blocks(const fhe_ctx* ctx, const LimbBatch& lb) {
   const uint64_t blocks = (uint64_t)(ctx->p.N >> kNttLogE) * lb.limbs * lb.npoly;
   if (blocks >= (1ull << 31)) fail(FHE_EINVAL, "NTT batch too large");
@@ -768,6 +1025,14 @@ void ntt_forward(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st) {
   ntt_phase<false, 2>(ctx, lb, "ntt_fwd_p2_q", "ntt_fwd_p2_p", false, st);
 }
 
+// Row phase of the inverse transform only (the column phase is fused into a consumer).
+static void ntt_inverse_rows(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st) {
+  if (lb.limbs == 0 || lb.npoly == 0) return;
+  check_batch(ctx, lb);
+  check_holes(ctx, lb);
+  ntt_phase<true, 2>(ctx, lb, "ntt_inv_p2_q", "ntt_inv_p2_p", lb.src != nullptr, st);
+}
+
 void ntt_inverse(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st) {
   if (lb.limbs == 0 || lb.npoly == 0) return;
   check_batch(ctx, lb);
@@ -798,6 +1063,47 @@ static uint32_t modup_rows(const Params& p, uint32_t nl) {
   return nl + p.np - cnt_last;
 }
 
+// Fused column-phase kernels (ModUp, ModDown): tile of 2^11 elements on 256 threads or 2^12 on 512
+// threads, 8 elements per thread. FHE_COLS_TILE=11|12 forces one; otherwise 2^11 while a tile row
+// still spans at least 8 columns (64 bytes).
+static uint32_t cols_log_e(const Params& p) {
+  static const int forced = [] {
+    const char* e = std::getenv("FHE_COLS_TILE");
+    return e ? std::atoi(e) : 0;
+  }();
+  if (forced == 11 || forced == 12) return (uint32_t)forced;
+  return (11 - (int)p.k1) >= 3 ? 11u : 12u;
+}
+
+static size_t cols_lds_bytes(uint32_t log_e, uint32_t ntiles) {
+  const size_t E = (size_t)1 << log_e;
+  return (E + (E >> 4) + (size_t)ntiles * E) * sizeof(uint64_t);
+}
+
+static size_t max_lds_per_block(int device) {
+  static size_t cached[64] = {0};
+  if (device < 0 || device >= 64) return 65536;
+  if (!cached[device]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess || v <= 0) v = 65536;
+    cached[device] = (size_t)v;
+  }
+  return cached[device];
+}
+
+// Opts a kernel into more than 64 KiB of dynamic LDS (once per kernel and size class).
+static void allow_lds(const void* kern, size_t bytes) {
+  if (bytes <= 65536) return;
+  HIPCHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+static bool cols_fusable(const fhe_ctx* ctx, uint32_t ntiles) {
+  const Params& p = ctx->p;
+  const uint32_t le = cols_log_e(p);
+  if ((uint32_t)p.k1 > le || (p.N >> le) == 0) return false;
+  return cols_lds_bytes(le, ntiles) <= max_lds_per_block(ctx->device);
+}
+
 size_t keyswitch_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t nl) {
   const Params& p = ctx->p;
   const size_t N = p.N, next = nl + p.np, beta = p.beta(nl), R = modup_rows(p, nl);
@@ -823,28 +1129,49 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
   LimbBatch lb_in{dcoef, nl, B, (uint64_t)nl * N, nl, 0};
   lb_in.src = in;
   lb_in.src_stride = in_stride;
-  ntt_inverse(ctx, lb_in, st);
-  // 2. ModUp: the limbs outside each digit.
-  FHE_LAUNCH("modup", e8 * (nl + beta * (next - alpha)), k_modup, grid_for((uint64_t)B * beta * N), 0, st, B, nl, K,
-             (uint32_t)p.nq, alpha, R, p.logN, mods_of(ctx), ctx->t.modup.u64() + ctx->t.modup_offset[nl], dcoef,
-             ext);
-  // 3. Column phase of the NTT of the extended rows (full digits, then a truncated last digit).
-  if (beta_full) {
-    LimbBatch lb{ext, next - alpha, beta_full * B, (uint64_t)R * N, nl - alpha, (uint32_t)p.nq};
-    lb.hole_items = B;
-    lb.hole_alpha = alpha;
-    lb.hole_len = alpha;
-    lb.hole_j0 = 0;
-    ntt_forward_cols(ctx, lb, st);
-  }
-  if (beta_full < beta) {
-    LimbBatch lb{ext + (size_t)beta_full * B * R * N, next - cnt_last, B, (uint64_t)R * N, nl - cnt_last,
-                 (uint32_t)p.nq};
-    lb.hole_items = B;
-    lb.hole_alpha = alpha;
-    lb.hole_len = cnt_last;
-    lb.hole_j0 = beta_full;
-    ntt_forward_cols(ctx, lb, st);
+  if (cols_fusable(ctx, alpha)) {
+    // 1-3 fused: row phase of the INTT here, then one kernel for the column phases and ModUp.
+    ntt_inverse_rows(ctx, lb_in, st);
+    const uint32_t le = cols_log_e(p);
+    const size_t lds_mu = cols_lds_bytes(le, alpha);
+    const uint64_t grid = (uint64_t)B * beta * (N >> le);
+    if (grid >= (1ull << 31)) fail(FHE_EINVAL, "key-switch batch too large");
+    const double bytes = e8 * beta * (double)next;  // nl digit rows read, beta * next - nl rows written
+    const uint64_t* mtab = ctx->t.modup.u64() + ctx->t.modup_offset[nl];
+    const double* twf0 = (const double*)ctx->t.twf.get();
+    if (le == 11) {
+      allow_lds((const void*)k_modup_cols<11, 256>, lds_mu);
+      FHE_LAUNCH_T("modup_cols", bytes, (k_modup_cols<11, 256>), grid, 256, lds_mu, st, B, nl, K, (uint32_t)p.nq,
+                   alpha, R, p.logN, p.k1, mods_of(ctx), twf0, ctx->t.tw.u64(), mtab, dcoef, ext);
+    } else {
+      allow_lds((const void*)k_modup_cols<12, 512>, lds_mu);
+      FHE_LAUNCH_T("modup_cols", bytes, (k_modup_cols<12, 512>), grid, 512, lds_mu, st, B, nl, K, (uint32_t)p.nq,
+                   alpha, R, p.logN, p.k1, mods_of(ctx), twf0, ctx->t.tw.u64(), mtab, dcoef, ext);
+    }
+  } else {
+    ntt_inverse(ctx, lb_in, st);
+    // 2. ModUp: the limbs outside each digit.
+    FHE_LAUNCH("modup", e8 * (nl + beta * (next - alpha)), k_modup, grid_for((uint64_t)B * beta * N), 0, st, B, nl,
+               K, (uint32_t)p.nq, alpha, R, p.logN, mods_of(ctx), ctx->t.modup.u64() + ctx->t.modup_offset[nl],
+               dcoef, ext);
+    // 3. Column phase of the NTT of the extended rows (full digits, then a truncated last digit).
+    if (beta_full) {
+      LimbBatch lb{ext, next - alpha, beta_full * B, (uint64_t)R * N, nl - alpha, (uint32_t)p.nq};
+      lb.hole_items = B;
+      lb.hole_alpha = alpha;
+      lb.hole_len = alpha;
+      lb.hole_j0 = 0;
+      ntt_forward_cols(ctx, lb, st);
+    }
+    if (beta_full < beta) {
+      LimbBatch lb{ext + (size_t)beta_full * B * R * N, next - cnt_last, B, (uint64_t)R * N, nl - cnt_last,
+                   (uint32_t)p.nq};
+      lb.hole_items = B;
+      lb.hole_alpha = alpha;
+      lb.hole_len = cnt_last;
+      lb.hole_j0 = beta_full;
+      ntt_forward_cols(ctx, lb, st);
+    }
   }
   // 4. Row phase fused with the key inner product (Q limbs on the FP64 path, P limbs on the integer path).
   const size_t lds = kNttLdsElems * sizeof(uint64_t);
@@ -853,16 +1180,41 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
   const double* twf = (const double*)ctx->t.twf.get();
   // per extended limb: beta digit words (input or ModUp row), 2 beta key words, 2 output words
   const double ib = 8.0 * N * (double)B * (3.0 * beta + 2.0);
-  FHE_LAUNCH_T("ntt_p2_inner_q", ib * nl, k_ntt_p2_inner<FpArith>, (uint64_t)B * nl * tiles, kInnerThreads, lds, st, B, nl, K,
-             (uint32_t)p.nq, alpha, R, 0u, nl, p.logN, p.k1, mods_of(ctx), twf, in, in_stride, ext, keys, u);
+  if (inner_occ2())
+    FHE_LAUNCH_T("ntt_p2_inner_q", ib * nl, k_ntt_p2_inner_occ2<FpArith>, (uint64_t)B * nl * tiles, kInnerThreads, lds,
+                 st, B, nl, K, (uint32_t)p.nq, alpha, R, 0u, nl, p.logN, p.k1, mods_of(ctx), twf, in, in_stride, ext,
+                 keys, u);
+  else
+    FHE_LAUNCH_T("ntt_p2_inner_q", ib * nl, k_ntt_p2_inner<FpArith>, (uint64_t)B * nl * tiles, kInnerThreads, lds, st,
+                 B, nl, K, (uint32_t)p.nq, alpha, R, 0u, nl, p.logN, p.k1, mods_of(ctx), twf, in, in_stride, ext, keys,
+                 u);
   FHE_LAUNCH_T("ntt_p2_inner_p", ib * K, k_ntt_p2_inner<IntArith>, (uint64_t)B * K * tiles, kInnerThreads, lds, st, B, nl, K,
              (uint32_t)p.nq, alpha, R, nl, K, p.logN, p.k1, mods_of(ctx), ctx->t.tw.u64(), in, in_stride, ext, keys,
              u);
   // 5. ModDown: INTT of the P limbs, conversion to Q_l, column phase, row phase fused with the combine.
-  ntt_inverse(ctx, LimbBatch{u + (size_t)nl * N, K, 2 * B, (uint64_t)next * N, 0, (uint32_t)p.nq}, st);
-  FHE_LAUNCH("moddown_conv", e8 * 2 * (K + nl), k_moddown_conv, grid_for((uint64_t)B * 2 * N), 0, st, B, nl, K,
-             (uint32_t)p.nq, p.logN, mods_of(ctx), ctx->t.moddown.u64(), u, conv);
-  ntt_forward_cols(ctx, LimbBatch{conv, nl, 2 * B, (uint64_t)nl * N, nl, 0}, st);
+  const LimbBatch lb_up{u + (size_t)nl * N, K, 2 * B, (uint64_t)next * N, 0, (uint32_t)p.nq};
+  if (cols_fusable(ctx, K)) {
+    ntt_inverse_rows(ctx, lb_up, st);
+    const uint32_t le = cols_log_e(p);
+    const size_t lds_md = cols_lds_bytes(le, K);
+    const uint64_t grid = (uint64_t)2 * B * (N >> le);
+    const double bytes = e8 * 2 * (K + nl);
+    const double* twf0 = (const double*)ctx->t.twf.get();
+    if (le == 11) {
+      allow_lds((const void*)k_moddown_cols<11, 256>, lds_md);
+      FHE_LAUNCH_T("moddown_cols", bytes, (k_moddown_cols<11, 256>), grid, 256, lds_md, st, nl, K, (uint32_t)p.nq,
+                   p.logN, p.k1, mods_of(ctx), twf0, ctx->t.tw.u64(), ctx->t.moddown.u64(), u, conv);
+    } else {
+      allow_lds((const void*)k_moddown_cols<12, 512>, lds_md);
+      FHE_LAUNCH_T("moddown_cols", bytes, (k_moddown_cols<12, 512>), grid, 512, lds_md, st, nl, K, (uint32_t)p.nq,
+                   p.logN, p.k1, mods_of(ctx), twf0, ctx->t.tw.u64(), ctx->t.moddown.u64(), u, conv);
+    }
+  } else {
+    ntt_inverse(ctx, lb_up, st);
+    FHE_LAUNCH("moddown_conv", e8 * 2 * (K + nl), k_moddown_conv, grid_for((uint64_t)B * 2 * N), 0, st, B, nl, K,
+               (uint32_t)p.nq, p.logN, mods_of(ctx), ctx->t.moddown.u64(), u, conv);
+    ntt_forward_cols(ctx, LimbBatch{conv, nl, 2 * B, (uint64_t)nl * N, nl, 0}, st);
+  }
   FHE_LAUNCH("ntt_p2_combine", e8 * 2 * nl * 3.5, k_ntt_p2_combine<FpArith>, (uint64_t)2 * B * nl * tiles, lds, st, nl,
              K, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.moddown.u64(), u, conv, add, out);
 }
@@ -921,7 +1273,8 @@ void to_montgomery(const fhe_ctx* ctx, uint64_t* x, uint32_t nlimbs, uint32_t n_
 
 void keygen_digit(const fhe_ctx* ctx, uint32_t nall, const uint64_t* a, const uint64_t* s, const uint64_t* e,
                   const uint64_t* sp, const uint64_t* pfac, uint64_t* bout, uint64_t* aout, hipStream_t st) {
-  FHE_LAUNCH("keygen_digit", 0.0, k_keygen_digit, grid_for((uint64_t)nall << ctx->p.logN), 0, st, nall, ctx->p.logN,
+  FHE_LAUNCH("keygen_digit", 0.0, k_keygen_digit, grid_for((uint64_t)nall << ctx->p.logN), 0, st, nall, (uint32_t)ctx->p.nq,
+             ctx->p.logN,
              mods_of(ctx), a, s, e, sp, pfac, bout, aout);
 }
 

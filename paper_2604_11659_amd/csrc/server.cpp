@@ -70,7 +70,18 @@ struct fhe_server {
       {
         std::unique_lock<std::mutex> lk(mu);
         cv.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
-        if (stop && queue.empty() && active.empty()) return;
+        if (stop) {  // closing: requests not yet admitted are cancelled, admitted ones run to the end
+          for (uint64_t t : queue) {
+            Req* r = reqs[t].get();
+            r->state = 3;
+            r->err = FHE_EAGAIN;
+            r->msg = "server closed before the request was admitted";
+            r->t_done = now_s();
+          }
+          queue.clear();
+          done_cv.notify_all();
+          if (active.empty()) return;
+        }
         // Admission: by slot and by HBM budget for the result buffers.
         while (!queue.empty() && (int)active.size() < max_inflight) {
           Req* r = reqs[queue.front()].get();

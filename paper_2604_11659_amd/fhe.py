@@ -61,6 +61,7 @@ _SIGS = {
     "fhe_spmspm": ([c_vp, c_vp, c_vp, c_vp, PP], c_i32),
     "fhe_spmspm_pairs": ([c_vp, c_vp, c_vp, c_i64, c_i64, c_vp, PP], c_i32),
     "fhe_spmspm_batch": ([c_vp, c_sz, PP, PP, c_vp, PP], c_i32),
+    "fhe_spmspm_batch_pairs": ([c_vp, c_sz, PP, PP, P_i64, P_i64, c_vp, PP], c_i32),
     "fhe_plan_stats": ([c_vp, c_vp, c_vp, P_i64], c_i32),
     "fhe_plan_pattern": ([c_i32, c_i32, c_i32, c_i32, c_i32, P_i32, P_i32, P_i32, P_i32, P_i64], c_i32),
     "fhe_plan_rotations": ([c_vp, c_vp, c_vp, P_i32, c_sz, ctypes.POINTER(c_sz)], c_i32),
@@ -289,15 +290,25 @@ class Context(_Handle):
         _check(_lib.fhe_spmspm(self._ptr, A._ptr, B._ptr, _stream(stream), ctypes.byref(out)))
         return Matrix(out.value, self)
 
-    def spmspm_batch(self, As, Bs, stream=None) -> list:
-        """[A_i B_i] in one merged launch stream (bit-identical to one-at-a-time spmspm)."""
+    def spmspm_batch(self, As, Bs, stream=None, pair_ranges=None) -> list:
+        """[A_i B_i] in one merged launch stream (bit-identical to one-at-a-time spmspm).
+
+        pair_ranges: optional [(begin, end)] per matmul, restricting each to those matched pairs."""
         n = len(As)
         assert len(Bs) == n
         pa = (c_vp * max(1, n))(*[a._ptr for a in As])
         pb = (c_vp * max(1, n))(*[b._ptr for b in Bs])
         out = (c_vp * max(1, n))()
-        _check(_lib.fhe_spmspm_batch(self._ptr, n, ctypes.cast(pa, PP), ctypes.cast(pb, PP), _stream(stream),
-                                     ctypes.cast(out, PP)))
+        if pair_ranges is None:
+            _check(_lib.fhe_spmspm_batch(self._ptr, n, ctypes.cast(pa, PP), ctypes.cast(pb, PP), _stream(stream),
+                                         ctypes.cast(out, PP)))
+        else:
+            assert len(pair_ranges) == n
+            lo = np.asarray([r[0] for r in pair_ranges] or [0], np.int64)
+            hi = np.asarray([r[1] for r in pair_ranges] or [0], np.int64)
+            _check(_lib.fhe_spmspm_batch_pairs(self._ptr, n, ctypes.cast(pa, PP), ctypes.cast(pb, PP),
+                                               _ptr(lo, c_i64), _ptr(hi, c_i64), _stream(stream),
+                                               ctypes.cast(out, PP)))
         return [Matrix(out[i], self) for i in range(n)]
 
     def spmspm_pairs(self, A: Matrix, B: Matrix, begin: int, end: int, stream=None) -> Matrix:

@@ -1,0 +1,159 @@
+"""Summaries of rocprofv3 CSV output for the kernels of this library.
+
+Two summaries, both short markdown files:
+
+* ``stats``: the ``*_kernel_stats.csv`` of a ``--kernel-trace --stats -f csv`` run, as a table of
+  calls / total / average per kernel.
+* ``traffic``: HBM bytes per dispatch of one kernel from two ``--pmc`` runs (``FETCH_SIZE``, then
+  ``WRITE_SIZE``, each in KiB per dispatch), each scaled by what the same counter reads for a plain
+  copy-like kernel of known size run in the same process (1 GiB read and 1 GiB written). The result
+  is embedded as a JSON block tagged with the SHA-256 of the kernel source it was measured on, so a
+  reader can tell when the numbers have gone stale.
+
+  python -m paper_2604_11659_amd.profiling stats CSV --title T --command C --out FILE
+  python -m paper_2604_11659_amd.profiling traffic FETCH_CSV WRITE_CSV --kernel REGEX --label NAME \
+      --calib REGEX --calib-bytes 1073741824 --title T --command C --out FILE
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import re
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hip")
+TRAFFIC_TAG = "fhe-traffic"
+
+
+def kernel_source_sha256(path: str = KERNEL_SOURCE) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def short_name(name: str) -> str:
+    n = name.replace("fhe::(anonymous namespace)::", "").replace("void ", "")
+    return re.sub(r"\(.*", "", n).strip()
+
+
+def stats_markdown(csv_path: str, title: str, command: str, note: str = "") -> str:
+    rows = list(csv.DictReader(open(csv_path)))
+    total = sum(int(r["TotalDurationNs"]) for r in rows)
+    out = [f"# {title}", ""]
+    if note:
+        out += [note, ""]
+    out += ["Command (from the repository root):", "", "```", command, "```", "",
+            f"Total kernel time: {total / 1e9:.3f} s over {sum(int(r['Calls']) for r in rows)} dispatches.", "",
+            "| kernel | calls | total (ms) | avg (us) | % |", "|---|---|---|---|---|"]
+    for r in rows:
+        if float(r["Percentage"]) < 0.05:
+            continue
+        out.append(f"| `{short_name(r['Kernel_Name'] if 'Kernel_Name' in r else r['Name'])}` | {r['Calls']} | "
+                   f"{int(r['TotalDurationNs']) / 1e6:.1f} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['Percentage']):.2f} |")
+    return "\n".join(out) + "\n"
+
+
+def _per_kernel(csv_path: str, counter: str) -> dict[str, list[float]]:
+    agg: dict[str, list[float]] = defaultdict(list)
+    for r in csv.DictReader(open(csv_path)):
+        if r["Counter_Name"] == counter:
+            agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return agg
+
+
+def _pick(agg: dict[str, list[float]], regex: str) -> list[float]:
+    vals: list[float] = []
+    for name, v in agg.items():
+        if re.search(regex, name):
+            vals += v
+    return vals
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, calib: str, calib_bytes: float) -> dict:
+    """Calibrated HBM bytes per dispatch of the kernels matching `kernel`."""
+    f = _per_kernel(fetch_csv, "FETCH_SIZE")
+    w = _per_kernel(write_csv, "WRITE_SIZE")
+    fk, wk = _pick(f, kernel), _pick(w, kernel)
+    fc, wc = _pick(f, calib), _pick(w, calib)
+    if not fk or not wk or not fc or not wc:
+        raise SystemExit("kernel or calibration kernel missing from the counter files")
+    # the calibration kernel reads and writes calib_bytes; counters are in KiB
+    f_scale = calib_bytes / (max(fc) * 1024.0)
+    w_scale = calib_bytes / (max(wc) * 1024.0)
+    fetch = sum(fk) / len(fk) * 1024.0 * f_scale
+    write = sum(wk) / len(wk) * 1024.0 * w_scale
+    return {"dispatches": len(fk), "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+            "bytes_per_launch": fetch + write, "fetch_scale": f_scale, "write_scale": w_scale,
+            "raw_fetch_kib_per_launch": sum(fk) / len(fk), "raw_write_kib_per_launch": sum(wk) / len(wk)}
+
+
+def traffic_markdown(t: dict, label: str, title: str, command: str, note: str = "") -> str:
+    block = dict(t, kernel=label, source_sha256=kernel_source_sha256())
+    out = [f"# {title}", ""]
+    if note:
+        out += [note, ""]
+    out += ["Commands (from the repository root; one counter per run):", "", "```", command, "```", "",
+            f"* FETCH_SIZE scale (1 GiB copy-like kernel): x{t['fetch_scale']:.3f}; "
+            f"WRITE_SIZE scale: x{t['write_scale']:.3f}",
+            f"* `{label}`: {t['dispatches']} dispatches; per dispatch "
+            f"{t['fetch_bytes_per_launch'] / 1e9:.3f} GB read + {t['write_bytes_per_launch'] / 1e9:.3f} GB written "
+            f"= {t['bytes_per_launch'] / 1e9:.3f} GB (raw {t['raw_fetch_kib_per_launch']:.0f} KiB fetched, "
+            f"{t['raw_write_kib_per_launch']:.0f} KiB written)", "",
+            f"```{TRAFFIC_TAG}", json.dumps(block, indent=1), "```", ""]
+    return "\n".join(out)
+
+
+def load_traffic(profiles_dir: str, label: str) -> dict | None:
+    """The traffic block for `label` measured on the current kernel source, if any."""
+    if not os.path.isdir(profiles_dir):
+        return None
+    sha = kernel_source_sha256()
+    for fn in sorted(os.listdir(profiles_dir)):
+        if not fn.endswith(".md"):
+            continue
+        text = open(os.path.join(profiles_dir, fn)).read()
+        for m in re.finditer(r"```" + TRAFFIC_TAG + r"\n(.*?)\n```", text, re.S):
+            try:
+                block = json.loads(m.group(1))
+            except json.JSONDecodeError:
+                continue
+            if block.get("kernel") == label and block.get("source_sha256") == sha:
+                return dict(block, file=fn)
+    return None
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_csv")
+    t.add_argument("write_csv")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--label", required=True)
+    t.add_argument("--calib", required=True)
+    t.add_argument("--calib-bytes", type=float, default=float(1 << 30))
+    for p in (s, t):
+        p.add_argument("--title", required=True)
+        p.add_argument("--command", required=True)
+        p.add_argument("--note", default="")
+        p.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        text = stats_markdown(a.csv, a.title, a.command, a.note)
+    else:
+        text = traffic_markdown(traffic(a.fetch_csv, a.write_csv, a.kernel, a.calib, a.calib_bytes), a.label,
+                                a.title, a.command, a.note)
+    with open(a.out, "w") as f:
+        f.write(text)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -78,3 +78,53 @@ WORKLOADS = {
     # 512x512 (95% zeros) times 512x512 (60% zeros), N = 2^16, 24 Q primes, 3 P primes
     "large": Workload("large", 16, 24, 3, 3, 3, 512, 512, 512, 0.95, 0.60, ("uniform", -0.1, 0.1), ("halfnormal",)),
 }
+
+
+@dataclass(frozen=True)
+class BatchWorkload:
+    """Many independent square matmuls of uneven size and sparsity under one parameter set."""
+    name: str
+    log_n: int
+    n_q: int
+    n_p: int
+    alpha: int
+    rot_digits: int
+    count: int
+    sizes: tuple
+    sparsity: tuple  # (low, high) of the per-operand uniform draw
+    seed: int
+
+    def specs(self):
+        """[(n, sparsity_a, sparsity_b)] for every matmul, from one seeded stream."""
+        r = np.random.Generator(np.random.PCG64(self.seed))
+        out = []
+        for _ in range(self.count):
+            n = int(r.choice(self.sizes))
+            sa, sb = (float(x) for x in r.uniform(self.sparsity[0], self.sparsity[1], size=2))
+            out.append((n, sa, sb))
+        return out
+
+    def operands(self, i: int, spec=None):
+        n, sa, sb = spec if spec is not None else self.specs()[i]
+        s = self.seed * 100000 + 4 * i
+        a = sparse_dense(n, n, sa, "uniform", s, s + 2)
+        b = sparse_dense(n, n, sb, "uniform", s + 1, s + 3)
+        return a, b
+
+
+BATCH_WORKLOADS = {
+    # 64 matmuls, square sizes from {32, 64, 128, 256}, per-operand sparsity U[0.5, 0.95], values
+    # U[-1, 1]; N = 2^16, 24 x 50-bit Q primes, 3 x 60-bit P primes, alpha = 3, 3 rotation digits
+    "batch": BatchWorkload("batch", 16, 24, 3, 3, 3, 64, (32, 64, 128, 256), (0.5, 0.95), 1),
+}
+
+
+def poisson_arrivals(rate: float, window_s: float, seed: int) -> np.ndarray:
+    """Arrival times in [0, window_s) of a Poisson process of the given rate (seeded)."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    t, out = 0.0, []
+    while True:
+        t += float(r.exponential(1.0 / rate))
+        if t >= window_s:
+            return np.asarray(out)
+        out.append(t)

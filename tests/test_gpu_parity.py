@@ -217,6 +217,29 @@ def test_spmspm_batch_matches_individual_and_oracle(fhe):
     assert (ctx.export(Cb[0], 0) == ref[0].data).all()
 
 
+def test_spmspm_batch_pair_ranges_match_single_ranges(fhe):
+    """Batched form restricted to per-matmul pair ranges equals fhe_spmspm_pairs on the same ranges."""
+    op, okeys, ctx, sk = _setup(fhe, OP_PARAMS[0])
+    shapes = [(5, 6, 4, 0.3, 0.4), (4, 7, 5, 0.5, 0.2), (6, 3, 6, 0.2, 0.5)]
+    As, Bs = [], []
+    for t, (m, k, n, sa, sb) in enumerate(shapes):
+        a = synth.sparse_dense(m, k, sa, "uniform", 150 + t, 250 + t)
+        b = synth.sparse_dense(k, n, sb, "uniform", 350 + t, 450 + t)
+        As.append(ctx.encrypt_csr(sk, m, k, *synth.to_csr(a), seed=73 + 10 * t))
+        Bs.append(ctx.encrypt_csc(sk, k, n, *synth.to_csc(b), seed=74 + 10 * t))
+    F = [ctx.plan_stats(A, B).matched_pairs for A, B in zip(As, Bs)]
+    ranges = [(0, F[0] // 2), (F[1] // 3, F[1]), (2, 2)]  # prefix, suffix, empty
+    _say(f"[batch-ranges] F={F} ranges={ranges}")
+    Cb = ctx.spmspm_batch(As, Bs, pair_ranges=ranges)
+    for t, (lo, hi) in enumerate(ranges):
+        Ci = ctx.spmspm_pairs(As[t], Bs[t], lo, hi)
+        for c in range(Ci.info()["chunks"]):
+            assert (ctx.export(Cb[t], c) == ctx.export(Ci, c)).all(), (t, c)
+    assert (ctx.export(Cb[2], 0) == 0).all()
+    with pytest.raises(fhe.FheError):
+        ctx.spmspm_batch(As[:1], Bs[:1], pair_ranges=[(3, 1)])
+
+
 def test_spmspm_full_sparsity_is_zero(fhe):
     op, _, ctx, sk = _setup(fhe, OP_PARAMS[0])
     z = np.zeros((4, 4))
