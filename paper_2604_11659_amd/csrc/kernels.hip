@@ -172,25 +172,37 @@ struct FpArith {
 // Thread group g holds x = (xh << (lo + M)) | (i << lo) | xl for i in [0, 2^M). At the stage on bit
 // b = lo + bl the twiddle index 2^s + floor(j / 2^(b+1)) depends on i only through i >> (bl + 1), so
 // each of the 2^(M - bl - 1) twiddles of the stage is loaded once and shared by 2^bl butterflies.
-template <int M, bool kInv, int kPhase, class A, int EPT, int NT>
+// kWave: every wavefront owns C / (NT / 64) of the tile's sub-transforms (columns in phase 1, rows in
+// phase 2) and only touches their LDS slots, so rounds need a wavefront-level sync only.
+template <int NT>
+struct WaveSplit {
+  static constexpr uint32_t kWaves = NT / 64;
+  static constexpr uint32_t kLogWaves = kWaves == 1 ? 0 : kWaves == 2 ? 1 : kWaves == 4 ? 2 : kWaves == 8 ? 3 : 4;
+};
+
+template <int M, bool kInv, int kPhase, class A, int EPT, int NT, bool kWave>
 __device__ __forceinline__ void ntt_round(uint64_t* lds, const A& ar, const typename A::W* tw2, uint32_t lo,
                                           uint32_t k, uint32_t logC, uint32_t sbase, uint64_t j0) {
   constexpr uint32_t GM = 1u << M, G = EPT >> M;
+  constexpr uint32_t TH = kWave ? 64 : NT, LW = kWave ? WaveSplit<NT>::kLogWaves : 0;
+  const uint32_t lane = kWave ? (threadIdx.x & 63) : threadIdx.x;
+  const uint32_t wbase = kWave ? (threadIdx.x >> 6) << (logC - LW) : 0;  // first sub-transform of this wave
+  const uint32_t logCw = logC - LW;
   typename A::T r[EPT];
   uint32_t xh[G], xl[G], cc[G];
 #pragma unroll
   for (uint32_t u = 0; u < G; ++u) {
-    const uint32_t gid = u * NT + threadIdx.x;
+    const uint32_t gid = u * TH + lane;
     if (kPhase == 1) {
-      cc[u] = gid & ((1u << logC) - 1);
-      const uint32_t rest = gid >> logC;
+      cc[u] = wbase + (gid & ((1u << logCw) - 1));
+      const uint32_t rest = gid >> logCw;
       xl[u] = rest & ((1u << lo) - 1);
       xh[u] = rest >> lo;
     } else {
       xl[u] = gid & ((1u << lo) - 1);
       const uint32_t rest = gid >> lo, nh = k - lo - M;
       xh[u] = rest & ((1u << nh) - 1);
-      cc[u] = rest >> nh;
+      cc[u] = wbase + (rest >> nh);
     }
     const uint32_t xb = (xh[u] << (lo + M)) | xl[u];
 #pragma unroll
@@ -234,7 +246,14 @@ __device__ __forceinline__ void ntt_round(uint64_t* lds, const A& ar, const type
   }
 }
 
-template <bool kInv, int kPhase, class A, int EPT, int NT>
+// Wavefront-level sync for LDS data exchanged among the lanes of one wavefront.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool kInv, int kPhase, class A, int EPT, int NT, bool kWave = false>
 __device__ __forceinline__ void ntt_rounds(uint64_t* lds, const A& ar, const typename A::W* tw2, uint32_t k,
                                            uint32_t logC, uint32_t sbase, uint64_t j0) {
   // Rounds of MB = log2(EPT) bits. Forward: chunks from the top ([k-MB, k), [k-2MB, k-MB), ...,
@@ -247,15 +266,18 @@ __device__ __forceinline__ void ntt_rounds(uint64_t* lds, const A& ar, const typ
     const uint32_t lo = hi >= MB ? hi - MB : 0;
     switch (hi - lo) {
       case 4:
-        if constexpr (MB >= 4) ntt_round<4, kInv, kPhase, A, EPT, NT>(lds, ar, tw2, lo, k, logC, sbase, j0);
+        if constexpr (MB >= 4) ntt_round<4, kInv, kPhase, A, EPT, NT, kWave>(lds, ar, tw2, lo, k, logC, sbase, j0);
         break;
       case 3:
-        if constexpr (MB >= 3) ntt_round<3, kInv, kPhase, A, EPT, NT>(lds, ar, tw2, lo, k, logC, sbase, j0);
+        if constexpr (MB >= 3) ntt_round<3, kInv, kPhase, A, EPT, NT, kWave>(lds, ar, tw2, lo, k, logC, sbase, j0);
         break;
-      case 2: ntt_round<2, kInv, kPhase, A, EPT, NT>(lds, ar, tw2, lo, k, logC, sbase, j0); break;
-      default: ntt_round<1, kInv, kPhase, A, EPT, NT>(lds, ar, tw2, lo, k, logC, sbase, j0); break;
+      case 2: ntt_round<2, kInv, kPhase, A, EPT, NT, kWave>(lds, ar, tw2, lo, k, logC, sbase, j0); break;
+      default: ntt_round<1, kInv, kPhase, A, EPT, NT, kWave>(lds, ar, tw2, lo, k, logC, sbase, j0); break;
     }
-    __syncthreads();
+    if (kWave)
+      wave_sync();
+    else
+      __syncthreads();
   }
 }
 
@@ -264,6 +286,7 @@ __global__ __launch_bounds__(kThreads) void k_ntt(LimbBatch lb, const ModInfo* _
                                                  const typename A::W* __restrict__ tw, uint32_t logN, uint32_t k1,
                                                  bool from_src) {
   extern __shared__ uint64_t lds[];
+  constexpr uint32_t kPer = kNttE / kThreads;
   const uint32_t N = 1u << logN, tiles = N >> kNttLogE;
   const uint32_t limb = blockIdx.x / tiles, tile = blockIdx.x - limb * tiles;
   const uint32_t poly = limb / lb.limbs, e = limb - poly * lb.limbs;
@@ -275,24 +298,42 @@ __global__ __launch_bounds__(kThreads) void k_ntt(LimbBatch lb, const ModInfo* _
   ar.init(m);
   const uint32_t k = kPhase == 1 ? k1 : logN - k1, k2 = logN - k1;
   const uint32_t logC = kNttLogE - k, C = 1u << logC;
-  const uint64_t j0 = (uint64_t)tile * kNttE;
-#pragma unroll
-  for (uint32_t r_ = 0; r_ < kNttE / kThreads; ++r_) {
-    const uint32_t idx = threadIdx.x + r_ * kThreads;
-    const uint32_t g = kPhase == 1 ? ((idx >> logC) << k2) + (tile << logC) + (idx & (C - 1)) : (uint32_t)j0 + idx;
-    lds[pad_idx(idx)] = ar.lds_in(in[g]);
-  }
-  __syncthreads();
+  const uint32_t j0 = tile * kNttE;
   const uint64_t toff = (uint64_t)mi * 4 * N + (kInv ? 2 * (uint64_t)N : 0);
-  ntt_rounds<kInv, kPhase, A, 16, kThreads>(lds, ar, tw + toff, k, logC, kPhase == 1 ? 0 : k1, j0);
-  const uint32_t tid = opaque(threadIdx.x);
+  if (kPhase == 2) {
+    // rows are contiguous: every wavefront loads, transforms and stores its own rows
+    const uint32_t wb = (threadIdx.x >> 6) * (kNttE / (kThreads / 64)), lane = threadIdx.x & 63;
 #pragma unroll
-  for (uint32_t r_ = 0; r_ < kNttE / kThreads; ++r_) {
-    const uint32_t idx = tid + r_ * kThreads;
-    const uint32_t g = kPhase == 1 ? ((idx >> logC) << k2) + (tile << logC) + (idx & (C - 1)) : (uint32_t)j0 + idx;
-    uint64_t v = ar.lds_out(lds[pad_idx(idx)]);
-    if (kInv && kPhase == 1) v = shoup_mul(v, m.n_inv, m.n_inv_shoup, m.q);
-    a[g] = v;
+    for (uint32_t r_ = 0; r_ < kPer; ++r_) {
+      const uint32_t idx = wb + lane + r_ * 64;
+      lds[pad_idx(idx)] = ar.lds_in(in[j0 + idx]);
+    }
+    wave_sync();
+    ntt_rounds<kInv, 2, A, 16, kThreads, true>(lds, ar, tw + toff, k, logC, k1, j0);
+    const uint32_t ln = opaque(lane);
+#pragma unroll
+    for (uint32_t r_ = 0; r_ < kPer; ++r_) {
+      const uint32_t idx = wb + ln + r_ * 64;
+      a[j0 + idx] = ar.lds_out(lds[pad_idx(idx)]);
+    }
+  } else {
+    // columns are strided: coalesced loads and stores across the workgroup, rounds per wavefront
+#pragma unroll
+    for (uint32_t r_ = 0; r_ < kPer; ++r_) {
+      const uint32_t idx = threadIdx.x + r_ * kThreads;
+      lds[pad_idx(idx)] = ar.lds_in(in[((idx >> logC) << k2) + (tile << logC) + (idx & (C - 1))]);
+    }
+    __syncthreads();
+    ntt_rounds<kInv, 1, A, 16, kThreads, true>(lds, ar, tw + toff, k, logC, 0, 0);
+    __syncthreads();
+    const uint32_t tid = opaque(threadIdx.x);
+#pragma unroll
+    for (uint32_t r_ = 0; r_ < kPer; ++r_) {
+      const uint32_t idx = tid + r_ * kThreads;
+      uint64_t v = ar.lds_out(lds[pad_idx(idx)]);
+      if (kInv) v = shoup_mul(v, m.n_inv, m.n_inv_shoup, m.q);
+      a[((idx >> logC) << k2) + (tile << logC) + (idx & (C - 1))] = v;
+    }
   }
 }
 
@@ -323,6 +364,9 @@ __device__ __forceinline__ void ntt_p2_inner_body(
   A ar;
   ar.init(m);
   const typename A::W* w = tw + (uint64_t)mi * 4 * N;
+  // every wavefront owns whole rows of the tile (contiguous): loads, rounds, products and stores
+  // stay inside the wavefront, so no workgroup barrier is needed
+  const uint32_t wb = (threadIdx.x >> 6) * (kNttE / (kInnerThreads / 64)), lane = threadIdx.x & 63;
   typename A::Acc acc0[kPer], acc1[kPer];
 #pragma unroll
   for (uint32_t r = 0; r < kPer; ++r) acc0[r] = acc1[r] = 0;
@@ -334,7 +378,7 @@ __device__ __forceinline__ void ntt_p2_inner_body(
       const uint64_t* x = in + (uint64_t)b * in_stride + (uint64_t)e * N + j0;
 #pragma unroll
       for (uint32_t r = 0; r < kPer; ++r) {
-        const uint32_t idx = threadIdx.x + r * kInnerThreads;
+        const uint32_t idx = wb + lane + r * 64;
         const typename A::T xv = ar.from_u64(x[idx]);
         acc0[r] = ar.kacc(acc0[r], xv, kb[idx]);
         acc1[r] = ar.kacc(acc1[r], xv, ka[idx]);
@@ -342,22 +386,22 @@ __device__ __forceinline__ void ntt_p2_inner_body(
     } else {
       const uint32_t row = e < lo ? e : e - cnt;
       const uint64_t* src = ext + (((uint64_t)j * B + b) * R + row) * N + j0;
-    #pragma unroll
-      for (uint32_t r_ = 0; r_ < kNttE / kInnerThreads; ++r_) {
-        const uint32_t idx = threadIdx.x + r_ * kInnerThreads;
-        lds[pad_idx(idx)] = ar.lds_in(src[idx]);
-      }
-      __syncthreads();
-      ntt_rounds<false, 2, A, 8, kInnerThreads>(lds, ar, w, k, logC, k1, j0);
-      const uint32_t tid = opaque(threadIdx.x);
 #pragma unroll
       for (uint32_t r = 0; r < kPer; ++r) {
-        const uint32_t idx = tid + r * kInnerThreads;
+        const uint32_t idx = wb + lane + r * 64;
+        lds[pad_idx(idx)] = ar.lds_in(src[idx]);
+      }
+      wave_sync();
+      ntt_rounds<false, 2, A, 8, kInnerThreads, true>(lds, ar, w, k, logC, k1, j0);
+      const uint32_t ln = opaque(lane);
+#pragma unroll
+      for (uint32_t r = 0; r < kPer; ++r) {
+        const uint32_t idx = wb + ln + r * 64;
         const typename A::T xv = ar.ld(lds[pad_idx(idx)]);
         acc0[r] = ar.kacc(acc0[r], xv, kb[idx]);
         acc1[r] = ar.kacc(acc1[r], xv, ka[idx]);
       }
-      __syncthreads();
+      wave_sync();
     }
     if ((j & 3) == 3) {
 #pragma unroll
@@ -371,7 +415,7 @@ __device__ __forceinline__ void ntt_p2_inner_body(
   uint64_t* u1 = u + ((uint64_t)(b * 2 + 1) * next + e) * N + j0;
 #pragma unroll
   for (uint32_t r = 0; r < kPer; ++r) {
-    const uint32_t idx = threadIdx.x + r * kInnerThreads;
+    const uint32_t idx = wb + lane + r * 64;
     u0[idx] = ar.kfinal(acc0[r]);
     u1[idx] = ar.kfinal(acc1[r]);
   }
@@ -417,23 +461,25 @@ __global__ __launch_bounds__(kThreads) void k_ntt_p2_combine(uint32_t nl, uint32
   const uint64_t j0 = (uint64_t)tile * kNttE;
   const uint32_t k = logN - k1, logC = kNttLogE - k;
   const uint64_t* src = conv + ((uint64_t)bc * nl + i) * N + j0;
+  constexpr uint32_t kPer = kNttE / kThreads;
+  const uint32_t wb = (threadIdx.x >> 6) * (kNttE / (kThreads / 64)), lane = threadIdx.x & 63;
 #pragma unroll
-  for (uint32_t r_ = 0; r_ < kNttE / kThreads; ++r_) {
-    const uint32_t idx = threadIdx.x + r_ * kThreads;
+  for (uint32_t r_ = 0; r_ < kPer; ++r_) {
+    const uint32_t idx = wb + lane + r_ * 64;
     lds[pad_idx(idx)] = ar.lds_in(src[idx]);
   }
-  __syncthreads();
+  wave_sync();
   const typename A::W* w = tw + (uint64_t)i * 4 * N;
-  ntt_rounds<false, 2, A, 16, kThreads>(lds, ar, w, k, logC, k1, j0);
+  ntt_rounds<false, 2, A, 16, kThreads, true>(lds, ar, w, k, logC, k1, j0);
   const uint64_t* pinv = tab + 2 * K + 2 * (uint64_t)K * nq + 2 * i;
   const uint64_t* uu = u + ((uint64_t)bc * next + i) * N + j0;
   const uint64_t* ad = add[bc];
   if (ad) ad += (uint64_t)i * N + j0;
   uint64_t* o = out[b] + ((uint64_t)c * nl + i) * N + j0;
-  const uint32_t tid = opaque(threadIdx.x);
+  const uint32_t ln = opaque(lane);
 #pragma unroll
-  for (uint32_t r_ = 0; r_ < kNttE / kThreads; ++r_) {
-    const uint32_t idx = tid + r_ * kThreads;
+  for (uint32_t r_ = 0; r_ < kPer; ++r_) {
+    const uint32_t idx = wb + ln + r_ * 64;
     uint64_t v = shoup_mul(sub_mod(uu[idx], ar.lds_out(lds[pad_idx(idx)]), m.q), pinv[0], pinv[1], m.q);
     if (ad) v = add_mod(v, ad[idx], m.q);
     o[idx] = v;
@@ -595,7 +641,8 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
     }
     __syncthreads();
     const double* w = twf + (uint64_t)(lo + i) * 4 * N + 2 * (uint64_t)N;
-    ntt_rounds<true, 1, FpArith, EPT, NT>(work, ar, w, k1, logC, 0, 0);
+    ntt_rounds<true, 1, FpArith, EPT, NT, true>(work, ar, w, k1, logC, 0, 0);
+    __syncthreads();  // rounds ran per wavefront; the loops below are workgroup-strided
     const double c = (double)shoup_mul(m.n_inv, blk[2 * i], blk[2 * i + 1], m.q);
     const double cq = c / ar.q;
   #pragma unroll
@@ -629,7 +676,8 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
       FpArith ar;
       ar.init(m);
       const double* w = twf + (uint64_t)mi * 4 * N;
-      ntt_rounds<false, 1, FpArith, EPT, NT>(work, ar, w, k1, logC, 0, 0);
+      ntt_rounds<false, 1, FpArith, EPT, NT, true>(work, ar, w, k1, logC, 0, 0);
+      __syncthreads();  // rounds ran per wavefront; the loops below are workgroup-strided
     #pragma unroll
       for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
         const uint32_t idx = threadIdx.x + r_ * NT;
@@ -639,7 +687,8 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
       IntArith ar;
       ar.init(m);
       const uint64_t* w = twi + (uint64_t)mi * 4 * N;
-      ntt_rounds<false, 1, IntArith, EPT, NT>(work, ar, w, k1, logC, 0, 0);
+      ntt_rounds<false, 1, IntArith, EPT, NT, true>(work, ar, w, k1, logC, 0, 0);
+      __syncthreads();  // rounds ran per wavefront; the loops below are workgroup-strided
     #pragma unroll
       for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
         const uint32_t idx = threadIdx.x + r_ * NT;
@@ -679,7 +728,8 @@ __global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, ui
     }
     __syncthreads();
     const uint64_t* w = twi + (uint64_t)(nq + kk) * 4 * N + 2 * (uint64_t)N;
-    ntt_rounds<true, 1, IntArith, EPT, NT>(work, ar, w, k1, logC, 0, 0);
+    ntt_rounds<true, 1, IntArith, EPT, NT, true>(work, ar, w, k1, logC, 0, 0);
+    __syncthreads();  // rounds ran per wavefront; the loops below are workgroup-strided
   #pragma unroll
     for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
       const uint32_t idx = threadIdx.x + r_ * NT;
@@ -709,7 +759,8 @@ __global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, ui
     FpArith ar;
     ar.init(m);
     const double* w = twf + (uint64_t)i * 4 * N;
-    ntt_rounds<false, 1, FpArith, EPT, NT>(work, ar, w, k1, logC, 0, 0);
+    ntt_rounds<false, 1, FpArith, EPT, NT, true>(work, ar, w, k1, logC, 0, 0);
+    __syncthreads();  // rounds ran per wavefront; the loops below are workgroup-strided
     uint64_t* o = conv + ((uint64_t)bc * nl + i) * N;
   #pragma unroll
     for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
@@ -765,6 +816,103 @@ __global__ __launch_bounds__(kThreads) void k_rescale_combine(uint32_t B, uint32
     const uint64_t q = mods[i].q;
     const uint64_t x = sub_mod(in[b][((uint64_t)c * nl + i) * N + k], w[t], q);
     out[b][((uint64_t)c * no + i) * N + k] = shoup_mul(x, inv[2 * i], inv[2 * i + 1], q);
+  }
+}
+
+// Rescale, column part: per (polynomial bc, tile), the dropped limb (row phase of its INTT already
+// applied, in tmp [BC][N]) goes through the inverse column phase mod q_l and N^-1, is centred
+// (v' = v - q_l when v > (q_l - 1)/2), and v' (|v'| < q_l/2 < q_i) goes through the forward column
+// phase of every remaining limb i; results in w [BC][nl-1][N].
+template <int LOG_E, int NT>
+__global__ __launch_bounds__(NT) void k_rescale_cols(uint32_t nl, uint32_t logN, uint32_t k1,
+                                                    const ModInfo* __restrict__ mods, const double* __restrict__ twf,
+                                                    const uint64_t* __restrict__ tmp, uint64_t* __restrict__ w) {
+  constexpr uint32_t E = 1u << LOG_E, EPT = E / NT, EP = E + (E >> 4);
+  extern __shared__ uint64_t lds[];
+  uint64_t* work = lds;
+  double* vs = (double*)(lds + EP);
+  const uint32_t N = 1u << logN, tiles = N >> LOG_E;
+  const uint32_t tile = blockIdx.x % tiles, bc = blockIdx.x / tiles;
+  const uint32_t no = nl - 1, k2 = logN - k1, logC = LOG_E - k1;
+  {
+    const ModInfo m = mods[no];
+    FpArith ar;
+    ar.init(m);
+    const uint64_t* src = tmp + ((uint64_t)bc << logN);
+#pragma unroll
+    for (uint32_t r_ = 0; r_ < EPT; ++r_) {
+      const uint32_t idx = threadIdx.x + r_ * NT;
+      work[pad_idx(idx)] = ar.lds_in(src[col_index(idx, logC, k2, tile)]);
+    }
+    __syncthreads();
+    ntt_rounds<true, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)no * 4 * N + 2 * (uint64_t)N, k1, logC, 0, 0);
+    __syncthreads();
+    const double c = (double)m.n_inv, cq = c / ar.q;
+#pragma unroll
+    for (uint32_t r_ = 0; r_ < EPT; ++r_) {
+      const uint32_t idx = threadIdx.x + r_ * NT;
+      double v = ar.mulc(ar.ld(work[pad_idx(idx)]), c, cq);  // |v| <= 0.7 q_l
+      v = v < 0.0 ? v + ar.q : v;                             // [0, q_l)
+      vs[idx] = v > 0.5 * (ar.q - 1.0) ? v - ar.q : v;        // centred
+    }
+  }
+  for (uint32_t i = 0; i < no; ++i) {
+    const ModInfo m = mods[i];
+    FpArith ar;
+    ar.init(m);
+#pragma unroll
+    for (uint32_t r_ = 0; r_ < EPT; ++r_) {
+      const uint32_t idx = threadIdx.x + r_ * NT;
+      work[pad_idx(idx)] = ar.st(vs[idx]);
+    }
+    __syncthreads();
+    ntt_rounds<false, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)i * 4 * N, k1, logC, 0, 0);
+    __syncthreads();
+    uint64_t* o = w + ((uint64_t)bc * no + i) * N;
+    const uint32_t tid = opaque(threadIdx.x);
+#pragma unroll
+    for (uint32_t r_ = 0; r_ < EPT; ++r_) {
+      const uint32_t idx = tid + r_ * NT;
+      o[col_index(idx, logC, k2, tile)] = ar.lds_out(work[pad_idx(idx)]);
+    }
+  }
+}
+
+// Rescale, row part: per (polynomial bc = b * ncomp + c, remaining limb i, tile), the forward row
+// phase of w in LDS fused with out = (in - w) q_l^-1 mod q_i (NTT domain), per wavefront.
+__global__ __launch_bounds__(kThreads) void k_rescale_rows(uint32_t ncomp, uint32_t nl, uint32_t nq, uint32_t logN,
+                                                          uint32_t k1, const ModInfo* __restrict__ mods,
+                                                          const double* __restrict__ twf,
+                                                          const uint64_t* __restrict__ tab,
+                                                          const uint64_t* const* __restrict__ in,
+                                                          const uint64_t* __restrict__ w,
+                                                          uint64_t* const* __restrict__ out) {
+  extern __shared__ uint64_t lds[];
+  constexpr uint32_t kPer = kNttE / kThreads;
+  const uint32_t N = 1u << logN, tiles = N >> kNttLogE, no = nl - 1;
+  const uint32_t tile = blockIdx.x % tiles, li = blockIdx.x / tiles;
+  const uint32_t i = li % no, bc = li / no, b = bc / ncomp, c = bc - b * ncomp;
+  const ModInfo m = mods[i];
+  FpArith ar;
+  ar.init(m);
+  const uint32_t j0 = tile * kNttE, k = logN - k1, logC = kNttLogE - k;
+  const uint32_t wb = (threadIdx.x >> 6) * (kNttE / (kThreads / 64)), lane = threadIdx.x & 63;
+  const uint64_t* src = w + ((uint64_t)bc * no + i) * N + j0;
+#pragma unroll
+  for (uint32_t r_ = 0; r_ < kPer; ++r_) {
+    const uint32_t idx = wb + lane + r_ * 64;
+    lds[pad_idx(idx)] = ar.lds_in(src[idx]);
+  }
+  wave_sync();
+  ntt_rounds<false, 2, FpArith, 16, kThreads, true>(lds, ar, twf + (uint64_t)i * 4 * N, k, logC, k1, j0);
+  const uint64_t* inv = tab + 2 * ((uint64_t)no * nq + i);
+  const uint64_t* x = in[b] + ((uint64_t)c * nl + i) * N + j0;
+  uint64_t* o = out[b] + ((uint64_t)c * no + i) * N + j0;
+  const uint32_t ln = opaque(lane);
+#pragma unroll
+  for (uint32_t r_ = 0; r_ < kPer; ++r_) {
+    const uint32_t idx = wb + ln + r_ * 64;
+    o[idx] = shoup_mul(sub_mod(x[idx], ar.lds_out(lds[pad_idx(idx)]), m.q), inv[0], inv[1], m.q);
   }
 }
 
@@ -1233,6 +1381,29 @@ void rescale(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const 
   uint64_t* tmp = ws;                       // [BC][N]
   uint64_t* w = ws + (size_t)BC * N;        // [BC][nl-1][N]
   FHE_LAUNCH("copy_last", e8 * 2, k_copy_last, grid_for((uint64_t)BC * N), 0, st, B, ncomp, nl, p.logN, in, tmp);
+  if (cols_fusable(ctx, 1)) {
+    // row phase of the dropped limb's INTT; column phases and the broadcast in one kernel; row
+    // phase of the broadcast fused with the combine
+    ntt_inverse_rows(ctx, LimbBatch{tmp, 1, BC, N, 0, nl - 1}, st);
+    const uint32_t le = cols_log_e(p);
+    const size_t lds_rs = cols_lds_bytes(le, 1);
+    const uint64_t grid = (uint64_t)BC * (N >> le);
+    const double* twf = (const double*)ctx->t.twf.get();
+    if (grid >= (1ull << 31)) fail(FHE_EINVAL, "rescale batch too large");
+    if (le == 11) {
+      allow_lds((const void*)k_rescale_cols<11, 256>, lds_rs);
+      FHE_LAUNCH_T("rescale_cols", e8 * nl, (k_rescale_cols<11, 256>), grid, 256, lds_rs, st, nl, p.logN, p.k1,
+                   mods_of(ctx), twf, tmp, w);
+    } else {
+      allow_lds((const void*)k_rescale_cols<12, 512>, lds_rs);
+      FHE_LAUNCH_T("rescale_cols", e8 * nl, (k_rescale_cols<12, 512>), grid, 512, lds_rs, st, nl, p.logN, p.k1,
+                   mods_of(ctx), twf, tmp, w);
+    }
+    const size_t lds = kNttLdsElems * sizeof(uint64_t);
+    FHE_LAUNCH("rescale_rows", e8 * 3 * (nl - 1), k_rescale_rows, (uint64_t)BC * (nl - 1) * (N >> kNttLogE), lds, st,
+               ncomp, nl, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.rescale.u64(), in, w, out);
+    return;
+  }
   ntt_inverse(ctx, LimbBatch{tmp, 1, BC, N, 0, nl - 1}, st);
   FHE_LAUNCH("rescale_bcast", e8 * nl, k_rescale_bcast, grid_for((uint64_t)BC * (nl - 1) * N), 0, st, BC, nl, p.logN,
              mods_of(ctx), tmp, w);
