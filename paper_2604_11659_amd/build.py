@@ -21,7 +21,7 @@ ARCH = os.environ.get("FHE_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-result",
+    "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-result", "-Wno-pass-failed",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 

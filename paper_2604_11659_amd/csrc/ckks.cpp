@@ -1,4 +1,6 @@
 // Context tables, key generation, encryption/decryption and single-ciphertext operations.
+#include <cstdlib>
+
 #include "ckks.h"
 
 #include <cmath>
@@ -67,7 +69,14 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
   p.alpha = d->alpha;
   p.rot_digits = d->rot_digits;
   p.rot_bits = (int)((p.logN - 1 + p.rot_digits - 1) / p.rot_digits);
-  p.k1 = p.logN / 2;
+  // NTT split: rows of 2^9 once N >= 2^15 (the column phase then has whole 3-stage rounds and
+  // wider row segments), halves below. FHE_NTT_K1 overrides it (any split gives the same
+  // transform; it only changes how the stages are grouped).
+  p.k1 = p.logN >= 15 ? p.logN - 9 : p.logN / 2;
+  if (const char* e = std::getenv("FHE_NTT_K1")) {
+    const int v = std::atoi(e);
+    if (v >= (int)p.logN - 9 && v <= 9 && v >= 1 && v < (int)p.logN) p.k1 = (uint32_t)v;
+  }
   const uint64_t m = 2ull * p.N;
   std::vector<uint64_t> qs = primes_below(d->q_bits, p.nq, m);
   if ((int)qs.size() != p.nq) fail(FHE_EINVAL, "not enough Q primes of the requested size");

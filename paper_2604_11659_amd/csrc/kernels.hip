@@ -260,6 +260,7 @@ __device__ __forceinline__ void ntt_rounds(uint64_t* lds, const A& ar, const typ
   // [0, rem)); inverse: the same chunks in reverse order.
   constexpr uint32_t MB = EPT == 16 ? 4 : (EPT == 8 ? 3 : 2);
   const uint32_t nr = (k + MB - 1) / MB;
+#pragma unroll
   for (uint32_t rr = 0; rr < nr; ++rr) {
     const uint32_t rf = kInv ? nr - 1 - rr : rr;
     const uint32_t hi = k - MB * rf;
@@ -606,52 +607,66 @@ __device__ __forceinline__ uint32_t col_index(uint32_t idx, uint32_t logC, uint3
   return ((idx >> logC) << k2) + (tile << logC) + (idx & ((1u << logC) - 1));
 }
 
-// ModUp fused with the column phases around it. Workgroup (digit j, item b, tile): the digit's limbs
-// (row phase of the inverse NTT already applied, in dc2 [B][nl][N]) go through the inverse column
-// phase in LDS and are scaled to y_i = d_i Dhat_i^-1 mod q_i (N^-1 folded in); then for every limb
-// outside the digit the converted row sum_i y_i (Dhat_i mod t) mod t is formed in LDS, goes through the
-// forward column phase of its modulus and is written to ext (layout as k_modup). The coefficient-
-// domain digits and converted rows never reach HBM.
-// LDS: one padded work tile plus alpha tiles of y.
-template <int LOG_E, int NT>
+// Column-phase slots owned by one wavefront in the fused column kernels: wavefront w owns columns
+// [w Cw, (w + 1) Cw) of the tile (Cw = C / waves) in every row; lane l handles slots l + 64 r.
+// Returns the LDS index of slot s; *g receives its coefficient index.
+__device__ __forceinline__ uint32_t wave_col_slot(uint32_t s, uint32_t wv, uint32_t logCw, uint32_t logC, uint32_t k2,
+                                                  uint32_t tile, uint32_t* g) {
+  const uint32_t row = s >> logCw, col = (wv << logCw) + (s & ((1u << logCw) - 1));
+  *g = (row << k2) + (tile << logC) + col;
+  return (row << logC) + col;
+}
+
+// ModUp fused with the column phases around it, per wavefront. Workgroup (digit j, item b, tile);
+// every wavefront owns a group of the tile's columns: the digit's limbs (row phase of the inverse
+// NTT already applied, in dc2 [B][nl][N]) go through the inverse column phase in LDS and are scaled
+// to y_i = d_i Dhat_i^-1 mod q_i (N^-1 folded in), kept in registers; then for every limb t outside
+// the digit the conversion sum_i y_i (Dhat_i mod t) mod t is formed (exact FP64 on Q primes,
+// integer on special primes), goes through the forward column phase of t and is written to ext
+// (layout as k_modup). No workgroup barrier; LDS holds one tile.
+template <int LOG_E, int NT, int ALPHA, int K1>
 __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint32_t K, uint32_t nq, uint32_t alpha,
-                                                  uint32_t R, uint32_t logN, uint32_t k1,
+                                                  uint32_t R, uint32_t logN,
                                                   const ModInfo* __restrict__ mods, const double* __restrict__ twf,
                                                   const uint64_t* __restrict__ twi, const uint64_t* __restrict__ tab,
                                                   const uint64_t* __restrict__ dc2, uint64_t* __restrict__ ext) {
-  constexpr uint32_t E = 1u << LOG_E, EPT = E / NT, EP = E + (E >> 4);
-  extern __shared__ uint64_t lds[];
-  uint64_t* work = lds;
-  uint64_t* ys = lds + EP;
+  constexpr uint32_t k1 = K1;  // column-phase stages (compile-time: round shapes and offsets fold)
+  constexpr uint32_t E = 1u << LOG_E, EPT = E / NT;
+  extern __shared__ uint64_t work[];
   const uint32_t N = 1u << logN, tiles = N >> LOG_E;
   const uint32_t tile = blockIdx.x % tiles, rest = blockIdx.x / tiles;
   const uint32_t b = rest % B, j = rest / B;
   const uint32_t next = nl + K, lo = j * alpha, cnt = min(alpha, nl - lo);
-  const uint32_t k2 = logN - k1, logC = LOG_E - k1;
+  const uint32_t k2 = logN - k1, logC = LOG_E - k1, logCw = logC - WaveSplit<NT>::kLogWaves;
+  const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t* blk = tab + (uint64_t)j * (2 * alpha + 2 * alpha * next);
-  for (uint32_t i = 0; i < cnt; ++i) {
+  double y[ALPHA][EPT];
+#pragma unroll
+  for (uint32_t i = 0; i < ALPHA; ++i) {
+    if (i >= cnt) break;
     const ModInfo m = mods[lo + i];
     FpArith ar;
     ar.init(m);
     const uint64_t* src = dc2 + ((uint64_t)b * nl + lo + i) * N;
-  #pragma unroll
-    for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
-      const uint32_t idx = threadIdx.x + r_ * NT;
-      work[pad_idx(idx)] = ar.lds_in(src[col_index(idx, logC, k2, tile)]);
+#pragma unroll
+    for (uint32_t r = 0; r < EPT; ++r) {
+      uint32_t g;
+      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
+      work[pad_idx(li)] = ar.lds_in(src[g]);
     }
-    __syncthreads();
-    const double* w = twf + (uint64_t)(lo + i) * 4 * N + 2 * (uint64_t)N;
-    ntt_rounds<true, 1, FpArith, EPT, NT, true>(work, ar, w, k1, logC, 0, 0);
-    __syncthreads();  // rounds ran per wavefront; the loops below are workgroup-strided
+    wave_sync();
+    ntt_rounds<true, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)(lo + i) * 4 * N + 2 * (uint64_t)N, k1,
+                                                logC, 0, 0);
     const double c = (double)shoup_mul(m.n_inv, blk[2 * i], blk[2 * i + 1], m.q);
     const double cq = c / ar.q;
-  #pragma unroll
-    for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
-      const uint32_t idx = threadIdx.x + r_ * NT;
-      const double y = ar.mulc(ar.ld(work[pad_idx(idx)]), c, cq);
-      ys[(uint64_t)i * E + idx] = (uint64_t)(y < 0.0 ? y + ar.q : y);
+#pragma unroll
+    for (uint32_t r = 0; r < EPT; ++r) {
+      uint32_t g;
+      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
+      const double v = ar.mulc(ar.ld(work[pad_idx(li)]), c, cq);
+      y[i][r] = v < 0.0 ? v + ar.q : v;  // [0, q_i)
     }
-    // the next limb's loads write only this thread's own slots: no barrier needed here
+    wave_sync();
   }
   uint64_t* out = ext + ((uint64_t)j * B + b) * R * N;
   for (uint32_t row = 0; row < next - cnt; ++row) {
@@ -659,114 +674,139 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
     const uint32_t mi = e < nl ? e : nq + (e - nl);
     const ModInfo m = mods[mi];
     const uint64_t* mrow = blk + 2 * alpha + 2 * (uint64_t)e;
-    const bool fp = e < nl;
-  #pragma unroll
-    for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
-      const uint32_t idx = threadIdx.x + r_ * NT;
-      uint64_t v = 0;
-      for (uint32_t i = 0; i < cnt; ++i) {
-        const uint64_t* cc = mrow + (uint64_t)i * 2 * next;
-        v = add_mod(v, shoup_mul(ys[(uint64_t)i * E + idx], cc[0], cc[1], m.q), m.q);
-      }
-      work[pad_idx(idx)] = fp ? (uint64_t)__double_as_longlong((double)v) : v;
-    }
-    __syncthreads();
     uint64_t* o = out + (uint64_t)row * N;
-    if (fp) {
+    if (e < nl) {
       FpArith ar;
       ar.init(m);
-      const double* w = twf + (uint64_t)mi * 4 * N;
-      ntt_rounds<false, 1, FpArith, EPT, NT, true>(work, ar, w, k1, logC, 0, 0);
-      __syncthreads();  // rounds ran per wavefront; the loops below are workgroup-strided
-    #pragma unroll
-      for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
-        const uint32_t idx = threadIdx.x + r_ * NT;
-        o[col_index(idx, logC, k2, tile)] = ar.lds_out(work[pad_idx(idx)]);
+      double cw[ALPHA], cwq[ALPHA];
+#pragma unroll
+      for (uint32_t i = 0; i < ALPHA; ++i) {
+        cw[i] = i < cnt ? (double)mrow[(uint64_t)i * 2 * next] : 0.0;
+        cwq[i] = cw[i] * ar.qinv;
+      }
+#pragma unroll
+      for (uint32_t r = 0; r < EPT; ++r) {
+        double v = 0.0;
+#pragma unroll
+        for (uint32_t i = 0; i < ALPHA; ++i)
+          if (i < cnt) v += ar.mulc(y[i][r], cw[i], cwq[i]);
+        uint32_t g;
+        const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
+        work[pad_idx(li)] = ar.st(ar.red(v));
+      }
+      wave_sync();
+      ntt_rounds<false, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)mi * 4 * N, k1, logC, 0, 0);
+#pragma unroll
+      for (uint32_t r = 0; r < EPT; ++r) {
+        uint32_t g;
+        const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
+        o[g] = ar.lds_out(work[pad_idx(li)]);
       }
     } else {
       IntArith ar;
       ar.init(m);
-      const uint64_t* w = twi + (uint64_t)mi * 4 * N;
-      ntt_rounds<false, 1, IntArith, EPT, NT, true>(work, ar, w, k1, logC, 0, 0);
-      __syncthreads();  // rounds ran per wavefront; the loops below are workgroup-strided
-    #pragma unroll
-      for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
-        const uint32_t idx = threadIdx.x + r_ * NT;
-        o[col_index(idx, logC, k2, tile)] = work[pad_idx(idx)];
+#pragma unroll
+      for (uint32_t r = 0; r < EPT; ++r) {
+        uint64_t v = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < ALPHA; ++i) {
+          if (i >= cnt) break;
+          const uint64_t* cc = mrow + (uint64_t)i * 2 * next;
+          v = add_mod(v, shoup_mul((uint64_t)y[i][r], cc[0], cc[1], m.q), m.q);
+        }
+        uint32_t g;
+        const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
+        work[pad_idx(li)] = v;
+      }
+      wave_sync();
+      ntt_rounds<false, 1, IntArith, EPT, NT, true>(work, ar, twi + (uint64_t)mi * 4 * N, k1, logC, 0, 0);
+#pragma unroll
+      for (uint32_t r = 0; r < EPT; ++r) {
+        uint32_t g;
+        const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
+        o[g] = work[pad_idx(li)];
       }
     }
-    // the next row's sums write only this thread's own slots: no barrier needed here
+    wave_sync();
   }
 }
 
-// ModDown conversion fused with the column phases around it. Workgroup (item b, component c, tile):
-// the K special-prime limbs of u (row phase of the inverse NTT already applied) go through the inverse
-// column phase in LDS and are scaled to z_k = [u_(p_k) (P/p_k)^-1]_(p_k) (N^-1 applied first), taken
-// as centred representatives as in k_moddown_conv; every Q limb's conversion is formed in LDS, goes
-// through the forward column phase and is written to conv [B][2][nl][N].
-template <int LOG_E, int NT>
-__global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, uint32_t nq, uint32_t logN, uint32_t k1,
+// ModDown conversion fused with the column phases around it, per wavefront. Workgroup (item b,
+// component c, tile): the K special-prime limbs of u (row phase of the inverse NTT already applied)
+// go through the inverse column phase in LDS and are scaled to z_k = [u_(p_k) (P/p_k)^-1]_(p_k)
+// (N^-1 applied first), kept in registers and taken as centred representatives as in
+// k_moddown_conv; every Q limb's conversion is formed, goes through the forward column phase and is
+// written to conv [B][2][nl][N].
+template <int LOG_E, int NT, int KP, int K1>
+__global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, uint32_t nq, uint32_t logN,
                                                     const ModInfo* __restrict__ mods, const double* __restrict__ twf,
                                                     const uint64_t* __restrict__ twi, const uint64_t* __restrict__ tab,
                                                     const uint64_t* __restrict__ u, uint64_t* __restrict__ conv) {
-  constexpr uint32_t E = 1u << LOG_E, EPT = E / NT, EP = E + (E >> 4);
-  extern __shared__ uint64_t lds[];
-  uint64_t* work = lds;
-  uint64_t* zs = lds + EP;
+  constexpr uint32_t k1 = K1;  // column-phase stages (compile-time: round shapes and offsets fold)
+  constexpr uint32_t E = 1u << LOG_E, EPT = E / NT;
+  extern __shared__ uint64_t work[];
   const uint32_t N = 1u << logN, tiles = N >> LOG_E;
   const uint32_t tile = blockIdx.x % tiles, bc = blockIdx.x / tiles;
-  const uint32_t next = nl + K, k2 = logN - k1, logC = LOG_E - k1;
-  for (uint32_t kk = 0; kk < K; ++kk) {
+  const uint32_t next = nl + K, k2 = logN - k1, logC = LOG_E - k1, logCw = logC - WaveSplit<NT>::kLogWaves;
+  const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint64_t z[KP][EPT];
+  uint64_t half[KP];
+#pragma unroll
+  for (uint32_t kk = 0; kk < KP; ++kk) {
     const ModInfo m = mods[nq + kk];
+    half[kk] = (m.q - 1) / 2;
     IntArith ar;
     ar.init(m);
     const uint64_t* src = u + ((uint64_t)bc * next + nl + kk) * N;
-  #pragma unroll
-    for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
-      const uint32_t idx = threadIdx.x + r_ * NT;
-      work[pad_idx(idx)] = src[col_index(idx, logC, k2, tile)];
+#pragma unroll
+    for (uint32_t r = 0; r < EPT; ++r) {
+      uint32_t g;
+      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
+      work[pad_idx(li)] = src[g];
     }
-    __syncthreads();
-    const uint64_t* w = twi + (uint64_t)(nq + kk) * 4 * N + 2 * (uint64_t)N;
-    ntt_rounds<true, 1, IntArith, EPT, NT, true>(work, ar, w, k1, logC, 0, 0);
-    __syncthreads();  // rounds ran per wavefront; the loops below are workgroup-strided
-  #pragma unroll
-    for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
-      const uint32_t idx = threadIdx.x + r_ * NT;
-      const uint64_t x = shoup_mul(work[pad_idx(idx)], m.n_inv, m.n_inv_shoup, m.q);
-      zs[(uint64_t)kk * E + idx] = shoup_mul(x, tab[2 * kk], tab[2 * kk + 1], m.q);
+    wave_sync();
+    ntt_rounds<true, 1, IntArith, EPT, NT, true>(work, ar, twi + (uint64_t)(nq + kk) * 4 * N + 2 * (uint64_t)N, k1,
+                                                 logC, 0, 0);
+#pragma unroll
+    for (uint32_t r = 0; r < EPT; ++r) {
+      uint32_t g;
+      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
+      const uint64_t x = shoup_mul(work[pad_idx(li)], m.n_inv, m.n_inv_shoup, m.q);
+      z[kk][r] = shoup_mul(x, tab[2 * kk], tab[2 * kk + 1], m.q);
     }
+    wave_sync();
   }
   const uint64_t* pq = tab + 2 * K;
   const uint64_t* pmod = tab + 2 * K + 2 * (uint64_t)K * nq + 2 * nq;
   for (uint32_t i = 0; i < nl; ++i) {
     const ModInfo m = mods[i];
-  #pragma unroll
-    for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
-      const uint32_t idx = threadIdx.x + r_ * NT;
-      uint64_t acc = 0;
-      uint32_t nneg = 0;
-      for (uint32_t kk = 0; kk < K; ++kk) {
-        const uint64_t z = zs[(uint64_t)kk * E + idx];
-        const uint64_t* cc = pq + 2 * ((uint64_t)kk * nq + i);
-        acc = add_mod(acc, shoup_mul(z, cc[0], cc[1], m.q), m.q);
-        nneg += z > (mods[nq + kk].q - 1) / 2 ? 1u : 0u;
-      }
-      for (uint32_t n = 0; n < nneg; ++n) acc = sub_mod(acc, pmod[i], m.q);
-      work[pad_idx(idx)] = (uint64_t)__double_as_longlong((double)acc);
-    }
-    __syncthreads();
     FpArith ar;
     ar.init(m);
-    const double* w = twf + (uint64_t)i * 4 * N;
-    ntt_rounds<false, 1, FpArith, EPT, NT, true>(work, ar, w, k1, logC, 0, 0);
-    __syncthreads();  // rounds ran per wavefront; the loops below are workgroup-strided
-    uint64_t* o = conv + ((uint64_t)bc * nl + i) * N;
-  #pragma unroll
-    for (uint32_t r_ = 0; r_ < E / NT; ++r_) {
-      const uint32_t idx = threadIdx.x + r_ * NT;
-      o[col_index(idx, logC, k2, tile)] = ar.lds_out(work[pad_idx(idx)]);
+#pragma unroll
+    for (uint32_t r = 0; r < EPT; ++r) {
+      uint64_t acc = 0;
+      uint32_t nneg = 0;
+#pragma unroll
+      for (uint32_t kk = 0; kk < KP; ++kk) {
+        const uint64_t* cc = pq + 2 * ((uint64_t)kk * nq + i);
+        acc = add_mod(acc, shoup_mul(z[kk][r], cc[0], cc[1], m.q), m.q);
+        nneg += z[kk][r] > half[kk] ? 1u : 0u;
+      }
+      for (uint32_t n = 0; n < nneg; ++n) acc = sub_mod(acc, pmod[i], m.q);
+      uint32_t g;
+      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
+      work[pad_idx(li)] = ar.lds_in(acc);
     }
+    wave_sync();
+    ntt_rounds<false, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)i * 4 * N, k1, logC, 0, 0);
+    uint64_t* o = conv + ((uint64_t)bc * nl + i) * N;
+#pragma unroll
+    for (uint32_t r = 0; r < EPT; ++r) {
+      uint32_t g;
+      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
+      o[g] = ar.lds_out(work[pad_idx(li)]);
+    }
+    wave_sync();
   }
 }
 
@@ -819,62 +859,67 @@ __global__ __launch_bounds__(kThreads) void k_rescale_combine(uint32_t B, uint32
   }
 }
 
-// Rescale, column part: per (polynomial bc, tile), the dropped limb (row phase of its INTT already
-// applied, in tmp [BC][N]) goes through the inverse column phase mod q_l and N^-1, is centred
-// (v' = v - q_l when v > (q_l - 1)/2), and v' (|v'| < q_l/2 < q_i) goes through the forward column
-// phase of every remaining limb i; results in w [BC][nl-1][N].
-template <int LOG_E, int NT>
-__global__ __launch_bounds__(NT) void k_rescale_cols(uint32_t nl, uint32_t logN, uint32_t k1,
+// Rescale, column part, per wavefront: per (polynomial bc, tile), the dropped limb (row phase of
+// its INTT already applied, in tmp [BC][N]) goes through the inverse column phase mod q_l and N^-1
+// and is centred (v' = v - q_l when v > (q_l - 1)/2), kept in registers; v' (|v'| < q_l/2 < q_i)
+// then goes through the forward column phase of every remaining limb i; results in w [BC][nl-1][N].
+template <int LOG_E, int NT, int K1>
+__global__ __launch_bounds__(NT) void k_rescale_cols(uint32_t nl, uint32_t logN,
                                                     const ModInfo* __restrict__ mods, const double* __restrict__ twf,
                                                     const uint64_t* __restrict__ tmp, uint64_t* __restrict__ w) {
-  constexpr uint32_t E = 1u << LOG_E, EPT = E / NT, EP = E + (E >> 4);
-  extern __shared__ uint64_t lds[];
-  uint64_t* work = lds;
-  double* vs = (double*)(lds + EP);
+  constexpr uint32_t k1 = K1;  // column-phase stages (compile-time: round shapes and offsets fold)
+  constexpr uint32_t E = 1u << LOG_E, EPT = E / NT;
+  extern __shared__ uint64_t work[];
   const uint32_t N = 1u << logN, tiles = N >> LOG_E;
   const uint32_t tile = blockIdx.x % tiles, bc = blockIdx.x / tiles;
-  const uint32_t no = nl - 1, k2 = logN - k1, logC = LOG_E - k1;
+  const uint32_t no = nl - 1, k2 = logN - k1, logC = LOG_E - k1, logCw = logC - WaveSplit<NT>::kLogWaves;
+  const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double vs[EPT];
   {
     const ModInfo m = mods[no];
     FpArith ar;
     ar.init(m);
     const uint64_t* src = tmp + ((uint64_t)bc << logN);
 #pragma unroll
-    for (uint32_t r_ = 0; r_ < EPT; ++r_) {
-      const uint32_t idx = threadIdx.x + r_ * NT;
-      work[pad_idx(idx)] = ar.lds_in(src[col_index(idx, logC, k2, tile)]);
+    for (uint32_t r = 0; r < EPT; ++r) {
+      uint32_t g;
+      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
+      work[pad_idx(li)] = ar.lds_in(src[g]);
     }
-    __syncthreads();
-    ntt_rounds<true, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)no * 4 * N + 2 * (uint64_t)N, k1, logC, 0, 0);
-    __syncthreads();
+    wave_sync();
+    ntt_rounds<true, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)no * 4 * N + 2 * (uint64_t)N, k1, logC, 0,
+                                                0);
     const double c = (double)m.n_inv, cq = c / ar.q;
 #pragma unroll
-    for (uint32_t r_ = 0; r_ < EPT; ++r_) {
-      const uint32_t idx = threadIdx.x + r_ * NT;
-      double v = ar.mulc(ar.ld(work[pad_idx(idx)]), c, cq);  // |v| <= 0.7 q_l
+    for (uint32_t r = 0; r < EPT; ++r) {
+      uint32_t g;
+      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
+      double v = ar.mulc(ar.ld(work[pad_idx(li)]), c, cq);  // |v| <= 0.7 q_l
       v = v < 0.0 ? v + ar.q : v;                             // [0, q_l)
-      vs[idx] = v > 0.5 * (ar.q - 1.0) ? v - ar.q : v;        // centred
+      vs[r] = v > 0.5 * (ar.q - 1.0) ? v - ar.q : v;          // centred
     }
+    wave_sync();
   }
   for (uint32_t i = 0; i < no; ++i) {
     const ModInfo m = mods[i];
     FpArith ar;
     ar.init(m);
 #pragma unroll
-    for (uint32_t r_ = 0; r_ < EPT; ++r_) {
-      const uint32_t idx = threadIdx.x + r_ * NT;
-      work[pad_idx(idx)] = ar.st(vs[idx]);
+    for (uint32_t r = 0; r < EPT; ++r) {
+      uint32_t g;
+      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
+      work[pad_idx(li)] = ar.st(vs[r]);
     }
-    __syncthreads();
+    wave_sync();
     ntt_rounds<false, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)i * 4 * N, k1, logC, 0, 0);
-    __syncthreads();
     uint64_t* o = w + ((uint64_t)bc * no + i) * N;
-    const uint32_t tid = opaque(threadIdx.x);
 #pragma unroll
-    for (uint32_t r_ = 0; r_ < EPT; ++r_) {
-      const uint32_t idx = tid + r_ * NT;
-      o[col_index(idx, logC, k2, tile)] = ar.lds_out(work[pad_idx(idx)]);
+    for (uint32_t r = 0; r < EPT; ++r) {
+      uint32_t g;
+      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
+      o[g] = ar.lds_out(work[pad_idx(li)]);
     }
+    wave_sync();
   }
 }
 
@@ -1211,21 +1256,13 @@ static uint32_t modup_rows(const Params& p, uint32_t nl) {
   return nl + p.np - cnt_last;
 }
 
-// Fused column-phase kernels (ModUp, ModDown): tile of 2^11 elements on 256 threads or 2^12 on 512
-// threads, 8 elements per thread. FHE_COLS_TILE=11|12 forces one; otherwise 2^11 while a tile row
-// still spans at least 8 columns (64 bytes).
-static uint32_t cols_log_e(const Params& p) {
-  static const int forced = [] {
-    const char* e = std::getenv("FHE_COLS_TILE");
-    return e ? std::atoi(e) : 0;
-  }();
-  if (forced == 11 || forced == 12) return (uint32_t)forced;
-  return (11 - (int)p.k1) >= 3 ? 11u : 12u;
-}
+// Fused column-phase kernels (ModUp, ModDown, rescale): 2048-element tiles on 256 threads (8
+// elements per thread), instantiated for column phases of k1 = 6, 7, 8 stages.
+static uint32_t cols_log_e(const Params&) { return 11; }
 
-static size_t cols_lds_bytes(uint32_t log_e, uint32_t ntiles) {
+static size_t cols_lds_bytes(uint32_t log_e) {
   const size_t E = (size_t)1 << log_e;
-  return (E + (E >> 4) + (size_t)ntiles * E) * sizeof(uint64_t);
+  return (E + (E >> 4)) * sizeof(uint64_t);
 }
 
 static size_t max_lds_per_block(int device) {
@@ -1245,11 +1282,12 @@ static void allow_lds(const void* kern, size_t bytes) {
   HIPCHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
 
-static bool cols_fusable(const fhe_ctx* ctx, uint32_t ntiles) {
+// The fused column kernels keep at most 4 digit limbs / special primes in registers and are
+// compiled for k1 in [6, 8]; other parameter sets take the unfused sequence.
+static bool cols_fusable(const fhe_ctx* ctx, uint32_t regs_needed) {
   const Params& p = ctx->p;
-  const uint32_t le = cols_log_e(p);
-  if ((uint32_t)p.k1 > le || (p.N >> le) == 0) return false;
-  return cols_lds_bytes(le, ntiles) <= max_lds_per_block(ctx->device);
+  if (regs_needed > 4 || p.k1 < 6 || p.k1 > 8) return false;
+  return cols_lds_bytes(cols_log_e(p)) <= max_lds_per_block(ctx->device);
 }
 
 size_t keyswitch_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t nl) {
@@ -1281,21 +1319,29 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
     // 1-3 fused: row phase of the INTT here, then one kernel for the column phases and ModUp.
     ntt_inverse_rows(ctx, lb_in, st);
     const uint32_t le = cols_log_e(p);
-    const size_t lds_mu = cols_lds_bytes(le, alpha);
+    const size_t lds_mu = cols_lds_bytes(le);
     const uint64_t grid = (uint64_t)B * beta * (N >> le);
     if (grid >= (1ull << 31)) fail(FHE_EINVAL, "key-switch batch too large");
     const double bytes = e8 * beta * (double)next;  // nl digit rows read, beta * next - nl rows written
     const uint64_t* mtab = ctx->t.modup.u64() + ctx->t.modup_offset[nl];
     const double* twf0 = (const double*)ctx->t.twf.get();
-    if (le == 11) {
-      allow_lds((const void*)k_modup_cols<11, 256>, lds_mu);
-      FHE_LAUNCH_T("modup_cols", bytes, (k_modup_cols<11, 256>), grid, 256, lds_mu, st, B, nl, K, (uint32_t)p.nq,
-                   alpha, R, p.logN, p.k1, mods_of(ctx), twf0, ctx->t.tw.u64(), mtab, dcoef, ext);
-    } else {
-      allow_lds((const void*)k_modup_cols<12, 512>, lds_mu);
-      FHE_LAUNCH_T("modup_cols", bytes, (k_modup_cols<12, 512>), grid, 512, lds_mu, st, B, nl, K, (uint32_t)p.nq,
-                   alpha, R, p.logN, p.k1, mods_of(ctx), twf0, ctx->t.tw.u64(), mtab, dcoef, ext);
+#define FHE_MODUP_COLS(AL, K1)                                                                                  \
+  FHE_LAUNCH_T("modup_cols", bytes, (k_modup_cols<11, 256, AL, K1>), grid, 256, lds_mu, st, B, nl, K,             \
+               (uint32_t)p.nq, alpha, R, p.logN, mods_of(ctx), twf0, ctx->t.tw.u64(), mtab, dcoef, ext)
+#define FHE_MODUP_COLS_K(AL)          \
+  switch (p.k1) {                     \
+    case 6: FHE_MODUP_COLS(AL, 6); break; \
+    case 7: FHE_MODUP_COLS(AL, 7); break; \
+    default: FHE_MODUP_COLS(AL, 8); break; \
+  }
+    switch (alpha) {
+      case 1: FHE_MODUP_COLS_K(1); break;
+      case 2: FHE_MODUP_COLS_K(2); break;
+      case 3: FHE_MODUP_COLS_K(3); break;
+      default: FHE_MODUP_COLS_K(4); break;
     }
+#undef FHE_MODUP_COLS_K
+#undef FHE_MODUP_COLS
   } else {
     ntt_inverse(ctx, lb_in, st);
     // 2. ModUp: the limbs outside each digit.
@@ -1344,19 +1390,27 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
   if (cols_fusable(ctx, K)) {
     ntt_inverse_rows(ctx, lb_up, st);
     const uint32_t le = cols_log_e(p);
-    const size_t lds_md = cols_lds_bytes(le, K);
+    const size_t lds_md = cols_lds_bytes(le);
     const uint64_t grid = (uint64_t)2 * B * (N >> le);
     const double bytes = e8 * 2 * (K + nl);
     const double* twf0 = (const double*)ctx->t.twf.get();
-    if (le == 11) {
-      allow_lds((const void*)k_moddown_cols<11, 256>, lds_md);
-      FHE_LAUNCH_T("moddown_cols", bytes, (k_moddown_cols<11, 256>), grid, 256, lds_md, st, nl, K, (uint32_t)p.nq,
-                   p.logN, p.k1, mods_of(ctx), twf0, ctx->t.tw.u64(), ctx->t.moddown.u64(), u, conv);
-    } else {
-      allow_lds((const void*)k_moddown_cols<12, 512>, lds_md);
-      FHE_LAUNCH_T("moddown_cols", bytes, (k_moddown_cols<12, 512>), grid, 512, lds_md, st, nl, K, (uint32_t)p.nq,
-                   p.logN, p.k1, mods_of(ctx), twf0, ctx->t.tw.u64(), ctx->t.moddown.u64(), u, conv);
+#define FHE_MODDOWN_COLS(KP, K1)                                                                            \
+  FHE_LAUNCH_T("moddown_cols", bytes, (k_moddown_cols<11, 256, KP, K1>), grid, 256, lds_md, st, nl, K,        \
+               (uint32_t)p.nq, p.logN, mods_of(ctx), twf0, ctx->t.tw.u64(), ctx->t.moddown.u64(), u, conv)
+#define FHE_MODDOWN_COLS_K(KP)             \
+  switch (p.k1) {                          \
+    case 6: FHE_MODDOWN_COLS(KP, 6); break; \
+    case 7: FHE_MODDOWN_COLS(KP, 7); break; \
+    default: FHE_MODDOWN_COLS(KP, 8); break; \
+  }
+    switch (K) {
+      case 1: FHE_MODDOWN_COLS_K(1); break;
+      case 2: FHE_MODDOWN_COLS_K(2); break;
+      case 3: FHE_MODDOWN_COLS_K(3); break;
+      default: FHE_MODDOWN_COLS_K(4); break;
     }
+#undef FHE_MODDOWN_COLS_K
+#undef FHE_MODDOWN_COLS
   } else {
     ntt_inverse(ctx, lb_up, st);
     FHE_LAUNCH("moddown_conv", e8 * 2 * (K + nl), k_moddown_conv, grid_for((uint64_t)B * 2 * N), 0, st, B, nl, K,
@@ -1386,18 +1440,23 @@ void rescale(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const 
     // phase of the broadcast fused with the combine
     ntt_inverse_rows(ctx, LimbBatch{tmp, 1, BC, N, 0, nl - 1}, st);
     const uint32_t le = cols_log_e(p);
-    const size_t lds_rs = cols_lds_bytes(le, 1);
+    const size_t lds_rs = cols_lds_bytes(le);
     const uint64_t grid = (uint64_t)BC * (N >> le);
     const double* twf = (const double*)ctx->t.twf.get();
     if (grid >= (1ull << 31)) fail(FHE_EINVAL, "rescale batch too large");
-    if (le == 11) {
-      allow_lds((const void*)k_rescale_cols<11, 256>, lds_rs);
-      FHE_LAUNCH_T("rescale_cols", e8 * nl, (k_rescale_cols<11, 256>), grid, 256, lds_rs, st, nl, p.logN, p.k1,
-                   mods_of(ctx), twf, tmp, w);
-    } else {
-      allow_lds((const void*)k_rescale_cols<12, 512>, lds_rs);
-      FHE_LAUNCH_T("rescale_cols", e8 * nl, (k_rescale_cols<12, 512>), grid, 512, lds_rs, st, nl, p.logN, p.k1,
-                   mods_of(ctx), twf, tmp, w);
+    switch (p.k1) {
+      case 6:
+        FHE_LAUNCH_T("rescale_cols", e8 * nl, (k_rescale_cols<11, 256, 6>), grid, 256, lds_rs, st, nl, p.logN,
+                     mods_of(ctx), twf, tmp, w);
+        break;
+      case 7:
+        FHE_LAUNCH_T("rescale_cols", e8 * nl, (k_rescale_cols<11, 256, 7>), grid, 256, lds_rs, st, nl, p.logN,
+                     mods_of(ctx), twf, tmp, w);
+        break;
+      default:
+        FHE_LAUNCH_T("rescale_cols", e8 * nl, (k_rescale_cols<11, 256, 8>), grid, 256, lds_rs, st, nl, p.logN,
+                     mods_of(ctx), twf, tmp, w);
+        break;
     }
     const size_t lds = kNttLdsElems * sizeof(uint64_t);
     FHE_LAUNCH("rescale_rows", e8 * 3 * (nl - 1), k_rescale_rows, (uint64_t)BC * (nl - 1) * (N >> kNttLogE), lds, st,
