@@ -21,6 +21,11 @@ struct LimbBatch {
   const uint64_t* src = nullptr;
   uint64_t src_stride = 0;
   uint32_t hole_items = 0, hole_alpha = 0, hole_len = 0, hole_j0 = 0;
+  // Nonzero: Q-prime limbs are written in the FP64 kernels' internal form (the bits of a double
+  // holding a representative in [-q/2 - 2, q/2 + 2]) instead of [0, q) integers; special-prime
+  // limbs are unaffected. Only for forward transforms and the row phase of inverse ones, whose
+  // consumers are the fused key-switch / rescale kernels.
+  uint32_t raw_out = 0;
 };
 
 // Negacyclic NTT, in place. Forward: coefficients -> evaluations at psi^(2 brv(i) + 1) (bit-reversed

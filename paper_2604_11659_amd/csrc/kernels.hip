@@ -315,7 +315,7 @@ __global__ __launch_bounds__(kThreads) void k_ntt(LimbBatch lb, const ModInfo* _
 #pragma unroll
     for (uint32_t r_ = 0; r_ < kPer; ++r_) {
       const uint32_t idx = wb + ln + r_ * 64;
-      a[j0 + idx] = ar.lds_out(lds[pad_idx(idx)]);
+      a[j0 + idx] = lb.raw_out ? lds[pad_idx(idx)] : ar.lds_out(lds[pad_idx(idx)]);
     }
   } else {
     // columns are strided: coalesced loads and stores across the workgroup, rounds per wavefront
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kThreads) void k_ntt(LimbBatch lb, const ModInfo* _
 #pragma unroll
     for (uint32_t r_ = 0; r_ < kPer; ++r_) {
       const uint32_t idx = tid + r_ * kThreads;
-      uint64_t v = ar.lds_out(lds[pad_idx(idx)]);
+      uint64_t v = lb.raw_out ? lds[pad_idx(idx)] : ar.lds_out(lds[pad_idx(idx)]);
       if (kInv) v = shoup_mul(v, m.n_inv, m.n_inv_shoup, m.q);
       a[((idx >> logC) << k2) + (tile << logC) + (idx & (C - 1))] = v;
     }
@@ -390,7 +390,7 @@ __device__ __forceinline__ void ntt_p2_inner_body(
 #pragma unroll
       for (uint32_t r = 0; r < kPer; ++r) {
         const uint32_t idx = wb + lane + r * 64;
-        lds[pad_idx(idx)] = ar.lds_in(src[idx]);
+        lds[pad_idx(idx)] = src[idx];  // ext rows: internal form on Q primes, integers on P
       }
       wave_sync();
       ntt_rounds<false, 2, A, 8, kInnerThreads, true>(lds, ar, w, k, logC, k1, j0);
@@ -422,23 +422,14 @@ __device__ __forceinline__ void ntt_p2_inner_body(
   }
 }
 
-#define FHE_P2_INNER_ARGS                                                                                  \
-  uint32_t B, uint32_t nl, uint32_t K, uint32_t nq, uint32_t alpha, uint32_t R, uint32_t e0, uint32_t ne,   \
-      uint32_t logN, uint32_t k1, const ModInfo *__restrict__ mods, const typename A::W *__restrict__ tw,   \
-      const uint64_t *__restrict__ in, uint64_t in_stride, const uint64_t *__restrict__ ext,                \
-      const uint64_t *const *__restrict__ keys, uint64_t *__restrict__ u
-// Two register budgets: one 512-thread workgroup per CU at the compiler's natural register count, or
-// two per CU (at most 128 VGPRs, a few spilled).
 template <class A>
-__global__ __launch_bounds__(kInnerThreads) void k_ntt_p2_inner(FHE_P2_INNER_ARGS) {
+__global__ __launch_bounds__(kInnerThreads) void k_ntt_p2_inner(
+    uint32_t B, uint32_t nl, uint32_t K, uint32_t nq, uint32_t alpha, uint32_t R, uint32_t e0, uint32_t ne,
+    uint32_t logN, uint32_t k1, const ModInfo* __restrict__ mods, const typename A::W* __restrict__ tw,
+    const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __restrict__ ext,
+    const uint64_t* const* __restrict__ keys, uint64_t* __restrict__ u) {
   ntt_p2_inner_body<A>(B, nl, K, nq, alpha, R, e0, ne, logN, k1, mods, tw, in, in_stride, ext, keys, u);
 }
-template <class A>
-__global__ __launch_bounds__(kInnerThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_ntt_p2_inner_occ2(
-    FHE_P2_INNER_ARGS) {
-  ntt_p2_inner_body<A>(B, nl, K, nq, alpha, R, e0, ne, logN, k1, mods, tw, in, in_stride, ext, keys, u);
-}
-#undef FHE_P2_INNER_ARGS
 
 // Row phase of the forward NTT of the ModDown conversion fused with the final combine:
 // out[b][c][i] = add[2b+c][i] + (u[b][c][i] - NTT(conv)[b][c][i]) P^-1 (NTT domain).
@@ -467,7 +458,7 @@ __global__ __launch_bounds__(kThreads) void k_ntt_p2_combine(uint32_t nl, uint32
 #pragma unroll
   for (uint32_t r_ = 0; r_ < kPer; ++r_) {
     const uint32_t idx = wb + lane + r_ * 64;
-    lds[pad_idx(idx)] = ar.lds_in(src[idx]);
+    lds[pad_idx(idx)] = src[idx];  // conv: internal FP64 form
   }
   wave_sync();
   const typename A::W* w = tw + (uint64_t)i * 4 * N;
@@ -652,7 +643,7 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
     for (uint32_t r = 0; r < EPT; ++r) {
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      work[pad_idx(li)] = ar.lds_in(src[g]);
+      work[pad_idx(li)] = src[g];  // row-phase output in internal FP64 form
     }
     wave_sync();
     ntt_rounds<true, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)(lo + i) * 4 * N + 2 * (uint64_t)N, k1,
@@ -700,7 +691,7 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
       for (uint32_t r = 0; r < EPT; ++r) {
         uint32_t g;
         const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-        o[g] = ar.lds_out(work[pad_idx(li)]);
+        o[g] = work[pad_idx(li)];  // internal FP64 form, read by the row-phase inner product
       }
     } else {
       IntArith ar;
@@ -804,7 +795,7 @@ __global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, ui
     for (uint32_t r = 0; r < EPT; ++r) {
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      o[g] = ar.lds_out(work[pad_idx(li)]);
+      o[g] = work[pad_idx(li)];  // internal FP64 form, read by the combine
     }
     wave_sync();
   }
@@ -884,7 +875,7 @@ __global__ __launch_bounds__(NT) void k_rescale_cols(uint32_t nl, uint32_t logN,
     for (uint32_t r = 0; r < EPT; ++r) {
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      work[pad_idx(li)] = ar.lds_in(src[g]);
+      work[pad_idx(li)] = src[g];  // row-phase output in internal FP64 form
     }
     wave_sync();
     ntt_rounds<true, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)no * 4 * N + 2 * (uint64_t)N, k1, logC, 0,
@@ -917,7 +908,7 @@ __global__ __launch_bounds__(NT) void k_rescale_cols(uint32_t nl, uint32_t logN,
     for (uint32_t r = 0; r < EPT; ++r) {
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      o[g] = ar.lds_out(work[pad_idx(li)]);
+      o[g] = work[pad_idx(li)];  // internal FP64 form, read by k_rescale_rows
     }
     wave_sync();
   }
@@ -946,7 +937,7 @@ __global__ __launch_bounds__(kThreads) void k_rescale_rows(uint32_t ncomp, uint3
 #pragma unroll
   for (uint32_t r_ = 0; r_ < kPer; ++r_) {
     const uint32_t idx = wb + lane + r_ * 64;
-    lds[pad_idx(idx)] = ar.lds_in(src[idx]);
+    lds[pad_idx(idx)] = src[idx];  // internal FP64 form
   }
   wave_sync();
   ntt_rounds<false, 2, FpArith, 16, kThreads, true>(lds, ar, twf + (uint64_t)i * 4 * N, k, logC, k1, j0);
@@ -1135,16 +1126,6 @@ static void check_batch(const fhe_ctx* ctx, const LimbBatch& lb) {
   if (mi >= (uint32_t)p.nmod() || mi0 >= (uint32_t)p.nmod()) fail(FHE_EINVAL, "NTT batch modulus index out of range");
 }
 
-// Register budget of the fused inner-product kernel on Q limbs: FHE_INNER_OCC=2 selects the variant
-// that fits two workgroups per CU.
-static bool inner_occ2() {
-  static const bool v = [] {
-    const char* e = std::getenv("FHE_INNER_OCC");
-    return e && std::atoi(e) == 2;
-  }();
-  return v;
-}
-
 static uint32_t ntt_blocks(const fhe_ctx* ctx, const LimbBatch& lb) {
   const uint64_t blocks = (uint64_t)(ctx->p.N >> kNttLogE) * lb.limbs * lb.npoly;
   if (blocks >= (1ull << 31)) fail(FHE_EINVAL, "NTT batch too large");
@@ -1228,6 +1209,7 @@ static void ntt_inverse_rows(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_
 
 void ntt_inverse(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st) {
   if (lb.limbs == 0 || lb.npoly == 0) return;
+  if (lb.raw_out) fail(FHE_EINVAL, "internal-form output is only for row phases of inverse transforms");
   check_batch(ctx, lb);
   check_holes(ctx, lb);
   ntt_phase<true, 2>(ctx, lb, "ntt_inv_p2_q", "ntt_inv_p2_p", lb.src != nullptr, st);
@@ -1317,7 +1299,9 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
   lb_in.src_stride = in_stride;
   if (cols_fusable(ctx, alpha)) {
     // 1-3 fused: row phase of the INTT here, then one kernel for the column phases and ModUp.
-    ntt_inverse_rows(ctx, lb_in, st);
+    LimbBatch lb_rows = lb_in;
+    lb_rows.raw_out = 1;
+    ntt_inverse_rows(ctx, lb_rows, st);
     const uint32_t le = cols_log_e(p);
     const size_t lds_mu = cols_lds_bytes(le);
     const uint64_t grid = (uint64_t)B * beta * (N >> le);
@@ -1355,6 +1339,7 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
       lb.hole_alpha = alpha;
       lb.hole_len = alpha;
       lb.hole_j0 = 0;
+      lb.raw_out = 1;
       ntt_forward_cols(ctx, lb, st);
     }
     if (beta_full < beta) {
@@ -1364,6 +1349,7 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
       lb.hole_alpha = alpha;
       lb.hole_len = cnt_last;
       lb.hole_j0 = beta_full;
+      lb.raw_out = 1;
       ntt_forward_cols(ctx, lb, st);
     }
   }
@@ -1374,14 +1360,9 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
   const double* twf = (const double*)ctx->t.twf.get();
   // per extended limb: beta digit words (input or ModUp row), 2 beta key words, 2 output words
   const double ib = 8.0 * N * (double)B * (3.0 * beta + 2.0);
-  if (inner_occ2())
-    FHE_LAUNCH_T("ntt_p2_inner_q", ib * nl, k_ntt_p2_inner_occ2<FpArith>, (uint64_t)B * nl * tiles, kInnerThreads, lds,
-                 st, B, nl, K, (uint32_t)p.nq, alpha, R, 0u, nl, p.logN, p.k1, mods_of(ctx), twf, in, in_stride, ext,
-                 keys, u);
-  else
-    FHE_LAUNCH_T("ntt_p2_inner_q", ib * nl, k_ntt_p2_inner<FpArith>, (uint64_t)B * nl * tiles, kInnerThreads, lds, st,
-                 B, nl, K, (uint32_t)p.nq, alpha, R, 0u, nl, p.logN, p.k1, mods_of(ctx), twf, in, in_stride, ext, keys,
-                 u);
+  FHE_LAUNCH_T("ntt_p2_inner_q", ib * nl, k_ntt_p2_inner<FpArith>, (uint64_t)B * nl * tiles, kInnerThreads, lds, st,
+               B, nl, K, (uint32_t)p.nq, alpha, R, 0u, nl, p.logN, p.k1, mods_of(ctx), twf, in, in_stride, ext, keys,
+               u);
   FHE_LAUNCH_T("ntt_p2_inner_p", ib * K, k_ntt_p2_inner<IntArith>, (uint64_t)B * K * tiles, kInnerThreads, lds, st, B, nl, K,
              (uint32_t)p.nq, alpha, R, nl, K, p.logN, p.k1, mods_of(ctx), ctx->t.tw.u64(), in, in_stride, ext, keys,
              u);
@@ -1415,7 +1396,9 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
     ntt_inverse(ctx, lb_up, st);
     FHE_LAUNCH("moddown_conv", e8 * 2 * (K + nl), k_moddown_conv, grid_for((uint64_t)B * 2 * N), 0, st, B, nl, K,
                (uint32_t)p.nq, p.logN, mods_of(ctx), ctx->t.moddown.u64(), u, conv);
-    ntt_forward_cols(ctx, LimbBatch{conv, nl, 2 * B, (uint64_t)nl * N, nl, 0}, st);
+    LimbBatch lb_conv{conv, nl, 2 * B, (uint64_t)nl * N, nl, 0};
+    lb_conv.raw_out = 1;
+    ntt_forward_cols(ctx, lb_conv, st);
   }
   FHE_LAUNCH("ntt_p2_combine", e8 * 2 * nl * 3.5, k_ntt_p2_combine<FpArith>, (uint64_t)2 * B * nl * tiles, lds, st, nl,
              K, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.moddown.u64(), u, conv, add, out);
@@ -1438,7 +1421,9 @@ void rescale(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const 
   if (cols_fusable(ctx, 1)) {
     // row phase of the dropped limb's INTT; column phases and the broadcast in one kernel; row
     // phase of the broadcast fused with the combine
-    ntt_inverse_rows(ctx, LimbBatch{tmp, 1, BC, N, 0, nl - 1}, st);
+    LimbBatch lb_last{tmp, 1, BC, N, 0, nl - 1};
+    lb_last.raw_out = 1;
+    ntt_inverse_rows(ctx, lb_last, st);
     const uint32_t le = cols_log_e(p);
     const size_t lds_rs = cols_lds_bytes(le);
     const uint64_t grid = (uint64_t)BC * (N >> le);

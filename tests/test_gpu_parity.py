@@ -169,6 +169,30 @@ def test_spmspm_parity_single_digit(fhe):
     _matmul_case(fhe, OP_PARAMS[1], 6, 5, 4, 0.4, 0.6, (4, 5, 6, 7))
 
 
+def test_unfused_split_fallback(fhe, monkeypatch):
+    """An NTT split outside the fused column kernels' compiled ones (k1 = 5 at N = 2^12) runs the
+    unfused ModUp / ModDown / rescale sequence and row-phase kernels with run-time stage counts;
+    the matmul stays bit-exact against the oracle."""
+    prm = OP_PARAMS[0]
+    op, okeys, _, _ = _setup(fhe, prm)
+    monkeypatch.setenv("FHE_NTT_K1", "5")
+    ctx = fhe.Context(*prm)
+    monkeypatch.delenv("FHE_NTT_K1")
+    sk = ctx.keygen(42)
+    m, k, n = 4, 5, 6
+    a = synth.sparse_dense(m, k, 0.4, "uniform", 21, 23)
+    b = synth.sparse_dense(k, n, 0.4, "uniform", 22, 24)
+    ipa, ixa, va = synth.to_csr(a)
+    ipb, ixb, vb = synth.to_csc(b)
+    _say("[fallback] k1=5 gpu")
+    C = ctx.spmspm(ctx.encrypt_csr(sk, m, k, ipa, ixa, va, seed=43), ctx.encrypt_csc(sk, k, n, ipb, ixb, vb, seed=44))
+    _say("[fallback] k1=5 oracle")
+    ref = spmspm.spmspm(op, okeys, spmspm.encrypt_csr(op, okeys, m, k, ipa, ixa, va, seed=43),
+                        spmspm.encrypt_csc(op, okeys, k, n, ipb, ixb, vb, seed=44))
+    for c, rct in enumerate(ref):
+        assert (ctx.export(C, c) == rct.data).all(), f"chunk {c}"
+
+
 @pytest.mark.parametrize("log_n", [14, 15, 16, 17])
 def test_ring_size_sweep(fhe, log_n):
     """Every supported ring size (two-phase NTT with 2-3 register rounds per phase, FP64 and integer
