@@ -191,6 +191,21 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
     md[2 * K + 2 * (size_t)K * p.nq + 2 * (size_t)p.nq + i] = P;
   }
   ctx->t.moddown = upload(md, st);
+  // FP64 form of the conversion constants for the fused kernel: per (k, i) the pair
+  // c0 = (P/p_k) mod q_i and c1 = c0 2^30 mod q_i, each with fl(c / q_i).
+  std::vector<double> mdf(4 * (size_t)K * p.nq, 0.0);
+  for (int kk = 0; kk < K; ++kk)
+    for (int i = 0; i < p.nq; ++i) {
+      const uint64_t qi = p.moduli[i];
+      const uint64_t c0 = md[2 * K + 2 * ((size_t)kk * p.nq + i)];
+      const uint64_t c1 = mulmod_host(c0, ((uint64_t)1 << 30) % qi, qi);
+      double* f = mdf.data() + 4 * ((size_t)kk * p.nq + i);
+      f[0] = (double)c0;
+      f[1] = (double)c0 / (double)qi;
+      f[2] = (double)c1;
+      f[3] = (double)c1 / (double)qi;
+    }
+  ctx->t.moddown_f = upload(mdf, st);
 
   // Rescale constants: q_l^-1 mod q_i for i < l.
   std::vector<uint64_t> rs(2 * (size_t)p.nq * p.nq, 0);

@@ -68,6 +68,10 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x) {
   asm volatile("" : "+v"(x));
   return x;
 }
+__device__ __forceinline__ double opaque(double x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
 
 // Integer arithmetic (special primes up to 61 bits): residues in [0, q) everywhere.
 // Key-switching key words are in Montgomery form (x R mod q, R = 2^64).
@@ -660,6 +664,7 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
     wave_sync();
   }
   uint64_t* out = ext + ((uint64_t)j * B + b) * R * N;
+#pragma unroll 1
   for (uint32_t row = 0; row < next - cnt; ++row) {
     const uint32_t e = row < lo ? row : row + cnt;
     const uint32_t mi = e < nl ? e : nq + (e - nl);
@@ -680,7 +685,7 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
         double v = 0.0;
 #pragma unroll
         for (uint32_t i = 0; i < ALPHA; ++i)
-          if (i < cnt) v += ar.mulc(y[i][r], cw[i], cwq[i]);
+          if (i < cnt) v += ar.mulc(opaque(y[i][r]), cw[i], cwq[i]);
         uint32_t g;
         const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
         work[pad_idx(li)] = ar.st(ar.red(v));
@@ -703,7 +708,7 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
         for (uint32_t i = 0; i < ALPHA; ++i) {
           if (i >= cnt) break;
           const uint64_t* cc = mrow + (uint64_t)i * 2 * next;
-          v = add_mod(v, shoup_mul((uint64_t)y[i][r], cc[0], cc[1], m.q), m.q);
+          v = add_mod(v, shoup_mul((uint64_t)opaque(y[i][r]), cc[0], cc[1], m.q), m.q);
         }
         uint32_t g;
         const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
@@ -725,14 +730,17 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
 // ModDown conversion fused with the column phases around it, per wavefront. Workgroup (item b,
 // component c, tile): the K special-prime limbs of u (row phase of the inverse NTT already applied)
 // go through the inverse column phase in LDS and are scaled to z_k = [u_(p_k) (P/p_k)^-1]_(p_k)
-// (N^-1 applied first), kept in registers and taken as centred representatives as in
-// k_moddown_conv; every Q limb's conversion is formed, goes through the forward column phase and is
-// written to conv [B][2][nl][N].
+// (N^-1 applied first) and centred (z_k - p_k when z_k > (p_k - 1)/2), which accounts for the
+// P mod q_i subtractions of k_moddown_conv. The centred z_k is kept in registers as two exact 30-bit
+// halves (high part signed), so every Q limb's conversion sum_k zc_k (P/p_k mod q_i) is formed in
+// exact FP64 from the constants c0 = (P/p_k) mod q_i and c1 = c0 2^30 mod q_i, goes through the
+// forward column phase and is written to conv [B][2][nl][N] in the FP64 kernels' internal form.
 template <int LOG_E, int NT, int KP, int K1>
 __global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, uint32_t nq, uint32_t logN,
                                                     const ModInfo* __restrict__ mods, const double* __restrict__ twf,
                                                     const uint64_t* __restrict__ twi, const uint64_t* __restrict__ tab,
-                                                    const uint64_t* __restrict__ u, uint64_t* __restrict__ conv) {
+                                                    const double* __restrict__ tabf, const uint64_t* __restrict__ u,
+                                                    uint64_t* __restrict__ conv) {
   constexpr uint32_t k1 = K1;  // column-phase stages (compile-time: round shapes and offsets fold)
   constexpr uint32_t E = 1u << LOG_E, EPT = E / NT;
   extern __shared__ uint64_t work[];
@@ -740,12 +748,11 @@ __global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, ui
   const uint32_t tile = blockIdx.x % tiles, bc = blockIdx.x / tiles;
   const uint32_t next = nl + K, k2 = logN - k1, logC = LOG_E - k1, logCw = logC - WaveSplit<NT>::kLogWaves;
   const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint64_t z[KP][EPT];
-  uint64_t half[KP];
+  int32_t zh[KP][EPT], zl[KP][EPT];
 #pragma unroll
   for (uint32_t kk = 0; kk < KP; ++kk) {
     const ModInfo m = mods[nq + kk];
-    half[kk] = (m.q - 1) / 2;
+    const uint64_t half = (m.q - 1) / 2;
     IntArith ar;
     ar.init(m);
     const uint64_t* src = u + ((uint64_t)bc * next + nl + kk) * N;
@@ -763,30 +770,39 @@ __global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, ui
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
       const uint64_t x = shoup_mul(work[pad_idx(li)], m.n_inv, m.n_inv_shoup, m.q);
-      z[kk][r] = shoup_mul(x, tab[2 * kk], tab[2 * kk + 1], m.q);
+      const uint64_t z = shoup_mul(x, tab[2 * kk], tab[2 * kk + 1], m.q);
+      const int64_t zc = z > half ? (int64_t)z - (int64_t)m.q : (int64_t)z;
+      zh[kk][r] = (int32_t)(zc >> 30);
+      zl[kk][r] = (int32_t)(zc & 0x3FFFFFFF);
     }
     wave_sync();
   }
-  const uint64_t* pq = tab + 2 * K;
-  const uint64_t* pmod = tab + 2 * K + 2 * (uint64_t)K * nq + 2 * nq;
+#pragma unroll 1
   for (uint32_t i = 0; i < nl; ++i) {
     const ModInfo m = mods[i];
     FpArith ar;
     ar.init(m);
+    double c0[KP], c0q[KP], c1[KP], c1q[KP];
+#pragma unroll
+    for (uint32_t kk = 0; kk < KP; ++kk) {
+      const double* f = tabf + 4 * ((uint64_t)kk * nq + i);
+      c0[kk] = f[0];
+      c0q[kk] = f[1];
+      c1[kk] = f[2];
+      c1q[kk] = f[3];
+    }
 #pragma unroll
     for (uint32_t r = 0; r < EPT; ++r) {
-      uint64_t acc = 0;
-      uint32_t nneg = 0;
+      // |zh|, zl < 2^30: each product's quotient estimate is off by at most 0.5 + 2^-22, so every
+      // term is below 0.6 q_i in magnitude and the sum of 2K terms stays far below 2^53
+      double acc = 0.0;
 #pragma unroll
-      for (uint32_t kk = 0; kk < KP; ++kk) {
-        const uint64_t* cc = pq + 2 * ((uint64_t)kk * nq + i);
-        acc = add_mod(acc, shoup_mul(z[kk][r], cc[0], cc[1], m.q), m.q);
-        nneg += z[kk][r] > half[kk] ? 1u : 0u;
-      }
-      for (uint32_t n = 0; n < nneg; ++n) acc = sub_mod(acc, pmod[i], m.q);
+      for (uint32_t kk = 0; kk < KP; ++kk)
+        acc += ar.mulc((double)(int32_t)opaque((uint32_t)zh[kk][r]), c1[kk], c1q[kk]) +
+               ar.mulc((double)(int32_t)opaque((uint32_t)zl[kk][r]), c0[kk], c0q[kk]);
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      work[pad_idx(li)] = ar.lds_in(acc);
+      work[pad_idx(li)] = ar.st(ar.red(acc));
     }
     wave_sync();
     ntt_rounds<false, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)i * 4 * N, k1, logC, 0, 0);
@@ -1377,7 +1393,8 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
     const double* twf0 = (const double*)ctx->t.twf.get();
 #define FHE_MODDOWN_COLS(KP, K1)                                                                            \
   FHE_LAUNCH_T("moddown_cols", bytes, (k_moddown_cols<11, 256, KP, K1>), grid, 256, lds_md, st, nl, K,        \
-               (uint32_t)p.nq, p.logN, mods_of(ctx), twf0, ctx->t.tw.u64(), ctx->t.moddown.u64(), u, conv)
+               (uint32_t)p.nq, p.logN, mods_of(ctx), twf0, ctx->t.tw.u64(), ctx->t.moddown.u64(),                 \
+               (const double*)ctx->t.moddown_f.get(), u, conv)
 #define FHE_MODDOWN_COLS_K(KP)             \
   switch (p.k1) {                          \
     case 6: FHE_MODDOWN_COLS(KP, 6); break; \
