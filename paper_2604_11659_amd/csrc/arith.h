@@ -29,6 +29,12 @@ FHE_HD uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a 
 
 FHE_HD uint64_t neg_mod(uint64_t a, uint64_t q) { return a == 0 ? 0 : q - a; }
 
+// a * w mod q up to one multiple of q: the result is in [0, 2q) for any a < 2^64 (Shoup's
+// estimate floor(a wp / 2^64) of floor(a w / q) is low by at most one).
+FHE_HD uint64_t shoup_mul_lazy(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+  return a * w - mulhi64(a, wp) * q;
+}
+
 // a * w mod q, w < q, wp = floor(w * 2^64 / q).
 FHE_HD uint64_t shoup_mul(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
   uint64_t qh = mulhi64(a, wp);

@@ -73,34 +73,46 @@ __device__ __forceinline__ double opaque(double x) {
   return x;
 }
 
-// Integer arithmetic (special primes up to 61 bits): residues in [0, q) everywhere.
-// Key-switching key words are in Montgomery form (x R mod q, R = 2^64).
+// Integer arithmetic for the special primes (p < 2^61, so 4p < 2^63), with lazy reduction in the
+// style of Harvey's NTT butterflies: forward butterflies keep values in [0, 4p) (the sum branch is
+// brought below 2p before use, the twiddle product is left in [0, 2p)), inverse butterflies keep
+// [0, 2p). Values leave the transform through lds_out / raw, which reduce to [0, p).
+// Key-switching key words are in Montgomery form (x R mod p, R = 2^64); the key product accepts
+// x < 4p since 4p * p < p * 2^64.
 struct IntArith {
   typedef uint64_t T;
   typedef uint64_t W;
   typedef uint64_t Acc;
-  uint64_t q, qinv;
+  uint64_t q, qinv, q2;
   __device__ __forceinline__ void init(const ModInfo& m) {
     q = m.q;
     qinv = m.qinv;
+    q2 = 2 * m.q;
   }
-  __device__ __forceinline__ uint64_t lds_in(uint64_t x) const { return x; }   // global -> LDS word
-  __device__ __forceinline__ uint64_t lds_out(uint64_t x) const { return x; }  // LDS word -> [0, q)
+  __device__ __forceinline__ uint64_t reduce4(uint64_t x) const {  // [0, 4p) -> [0, p)
+    x = x >= q2 ? x - q2 : x;
+    return x >= q ? x - q : x;
+  }
+  __device__ __forceinline__ uint64_t lds_in(uint64_t x) const { return x; }  // global -> LDS word
+  __device__ __forceinline__ uint64_t lds_out(uint64_t x) const { return reduce4(x); }  // -> [0, p)
+  __device__ __forceinline__ uint64_t raw(uint64_t x) const { return reduce4(x); }
   __device__ __forceinline__ T ld(uint64_t x) const { return x; }
   __device__ __forceinline__ uint64_t st(T x) const { return x; }
   __device__ __forceinline__ T from_u64(uint64_t x) const { return x; }
   __device__ __forceinline__ void round_end(T&) const {}
   __device__ __forceinline__ void ct(T& a, T& b, W w, W wx) const {
-    const T v = shoup_mul(b, w, wx, q);
-    b = sub_mod(a, v, q);
-    a = add_mod(a, v, q);
+    const T x = a >= q2 ? a - q2 : a;           // [0, 2p)
+    const T t = shoup_mul_lazy(b, w, wx, q);    // [0, 2p)
+    a = x + t;                                  // [0, 4p)
+    b = x - t + q2;                             // (0, 4p)
   }
   __device__ __forceinline__ void gs(T& a, T& b, W w, W wx) const {
-    const T u = a, v = b;
-    a = add_mod(u, v, q);
-    b = shoup_mul(sub_mod(u, v, q), w, wx, q);
+    const T u = a, v = b;                       // [0, 2p)
+    const T s = u + v;
+    a = s >= q2 ? s - q2 : s;                   // [0, 2p)
+    b = shoup_mul_lazy(u - v + q2, w, wx, q);   // [0, 2p)
   }
-  // Key inner product: acc + x * key (key word in Montgomery form), in [0, q).
+  // Key inner product: acc + x * key (key word in Montgomery form), in [0, p).
   __device__ __forceinline__ Acc kacc(Acc acc, T x, uint64_t kw) const {
     return add_mod(acc, mont_mul(x, kw, q, qinv), q);
   }
@@ -132,6 +144,7 @@ struct FpArith {
     const double x = __longlong_as_double((long long)bits);
     return (uint64_t)(x < 0.0 ? x + q : x);
   }
+  __device__ __forceinline__ uint64_t raw(uint64_t bits) const { return bits; }  // internal form as is
   __device__ __forceinline__ T ld(uint64_t bits) const { return __longlong_as_double((long long)bits); }
   __device__ __forceinline__ uint64_t st(T x) const { return (uint64_t)__double_as_longlong(x); }
   __device__ __forceinline__ T from_u64(uint64_t x) const { return (double)x; }
@@ -319,7 +332,7 @@ __global__ __launch_bounds__(kThreads) void k_ntt(LimbBatch lb, const ModInfo* _
 #pragma unroll
     for (uint32_t r_ = 0; r_ < kPer; ++r_) {
       const uint32_t idx = wb + ln + r_ * 64;
-      a[j0 + idx] = lb.raw_out ? lds[pad_idx(idx)] : ar.lds_out(lds[pad_idx(idx)]);
+      a[j0 + idx] = lb.raw_out ? ar.raw(lds[pad_idx(idx)]) : ar.lds_out(lds[pad_idx(idx)]);
     }
   } else {
     // columns are strided: coalesced loads and stores across the workgroup, rounds per wavefront
@@ -335,7 +348,7 @@ __global__ __launch_bounds__(kThreads) void k_ntt(LimbBatch lb, const ModInfo* _
 #pragma unroll
     for (uint32_t r_ = 0; r_ < kPer; ++r_) {
       const uint32_t idx = tid + r_ * kThreads;
-      uint64_t v = lb.raw_out ? lds[pad_idx(idx)] : ar.lds_out(lds[pad_idx(idx)]);
+      uint64_t v = lb.raw_out ? ar.raw(lds[pad_idx(idx)]) : ar.lds_out(lds[pad_idx(idx)]);
       if (kInv) v = shoup_mul(v, m.n_inv, m.n_inv_shoup, m.q);
       a[((idx >> logC) << k2) + (tile << logC) + (idx & (C - 1))] = v;
     }
@@ -720,7 +733,7 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
       for (uint32_t r = 0; r < EPT; ++r) {
         uint32_t g;
         const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-        o[g] = work[pad_idx(li)];
+        o[g] = ar.lds_out(work[pad_idx(li)]);
       }
     }
     wave_sync();
