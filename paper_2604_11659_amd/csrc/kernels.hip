@@ -486,12 +486,16 @@ __global__ __launch_bounds__(kThreads) void k_ntt_p2_combine(uint32_t nl, uint32
   if (ad) ad += (uint64_t)i * N + j0;
   uint64_t* o = out[b] + ((uint64_t)c * nl + i) * N + j0;
   const uint32_t ln = opaque(lane);
+  // exact FP64: |u - conv| < 1.5q + 2, so the product with P^-1 is below 0.9q and adding the
+  // [0, q) addend keeps the sum below 2q before the final reduction
+  const double pv = (double)pinv[0], pvq = pv * ar.qinv;
 #pragma unroll
   for (uint32_t r_ = 0; r_ < kPer; ++r_) {
     const uint32_t idx = wb + ln + r_ * 64;
-    uint64_t v = shoup_mul(sub_mod(uu[idx], ar.lds_out(lds[pad_idx(idx)]), m.q), pinv[0], pinv[1], m.q);
-    if (ad) v = add_mod(v, ad[idx], m.q);
-    o[idx] = v;
+    double v = ar.mulc((double)uu[idx] - ar.ld(lds[pad_idx(idx)]), pv, pvq);
+    if (ad) v += (double)ad[idx];
+    v = ar.red(v);
+    o[idx] = (uint64_t)(v < 0.0 ? v + ar.q : v);
   }
 }
 
@@ -974,10 +978,12 @@ __global__ __launch_bounds__(kThreads) void k_rescale_rows(uint32_t ncomp, uint3
   const uint64_t* x = in[b] + ((uint64_t)c * nl + i) * N + j0;
   uint64_t* o = out[b] + ((uint64_t)c * no + i) * N + j0;
   const uint32_t ln = opaque(lane);
+  const double iv = (double)inv[0], ivq = iv * ar.qinv;  // exact FP64 as in k_ntt_p2_combine
 #pragma unroll
   for (uint32_t r_ = 0; r_ < kPer; ++r_) {
     const uint32_t idx = wb + ln + r_ * 64;
-    o[idx] = shoup_mul(sub_mod(x[idx], ar.lds_out(lds[pad_idx(idx)]), m.q), inv[0], inv[1], m.q);
+    const double v = ar.red(ar.mulc((double)x[idx] - ar.ld(lds[pad_idx(idx)]), iv, ivq));
+    o[idx] = (uint64_t)(v < 0.0 ? v + ar.q : v);
   }
 }
 
