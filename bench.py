@@ -259,6 +259,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dnn", choices=sorted(synth.WORKLOADS) + sorted(synth.BATCH_WORKLOADS))
     ap.add_argument("--batch-cap", type=int, default=256, help="batching workload: matched pairs run per matmul")
+    ap.add_argument("--autotune", type=int, default=1, help="1: pick the NTT split by timing (untimed set-up)")
     ap.add_argument("--serve", action="store_true", help="run the request-loop benchmark instead")
     ap.add_argument("--serve-mix", type=int, default=1, help="1: N=2^16 and N=2^17 parameter sets, 0: N=2^16 only")
     ap.add_argument("--serve-sizes", default="16,32")
@@ -312,6 +313,8 @@ def main():
     B = ctx.encrypt_csc(sk, w.k, w.n, ipb, ixb, vb, seed=44)
     if w.rot_digits == 1:
         ctx.keygen_rotations(sk, ctx.plan_rotations(A, B))
+    tuned = ctx.autotune() if args.autotune else None  # schedule choice only: results are unchanged
+    log(f"autotune: {tuned}")
     setup_s = time.perf_counter() - t0
     st = ctx.plan_stats(A, B)
     log(f"setup {setup_s:.1f} s; plan {st}")
@@ -348,7 +351,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(1000 * dt / args.steps, 2), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": describe(w), "matched_pairs": st.matched_pairs, "products": st.products,
-                   "keyswitches": st.keyswitches, "parallelism": "single GPU, batched launches"},
+                   "keyswitches": st.keyswitches, "parallelism": "single GPU, batched launches",
+                   "ntt_split_autotuned": tuned},
         "matched_pairs_per_s": round(st.matched_pairs * value, 1),
         "keyswitch_per_s": round(st.keyswitches * value, 1),
         "ntt_keyswitch_algo_GBps": round(ks_bytes / (ks_ms * 1e6), 1) if ks_ms > 0 else None,

@@ -37,6 +37,10 @@ class ArgPack {
 };
 
 void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d);
+// Times top-level key switches of B synthetic polynomials for every admissible NTT split, keeps
+// the fastest in ctx (results are identical for every split). tried: (k1, ms per batch).
+void autotune_split(fhe_ctx* ctx, hipStream_t st, uint32_t B, std::vector<std::pair<int, double>>& tried,
+                    int& best_k1, double& best_ms);
 void keygen(fhe_ctx* ctx, uint64_t seed, hipStream_t st, fhe_sk* sk);
 void keygen_rotation_steps(fhe_ctx* ctx, const fhe_sk* sk, const std::vector<uint32_t>& steps, hipStream_t st);
 

@@ -1,0 +1,89 @@
+// Autotuner for the schedule choices that leave every result bit unchanged.
+//
+// The one knob with a real effect is the NTT split: a limb is transformed as 2^k1 columns by
+// 2^(logN - k1) rows, and k1 decides how the stages are grouped into LDS rounds, how wide the
+// column segments are and which kernels (fused column kernels for k1 in [6, 8]) run. The transform
+// itself is the same for every split, so the tuner may pick any of them. It times a batch of
+// synthetic key switches at the top level (the operation that dominates the matmul) for every
+// admissible split, keeps the fastest in the context and reports the timings.
+#include <random>
+
+#include "ckks.h"
+#include "kernels.h"
+
+using namespace fhe;
+
+namespace {
+
+// Mean time of `reps` batched key switches of `B` synthetic polynomials at `nl` limbs.
+double time_keyswitch(fhe_ctx* ctx, uint32_t B, uint32_t nl, const DevBuf& in, const ArgPack& ap, size_t o_key,
+                      size_t o_add, size_t o_out, DevBuf& ws, int reps, hipStream_t st) {
+  hipEvent_t a, b;
+  HIPCHECK(hipEventCreate(&a));
+  HIPCHECK(hipEventCreate(&b));
+  const uint64_t stride = (uint64_t)nl * ctx->p.N;
+  // warm-up (code objects, caches)
+  keyswitch(ctx, B, nl, in.u64(), stride, ap.at<const uint64_t*>(o_key), ap.at<const uint64_t*>(o_add),
+            ap.at<uint64_t*>(o_out), ws.u64(), st);
+  HIPCHECK(hipEventRecord(a, st));
+  for (int r = 0; r < reps; ++r)
+    keyswitch(ctx, B, nl, in.u64(), stride, ap.at<const uint64_t*>(o_key), ap.at<const uint64_t*>(o_add),
+              ap.at<uint64_t*>(o_out), ws.u64(), st);
+  HIPCHECK(hipEventRecord(b, st));
+  HIPCHECK(hipEventSynchronize(b));
+  float ms = 0;
+  HIPCHECK(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms / reps;
+}
+
+}  // namespace
+
+void fhe::autotune_split(fhe_ctx* ctx, hipStream_t st, uint32_t B, std::vector<std::pair<int, double>>& tried,
+                         int& best_k1, double& best_ms) {
+  if (B < 1 || B > 4096) fail(FHE_EINVAL, "autotune batch must be in [1, 4096]");
+  if (!ctx->relin) fail(FHE_EKEY, "autotuning times key switches with the relinearisation key: run keygen first");
+  std::lock_guard<std::mutex> lk(ctx->exec_mu);
+  Params& p = ctx->p;
+  const uint32_t N = p.N, nl = (uint32_t)p.nq;
+  // synthetic input: residues in [0, q_i) on every limb (values do not matter for timing)
+  std::vector<uint64_t> host((size_t)B * nl * N);
+  std::mt19937_64 rng(12345);
+  for (uint32_t b = 0; b < B; ++b)
+    for (uint32_t i = 0; i < nl; ++i) {
+      uint64_t* row = host.data() + ((size_t)b * nl + i) * N;
+      for (uint32_t k = 0; k < N; ++k) row[k] = rng() % p.moduli[i];
+    }
+  DevBuf in = upload(host, st);
+  DevBuf out((size_t)B * 2 * nl * N * 8, st);
+  DevBuf ws(keyswitch_ws_elems(ctx, B, nl) * 8, st);
+  ArgPack ap;
+  std::vector<const uint64_t*> keys(B, ctx->relin->buf.u64());
+  std::vector<uint64_t*> outs(B);
+  for (uint32_t b = 0; b < B; ++b) outs[b] = out.u64() + (size_t)b * 2 * nl * N;
+  const std::vector<const uint64_t*> adds(2 * (size_t)B, nullptr);  // no addend
+  const size_t o_key = ap.push(keys), o_add = ap.push(adds), o_out = ap.push(outs);
+  ap.upload(st);
+  const uint32_t k1_orig = p.k1;
+  const int lo = std::max<int>(1, (int)p.logN - 9), hi = std::min<int>(9, (int)p.logN - 1);
+  tried.clear();
+  best_k1 = (int)k1_orig;
+  best_ms = 0;
+  try {
+    for (int k1 = lo; k1 <= hi; ++k1) {
+      p.k1 = (uint32_t)k1;
+      const double ms = time_keyswitch(ctx, B, nl, in, ap, o_key, o_add, o_out, ws, 3, st);
+      tried.emplace_back(k1, ms);
+      if (best_ms == 0 || ms < best_ms) {
+        best_ms = ms;
+        best_k1 = k1;
+      }
+    }
+  } catch (...) {
+    p.k1 = k1_orig;
+    throw;
+  }
+  p.k1 = (uint32_t)best_k1;
+  HIPCHECK(hipStreamSynchronize(st));
+}

@@ -193,6 +193,31 @@ def test_unfused_split_fallback(fhe, monkeypatch):
         assert (ctx.export(C, c) == rct.data).all(), f"chunk {c}"
 
 
+def test_autotune_keeps_results_bit_exact(fhe):
+    """The autotuner tries every admissible NTT split and keeps the fastest; the transform is the same
+    for all of them, so a matmul afterwards is still bit-exact against the oracle."""
+    prm = OP_PARAMS[0]
+    op, okeys, _, _ = _setup(fhe, prm)
+    ctx = fhe.Context(*prm)
+    sk = ctx.keygen(42)
+    _say("[autotune] tuning")
+    rep = ctx.autotune(batch=4)
+    log_n = prm[0]
+    assert sorted(rep["tried"]) == list(range(max(1, log_n - 9), min(9, log_n - 1) + 1))
+    assert rep["k1"] in rep["tried"] and rep["ms_per_batch"] > 0
+    m, k, n = 3, 4, 5
+    a = synth.sparse_dense(m, k, 0.3, "uniform", 31, 33)
+    b = synth.sparse_dense(k, n, 0.3, "uniform", 32, 34)
+    ipa, ixa, va = synth.to_csr(a)
+    ipb, ixb, vb = synth.to_csc(b)
+    _say(f"[autotune] k1={rep['k1']} matmul")
+    C = ctx.spmspm(ctx.encrypt_csr(sk, m, k, ipa, ixa, va, seed=43), ctx.encrypt_csc(sk, k, n, ipb, ixb, vb, seed=44))
+    ref = spmspm.spmspm(op, okeys, spmspm.encrypt_csr(op, okeys, m, k, ipa, ixa, va, seed=43),
+                        spmspm.encrypt_csc(op, okeys, k, n, ipb, ixb, vb, seed=44))
+    for c, rct in enumerate(ref):
+        assert (ctx.export(C, c) == rct.data).all(), f"chunk {c}"
+
+
 @pytest.mark.parametrize("log_n", [14, 15, 16, 17])
 def test_ring_size_sweep(fhe, log_n):
     """Every supported ring size (two-phase NTT with 2-3 register rounds per phase, FP64 and integer
