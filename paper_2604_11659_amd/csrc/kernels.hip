@@ -62,6 +62,25 @@ constexpr uint32_t kNttLdsElems = kNttE + (kNttE >> 4);
 
 __device__ __forceinline__ uint32_t pad_idx(uint32_t i) { return i + (i >> 4); }
 
+// LDS layouts of a tile: the default pads one word per 16 (rows of the row phase, columns of the
+// standalone column phase); ColSwz<K1> is the column layout of the fused column kernels (2048-element
+// tiles, 4 wavefronts, K1 column stages): column c of row x is stored at x C + (c ^ (h(x) Cw)), an
+// XOR swizzle inside the row that sends the rows touched by one 16-lane LDS access to different
+// banks (conflict-free for K1 = 6, 7; two-way for K1 = 8).
+struct PadLayout {
+  __device__ __forceinline__ static uint32_t idx(uint32_t i) { return i + (i >> 4); }
+};
+template <int K1>
+struct ColSwz {
+  static constexpr uint32_t kLogC = 11 - K1, kLogCw = kLogC - 2;
+  __device__ __forceinline__ static uint32_t h(uint32_t x) {
+    if (K1 == 6) return (x ^ (x >> 3)) & 1;
+    if (K1 == 7) return (x ^ (x >> 1) ^ (x >> 3)) & 3;
+    return (x ^ (x >> 2)) & 3;
+  }
+  __device__ __forceinline__ static uint32_t idx(uint32_t li) { return li ^ (h(li >> kLogC) << kLogCw); }
+};
+
 // A copy of x the compiler cannot see through: index arithmetic derived from it is recomputed
 // where it is used instead of being kept live (in registers) across the transform rounds.
 __device__ __forceinline__ uint32_t opaque(uint32_t x) {
@@ -197,7 +216,7 @@ struct WaveSplit {
   static constexpr uint32_t kLogWaves = kWaves == 1 ? 0 : kWaves == 2 ? 1 : kWaves == 4 ? 2 : kWaves == 8 ? 3 : 4;
 };
 
-template <int M, bool kInv, int kPhase, class A, int EPT, int NT, bool kWave>
+template <int M, bool kInv, int kPhase, class A, int EPT, int NT, bool kWave, class L>
 __device__ __forceinline__ void ntt_round(uint64_t* lds, const A& ar, const typename A::W* tw2, uint32_t lo,
                                           uint32_t k, uint32_t logC, uint32_t sbase, uint64_t j0) {
   constexpr uint32_t GM = 1u << M, G = EPT >> M;
@@ -226,7 +245,7 @@ __device__ __forceinline__ void ntt_round(uint64_t* lds, const A& ar, const type
     for (uint32_t i = 0; i < GM; ++i) {
       const uint32_t x = xb | (i << lo);
       const uint32_t li = kPhase == 1 ? (x << logC) + cc[u] : (cc[u] << k) + x;
-      r[u * GM + i] = ar.ld(lds[pad_idx(li)]);
+      r[u * GM + i] = ar.ld(lds[L::idx(li)]);
     }
   }
 #pragma unroll
@@ -258,7 +277,7 @@ __device__ __forceinline__ void ntt_round(uint64_t* lds, const A& ar, const type
       const uint32_t x = xb | (i << lo);
       const uint32_t li = kPhase == 1 ? (x << logC) + cc[u] : (cc[u] << k) + x;
       ar.round_end(r[u * GM + i]);
-      lds[pad_idx(li)] = ar.st(r[u * GM + i]);
+      lds[L::idx(li)] = ar.st(r[u * GM + i]);
     }
   }
 }
@@ -270,7 +289,7 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <bool kInv, int kPhase, class A, int EPT, int NT, bool kWave = false>
+template <bool kInv, int kPhase, class A, int EPT, int NT, bool kWave = false, class L = PadLayout>
 __device__ __forceinline__ void ntt_rounds(uint64_t* lds, const A& ar, const typename A::W* tw2, uint32_t k,
                                            uint32_t logC, uint32_t sbase, uint64_t j0) {
   // Rounds of MB = log2(EPT) bits. Forward: chunks from the top ([k-MB, k), [k-2MB, k-MB), ...,
@@ -284,13 +303,13 @@ __device__ __forceinline__ void ntt_rounds(uint64_t* lds, const A& ar, const typ
     const uint32_t lo = hi >= MB ? hi - MB : 0;
     switch (hi - lo) {
       case 4:
-        if constexpr (MB >= 4) ntt_round<4, kInv, kPhase, A, EPT, NT, kWave>(lds, ar, tw2, lo, k, logC, sbase, j0);
+        if constexpr (MB >= 4) ntt_round<4, kInv, kPhase, A, EPT, NT, kWave, L>(lds, ar, tw2, lo, k, logC, sbase, j0);
         break;
       case 3:
-        if constexpr (MB >= 3) ntt_round<3, kInv, kPhase, A, EPT, NT, kWave>(lds, ar, tw2, lo, k, logC, sbase, j0);
+        if constexpr (MB >= 3) ntt_round<3, kInv, kPhase, A, EPT, NT, kWave, L>(lds, ar, tw2, lo, k, logC, sbase, j0);
         break;
-      case 2: ntt_round<2, kInv, kPhase, A, EPT, NT, kWave>(lds, ar, tw2, lo, k, logC, sbase, j0); break;
-      default: ntt_round<1, kInv, kPhase, A, EPT, NT, kWave>(lds, ar, tw2, lo, k, logC, sbase, j0); break;
+      case 2: ntt_round<2, kInv, kPhase, A, EPT, NT, kWave, L>(lds, ar, tw2, lo, k, logC, sbase, j0); break;
+      default: ntt_round<1, kInv, kPhase, A, EPT, NT, kWave, L>(lds, ar, tw2, lo, k, logC, sbase, j0); break;
     }
     if (kWave)
       wave_sync();
@@ -643,6 +662,8 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
                                                   const uint64_t* __restrict__ twi, const uint64_t* __restrict__ tab,
                                                   const uint64_t* __restrict__ dc2, uint64_t* __restrict__ ext) {
   constexpr uint32_t k1 = K1;  // column-phase stages (compile-time: round shapes and offsets fold)
+  typedef ColSwz<K1> Lay;
+  static_assert(LOG_E == 11 && NT == 256, "ColSwz assumes 2048-element tiles on 4 wavefronts");
   constexpr uint32_t E = 1u << LOG_E, EPT = E / NT;
   extern __shared__ uint64_t work[];
   const uint32_t N = 1u << logN, tiles = N >> LOG_E;
@@ -664,10 +685,10 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
     for (uint32_t r = 0; r < EPT; ++r) {
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      work[pad_idx(li)] = src[g];  // row-phase output in internal FP64 form
+      work[Lay::idx(li)] = src[g];  // row-phase output in internal FP64 form
     }
     wave_sync();
-    ntt_rounds<true, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)(lo + i) * 4 * N + 2 * (uint64_t)N, k1,
+    ntt_rounds<true, 1, FpArith, EPT, NT, true, Lay>(work, ar, twf + (uint64_t)(lo + i) * 4 * N + 2 * (uint64_t)N, k1,
                                                 logC, 0, 0);
     const double c = (double)shoup_mul(m.n_inv, blk[2 * i], blk[2 * i + 1], m.q);
     const double cq = c / ar.q;
@@ -675,7 +696,7 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
     for (uint32_t r = 0; r < EPT; ++r) {
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      const double v = ar.mulc(ar.ld(work[pad_idx(li)]), c, cq);
+      const double v = ar.mulc(ar.ld(work[Lay::idx(li)]), c, cq);
       y[i][r] = v < 0.0 ? v + ar.q : v;  // [0, q_i)
     }
     wave_sync();
@@ -705,15 +726,15 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
           if (i < cnt) v += ar.mulc(opaque(y[i][r]), cw[i], cwq[i]);
         uint32_t g;
         const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-        work[pad_idx(li)] = ar.st(ar.red(v));
+        work[Lay::idx(li)] = ar.st(ar.red(v));
       }
       wave_sync();
-      ntt_rounds<false, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)mi * 4 * N, k1, logC, 0, 0);
+      ntt_rounds<false, 1, FpArith, EPT, NT, true, Lay>(work, ar, twf + (uint64_t)mi * 4 * N, k1, logC, 0, 0);
 #pragma unroll
       for (uint32_t r = 0; r < EPT; ++r) {
         uint32_t g;
         const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-        o[g] = work[pad_idx(li)];  // internal FP64 form, read by the row-phase inner product
+        o[g] = work[Lay::idx(li)];  // internal FP64 form, read by the row-phase inner product
       }
     } else {
       IntArith ar;
@@ -729,15 +750,15 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
         }
         uint32_t g;
         const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-        work[pad_idx(li)] = v;
+        work[Lay::idx(li)] = v;
       }
       wave_sync();
-      ntt_rounds<false, 1, IntArith, EPT, NT, true>(work, ar, twi + (uint64_t)mi * 4 * N, k1, logC, 0, 0);
+      ntt_rounds<false, 1, IntArith, EPT, NT, true, Lay>(work, ar, twi + (uint64_t)mi * 4 * N, k1, logC, 0, 0);
 #pragma unroll
       for (uint32_t r = 0; r < EPT; ++r) {
         uint32_t g;
         const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-        o[g] = ar.lds_out(work[pad_idx(li)]);
+        o[g] = ar.lds_out(work[Lay::idx(li)]);
       }
     }
     wave_sync();
@@ -759,6 +780,8 @@ __global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, ui
                                                     const double* __restrict__ tabf, const uint64_t* __restrict__ u,
                                                     uint64_t* __restrict__ conv) {
   constexpr uint32_t k1 = K1;  // column-phase stages (compile-time: round shapes and offsets fold)
+  typedef ColSwz<K1> Lay;
+  static_assert(LOG_E == 11 && NT == 256, "ColSwz assumes 2048-element tiles on 4 wavefronts");
   constexpr uint32_t E = 1u << LOG_E, EPT = E / NT;
   extern __shared__ uint64_t work[];
   const uint32_t N = 1u << logN, tiles = N >> LOG_E;
@@ -777,16 +800,16 @@ __global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, ui
     for (uint32_t r = 0; r < EPT; ++r) {
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      work[pad_idx(li)] = src[g];
+      work[Lay::idx(li)] = src[g];
     }
     wave_sync();
-    ntt_rounds<true, 1, IntArith, EPT, NT, true>(work, ar, twi + (uint64_t)(nq + kk) * 4 * N + 2 * (uint64_t)N, k1,
+    ntt_rounds<true, 1, IntArith, EPT, NT, true, Lay>(work, ar, twi + (uint64_t)(nq + kk) * 4 * N + 2 * (uint64_t)N, k1,
                                                  logC, 0, 0);
 #pragma unroll
     for (uint32_t r = 0; r < EPT; ++r) {
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      const uint64_t x = shoup_mul(work[pad_idx(li)], m.n_inv, m.n_inv_shoup, m.q);
+      const uint64_t x = shoup_mul(work[Lay::idx(li)], m.n_inv, m.n_inv_shoup, m.q);
       const uint64_t z = shoup_mul(x, tab[2 * kk], tab[2 * kk + 1], m.q);
       const int64_t zc = z > half ? (int64_t)z - (int64_t)m.q : (int64_t)z;
       zh[kk][r] = (int32_t)(zc >> 30);
@@ -819,16 +842,16 @@ __global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, ui
                ar.mulc((double)(int32_t)opaque((uint32_t)zl[kk][r]), c0[kk], c0q[kk]);
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      work[pad_idx(li)] = ar.st(ar.red(acc));
+      work[Lay::idx(li)] = ar.st(ar.red(acc));
     }
     wave_sync();
-    ntt_rounds<false, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)i * 4 * N, k1, logC, 0, 0);
+    ntt_rounds<false, 1, FpArith, EPT, NT, true, Lay>(work, ar, twf + (uint64_t)i * 4 * N, k1, logC, 0, 0);
     uint64_t* o = conv + ((uint64_t)bc * nl + i) * N;
 #pragma unroll
     for (uint32_t r = 0; r < EPT; ++r) {
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      o[g] = work[pad_idx(li)];  // internal FP64 form, read by the combine
+      o[g] = work[Lay::idx(li)];  // internal FP64 form, read by the combine
     }
     wave_sync();
   }
@@ -892,6 +915,8 @@ __global__ __launch_bounds__(NT) void k_rescale_cols(uint32_t nl, uint32_t logN,
                                                     const ModInfo* __restrict__ mods, const double* __restrict__ twf,
                                                     const uint64_t* __restrict__ tmp, uint64_t* __restrict__ w) {
   constexpr uint32_t k1 = K1;  // column-phase stages (compile-time: round shapes and offsets fold)
+  typedef ColSwz<K1> Lay;
+  static_assert(LOG_E == 11 && NT == 256, "ColSwz assumes 2048-element tiles on 4 wavefronts");
   constexpr uint32_t E = 1u << LOG_E, EPT = E / NT;
   extern __shared__ uint64_t work[];
   const uint32_t N = 1u << logN, tiles = N >> LOG_E;
@@ -908,17 +933,17 @@ __global__ __launch_bounds__(NT) void k_rescale_cols(uint32_t nl, uint32_t logN,
     for (uint32_t r = 0; r < EPT; ++r) {
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      work[pad_idx(li)] = src[g];  // row-phase output in internal FP64 form
+      work[Lay::idx(li)] = src[g];  // row-phase output in internal FP64 form
     }
     wave_sync();
-    ntt_rounds<true, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)no * 4 * N + 2 * (uint64_t)N, k1, logC, 0,
+    ntt_rounds<true, 1, FpArith, EPT, NT, true, Lay>(work, ar, twf + (uint64_t)no * 4 * N + 2 * (uint64_t)N, k1, logC, 0,
                                                 0);
     const double c = (double)m.n_inv, cq = c / ar.q;
 #pragma unroll
     for (uint32_t r = 0; r < EPT; ++r) {
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      double v = ar.mulc(ar.ld(work[pad_idx(li)]), c, cq);  // |v| <= 0.7 q_l
+      double v = ar.mulc(ar.ld(work[Lay::idx(li)]), c, cq);  // |v| <= 0.7 q_l
       v = v < 0.0 ? v + ar.q : v;                             // [0, q_l)
       vs[r] = v > 0.5 * (ar.q - 1.0) ? v - ar.q : v;          // centred
     }
@@ -932,16 +957,16 @@ __global__ __launch_bounds__(NT) void k_rescale_cols(uint32_t nl, uint32_t logN,
     for (uint32_t r = 0; r < EPT; ++r) {
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      work[pad_idx(li)] = ar.st(vs[r]);
+      work[Lay::idx(li)] = ar.st(vs[r]);
     }
     wave_sync();
-    ntt_rounds<false, 1, FpArith, EPT, NT, true>(work, ar, twf + (uint64_t)i * 4 * N, k1, logC, 0, 0);
+    ntt_rounds<false, 1, FpArith, EPT, NT, true, Lay>(work, ar, twf + (uint64_t)i * 4 * N, k1, logC, 0, 0);
     uint64_t* o = w + ((uint64_t)bc * no + i) * N;
 #pragma unroll
     for (uint32_t r = 0; r < EPT; ++r) {
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      o[g] = work[pad_idx(li)];  // internal FP64 form, read by k_rescale_rows
+      o[g] = work[Lay::idx(li)];  // internal FP64 form, read by k_rescale_rows
     }
     wave_sync();
   }
