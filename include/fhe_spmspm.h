@@ -143,9 +143,10 @@ int fhe_spmspm_batch(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fh
 int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B,
                            const int64_t* pair_begin, const int64_t* pair_end, void* stream, fhe_mat** C_out);
 
-/* Autotuner (batch scheduler): times `batch` synthetic key switches at the top level (with the
- * relinearisation key) for every admissible NTT split 2^k1 x 2^(log_n - k1) and keeps the fastest in
- * ctx for all later calls. Every split computes the same transform, so results are unchanged; only
+/* Autotuner (batch scheduler): times `batch` synthetic key switches at the top level and two levels
+ * below it (median of 5 runs each, relinearisation key) for every admissible NTT split
+ * 2^k1 x 2^(log_n - k1) and keeps the fastest in ctx for all later calls (the current split unless
+ * another one is at least 2% faster). Every split computes the same transform, so results are unchanged; only
  * the kernel schedule (LDS rounds, fused column kernels, row segment width) differs. Reports the
  * chosen k1 and its time per batch (ms); if cap > 0, the first cap candidates tried (k1_tried[i],
  * ms_tried[i]) and their count (n_tried). Needs fhe_keygen first (FHE_EKEY); batch in [1, 4096]

@@ -51,9 +51,13 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
                hipStream_t st);
 
 // Rescale of B ciphertexts [ncomp][nl][N] -> [ncomp][nl-1][N] (nearest rounding of the dropped limb).
+// With mask_galois (device array of B Galois elements, needs rescale_fuses_mask and nl <= nq - 1),
+// every input is first multiplied by its one-hot mask tau_(galois[b])(base mask), on the fly: the
+// result equals mask_mul followed by rescale.
 size_t rescale_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl);
+bool rescale_fuses_mask(const fhe_ctx* ctx);
 void rescale(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const uint64_t* const* in,
-             uint64_t* const* out, uint64_t* ws, hipStream_t st);
+             uint64_t* const* out, uint64_t* ws, hipStream_t st, const uint32_t* mask_galois = nullptr);
 
 // out[b] = in[b] * tau_(galois[b])(base mask) (one-hot mask), [2][nl][N], nl <= nq - 1.
 void mask_mul(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* const* in, const uint32_t* galois,

@@ -857,7 +857,12 @@ __global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, ui
   }
 }
 
+// tmp[bc] = the last limb of in[b] component c; with galois != NULL, multiplied by the one-hot mask
+// tau_(galois[b])(base mask) on the fly (the mask multiply fused into rescale).
 __global__ __launch_bounds__(kThreads) void k_copy_last(uint32_t B, uint32_t ncomp, uint32_t nl, uint32_t logN,
+                                                       const ModInfo* __restrict__ mods,
+                                                       const uint64_t* __restrict__ maskm,
+                                                       const uint32_t* __restrict__ galois,
                                                        const uint64_t* const* __restrict__ in,
                                                        uint64_t* __restrict__ tmp) {
   const uint32_t N = 1u << logN;
@@ -865,7 +870,12 @@ __global__ __launch_bounds__(kThreads) void k_copy_last(uint32_t B, uint32_t nco
   for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < total; t += (uint64_t)gridDim.x * kThreads) {
     const uint32_t k = (uint32_t)t & (N - 1);
     const uint32_t bc = (uint32_t)(t >> logN), b = bc / ncomp, c = bc - b * ncomp;
-    tmp[t] = in[b][((uint64_t)c * nl + nl - 1) * N + k];
+    uint64_t v = in[b][((uint64_t)c * nl + nl - 1) * N + k];
+    if (galois) {
+      const ModInfo m = mods[nl - 1];
+      v = mont_mul(v, maskm[((uint64_t)(nl - 1) << logN) + automorph_src(k, galois[b], logN)], m.q, m.qinv);
+    }
+    tmp[t] = v;
   }
 }
 
@@ -978,6 +988,8 @@ __global__ __launch_bounds__(kThreads) void k_rescale_rows(uint32_t ncomp, uint3
                                                           uint32_t k1, const ModInfo* __restrict__ mods,
                                                           const double* __restrict__ twf,
                                                           const uint64_t* __restrict__ tab,
+                                                          const uint64_t* __restrict__ maskm,
+                                                          const uint32_t* __restrict__ galois,
                                                           const uint64_t* const* __restrict__ in,
                                                           const uint64_t* __restrict__ w,
                                                           uint64_t* const* __restrict__ out) {
@@ -1007,7 +1019,10 @@ __global__ __launch_bounds__(kThreads) void k_rescale_rows(uint32_t ncomp, uint3
 #pragma unroll
   for (uint32_t r_ = 0; r_ < kPer; ++r_) {
     const uint32_t idx = wb + ln + r_ * 64;
-    const double v = ar.red(ar.mulc((double)x[idx] - ar.ld(lds[pad_idx(idx)]), iv, ivq));
+    uint64_t xv = x[idx];
+    if (galois)  // one-hot mask multiply fused in (mask in Montgomery form)
+      xv = mont_mul(xv, maskm[((uint64_t)i << logN) + automorph_src(j0 + idx, galois[b], logN)], m.q, m.qinv);
+    const double v = ar.red(ar.mulc((double)xv - ar.ld(lds[pad_idx(idx)]), iv, ivq));
     o[idx] = (uint64_t)(v < 0.0 ? v + ar.q : v);
   }
 }
@@ -1469,16 +1484,21 @@ size_t rescale_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t
   return (size_t)B * ncomp * ctx->p.N * nl;
 }
 
+bool rescale_fuses_mask(const fhe_ctx* ctx) { return cols_fusable(ctx, 1); }
+
 void rescale(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const uint64_t* const* in,
-             uint64_t* const* out, uint64_t* ws, hipStream_t st) {
+             uint64_t* const* out, uint64_t* ws, hipStream_t st, const uint32_t* mask_galois) {
   if (!B) return;
   const Params& p = ctx->p;
   if (nl < 2 || nl > (uint32_t)p.nq) fail(FHE_ELEVEL, "rescale needs at least two limbs");
+  if (mask_galois && (!rescale_fuses_mask(ctx) || nl > (uint32_t)p.nq - 1))
+    fail(FHE_EINVAL, "mask-fused rescale needs the fused column kernels and a level below the top");
   const uint32_t N = p.N, BC = B * ncomp;
   const double e8 = 8.0 * N * BC;
   uint64_t* tmp = ws;                       // [BC][N]
   uint64_t* w = ws + (size_t)BC * N;        // [BC][nl-1][N]
-  FHE_LAUNCH("copy_last", e8 * 2, k_copy_last, grid_for((uint64_t)BC * N), 0, st, B, ncomp, nl, p.logN, in, tmp);
+  FHE_LAUNCH("copy_last", e8 * 2, k_copy_last, grid_for((uint64_t)BC * N), 0, st, B, ncomp, nl, p.logN, mods_of(ctx),
+             ctx->t.mask.u64(), mask_galois, in, tmp);
   if (cols_fusable(ctx, 1)) {
     // row phase of the dropped limb's INTT; column phases and the broadcast in one kernel; row
     // phase of the broadcast fused with the combine
@@ -1506,7 +1526,8 @@ void rescale(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const 
     }
     const size_t lds = kNttLdsElems * sizeof(uint64_t);
     FHE_LAUNCH("rescale_rows", e8 * 3 * (nl - 1), k_rescale_rows, (uint64_t)BC * (nl - 1) * (N >> kNttLogE), lds, st,
-               ncomp, nl, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.rescale.u64(), in, w, out);
+               ncomp, nl, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.rescale.u64(), ctx->t.mask.u64(),
+               mask_galois, in, w, out);
     return;
   }
   ntt_inverse(ctx, LimbBatch{tmp, 1, BC, N, 0, nl - 1}, st);

@@ -330,8 +330,13 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st) {
                    o_cu = ap.push(cur);
       const uint32_t Bn = (uint32_t)nb;
       ops.push_back([=, &ap] {
-        mask_mul(ctx, Bn, nl1, ap.at<const uint64_t*>(o_mi), ap.at<uint32_t>(o_mg), ap.at<uint64_t*>(o_mo), st);
-        rescale(ctx, Bn, 2, nl1, ap.at<const uint64_t*>(o_ri), ap.at<uint64_t*>(o_cu), ws.rsws, st);
+        if (rescale_fuses_mask(ctx)) {  // mask multiply applied inside the rescale's reads
+          rescale(ctx, Bn, 2, nl1, ap.at<const uint64_t*>(o_mi), ap.at<uint64_t*>(o_cu), ws.rsws, st,
+                  ap.at<uint32_t>(o_mg));
+        } else {
+          mask_mul(ctx, Bn, nl1, ap.at<const uint64_t*>(o_mi), ap.at<uint32_t>(o_mg), ap.at<uint64_t*>(o_mo), st);
+          rescale(ctx, Bn, 2, nl1, ap.at<const uint64_t*>(o_ri), ap.at<uint64_t*>(o_cu), ws.rsws, st);
+        }
       });
       for (int t = 0; t < p.rot_digits; ++t) {
         std::vector<const uint64_t*> src;

@@ -321,7 +321,7 @@ class Context(_Handle):
     def autotune(self, batch: int | None = None, stream=None) -> dict:
         """Pick the fastest NTT split for this context (results are unchanged); returns the timings."""
         if batch is None:
-            batch = 32 if self.N <= (1 << 15) else 8
+            batch = {12: 256, 13: 256, 14: 256, 15: 128, 16: 32}.get(self.N.bit_length() - 1, 12)
         k1, ms, n = c_i32(), c_dbl(), c_i32()
         kt = np.zeros(16, np.int32)
         mt = np.zeros(16, np.float64)
