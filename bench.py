@@ -260,6 +260,7 @@ def main():
     ap.add_argument("--workload", default="dnn", choices=sorted(synth.WORKLOADS) + sorted(synth.BATCH_WORKLOADS))
     ap.add_argument("--batch-cap", type=int, default=256, help="batching workload: matched pairs run per matmul")
     ap.add_argument("--autotune", type=int, default=1, help="1: pick the NTT split by timing (untimed set-up)")
+    ap.add_argument("--autotune-pairs", type=int, default=4000, help="matched pairs timed per candidate split")
     ap.add_argument("--serve", action="store_true", help="run the request-loop benchmark instead")
     ap.add_argument("--serve-mix", type=int, default=1, help="1: N=2^16 and N=2^17 parameter sets, 0: N=2^16 only")
     ap.add_argument("--serve-sizes", default="16,32")
@@ -313,7 +314,8 @@ def main():
     B = ctx.encrypt_csc(sk, w.k, w.n, ipb, ixb, vb, seed=44)
     if w.rot_digits == 1:
         ctx.keygen_rotations(sk, ctx.plan_rotations(A, B))
-    tuned = ctx.autotune() if args.autotune else None  # schedule choice only: results are unchanged
+    # schedule choice only (results are unchanged): time a prefix of this matmul's own plan per split
+    tuned = ctx.autotune(A, B, pairs=args.autotune_pairs) if args.autotune else None
     log(f"autotune: {tuned}")
     setup_s = time.perf_counter() - t0
     st = ctx.plan_stats(A, B)

@@ -205,16 +205,22 @@ int fhe_spmspm_batch(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fh
   return fhe_spmspm_batch_pairs(ctx, cnt, A, B, nullptr, nullptr, stream, C_out);
 }
 
-int fhe_autotune(fhe_ctx* ctx, void* stream, int32_t batch, int32_t* k1_out, double* ms_out, int32_t* n_tried,
-                 int32_t* k1_tried, double* ms_tried, int32_t cap) {
+int fhe_autotune(fhe_ctx* ctx, void* stream, const fhe_mat* A, const fhe_mat* B, int64_t pairs, int32_t batch,
+                 int32_t* k1_out, double* ms_out, int32_t* n_tried, int32_t* k1_tried, double* ms_tried, int32_t cap) {
   return guarded([&] {
     need(ctx, "ctx");
     if (cap < 0 || (cap > 0 && (!k1_tried || !ms_tried))) fail(FHE_EINVAL, "bad report arrays");
+    if ((A == nullptr) != (B == nullptr)) fail(FHE_EINVAL, "A and B go together");
     set_dev(ctx);
     std::vector<std::pair<int, double>> tried;
     int best = 0;
     double ms = 0;
-    autotune_split(ctx, as_stream(stream), batch < 1 ? 0u : (uint32_t)batch, tried, best, ms);
+    if (A) {
+      check_operands(A, B);
+      autotune_plan(ctx, as_stream(stream), A, B, pairs, tried, best, ms);
+    } else {
+      autotune_split(ctx, as_stream(stream), batch < 1 ? 0u : (uint32_t)batch, tried, best, ms);
+    }
     for (size_t i = 0; i < tried.size() && (int32_t)i < cap; ++i) {
       k1_tried[i] = tried[i].first;
       ms_tried[i] = tried[i].second;

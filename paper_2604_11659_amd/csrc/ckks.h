@@ -41,6 +41,9 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d);
 // the fastest in ctx (results are identical for every split). tried: (k1, ms per batch).
 void autotune_split(fhe_ctx* ctx, hipStream_t st, uint32_t B, std::vector<std::pair<int, double>>& tried,
                     int& best_k1, double& best_ms);
+// As autotune_split, timing the first `pairs` matched pairs of A B (the real per-pair sequence).
+void autotune_plan(fhe_ctx* ctx, hipStream_t st, const fhe_mat* A, const fhe_mat* B, int64_t pairs,
+                   std::vector<std::pair<int, double>>& tried, int& best_k1, double& best_ms);
 void keygen(fhe_ctx* ctx, uint64_t seed, hipStream_t st, fhe_sk* sk);
 void keygen_rotation_steps(fhe_ctx* ctx, const fhe_sk* sk, const std::vector<uint32_t>& steps, hipStream_t st);
 

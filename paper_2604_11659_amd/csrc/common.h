@@ -106,7 +106,8 @@ struct fhe_ctx {
   fhe::Tables t;
   std::unique_ptr<fhe::SwitchKey> relin;
   std::map<uint32_t, std::unique_ptr<fhe::SwitchKey>> rot;  // keyed by Galois element 5^r mod 2N
-  std::mutex exec_mu;    // one matmul execution at a time per context (shared scratch)
+  std::recursive_mutex exec_mu;  // one matmul execution at a time per context (shared scratch); the
+                                 // autotuner holds it across the matmuls it times
   fhe::DevBuf ws_cache;  // executor scratch, grown on demand
 };
 

@@ -178,7 +178,7 @@ void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st) {
 void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st) {
   const Params& p = ctx->p;
   const uint32_t N = p.N, nq = p.nq, nl1 = nq - 1, nl2 = nq - 2;
-  std::lock_guard<std::mutex> exec_lock(ctx->exec_mu);
+  std::lock_guard<std::recursive_mutex> exec_lock(ctx->exec_mu);
   // Merge the slices: products [lo, hi) of each job and their pairs, with result-chunk pointers.
   Plan plan;
   std::vector<uint64_t*> result_ptr;

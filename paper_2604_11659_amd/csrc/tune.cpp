@@ -11,6 +11,7 @@
 
 #include "ckks.h"
 #include "kernels.h"
+#include "spmspm.h"
 
 using namespace fhe;
 
@@ -50,7 +51,7 @@ void fhe::autotune_split(fhe_ctx* ctx, hipStream_t st, uint32_t B, std::vector<s
                          int& best_k1, double& best_ms) {
   if (B < 1 || B > 4096) fail(FHE_EINVAL, "autotune batch must be in [1, 4096]");
   if (!ctx->relin) fail(FHE_EKEY, "autotuning times key switches with the relinearisation key: run keygen first");
-  std::lock_guard<std::mutex> lk(ctx->exec_mu);
+  std::lock_guard<std::recursive_mutex> lk(ctx->exec_mu);
   Params& p = ctx->p;
   const uint32_t N = p.N, nl = (uint32_t)p.nq;
   // synthetic input: residues in [0, q_i) on every limb (values do not matter for timing)
@@ -103,4 +104,61 @@ void fhe::autotune_split(fhe_ctx* ctx, hipStream_t st, uint32_t B, std::vector<s
   }
   p.k1 = (uint32_t)best_k1;
   HIPCHECK(hipStreamSynchronize(st));
+}
+
+void fhe::autotune_plan(fhe_ctx* ctx, hipStream_t st, const fhe_mat* A, const fhe_mat* B, int64_t pairs,
+                        std::vector<std::pair<int, double>>& tried, int& best_k1, double& best_ms) {
+  if (pairs < 1) fail(FHE_EINVAL, "autotune pair count must be positive");
+  std::lock_guard<std::recursive_mutex> lk(ctx->exec_mu);
+  Params& p = ctx->p;
+  const uint32_t k1_orig = p.k1;
+  const int lo = std::max<int>(1, (int)p.logN - 9), hi = std::min<int>(9, (int)p.logN - 1);
+  hipEvent_t a, b;
+  HIPCHECK(hipEventCreate(&a));
+  HIPCHECK(hipEventCreate(&b));
+  // the first `pairs` matched pairs of the plan, each with its full sequence (alignment, product,
+  // mask, rescales, target rotation, accumulation), timed as one matmul call
+  auto run = [&]() -> double {
+    fhe_mat C;
+    std::vector<Job> jobs(1);
+    jobs[0] = Job{A, B, build_plan(p, A, B, 0, pairs), &C};
+    HIPCHECK(hipEventRecord(a, st));
+    execute_jobs(ctx, jobs, st);
+    HIPCHECK(hipEventRecord(b, st));
+    HIPCHECK(hipEventSynchronize(b));
+    float ms = 0;
+    HIPCHECK(hipEventElapsedTime(&ms, a, b));
+    return ms;
+  };
+  tried.clear();
+  best_k1 = (int)k1_orig;
+  best_ms = 0;
+  double orig_ms = 0;
+  try {
+    for (int k1 = lo; k1 <= hi; ++k1) {
+      p.k1 = (uint32_t)k1;
+      run();  // warm-up
+      std::vector<double> t{run(), run(), run()};
+      std::sort(t.begin(), t.end());
+      const double ms = t[1];
+      tried.emplace_back(k1, ms);
+      if ((uint32_t)k1 == k1_orig) orig_ms = ms;
+      if (best_ms == 0 || ms < best_ms) {
+        best_ms = ms;
+        best_k1 = k1;
+      }
+    }
+  } catch (...) {
+    p.k1 = k1_orig;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    throw;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (orig_ms > 0 && best_ms > 0.98 * orig_ms) {
+    best_k1 = (int)k1_orig;
+    best_ms = orig_ms;
+  }
+  p.k1 = (uint32_t)best_k1;
 }

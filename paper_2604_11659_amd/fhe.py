@@ -63,8 +63,8 @@ _SIGS = {
     "fhe_spmspm_batch": ([c_vp, c_sz, PP, PP, c_vp, PP], c_i32),
     "fhe_spmspm_batch_pairs": ([c_vp, c_sz, PP, PP, P_i64, P_i64, c_vp, PP], c_i32),
     "fhe_plan_stats": ([c_vp, c_vp, c_vp, P_i64], c_i32),
-    "fhe_autotune": ([c_vp, c_vp, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_dbl), ctypes.POINTER(c_i32), P_i32,
-                      P_dbl, c_i32], c_i32),
+    "fhe_autotune": ([c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_dbl),
+                      ctypes.POINTER(c_i32), P_i32, P_dbl, c_i32], c_i32),
     "fhe_plan_pattern": ([c_i32, c_i32, c_i32, c_i32, c_i32, P_i32, P_i32, P_i32, P_i32, P_i64], c_i32),
     "fhe_plan_rotations": ([c_vp, c_vp, c_vp, P_i32, c_sz, ctypes.POINTER(c_sz)], c_i32),
     "fhe_decrypt_decode": ([c_vp, c_vp, c_vp, c_vp, P_dbl, c_sz], c_i32),
@@ -318,17 +318,22 @@ class Context(_Handle):
         _check(_lib.fhe_spmspm_pairs(self._ptr, A._ptr, B._ptr, begin, end, _stream(stream), ctypes.byref(out)))
         return Matrix(out.value, self)
 
-    def autotune(self, batch: int | None = None, stream=None) -> dict:
-        """Pick the fastest NTT split for this context (results are unchanged); returns the timings."""
+    def autotune(self, A: Matrix | None = None, B: Matrix | None = None, pairs: int = 2000,
+                 batch: int | None = None, stream=None) -> dict:
+        """Pick the fastest NTT split for this context (results are unchanged); returns the timings.
+
+        With A and B: times the first `pairs` matched pairs of A B; else synthetic key switches."""
         if batch is None:
             batch = {12: 256, 13: 256, 14: 256, 15: 128, 16: 32}.get(self.N.bit_length() - 1, 12)
         k1, ms, n = c_i32(), c_dbl(), c_i32()
         kt = np.zeros(16, np.int32)
         mt = np.zeros(16, np.float64)
-        _check(_lib.fhe_autotune(self._ptr, _stream(stream), batch, ctypes.byref(k1), ctypes.byref(ms), ctypes.byref(n),
-                                 _ptr(kt, c_i32), _ptr(mt, c_dbl), 16))
+        _check(_lib.fhe_autotune(self._ptr, _stream(stream), A._ptr if A else None, B._ptr if B else None, pairs,
+                                 batch, ctypes.byref(k1), ctypes.byref(ms), ctypes.byref(n), _ptr(kt, c_i32),
+                                 _ptr(mt, c_dbl), 16))
         m = min(n.value, 16)
-        return {"k1": k1.value, "ms_per_batch": ms.value, "batch": batch,
+        return {"k1": k1.value, "ms": ms.value, "mode": "plan" if A else "keyswitch",
+                "pairs" if A else "batch": pairs if A else batch,
                 "tried": {int(kt[i]): round(float(mt[i]), 3) for i in range(m)}}
 
     def plan_stats(self, A: Matrix, B: Matrix) -> PlanStats:

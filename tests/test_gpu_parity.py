@@ -200,18 +200,23 @@ def test_autotune_keeps_results_bit_exact(fhe):
     op, okeys, _, _ = _setup(fhe, prm)
     ctx = fhe.Context(*prm)
     sk = ctx.keygen(42)
-    _say("[autotune] tuning")
+    _say("[autotune] synthetic key switches")
     rep = ctx.autotune(batch=4)
     log_n = prm[0]
     assert sorted(rep["tried"]) == list(range(max(1, log_n - 9), min(9, log_n - 1) + 1))
-    assert rep["k1"] in rep["tried"] and rep["ms_per_batch"] > 0
+    assert rep["k1"] in rep["tried"] and rep["ms"] > 0
     m, k, n = 3, 4, 5
     a = synth.sparse_dense(m, k, 0.3, "uniform", 31, 33)
     b = synth.sparse_dense(k, n, 0.3, "uniform", 32, 34)
     ipa, ixa, va = synth.to_csr(a)
     ipb, ixb, vb = synth.to_csc(b)
-    _say(f"[autotune] k1={rep['k1']} matmul")
-    C = ctx.spmspm(ctx.encrypt_csr(sk, m, k, ipa, ixa, va, seed=43), ctx.encrypt_csc(sk, k, n, ipb, ixb, vb, seed=44))
+    A = ctx.encrypt_csr(sk, m, k, ipa, ixa, va, seed=43)
+    B = ctx.encrypt_csc(sk, k, n, ipb, ixb, vb, seed=44)
+    _say("[autotune] plan prefix")
+    rep2 = ctx.autotune(A, B, pairs=6)
+    assert rep2["mode"] == "plan" and rep2["k1"] in rep2["tried"] and rep2["ms"] > 0
+    _say(f"[autotune] k1={rep2['k1']} matmul")
+    C = ctx.spmspm(A, B)
     ref = spmspm.spmspm(op, okeys, spmspm.encrypt_csr(op, okeys, m, k, ipa, ixa, va, seed=43),
                         spmspm.encrypt_csc(op, okeys, k, n, ipb, ixb, vb, seed=44))
     for c, rct in enumerate(ref):
