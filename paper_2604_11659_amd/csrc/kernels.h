@@ -45,10 +45,13 @@ void tensor(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* const* 
 // Hybrid key switch of B polynomials at nl limbs (NTT domain). Input item b is `in + b * in_stride`
 // ([nl][N]); it is read, not modified. keys[b]: switching key. add[2b + c] (may be NULL): [nl][N] added to
 // output component c. out[b]: [2][nl][N]. ws: keyswitch_ws_elems(ctx, B, nl) uint64 of workspace.
+// With galois (device array of B Galois elements), add[2b] (component 0) is read through the
+// automorphism tau_(galois[b]) (NTT domain): a rotation then needs tau of component 1 only; out[b]
+// must not overlap add[2b] in that case.
 size_t keyswitch_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t nl);
 void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, uint64_t in_stride,
                const uint64_t* const* keys, const uint64_t* const* add, uint64_t* const* out, uint64_t* ws,
-               hipStream_t st);
+               hipStream_t st, const uint32_t* galois = nullptr);
 
 // Rescale of B ciphertexts [ncomp][nl][N] -> [ncomp][nl-1][N] (nearest rounding of the dropped limb).
 // With mask_galois (device array of B Galois elements, needs rescale_fuses_mask and nl <= nq - 1),

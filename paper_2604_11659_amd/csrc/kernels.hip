@@ -478,6 +478,7 @@ __global__ __launch_bounds__(kThreads) void k_ntt_p2_combine(uint32_t nl, uint32
                                                             const uint64_t* __restrict__ u,
                                                             const uint64_t* __restrict__ conv,
                                                             const uint64_t* const* __restrict__ add,
+                                                            const uint32_t* __restrict__ galois,
                                                             uint64_t* const* __restrict__ out) {
   extern __shared__ uint64_t lds[];
   const uint32_t N = 1u << logN, tiles = N >> kNttLogE, next = nl + K;
@@ -502,7 +503,8 @@ __global__ __launch_bounds__(kThreads) void k_ntt_p2_combine(uint32_t nl, uint32
   const uint64_t* pinv = tab + 2 * K + 2 * (uint64_t)K * nq + 2 * i;
   const uint64_t* uu = u + ((uint64_t)bc * next + i) * N + j0;
   const uint64_t* ad = add[bc];
-  if (ad) ad += (uint64_t)i * N + j0;
+  const uint32_t gal = galois ? galois[b] : 0;  // rotation form: the addend goes through tau_gal
+  if (ad) ad += (uint64_t)i * N + (galois ? 0 : j0);
   uint64_t* o = out[b] + ((uint64_t)c * nl + i) * N + j0;
   const uint32_t ln = opaque(lane);
   // exact FP64: |u - conv| < 1.5q + 2, so the product with P^-1 is below 0.9q and adding the
@@ -512,7 +514,7 @@ __global__ __launch_bounds__(kThreads) void k_ntt_p2_combine(uint32_t nl, uint32
   for (uint32_t r_ = 0; r_ < kPer; ++r_) {
     const uint32_t idx = wb + ln + r_ * 64;
     double v = ar.mulc((double)uu[idx] - ar.ld(lds[pad_idx(idx)]), pv, pvq);
-    if (ad) v += (double)ad[idx];
+    if (ad) v += (double)(galois ? ad[automorph_src(j0 + idx, gal, logN)] : ad[idx]);
     v = ar.red(v);
     o[idx] = (uint64_t)(v < 0.0 ? v + ar.q : v);
   }
@@ -1355,7 +1357,7 @@ size_t keyswitch_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t nl) {
 
 void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, uint64_t in_stride,
                const uint64_t* const* keys, const uint64_t* const* add, uint64_t* const* out, uint64_t* ws,
-               hipStream_t st) {
+               hipStream_t st, const uint32_t* galois) {
   if (!B) return;
   const Params& p = ctx->p;
   if (p.alpha > kMaxAlpha || p.np > kMaxK) fail(FHE_EINVAL, "alpha or n_p above kernel limits");
@@ -1477,7 +1479,7 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
     ntt_forward_cols(ctx, lb_conv, st);
   }
   FHE_LAUNCH("ntt_p2_combine", e8 * 2 * nl * 3.5, k_ntt_p2_combine<FpArith>, (uint64_t)2 * B * nl * tiles, lds, st, nl,
-             K, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.moddown.u64(), u, conv, add, out);
+             K, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.moddown.u64(), u, conv, add, galois, out);
 }
 
 size_t rescale_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl) {

@@ -109,21 +109,35 @@ size_t workspace_budget_bytes() {
 }
 
 // One batched rotation step over `items`: src[b] -> out[b] rotated left by steps[b] (one key switch).
+// gather: only component 1 goes through the automorphism into scratch (the key switch input);
+// component 0 is read through it by the final combine, so out[b] must be disjoint from src[b].
+// Otherwise both components go to scratch first, and out[b] may equal src[b].
 void enqueue_rotation(fhe_ctx* ctx, ArgPack& ap, std::vector<std::function<void()>>& ops, uint32_t nl,
                       const std::vector<const uint64_t*>& src, const std::vector<uint32_t>& steps,
-                      const std::vector<uint64_t*>& out, const Workspace& ws, hipStream_t st) {
+                      const std::vector<uint64_t*>& out, const Workspace& ws, hipStream_t st, bool gather) {
   const Params& p = ctx->p;
   const uint32_t N = p.N, B = (uint32_t)src.size();
   if (!B) return;
   std::vector<uint32_t> gal(B);
-  std::vector<const uint64_t*> keys(B), add(2 * B);
+  std::vector<const uint64_t*> keys(B), add(2 * B), src1(B);
   for (uint32_t b = 0; b < B; ++b) {
+    if (gather && out[b] == src[b]) fail(FHE_EINVAL, "rotation with a gathered addend cannot run in place");
     gal[b] = galois_of_step(p, steps[b]);
     keys[b] = rotation_key(ctx, steps[b])->buf.u64();
-    add[2 * b] = ws.rtmp + (size_t)b * 2 * nl * N;
+    add[2 * b] = gather ? src[b] : ws.rtmp + (size_t)b * 2 * nl * N;
     add[2 * b + 1] = nullptr;
+    src1[b] = src[b] + (size_t)nl * N;
   }
-  const size_t o_src = ap.push(src), o_g = ap.push(gal), o_k = ap.push(keys), o_a = ap.push(add), o_o = ap.push(out);
+  const size_t o_src = ap.push(src), o_s1 = ap.push(src1), o_g = ap.push(gal), o_k = ap.push(keys),
+               o_a = ap.push(add), o_o = ap.push(out);
+  if (gather) {
+    ops.push_back([=, &ap] {
+      automorph(ctx, B, 1, nl, ap.at<const uint64_t*>(o_s1), ap.at<uint32_t>(o_g), ws.rtmp, st);
+      keyswitch(ctx, B, nl, ws.rtmp, (uint64_t)nl * N, ap.at<const uint64_t*>(o_k), ap.at<const uint64_t*>(o_a),
+                ap.at<uint64_t*>(o_o), ws.ksws, st, ap.at<uint32_t>(o_g));
+    });
+    return;
+  }
   ops.push_back([=, &ap] {
     automorph(ctx, B, 2, nl, ap.at<const uint64_t*>(o_src), ap.at<uint32_t>(o_g), ws.rtmp, st);
     keyswitch(ctx, B, nl, ws.rtmp + (size_t)nl * N, (uint64_t)2 * nl * N, ap.at<const uint64_t*>(o_k),
@@ -254,17 +268,15 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st) {
     std::vector<std::function<void()>> ops;
 
     // (1) Alignment rotations (Algorithm 1): rotate the operand whose value sits at the later slot.
+    // Rotation steps alternate between two scratch buffers per product (align, then the relinearised
+    // product's buffer, free until step (2) writes it), so every key switch reads its input through
+    // the automorphism without an in-place hazard.
     std::vector<const uint64_t*> cur_src(npb), opa(npb), opb(npb);
-    std::vector<std::vector<uint32_t>> steps(npb);
     for (size_t k = 0; k < npb; ++k) {
       const PlanProduct& pr = plan.prods[p0 + k];
       opa[k] = job_of[pr.job]->A->chunk(pr.ca, N);
       opb[k] = job_of[pr.job]->B->chunk(pr.cb, N);
       cur_src[k] = pr.d > 0 ? opb[k] : opa[k];
-      steps[k] = rotation_steps(p, pr.d > 0 ? pr.d : -pr.d);
-      uint64_t* al = ws.align + k * 2 * nq * N;
-      if (pr.d > 0) opb[k] = al;
-      if (pr.d < 0) opa[k] = al;
     }
     for (int t = 0; t < p.rot_digits; ++t) {
       std::vector<const uint64_t*> src;
@@ -278,12 +290,19 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st) {
         const uint32_t rt_ = (amt >> (b * t)) & mask;
         if (!rt_) continue;
         uint64_t* al = ws.align + k * 2 * nq * N;
+        uint64_t* pf = ws.pfull + k * 2 * nq * N;
+        uint64_t* dst = cur_src[k] == al ? pf : al;
         src.push_back(cur_src[k]);
         st_amt.push_back(rt_ << (b * t));
-        out.push_back(al);
-        cur_src[k] = al;
+        out.push_back(dst);
+        cur_src[k] = dst;
       }
-      enqueue_rotation(ctx, ap, ops, nq, src, st_amt, out, ws, st);
+      enqueue_rotation(ctx, ap, ops, nq, src, st_amt, out, ws, st, true);
+    }
+    for (size_t k = 0; k < npb; ++k) {
+      const PlanProduct& pr = plan.prods[p0 + k];
+      if (pr.d > 0) opb[k] = cur_src[k];
+      if (pr.d < 0) opa[k] = cur_src[k];
     }
     // (2) EvalMult + Relinearize + Rescale (Algorithm 2, first three steps), once per product.
     {
@@ -313,11 +332,13 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st) {
       if (a.chunk != b.chunk) return a.chunk < b.chunk;
       return a.rot < b.rot;
     });
+    const bool fused_mask = rescale_fuses_mask(ctx);
+    const uint32_t rbits = p.rot_bits, rmask = (1u << rbits) - 1;
     for (size_t q0 = 0; q0 < pairs.size(); q0 += BB) {
       const size_t q1 = std::min(pairs.size(), q0 + BB), nb = q1 - q0;
       std::vector<const uint64_t*> min_(nb), rin(nb);
       std::vector<uint32_t> mg(nb);
-      std::vector<uint64_t*> mout(nb), cur(nb);
+      std::vector<uint64_t*> mout(nb), cur(nb), alt(nb), where(nb);
       for (size_t k = 0; k < nb; ++k) {
         const PlanPair& pa = plan.pairs[pairs[q0 + k]];
         min_[k] = ws.prod + (size_t)(pa.prod - p0) * 2 * nl1 * N;
@@ -325,9 +346,15 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st) {
         mout[k] = ws.msk + k * 2 * nl1 * N;
         rin[k] = mout[k];
         cur[k] = ws.cur + k * 2 * nl2 * N;
+        // With the mask fused into the rescale, the mask buffer is free: the target rotation steps
+        // alternate between it and cur, starting where an even number of steps ends in cur.
+        alt[k] = ws.msk + k * 2 * nl1 * N;
+        int nz = 0;
+        for (int t = 0; t < p.rot_digits; ++t) nz += ((pa.rot >> (rbits * t)) & rmask) != 0;
+        where[k] = (fused_mask && (nz & 1)) ? alt[k] : cur[k];
       }
       const size_t o_mi = ap.push(min_), o_mg = ap.push(mg), o_mo = ap.push(mout), o_ri = ap.push(rin),
-                   o_cu = ap.push(cur);
+                   o_cu = ap.push(fused_mask ? where : cur);
       const uint32_t Bn = (uint32_t)nb;
       ops.push_back([=, &ap] {
         if (rescale_fuses_mask(ctx)) {  // mask multiply applied inside the rescale's reads
@@ -342,16 +369,17 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st) {
         std::vector<const uint64_t*> src;
         std::vector<uint32_t> st_amt;
         std::vector<uint64_t*> out;
-        const uint32_t b = p.rot_bits, mask = (1u << b) - 1;
         for (size_t k = 0; k < nb; ++k) {
           const uint32_t r = plan.pairs[pairs[q0 + k]].rot;
-          const uint32_t rt_ = (r >> (b * t)) & mask;
+          const uint32_t rt_ = (r >> (rbits * t)) & rmask;
           if (!rt_) continue;
-          src.push_back(cur[k]);
-          st_amt.push_back(rt_ << (b * t));
-          out.push_back(cur[k]);
+          uint64_t* dst = fused_mask ? (where[k] == cur[k] ? alt[k] : cur[k]) : cur[k];
+          src.push_back(where[k]);
+          st_amt.push_back(rt_ << (rbits * t));
+          out.push_back(dst);
+          where[k] = dst;
         }
-        enqueue_rotation(ctx, ap, ops, nl2, src, st_amt, out, ws, st);
+        enqueue_rotation(ctx, ap, ops, nl2, src, st_amt, out, ws, st, fused_mask);
       }
       std::vector<uint32_t> seg;
       for (size_t k = 0; k < nb;) {
