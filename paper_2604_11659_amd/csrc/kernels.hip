@@ -318,12 +318,12 @@ __device__ __forceinline__ void ntt_rounds(uint64_t* lds, const A& ar, const typ
   }
 }
 
-template <bool kInv, int kPhase, class A>
-__global__ __launch_bounds__(kThreads) void k_ntt(LimbBatch lb, const ModInfo* __restrict__ mods,
+template <bool kInv, int kPhase, class A, int NT>
+__global__ __launch_bounds__(NT) void k_ntt(LimbBatch lb, const ModInfo* __restrict__ mods,
                                                  const typename A::W* __restrict__ tw, uint32_t logN, uint32_t k1,
                                                  bool from_src) {
   extern __shared__ uint64_t lds[];
-  constexpr uint32_t kPer = kNttE / kThreads;
+  constexpr uint32_t kPer = kNttE / NT;
   const uint32_t N = 1u << logN, tiles = N >> kNttLogE;
   const uint32_t limb = blockIdx.x / tiles, tile = blockIdx.x - limb * tiles;
   const uint32_t poly = limb / lb.limbs, e = limb - poly * lb.limbs;
@@ -339,14 +339,14 @@ __global__ __launch_bounds__(kThreads) void k_ntt(LimbBatch lb, const ModInfo* _
   const uint64_t toff = (uint64_t)mi * 4 * N + (kInv ? 2 * (uint64_t)N : 0);
   if (kPhase == 2) {
     // rows are contiguous: every wavefront loads, transforms and stores its own rows
-    const uint32_t wb = (threadIdx.x >> 6) * (kNttE / (kThreads / 64)), lane = threadIdx.x & 63;
+    const uint32_t wb = (threadIdx.x >> 6) * (kNttE / (NT / 64)), lane = threadIdx.x & 63;
 #pragma unroll
     for (uint32_t r_ = 0; r_ < kPer; ++r_) {
       const uint32_t idx = wb + lane + r_ * 64;
       lds[pad_idx(idx)] = ar.lds_in(in[j0 + idx]);
     }
     wave_sync();
-    ntt_rounds<kInv, 2, A, 16, kThreads, true>(lds, ar, tw + toff, k, logC, k1, j0);
+    ntt_rounds<kInv, 2, A, kPer, NT, true>(lds, ar, tw + toff, k, logC, k1, j0);
     const uint32_t ln = opaque(lane);
 #pragma unroll
     for (uint32_t r_ = 0; r_ < kPer; ++r_) {
@@ -357,16 +357,16 @@ __global__ __launch_bounds__(kThreads) void k_ntt(LimbBatch lb, const ModInfo* _
     // columns are strided: coalesced loads and stores across the workgroup, rounds per wavefront
 #pragma unroll
     for (uint32_t r_ = 0; r_ < kPer; ++r_) {
-      const uint32_t idx = threadIdx.x + r_ * kThreads;
+      const uint32_t idx = threadIdx.x + r_ * NT;
       lds[pad_idx(idx)] = ar.lds_in(in[((idx >> logC) << k2) + (tile << logC) + (idx & (C - 1))]);
     }
     __syncthreads();
-    ntt_rounds<kInv, 1, A, 16, kThreads, true>(lds, ar, tw + toff, k, logC, 0, 0);
+    ntt_rounds<kInv, 1, A, kPer, NT, true>(lds, ar, tw + toff, k, logC, 0, 0);
     __syncthreads();
     const uint32_t tid = opaque(threadIdx.x);
 #pragma unroll
     for (uint32_t r_ = 0; r_ < kPer; ++r_) {
-      const uint32_t idx = tid + r_ * kThreads;
+      const uint32_t idx = tid + r_ * NT;
       uint64_t v = lb.raw_out ? ar.raw(lds[pad_idx(idx)]) : ar.lds_out(lds[pad_idx(idx)]);
       if (kInv) v = shoup_mul(v, m.n_inv, m.n_inv_shoup, m.q);
       a[((idx >> logC) << k2) + (tile << logC) + (idx & (C - 1))] = v;
@@ -470,8 +470,8 @@ __global__ __launch_bounds__(kInnerThreads) void k_ntt_p2_inner(
 // Row phase of the forward NTT of the ModDown conversion fused with the final combine:
 // out[b][c][i] = add[2b+c][i] + (u[b][c][i] - NTT(conv)[b][c][i]) P^-1 (NTT domain).
 // Workgroup (poly bc = 2b + c, limb i, tile); conv has had its column phase.
-template <class A>
-__global__ __launch_bounds__(kThreads) void k_ntt_p2_combine(uint32_t nl, uint32_t K, uint32_t nq, uint32_t logN,
+template <class A, int NT>
+__global__ __launch_bounds__(NT) void k_ntt_p2_combine(uint32_t nl, uint32_t K, uint32_t nq, uint32_t logN,
                                                             uint32_t k1, const ModInfo* __restrict__ mods,
                                                             const typename A::W* __restrict__ tw,
                                                             const uint64_t* __restrict__ tab,
@@ -490,8 +490,8 @@ __global__ __launch_bounds__(kThreads) void k_ntt_p2_combine(uint32_t nl, uint32
   const uint64_t j0 = (uint64_t)tile * kNttE;
   const uint32_t k = logN - k1, logC = kNttLogE - k;
   const uint64_t* src = conv + ((uint64_t)bc * nl + i) * N + j0;
-  constexpr uint32_t kPer = kNttE / kThreads;
-  const uint32_t wb = (threadIdx.x >> 6) * (kNttE / (kThreads / 64)), lane = threadIdx.x & 63;
+  constexpr uint32_t kPer = kNttE / NT;
+  const uint32_t wb = (threadIdx.x >> 6) * (kNttE / (NT / 64)), lane = threadIdx.x & 63;
 #pragma unroll
   for (uint32_t r_ = 0; r_ < kPer; ++r_) {
     const uint32_t idx = wb + lane + r_ * 64;
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(kThreads) void k_ntt_p2_combine(uint32_t nl, uint32
   }
   wave_sync();
   const typename A::W* w = tw + (uint64_t)i * 4 * N;
-  ntt_rounds<false, 2, A, 16, kThreads, true>(lds, ar, w, k, logC, k1, j0);
+  ntt_rounds<false, 2, A, kPer, NT, true>(lds, ar, w, k, logC, k1, j0);
   const uint64_t* pinv = tab + 2 * K + 2 * (uint64_t)K * nq + 2 * i;
   const uint64_t* uu = u + ((uint64_t)bc * next + i) * N + j0;
   const uint64_t* ad = add[bc];
@@ -986,7 +986,8 @@ __global__ __launch_bounds__(NT) void k_rescale_cols(uint32_t nl, uint32_t logN,
 
 // Rescale, row part: per (polynomial bc = b * ncomp + c, remaining limb i, tile), the forward row
 // phase of w in LDS fused with out = (in - w) q_l^-1 mod q_i (NTT domain), per wavefront.
-__global__ __launch_bounds__(kThreads) void k_rescale_rows(uint32_t ncomp, uint32_t nl, uint32_t nq, uint32_t logN,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_rescale_rows(uint32_t ncomp, uint32_t nl, uint32_t nq, uint32_t logN,
                                                           uint32_t k1, const ModInfo* __restrict__ mods,
                                                           const double* __restrict__ twf,
                                                           const uint64_t* __restrict__ tab,
@@ -996,7 +997,7 @@ __global__ __launch_bounds__(kThreads) void k_rescale_rows(uint32_t ncomp, uint3
                                                           const uint64_t* __restrict__ w,
                                                           uint64_t* const* __restrict__ out) {
   extern __shared__ uint64_t lds[];
-  constexpr uint32_t kPer = kNttE / kThreads;
+  constexpr uint32_t kPer = kNttE / NT;
   const uint32_t N = 1u << logN, tiles = N >> kNttLogE, no = nl - 1;
   const uint32_t tile = blockIdx.x % tiles, li = blockIdx.x / tiles;
   const uint32_t i = li % no, bc = li / no, b = bc / ncomp, c = bc - b * ncomp;
@@ -1004,7 +1005,7 @@ __global__ __launch_bounds__(kThreads) void k_rescale_rows(uint32_t ncomp, uint3
   FpArith ar;
   ar.init(m);
   const uint32_t j0 = tile * kNttE, k = logN - k1, logC = kNttLogE - k;
-  const uint32_t wb = (threadIdx.x >> 6) * (kNttE / (kThreads / 64)), lane = threadIdx.x & 63;
+  const uint32_t wb = (threadIdx.x >> 6) * (kNttE / (NT / 64)), lane = threadIdx.x & 63;
   const uint64_t* src = w + ((uint64_t)bc * no + i) * N + j0;
 #pragma unroll
   for (uint32_t r_ = 0; r_ < kPer; ++r_) {
@@ -1012,7 +1013,7 @@ __global__ __launch_bounds__(kThreads) void k_rescale_rows(uint32_t ncomp, uint3
     lds[pad_idx(idx)] = src[idx];  // internal FP64 form
   }
   wave_sync();
-  ntt_rounds<false, 2, FpArith, 16, kThreads, true>(lds, ar, twf + (uint64_t)i * 4 * N, k, logC, k1, j0);
+  ntt_rounds<false, 2, FpArith, kPer, NT, true>(lds, ar, twf + (uint64_t)i * 4 * N, k, logC, k1, j0);
   const uint64_t* inv = tab + 2 * ((uint64_t)no * nq + i);
   const uint64_t* x = in[b] + ((uint64_t)c * nl + i) * N + j0;
   uint64_t* o = out[b] + ((uint64_t)c * no + i) * N + j0;
@@ -1203,6 +1204,16 @@ static void check_batch(const fhe_ctx* ctx, const LimbBatch& lb) {
   if (mi >= (uint32_t)p.nmod() || mi0 >= (uint32_t)p.nmod()) fail(FHE_EINVAL, "NTT batch modulus index out of range");
 }
 
+// Row-phase kernels: 512 threads x 8 elements (3-stage rounds; about 66 VGPRs, three workgroups
+// per CU), or 256 x 16 with FHE_ROWS_NT=256.
+static int rows_nt() {
+  static const int v = [] {
+    const char* e = std::getenv("FHE_ROWS_NT");
+    return e && std::atoi(e) == 256 ? 256 : 512;
+  }();
+  return v;
+}
+
 static uint32_t ntt_blocks(const fhe_ctx* ctx, const LimbBatch& lb) {
   const uint64_t blocks = (uint64_t)(ctx->p.N >> kNttLogE) * lb.limbs * lb.npoly;
   if (blocks >= (1ull << 31)) fail(FHE_EINVAL, "NTT batch too large");
@@ -1247,12 +1258,22 @@ static void ntt_phase(const fhe_ctx* ctx, const LimbBatch& lb, const char* name_
     }
     const uint32_t blocks = ntt_blocks(ctx, sub);
     const double bytes = 16.0 * p.N * sub.limbs * sub.npoly;
-    if (r.q)
-      FHE_LAUNCH(name_q, bytes, (k_ntt<kInv, kPhase, FpArith>), blocks, lds, st, sub, mods_of(ctx), twf, p.logN, p.k1,
-                 from_src);
-    else
-      FHE_LAUNCH(name_p, bytes, (k_ntt<kInv, kPhase, IntArith>), blocks, lds, st, sub, mods_of(ctx), ctx->t.tw.u64(),
-                 p.logN, p.k1, from_src);
+    // row phase: the 512-thread variant (see rows_nt); column phase: 256 threads x 16 elements
+    if (kPhase == 2 && rows_nt() == 512) {
+      if (r.q)
+        FHE_LAUNCH_T(name_q, bytes, (k_ntt<kInv, kPhase, FpArith, 512>), blocks, 512, lds, st, sub, mods_of(ctx), twf,
+                     p.logN, p.k1, from_src);
+      else
+        FHE_LAUNCH_T(name_p, bytes, (k_ntt<kInv, kPhase, IntArith, 512>), blocks, 512, lds, st, sub, mods_of(ctx),
+                     ctx->t.tw.u64(), p.logN, p.k1, from_src);
+    } else {
+      if (r.q)
+        FHE_LAUNCH(name_q, bytes, (k_ntt<kInv, kPhase, FpArith, kThreads>), blocks, lds, st, sub, mods_of(ctx), twf,
+                   p.logN, p.k1, from_src);
+      else
+        FHE_LAUNCH(name_p, bytes, (k_ntt<kInv, kPhase, IntArith, kThreads>), blocks, lds, st, sub, mods_of(ctx),
+                   ctx->t.tw.u64(), p.logN, p.k1, from_src);
+    }
   }
 }
 
@@ -1478,8 +1499,14 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
     lb_conv.raw_out = 1;
     ntt_forward_cols(ctx, lb_conv, st);
   }
-  FHE_LAUNCH("ntt_p2_combine", e8 * 2 * nl * 3.5, k_ntt_p2_combine<FpArith>, (uint64_t)2 * B * nl * tiles, lds, st, nl,
-             K, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.moddown.u64(), u, conv, add, galois, out);
+  if (rows_nt() == 512)
+    FHE_LAUNCH_T("ntt_p2_combine", e8 * 2 * nl * 3.5, (k_ntt_p2_combine<FpArith, 512>), (uint64_t)2 * B * nl * tiles,
+                 512, lds, st, nl, K, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.moddown.u64(), u, conv,
+                 add, galois, out);
+  else
+    FHE_LAUNCH_T("ntt_p2_combine", e8 * 2 * nl * 3.5, (k_ntt_p2_combine<FpArith, 256>), (uint64_t)2 * B * nl * tiles,
+                 256, lds, st, nl, K, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.moddown.u64(), u, conv,
+                 add, galois, out);
 }
 
 size_t rescale_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl) {
@@ -1527,9 +1554,14 @@ void rescale(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const 
         break;
     }
     const size_t lds = kNttLdsElems * sizeof(uint64_t);
-    FHE_LAUNCH("rescale_rows", e8 * 3 * (nl - 1), k_rescale_rows, (uint64_t)BC * (nl - 1) * (N >> kNttLogE), lds, st,
-               ncomp, nl, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.rescale.u64(), ctx->t.mask.u64(),
-               mask_galois, in, w, out);
+    if (rows_nt() == 512)
+      FHE_LAUNCH_T("rescale_rows", e8 * 3 * (nl - 1), k_rescale_rows<512>, (uint64_t)BC * (nl - 1) * (N >> kNttLogE),
+                   512, lds, st, ncomp, nl, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.rescale.u64(),
+                   ctx->t.mask.u64(), mask_galois, in, w, out);
+    else
+      FHE_LAUNCH_T("rescale_rows", e8 * 3 * (nl - 1), k_rescale_rows<256>, (uint64_t)BC * (nl - 1) * (N >> kNttLogE),
+                   256, lds, st, ncomp, nl, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.rescale.u64(),
+                   ctx->t.mask.u64(), mask_galois, in, w, out);
     return;
   }
   ntt_inverse(ctx, LimbBatch{tmp, 1, BC, N, 0, nl - 1}, st);
