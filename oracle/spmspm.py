@@ -13,6 +13,14 @@ Readings where the paper is silent (listed in the design notes):
     chunk starts as the all-zero ciphertext two levels below the top;
   * rotations are cyclic over all S slots, a rotation by 0 is the identity,
     the Relinearize after the plaintext mask multiply is the identity.
+
+A second, grouped form (``grouped=True``) follows the paper's aim of issuing as few
+rotations as possible (Section 3.2, mitigating the overhead of rotations): the
+Isolation step leaves each masked product in one slot, so products bound for the
+same result chunk with the same target rotation can be added before a single
+second rescale and a single rotation. Its ciphertext bits differ from the
+per-pair form (fewer roundings and key switches); its decryption does not
+beyond noise.
 """
 from __future__ import annotations
 
@@ -102,22 +110,56 @@ def target(params: Params, i: int, j: int, n: int, min_pos: int):
     return cr, (min_pos - lt) % params.S
 
 
-def pair_contribution(params: Params, keys: Keys, A: EncSparse, B: EncSparse, i: int, j: int, a_pos: int,
-                      b_pos: int) -> tuple:
+def masked_product(params: Params, keys: Keys, A: EncSparse, B: EncSparse, a_pos: int, b_pos: int) -> Ct:
+    """Algorithm 1's alignment, then Algorithm 2 up to the mask: EvalMult, Relinearize, Rescale and
+    the product with the one-hot mask at min_pos (one level below the top, before the second rescale)."""
     ca, cb, ra, rb, mn = alignment(params, a_pos, b_pos)
     vA, vB = A.chunks[ca], B.chunks[cb]
     if rb:
         vB = ckks.rotate(params, keys, vB, rb)
     if ra:
         vA = ckks.rotate(params, keys, vA, ra)
-    # Algorithm 2
     d = ckks.mult_relin(params, keys, vA, vB)
     d = ckks.rescale(params, d)
-    d = ckks.mul_plain(params, d, ckks.mask(params, mn), params.delta_mask)
+    return ckks.mul_plain(params, d, ckks.mask(params, mn), params.delta_mask)
+
+
+def pair_contribution(params: Params, keys: Keys, A: EncSparse, B: EncSparse, i: int, j: int, a_pos: int,
+                      b_pos: int) -> tuple:
+    # Algorithm 2 for one matched pair: masked product, second rescale, target rotation
+    d = masked_product(params, keys, A, B, a_pos, b_pos)
     d = ckks.rescale(params, d)
+    mn = alignment(params, a_pos, b_pos)[4]
     cr, rot = target(params, i, j, B.cols, mn)
     d = ckks.rotate(params, keys, d, rot)
     return cr, d
+
+
+def target_groups(params: Params, pairs: list, n: int) -> list:
+    """Matched pairs grouped by (result chunk, target rotation), in order of first appearance:
+    [((chunk, rot), [pairs...]), ...]. Within a group the isolated slots min_pos differ exactly when
+    the targets differ (min_pos = (lt + rot) mod S), so the masked products of a group occupy
+    distinct slots unless they belong to the same output entry, where they are meant to add up."""
+    groups: dict = {}
+    for pair in pairs:
+        i, j, a_pos, b_pos = pair
+        mn = alignment(params, a_pos, b_pos)[4]
+        groups.setdefault(target(params, i, j, n, mn), []).append(pair)
+    return list(groups.items())
+
+
+def group_contribution(params: Params, keys: Keys, A: EncSparse, B: EncSparse, rot: int, members: list) -> Ct:
+    """Grouped form of Algorithm 2's tail: the masked products of all pairs sharing (result chunk,
+    target rotation) are added (exactly, mod q), then rescaled once and rotated once. Rotation and
+    rescale act on the sum as on each term up to rounding, and the masks keep the terms in distinct
+    slots, so the decrypted contribution is the same as the per-pair sequence's; the ciphertext bits
+    are not (one rounding and one key switch per group instead of per pair)."""
+    acc = None
+    for (_, _, a_pos, b_pos) in members:
+        d = masked_product(params, keys, A, B, a_pos, b_pos)
+        acc = d if acc is None else ckks.add(params, acc, d)
+    acc = ckks.rescale(params, acc)
+    return ckks.rotate(params, keys, acc, rot)
 
 
 def result_chunks(params: Params, m: int, n: int) -> int:
@@ -132,11 +174,21 @@ def _accumulate(params: Params, keys: Keys, A: EncSparse, B: EncSparse, pairs: l
     return [None if r is None else r.data for r in res]
 
 
+def _accumulate_groups(params: Params, keys: Keys, A: EncSparse, B: EncSparse, groups: list) -> list:
+    res = [None] * result_chunks(params, A.rows, B.cols)
+    for ((cr, rot), members) in groups:
+        d = group_contribution(params, keys, A, B, rot, members)
+        res[cr] = d if res[cr] is None else ckks.add(params, res[cr], d)
+    return [None if r is None else r.data for r in res]
+
+
 _G = {}
 
 
 def _worker(idx):
     g = _G
+    if g["grouped"]:
+        return _accumulate_groups(g["params"], g["keys"], g["A"], g["B"], g["parts"][idx])
     return _accumulate(g["params"], g["keys"], g["A"], g["B"], g["parts"][idx])
 
 
@@ -156,29 +208,32 @@ def rotation_elements(params: Params, A: EncSparse, B: EncSparse, pairs: list) -
     return gs
 
 
-def spmspm(params: Params, keys: Keys, A: EncSparse, B: EncSparse, workers: int = 1, pairs: list | None = None) -> list:
+def spmspm(params: Params, keys: Keys, A: EncSparse, B: EncSparse, workers: int = 1, pairs: list | None = None,
+           grouped: bool = False) -> list:
     """Encrypted C = A B as a list of result-chunk ciphertexts (row-major slots).
 
     ``pairs`` restricts the sum to a subset of matched pairs (default: all).
-    With workers > 1 the matched pairs are split across processes and the
-    partial results are added; addition mod q is exact, so the result does
-    not depend on the split."""
+    ``grouped``: pairs sharing (result chunk, target rotation) go through one second rescale and one
+    target rotation together (``group_contribution``); groups are formed over ``pairs``.
+    With workers > 1 the pairs (or groups) are split across processes and the partial results are
+    added; addition mod q is exact, so the result does not depend on the split."""
     assert A.cols == B.rows
     if pairs is None:
         pairs = matched_pairs(A.rows, B.cols, A.indptr, A.indices, B.indptr, B.indices)
+    units = target_groups(params, pairs, B.cols) if grouped else pairs
     out_nl = params.n_q - 2
     nres = result_chunks(params, A.rows, B.cols)
-    if workers <= 1 or len(pairs) < 2:
-        parts = [_accumulate(params, keys, A, B, pairs)]
+    if workers <= 1 or len(units) < 2:
+        parts = [_accumulate_groups(params, keys, A, B, units) if grouped else _accumulate(params, keys, A, B, units)]
     else:
         gs = sorted(rotation_elements(params, A, B, pairs) - set(keys._rot))
         ctx = mp.get_context("fork")
-        _G.update(params=params, keys=keys, A=A, B=B)
+        _G.update(params=params, keys=keys, A=A, B=B, grouped=grouped)
         if gs:
             with ctx.Pool(workers) as pool:
                 for gval, key in pool.imap_unordered(_keygen_worker, gs):
                     keys._rot[gval] = key
-        _G["parts"] = [pairs[w::workers] for w in range(workers)]
+        _G["parts"] = [units[w::workers] for w in range(workers)]
         with ctx.Pool(workers) as pool:
             parts = pool.map(_worker, range(workers))
         _G.clear()
