@@ -252,6 +252,36 @@ def run_serve(args) -> dict:
     }
 
 
+def run_grouped(ctx, sk, A, B, st, ref, steps: int) -> dict:
+    """The grouped plan on the same operands: masked products sharing (result chunk, target rotation)
+    summed, then one rescale and one rotation per group. Different ciphertext bits from the per-pair
+    plan (its own oracle mode), same decryption up to noise."""
+    import torch
+    groups, gks = ctx.plan_groups(A, B)
+    C = ctx.spmspm(A, B, grouped=True)  # warm-up (allocates the group accumulators)
+    C.close()
+    torch.cuda.synchronize()
+    log(f"grouped warm-up done: {groups} groups, {gks} target key switches")
+    t0 = time.perf_counter()
+    C = None
+    for _ in range(steps):
+        if C is not None:
+            C.close()
+        C = ctx.spmspm(A, B, grouped=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dec = ctx.decrypt_decode(sk, C)
+    C.close()
+    ks = st.align_keyswitches + st.relin_keyswitches + gks
+    v = steps / dt
+    log(f"grouped: {1000 * dt / steps:.1f} ms/step")
+    return {"plan": "grouped target rotations", "value": round(v, 6), "unit": "SpMSpM/s", "steps": steps,
+            "ms_per_step": round(1000 * dt / steps, 2), "groups": groups, "target_keyswitches": gks,
+            "keyswitches": ks, "matched_pairs_per_s": round(st.matched_pairs * v, 1),
+            "keyswitch_per_s": round(ks * v, 1), "max_abs_err": float(np.abs(dec - ref).max()),
+            "frobenius_err": float(np.sqrt(((dec - ref) ** 2).sum()))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +301,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=int, default=16)
     ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle pairs to time (0 = skip, -1 = one per core)")
     ap.add_argument("--kernels-out", default=None, help="write per-kernel timings (JSON) here")
+    ap.add_argument("--grouped-steps", type=int, default=2,
+                    help="also time this many steps of the grouped plan (one rescale and rotation per result "
+                         "chunk and target rotation; 0 = skip), after one warm-up step")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="run one 1 GiB device-to-device tensor copy first (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -362,6 +395,8 @@ def main():
         "max_abs_err": err, "frobenius_err": frob, "setup_s": round(setup_s, 2),
         "roofline": roof, "cpu_baseline": cpu,
     }
+    if args.grouped_steps > 0:
+        line["grouped"] = run_grouped(ctx, sk, A, B, st, ref, args.grouped_steps)
     if args.kernels_out:
         with open(args.kernels_out, "w") as f:
             json.dump({"kernels": kernels, "plan": st.__dict__}, f, indent=1)

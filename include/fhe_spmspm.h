@@ -143,6 +143,26 @@ int fhe_spmspm_batch(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fh
 int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B,
                            const int64_t* pair_begin, const int64_t* pair_end, void* stream, fhe_mat** C_out);
 
+/* Plan modes of fhe_spmspm_plan. */
+#define FHE_PLAN_PER_PAIR 0 /* Algorithm 2 per matched pair (the form of fhe_spmspm) */
+#define FHE_PLAN_GROUPED 1  /* grouped target rotations, see fhe_spmspm_plan */
+
+/* General form of the matmul calls: C_out[i] = A[i] B[i] for i < cnt as one merged launch stream,
+ * each restricted to the matched pairs with traversal index in [pair_begin[i], pair_end[i]) (both
+ * NULL: all pairs), in plan mode `mode`. FHE_PLAN_PER_PAIR gives exactly fhe_spmspm_batch_pairs.
+ * FHE_PLAN_GROUPED follows the paper's aim of issuing as few rotations as possible (Section 3.2):
+ * after its one-hot mask every matched pair's product occupies one slot, so the masked products
+ * of a matmul's pairs that share (result chunk, target rotation) are added (exactly, mod q) and go
+ * through one second rescale and one target rotation. The groups are formed over the pairs of the
+ * call's range. Decrypted results equal the per-pair form's up to noise (lower: fewer roundings
+ * and key switches); the ciphertext limbs are those of that grouped sequence, not the per-pair
+ * ones. The grouped form keeps one accumulator of 2 (n_q - 1) N words per group in device memory,
+ * up to FHE_GROUP_MB (environment, default 49152 MiB); beyond that it runs the groups in passes and
+ * each pass recomputes the products its pairs use. Errors as fhe_spmspm_batch_pairs, FHE_EINVAL for
+ * an unknown mode; on error all C_out[i] are NULL. */
+int fhe_spmspm_plan(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B,
+                    const int64_t* pair_begin, const int64_t* pair_end, int32_t mode, void* stream, fhe_mat** C_out);
+
 /* Autotuner (batch scheduler): picks the NTT split 2^k1 x 2^(log_n - k1) for ctx by timing every
  * admissible one (k1 in [max(1, log_n - 9), min(9, log_n - 1)]); keeps the current split unless
  * another is at least 2% faster. Every split computes the same transform, so results are unchanged;
@@ -160,6 +180,11 @@ int fhe_autotune(fhe_ctx* ctx, void* stream, const fhe_mat* A, const fhe_mat* B,
  * [2] = alignment key switches, [3] = product relinearisations, [4] = target-rotation key switches,
  * [5] = result chunks. Errors as fhe_spmspm. */
 int fhe_plan_stats(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t counts[6]);
+
+/* Grouped-plan statistics of A B: counts[0] = groups (distinct result chunk and target rotation),
+ * counts[1] = their target-rotation key switches (the other counts are those of fhe_plan_stats).
+ * Errors as fhe_spmspm. */
+int fhe_plan_groups(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t counts[2]);
 
 /* Host-only planning from the public patterns (no context, no device): the same counts as
  * fhe_plan_stats for A (m x k, CSR pattern) times B (k x n, CSC pattern) at ring dimension 2^log_n

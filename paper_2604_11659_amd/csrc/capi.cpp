@@ -172,8 +172,8 @@ int fhe_spmspm_pairs(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t p
   });
 }
 
-int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B,
-                           const int64_t* pair_begin, const int64_t* pair_end, void* stream, fhe_mat** C_out) {
+int fhe_spmspm_plan(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B,
+                    const int64_t* pair_begin, const int64_t* pair_end, int32_t mode, void* stream, fhe_mat** C_out) {
   return guarded([&] {
     need(ctx, "ctx");
     need(C_out, "C_out");
@@ -182,6 +182,7 @@ int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, co
       need(B, "B");
     }
     for (size_t i = 0; i < cnt; ++i) C_out[i] = nullptr;
+    if (mode != FHE_PLAN_PER_PAIR && mode != FHE_PLAN_GROUPED) fail(FHE_EINVAL, "unknown plan mode");
     if ((pair_begin == nullptr) != (pair_end == nullptr)) fail(FHE_EINVAL, "pair_begin and pair_end go together");
     for (size_t i = 0; i < cnt; ++i) {
       check_operands(A[i], B[i]);
@@ -195,9 +196,14 @@ int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, co
       const int64_t lo = pair_begin ? pair_begin[i] : 0, hi = pair_end ? pair_end[i] : INT64_MAX;
       jobs[i] = Job{A[i], B[i], build_plan(ctx->p, A[i], B[i], lo, hi), Cs[i].get()};
     }
-    execute_jobs(ctx, jobs, as_stream(stream));
+    execute_jobs(ctx, jobs, as_stream(stream), mode == FHE_PLAN_GROUPED);
     for (size_t i = 0; i < cnt; ++i) C_out[i] = Cs[i].release();
   });
+}
+
+int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B,
+                           const int64_t* pair_begin, const int64_t* pair_end, void* stream, fhe_mat** C_out) {
+  return fhe_spmspm_plan(ctx, cnt, A, B, pair_begin, pair_end, FHE_PLAN_PER_PAIR, stream, C_out);
 }
 
 int fhe_spmspm_batch(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B, void* stream,
@@ -242,6 +248,16 @@ int fhe_plan_stats(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t cou
     check_operands(A, B);
     Plan plan = build_plan(ctx->p, A, B, 0, INT64_MAX);
     plan_counts(ctx->p, plan, counts);
+  });
+}
+
+int fhe_plan_groups(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t counts[2]) {
+  return guarded([&] {
+    need(ctx, "ctx");
+    need(counts, "counts");
+    check_operands(A, B);
+    Plan plan = build_plan(ctx->p, A, B, 0, INT64_MAX);
+    plan_group_counts(ctx->p, plan, counts);
   });
 }
 

@@ -66,6 +66,13 @@ void rescale(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const 
 void mask_mul(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* const* in, const uint32_t* galois,
               uint64_t* const* out, hipStream_t st);
 
+// Grouped masked sums (nl <= nq - 1): for segment s, accumulator seg[4s] (acc + seg[4s] * 2 nl N,
+// [2][nl][N]) is set (seg[4s+3] = 1) or incremented (0) by the sum over entries e in
+// [seg[4s+1], seg[4s+2]) of in[e] * tau_(galois[e])(base mask). `seg` (4 nseg words), `in` and
+// `galois` (nentries each) are device arrays.
+void mask_sum(const fhe_ctx* ctx, uint32_t nseg, uint32_t nentries, uint32_t nl, const uint32_t* seg,
+              const uint64_t* const* in, const uint32_t* galois, uint64_t* acc, hipStream_t st);
+
 // results[seg[3s]] += sum of contrib[b] for b in [seg[3s+1], seg[3s+2]); [2][nl][N] each; `results` is
 // a device array of result-chunk pointers. ncontrib (the number of contributions the segments cover)
 // only sizes the launch's traffic figure for the kernel timer.

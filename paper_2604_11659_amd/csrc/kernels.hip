@@ -1052,6 +1052,45 @@ __global__ __launch_bounds__(kThreads) void k_mask_mul(uint32_t B, uint32_t nl, 
   }
 }
 
+// Grouped masked sums. Segment s: accumulator seg[4s] (at acc + seg[4s] * 2 nl N), entries
+// [seg[4s+1], seg[4s+2]), and seg[4s+3] = 1 to overwrite the accumulator (first products of its
+// group), 0 to add to it. acc[c][i][k] (+)= sum over the entries e of in[e][c][i][k] times the one-hot
+// mask tau_(galois[e])(base mask) at limb i, coefficient k (NTT domain, mask in Montgomery form).
+// One thread per (segment, limb, coefficient): both components share the mask word.
+__global__ __launch_bounds__(kThreads) void k_mask_sum(uint32_t nseg, uint32_t nl, uint32_t logN,
+                                                      const ModInfo* __restrict__ mods,
+                                                      const uint64_t* __restrict__ maskm,
+                                                      const uint32_t* __restrict__ seg,
+                                                      const uint64_t* const* __restrict__ in,
+                                                      const uint32_t* __restrict__ galois,
+                                                      uint64_t* __restrict__ acc) {
+  const uint32_t N = 1u << logN;
+  const uint64_t per = (uint64_t)nl << logN;  // (limb, coefficient) positions per segment
+  const uint64_t total = (uint64_t)nseg * per;
+  for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < total; t += (uint64_t)gridDim.x * kThreads) {
+    const uint32_t s = (uint32_t)(t / per);
+    const uint64_t off = t - (uint64_t)s * per;
+    const uint32_t i = (uint32_t)(off >> logN), k = (uint32_t)off & (N - 1);
+    const ModInfo m = mods[i];
+    const uint32_t e0 = seg[4 * s + 1], e1 = seg[4 * s + 2];
+    uint64_t* a = acc + (uint64_t)seg[4 * s] * 2 * per + off;
+    uint64_t v0 = 0, v1 = 0;
+    if (!seg[4 * s + 3]) {
+      v0 = a[0];
+      v1 = a[per];
+    }
+    const uint64_t* mrow = maskm + ((uint64_t)i << logN);
+    for (uint32_t e = e0; e < e1; ++e) {
+      const uint64_t mk = mrow[automorph_src(k, galois[e], logN)];
+      const uint64_t* x = in[e] + off;
+      v0 = add_mod(v0, mont_mul(x[0], mk, m.q, m.qinv), m.q);
+      v1 = add_mod(v1, mont_mul(x[per], mk, m.q, m.qinv), m.q);
+    }
+    a[0] = v0;
+    a[per] = v1;
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_accumulate(uint32_t nseg, uint32_t nl, uint32_t logN,
                                                         const ModInfo* __restrict__ mods,
                                                         const uint32_t* __restrict__ seg,
@@ -1579,6 +1618,17 @@ void mask_mul(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* const
   const double bytes = 8.0 * ctx->p.N * nl * (4.0 * B + 1);
   FHE_LAUNCH("mask_mul", bytes, k_mask_mul, grid_for((uint64_t)B << ctx->p.logN), 0, st, B, nl, ctx->p.logN,
              mods_of(ctx), ctx->t.mask.u64(), in, galois, out);
+}
+
+void mask_sum(const fhe_ctx* ctx, uint32_t nseg, uint32_t nentries, uint32_t nl, const uint32_t* seg,
+              const uint64_t* const* in, const uint32_t* galois, uint64_t* acc, hipStream_t st) {
+  if (!nseg) return;
+  if (nl > (uint32_t)ctx->p.nq - 1) fail(FHE_ESHAPE, "mask multiply above level top-1");
+  // every entry's two components and one mask row read, every accumulator written (read once more
+  // when it already holds a partial sum; counted as written only)
+  const double bytes = 8.0 * nl * ctx->p.N * (3.0 * nentries + 2.0 * nseg);
+  FHE_LAUNCH("mask_sum", bytes, k_mask_sum, grid_for((uint64_t)nseg * nl << ctx->p.logN), 0, st, nseg, nl,
+             ctx->p.logN, mods_of(ctx), ctx->t.mask.u64(), seg, in, galois, acc);
 }
 
 void accumulate(const fhe_ctx* ctx, uint32_t nseg, uint32_t ncontrib, uint32_t nl, const uint32_t* seg,

@@ -94,6 +94,18 @@ void plan_counts(const Params& p, const Plan& plan, int64_t out[6]) {
   out[5] = plan.nres;
 }
 
+void plan_group_counts(const Params& p, const Plan& plan, int64_t out[2]) {
+  std::vector<uint64_t> keys;
+  keys.reserve(plan.pairs.size());
+  for (const auto& pa : plan.pairs) keys.push_back(((uint64_t)(uint32_t)pa.chunk << 32) | pa.rot);
+  std::sort(keys.begin(), keys.end());
+  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+  int64_t target = 0;
+  for (uint64_t k : keys) target += (int64_t)rotation_steps(p, (uint32_t)k).size();
+  out[0] = (int64_t)keys.size();
+  out[1] = target;
+}
+
 namespace {
 
 struct Workspace {
@@ -180,16 +192,274 @@ void prepare_result(fhe_ctx* ctx, Job& J, hipStream_t st) {
   HIPCHECK(hipMemsetAsync(C->data.get(), 0, (size_t)J.plan.nres * chunk_elems * 8, st));
 }
 
-void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st) {
+void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool grouped) {
   std::vector<Slice> slices;
   for (auto& J : jobs) {
     prepare_result(ctx, J, st);
     slices.push_back(Slice{&J, 0, (int32_t)J.plan.prods.size()});
   }
-  execute_slices(ctx, slices, st);
+  execute_slices(ctx, slices, st, grouped);
 }
 
-void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st) {
+namespace {
+
+// A ciphertext entering the tail of the sequence: second rescale (with its one-hot mask fused in or
+// applied first when `galois` is used), target rotation, accumulation into result chunk `chunk`.
+struct TailItem {
+  const uint64_t* src;
+  uint32_t galois;
+  int32_t chunk;
+  uint32_t rot;
+};
+
+using Ops = std::vector<std::function<void()>>;
+
+// EvalMult -> Relinearize -> Rescale of the products ids[k] (after their alignment rotations) into
+// ws.prod slot k, [2][nq - 1][N] each.
+void enqueue_products(fhe_ctx* ctx, ArgPack& ap, Ops& ops, const Plan& plan, const std::vector<const Job*>& job_of,
+                      const int32_t* ids, size_t npb, const Workspace& ws, hipStream_t st) {
+  const Params& p = ctx->p;
+  const uint32_t N = p.N, nq = p.nq, nl1 = nq - 1;
+  // (1) Alignment rotations (Algorithm 1): rotate the operand whose value sits at the later slot.
+  // Rotation steps alternate between two scratch buffers per product (align, then the relinearised
+  // product's buffer, free until step (2) writes it), so every key switch reads its input through
+  // the automorphism without an in-place hazard.
+  std::vector<const uint64_t*> cur_src(npb), opa(npb), opb(npb);
+  for (size_t k = 0; k < npb; ++k) {
+    const PlanProduct& pr = plan.prods[ids[k]];
+    opa[k] = job_of[pr.job]->A->chunk(pr.ca, N);
+    opb[k] = job_of[pr.job]->B->chunk(pr.cb, N);
+    cur_src[k] = pr.d > 0 ? opb[k] : opa[k];
+  }
+  for (int t = 0; t < p.rot_digits; ++t) {
+    std::vector<const uint64_t*> src;
+    std::vector<uint32_t> st_amt;
+    std::vector<uint64_t*> out;
+    const uint32_t b = p.rot_bits, mask = (1u << b) - 1;
+    for (size_t k = 0; k < npb; ++k) {
+      const PlanProduct& pr = plan.prods[ids[k]];
+      if (pr.d == 0) continue;
+      const uint32_t amt = (uint32_t)((pr.d > 0 ? pr.d : -pr.d) % (int32_t)p.S);
+      const uint32_t rt_ = (amt >> (b * t)) & mask;
+      if (!rt_) continue;
+      uint64_t* al = ws.align + k * 2 * nq * N;
+      uint64_t* pf = ws.pfull + k * 2 * nq * N;
+      uint64_t* dst = cur_src[k] == al ? pf : al;
+      src.push_back(cur_src[k]);
+      st_amt.push_back(rt_ << (b * t));
+      out.push_back(dst);
+      cur_src[k] = dst;
+    }
+    enqueue_rotation(ctx, ap, ops, nq, src, st_amt, out, ws, st, true);
+  }
+  for (size_t k = 0; k < npb; ++k) {
+    const PlanProduct& pr = plan.prods[ids[k]];
+    if (pr.d > 0) opb[k] = cur_src[k];
+    if (pr.d < 0) opa[k] = cur_src[k];
+  }
+  // (2) EvalMult + Relinearize + Rescale (Algorithm 2, first three steps), once per product.
+  std::vector<const uint64_t*> keys(npb, ctx->relin->buf.u64()), add(2 * npb), pin(npb);
+  std::vector<uint64_t*> pout(npb), rout(npb);
+  for (size_t k = 0; k < npb; ++k) {
+    add[2 * k] = ws.tens + k * 3 * nq * N;
+    add[2 * k + 1] = ws.tens + k * 3 * nq * N + (size_t)nq * N;
+    pout[k] = ws.pfull + k * 2 * nq * N;
+    pin[k] = pout[k];
+    rout[k] = ws.prod + k * 2 * nl1 * N;
+  }
+  const size_t o_a = ap.push(opa), o_b = ap.push(opb), o_k = ap.push(keys), o_ad = ap.push(add),
+               o_po = ap.push(pout), o_pi = ap.push(pin), o_ro = ap.push(rout);
+  const uint32_t Bn = (uint32_t)npb;
+  ops.push_back([=, &ap] {
+    tensor(ctx, Bn, nq, ap.at<const uint64_t*>(o_a), ap.at<const uint64_t*>(o_b), ws.tens, st);
+    keyswitch(ctx, Bn, nq, ws.tens + (size_t)2 * nq * N, (uint64_t)3 * nq * N, ap.at<const uint64_t*>(o_k),
+              ap.at<const uint64_t*>(o_ad), ap.at<uint64_t*>(o_po), ws.ksws, st);
+    rescale(ctx, Bn, 2, nq, ap.at<const uint64_t*>(o_pi), ap.at<uint64_t*>(o_ro), ws.rsws, st);
+  });
+}
+
+// The tail of Algorithm 2 for up to BB items at level top - 1 (sorted by result chunk, then
+// rotation): (masked) rescale, target rotation, accumulation into the result chunks.
+void enqueue_tail(fhe_ctx* ctx, ArgPack& ap, Ops& ops, const std::vector<TailItem>& items, bool masked,
+                  const Workspace& ws, uint64_t* const* res, hipStream_t st) {
+  const Params& p = ctx->p;
+  const uint32_t N = p.N, nl1 = p.nq - 1, nl2 = p.nq - 2;
+  const size_t nb = items.size();
+  if (!nb) return;
+  // Without a separate mask multiply the mask buffer is free: the target rotation steps alternate
+  // between it and cur, starting where an even number of steps ends in cur.
+  const bool pingpong = !masked || rescale_fuses_mask(ctx);
+  const uint32_t rbits = p.rot_bits, rmask = (1u << rbits) - 1;
+  std::vector<const uint64_t*> min_(nb), rin(nb);
+  std::vector<uint32_t> mg(nb);
+  std::vector<uint64_t*> mout(nb), cur(nb), alt(nb), where(nb);
+  for (size_t k = 0; k < nb; ++k) {
+    const TailItem& it = items[k];
+    min_[k] = it.src;
+    mg[k] = it.galois;
+    mout[k] = ws.msk + k * 2 * nl1 * N;
+    rin[k] = mout[k];
+    cur[k] = ws.cur + k * 2 * nl2 * N;
+    alt[k] = ws.msk + k * 2 * nl1 * N;
+    int nz = 0;
+    for (int t = 0; t < p.rot_digits; ++t) nz += ((it.rot >> (rbits * t)) & rmask) != 0;
+    where[k] = (pingpong && (nz & 1)) ? alt[k] : cur[k];
+  }
+  const size_t o_mi = ap.push(min_), o_mg = ap.push(mg), o_mo = ap.push(mout), o_ri = ap.push(rin),
+               o_cu = ap.push(pingpong ? where : cur);
+  const uint32_t Bn = (uint32_t)nb;
+  ops.push_back([=, &ap] {
+    if (!masked) {
+      rescale(ctx, Bn, 2, nl1, ap.at<const uint64_t*>(o_mi), ap.at<uint64_t*>(o_cu), ws.rsws, st);
+    } else if (rescale_fuses_mask(ctx)) {  // mask multiply applied inside the rescale's reads
+      rescale(ctx, Bn, 2, nl1, ap.at<const uint64_t*>(o_mi), ap.at<uint64_t*>(o_cu), ws.rsws, st,
+              ap.at<uint32_t>(o_mg));
+    } else {
+      mask_mul(ctx, Bn, nl1, ap.at<const uint64_t*>(o_mi), ap.at<uint32_t>(o_mg), ap.at<uint64_t*>(o_mo), st);
+      rescale(ctx, Bn, 2, nl1, ap.at<const uint64_t*>(o_ri), ap.at<uint64_t*>(o_cu), ws.rsws, st);
+    }
+  });
+  for (int t = 0; t < p.rot_digits; ++t) {
+    std::vector<const uint64_t*> src;
+    std::vector<uint32_t> st_amt;
+    std::vector<uint64_t*> out;
+    for (size_t k = 0; k < nb; ++k) {
+      const uint32_t rt_ = (items[k].rot >> (rbits * t)) & rmask;
+      if (!rt_) continue;
+      uint64_t* dst = pingpong ? (where[k] == cur[k] ? alt[k] : cur[k]) : cur[k];
+      src.push_back(where[k]);
+      st_amt.push_back(rt_ << (rbits * t));
+      out.push_back(dst);
+      where[k] = dst;
+    }
+    enqueue_rotation(ctx, ap, ops, nl2, src, st_amt, out, ws, st, pingpong);
+  }
+  std::vector<uint32_t> seg;
+  for (size_t k = 0; k < nb;) {
+    const int32_t ch = items[k].chunk;
+    size_t k2 = k;
+    while (k2 < nb && items[k2].chunk == ch) ++k2;
+    seg.push_back((uint32_t)ch);
+    seg.push_back((uint32_t)k);
+    seg.push_back((uint32_t)k2);
+    k = k2;
+  }
+  const size_t o_sg = ap.push(seg);
+  const uint32_t nseg = (uint32_t)(seg.size() / 3);
+  const uint32_t ncontrib = (uint32_t)nb;
+  ops.push_back([=, &ap] { accumulate(ctx, nseg, ncontrib, nl2, ap.at<uint32_t>(o_sg), ws.cur, res, st); });
+}
+
+size_t group_budget_bytes() {
+  const char* e = getenv("FHE_GROUP_MB");
+  long long mb = e ? atoll(e) : 49152;
+  if (mb < 1) mb = 1;
+  return (size_t)mb << 20;
+}
+
+// Grouped tail: the masked products of all pairs sharing (result chunk, target rotation) are summed
+// into one accumulator per group (exact, mod q), then each group is rescaled, rotated and
+// accumulated once. Accumulators for all groups are kept when they fit the group budget; otherwise
+// the groups are processed in passes and each pass recomputes the products its pairs use.
+void execute_grouped(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job*>& job_of, const Workspace& ws,
+                     size_t PB, size_t BB, uint64_t* const* res, std::vector<std::unique_ptr<ArgPack>>& packs,
+                     DevBuf& gacc, hipStream_t st) {
+  const Params& p = ctx->p;
+  const uint32_t N = p.N, nl1 = p.nq - 1;
+  const size_t npairs = plan.pairs.size(), nprod = plan.prods.size();
+  // groups ordered by (chunk, rotation): equal rotation keys sit together in the tail batches
+  std::vector<uint64_t> keys(npairs);
+  for (size_t k = 0; k < npairs; ++k) keys[k] = ((uint64_t)(uint32_t)plan.pairs[k].chunk << 32) | plan.pairs[k].rot;
+  std::vector<uint64_t> gkeys(keys);
+  std::sort(gkeys.begin(), gkeys.end());
+  gkeys.erase(std::unique(gkeys.begin(), gkeys.end()), gkeys.end());
+  const size_t ng = gkeys.size();
+  std::vector<size_t> gfirst(ng + 1, 0);
+  std::vector<uint32_t> gpair(npairs), pg(npairs);
+  for (size_t k = 0; k < npairs; ++k) {
+    pg[k] = (uint32_t)(std::lower_bound(gkeys.begin(), gkeys.end(), keys[k]) - gkeys.begin());
+    ++gfirst[pg[k] + 1];
+  }
+  for (size_t g = 0; g < ng; ++g) gfirst[g + 1] += gfirst[g];
+  {
+    std::vector<size_t> fill(gfirst.begin(), gfirst.end() - 1);
+    for (size_t k = 0; k < npairs; ++k) gpair[fill[pg[k]]++] = (uint32_t)k;
+  }
+  const size_t acc_elems = (size_t)2 * nl1 * N;
+  const size_t GA = std::max<size_t>(1, std::min<size_t>(ng, group_budget_bytes() / (acc_elems * 8)));
+  if (gacc.bytes() < GA * acc_elems * 8) {
+    gacc.reset();
+    gacc = DevBuf(GA * acc_elems * 8, st);
+  }
+  uint64_t* acc = gacc.u64();
+  std::vector<int32_t> slot(nprod, -1);
+  std::vector<char> used(nprod, 0);
+  for (size_t g0 = 0; g0 < ng; g0 += GA) {
+    const size_t g1 = std::min(ng, g0 + GA);
+    std::vector<int32_t> need;
+    for (size_t k = gfirst[g0]; k < gfirst[g1]; ++k) {
+      const int32_t pid = plan.pairs[gpair[k]].prod;
+      if (!used[pid]) {
+        used[pid] = 1;
+        need.push_back(pid);
+      }
+    }
+    std::sort(need.begin(), need.end());
+    for (int32_t pid : need) used[pid] = 0;
+    std::vector<char> touched(g1 - g0, 0);
+    for (size_t b0 = 0; b0 < need.size(); b0 += PB) {
+      const size_t b1 = std::min(need.size(), b0 + PB), npb = b1 - b0;
+      packs.emplace_back(new ArgPack());
+      ArgPack& ap = *packs.back();
+      Ops ops;
+      enqueue_products(ctx, ap, ops, plan, job_of, need.data() + b0, npb, ws, st);
+      for (size_t k = 0; k < npb; ++k) slot[need[b0 + k]] = (int32_t)k;
+      // masked products of this batch into their groups' accumulators
+      std::vector<uint32_t> seg, gal;
+      std::vector<const uint64_t*> in;
+      for (size_t g = g0; g < g1; ++g) {
+        const size_t e0 = in.size();
+        for (size_t k = gfirst[g]; k < gfirst[g + 1]; ++k) {
+          const PlanPair& pa = plan.pairs[gpair[k]];
+          if (slot[pa.prod] < 0) continue;
+          in.push_back(ws.prod + (size_t)slot[pa.prod] * acc_elems);
+          gal.push_back(mask_galois(p, pa.min_pos));
+        }
+        if (in.size() == e0) continue;
+        seg.push_back((uint32_t)(g - g0));
+        seg.push_back((uint32_t)e0);
+        seg.push_back((uint32_t)in.size());
+        seg.push_back(touched[g - g0] ? 0u : 1u);
+        touched[g - g0] = 1;
+      }
+      for (size_t k = 0; k < npb; ++k) slot[need[b0 + k]] = -1;
+      const size_t o_sg = ap.push(seg), o_in = ap.push(in), o_ga = ap.push(gal);
+      const uint32_t nseg = (uint32_t)(seg.size() / 4), nent = (uint32_t)in.size();
+      ops.push_back([=, &ap] {
+        mask_sum(ctx, nseg, nent, nl1, ap.at<uint32_t>(o_sg), ap.at<const uint64_t*>(o_in), ap.at<uint32_t>(o_ga), acc,
+                 st);
+      });
+      ap.upload(st);
+      for (auto& op : ops) op();
+    }
+    for (size_t t0 = g0; t0 < g1; t0 += BB) {
+      const size_t t1 = std::min(g1, t0 + BB);
+      std::vector<TailItem> items;
+      for (size_t g = t0; g < t1; ++g)
+        items.push_back(TailItem{acc + (g - g0) * acc_elems, 0u, (int32_t)(gkeys[g] >> 32), (uint32_t)gkeys[g]});
+      packs.emplace_back(new ArgPack());
+      ArgPack& ap = *packs.back();
+      Ops ops;
+      enqueue_tail(ctx, ap, ops, items, false, ws, res, st);
+      ap.upload(st);
+      for (auto& op : ops) op();
+    }
+  }
+}
+
+}  // namespace
+
+void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bool grouped) {
   const Params& p = ctx->p;
   const uint32_t N = p.N, nq = p.nq, nl1 = nq - 1, nl2 = nq - 2;
   std::lock_guard<std::recursive_mutex> exec_lock(ctx->exec_mu);
@@ -260,71 +530,22 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st) {
   ws.ksws = w; w += sz_ks;
   ws.rsws = w;
 
+  uint64_t* const* res = (uint64_t* const*)result_dev.get();
   std::vector<std::unique_ptr<ArgPack>> packs;
+  DevBuf gacc;  // group accumulators (grouped form), released after the final synchronisation
+  if (grouped) {
+    execute_grouped(ctx, plan, job_of, ws, PB, BB, res, packs, gacc, st);
+    HIPCHECK(hipStreamSynchronize(st));
+    return;
+  }
+  std::vector<int32_t> ids(nprod);
+  for (size_t i = 0; i < nprod; ++i) ids[i] = (int32_t)i;
   for (size_t p0 = 0; p0 < nprod; p0 += PB) {
     const size_t p1 = std::min(nprod, p0 + PB), npb = p1 - p0;
     packs.emplace_back(new ArgPack());
     ArgPack& ap = *packs.back();
-    std::vector<std::function<void()>> ops;
-
-    // (1) Alignment rotations (Algorithm 1): rotate the operand whose value sits at the later slot.
-    // Rotation steps alternate between two scratch buffers per product (align, then the relinearised
-    // product's buffer, free until step (2) writes it), so every key switch reads its input through
-    // the automorphism without an in-place hazard.
-    std::vector<const uint64_t*> cur_src(npb), opa(npb), opb(npb);
-    for (size_t k = 0; k < npb; ++k) {
-      const PlanProduct& pr = plan.prods[p0 + k];
-      opa[k] = job_of[pr.job]->A->chunk(pr.ca, N);
-      opb[k] = job_of[pr.job]->B->chunk(pr.cb, N);
-      cur_src[k] = pr.d > 0 ? opb[k] : opa[k];
-    }
-    for (int t = 0; t < p.rot_digits; ++t) {
-      std::vector<const uint64_t*> src;
-      std::vector<uint32_t> st_amt;
-      std::vector<uint64_t*> out;
-      const uint32_t b = p.rot_bits, mask = (1u << b) - 1;
-      for (size_t k = 0; k < npb; ++k) {
-        const PlanProduct& pr = plan.prods[p0 + k];
-        if (pr.d == 0) continue;
-        const uint32_t amt = (uint32_t)((pr.d > 0 ? pr.d : -pr.d) % (int32_t)p.S);
-        const uint32_t rt_ = (amt >> (b * t)) & mask;
-        if (!rt_) continue;
-        uint64_t* al = ws.align + k * 2 * nq * N;
-        uint64_t* pf = ws.pfull + k * 2 * nq * N;
-        uint64_t* dst = cur_src[k] == al ? pf : al;
-        src.push_back(cur_src[k]);
-        st_amt.push_back(rt_ << (b * t));
-        out.push_back(dst);
-        cur_src[k] = dst;
-      }
-      enqueue_rotation(ctx, ap, ops, nq, src, st_amt, out, ws, st, true);
-    }
-    for (size_t k = 0; k < npb; ++k) {
-      const PlanProduct& pr = plan.prods[p0 + k];
-      if (pr.d > 0) opb[k] = cur_src[k];
-      if (pr.d < 0) opa[k] = cur_src[k];
-    }
-    // (2) EvalMult + Relinearize + Rescale (Algorithm 2, first three steps), once per product.
-    {
-      std::vector<const uint64_t*> keys(npb, ctx->relin->buf.u64()), add(2 * npb), pin(npb);
-      std::vector<uint64_t*> pout(npb), rout(npb);
-      for (size_t k = 0; k < npb; ++k) {
-        add[2 * k] = ws.tens + k * 3 * nq * N;
-        add[2 * k + 1] = ws.tens + k * 3 * nq * N + (size_t)nq * N;
-        pout[k] = ws.pfull + k * 2 * nq * N;
-        pin[k] = pout[k];
-        rout[k] = ws.prod + k * 2 * nl1 * N;
-      }
-      const size_t o_a = ap.push(opa), o_b = ap.push(opb), o_k = ap.push(keys), o_ad = ap.push(add),
-                   o_po = ap.push(pout), o_pi = ap.push(pin), o_ro = ap.push(rout);
-      const uint32_t Bn = (uint32_t)npb;
-      ops.push_back([=, &ap] {
-        tensor(ctx, Bn, nq, ap.at<const uint64_t*>(o_a), ap.at<const uint64_t*>(o_b), ws.tens, st);
-        keyswitch(ctx, Bn, nq, ws.tens + (size_t)2 * nq * N, (uint64_t)3 * nq * N, ap.at<const uint64_t*>(o_k),
-                  ap.at<const uint64_t*>(o_ad), ap.at<uint64_t*>(o_po), ws.ksws, st);
-        rescale(ctx, Bn, 2, nq, ap.at<const uint64_t*>(o_pi), ap.at<uint64_t*>(o_ro), ws.rsws, st);
-      });
-    }
+    Ops ops;
+    enqueue_products(ctx, ap, ops, plan, job_of, ids.data() + p0, npb, ws, st);
     // (3) Pairs of these products: mask, rescale, target rotation, accumulate.
     std::vector<uint32_t> pairs(by_prod.begin() + first[p0], by_prod.begin() + first[p1]);
     std::stable_sort(pairs.begin(), pairs.end(), [&](uint32_t x, uint32_t y) {
@@ -332,70 +553,15 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st) {
       if (a.chunk != b.chunk) return a.chunk < b.chunk;
       return a.rot < b.rot;
     });
-    const bool fused_mask = rescale_fuses_mask(ctx);
-    const uint32_t rbits = p.rot_bits, rmask = (1u << rbits) - 1;
     for (size_t q0 = 0; q0 < pairs.size(); q0 += BB) {
-      const size_t q1 = std::min(pairs.size(), q0 + BB), nb = q1 - q0;
-      std::vector<const uint64_t*> min_(nb), rin(nb);
-      std::vector<uint32_t> mg(nb);
-      std::vector<uint64_t*> mout(nb), cur(nb), alt(nb), where(nb);
-      for (size_t k = 0; k < nb; ++k) {
-        const PlanPair& pa = plan.pairs[pairs[q0 + k]];
-        min_[k] = ws.prod + (size_t)(pa.prod - p0) * 2 * nl1 * N;
-        mg[k] = mask_galois(p, pa.min_pos);
-        mout[k] = ws.msk + k * 2 * nl1 * N;
-        rin[k] = mout[k];
-        cur[k] = ws.cur + k * 2 * nl2 * N;
-        // With the mask fused into the rescale, the mask buffer is free: the target rotation steps
-        // alternate between it and cur, starting where an even number of steps ends in cur.
-        alt[k] = ws.msk + k * 2 * nl1 * N;
-        int nz = 0;
-        for (int t = 0; t < p.rot_digits; ++t) nz += ((pa.rot >> (rbits * t)) & rmask) != 0;
-        where[k] = (fused_mask && (nz & 1)) ? alt[k] : cur[k];
+      const size_t q1 = std::min(pairs.size(), q0 + BB);
+      std::vector<TailItem> items;
+      for (size_t k = q0; k < q1; ++k) {
+        const PlanPair& pa = plan.pairs[pairs[k]];
+        items.push_back(TailItem{ws.prod + (size_t)(pa.prod - p0) * 2 * nl1 * N, mask_galois(p, pa.min_pos), pa.chunk,
+                                 pa.rot});
       }
-      const size_t o_mi = ap.push(min_), o_mg = ap.push(mg), o_mo = ap.push(mout), o_ri = ap.push(rin),
-                   o_cu = ap.push(fused_mask ? where : cur);
-      const uint32_t Bn = (uint32_t)nb;
-      ops.push_back([=, &ap] {
-        if (rescale_fuses_mask(ctx)) {  // mask multiply applied inside the rescale's reads
-          rescale(ctx, Bn, 2, nl1, ap.at<const uint64_t*>(o_mi), ap.at<uint64_t*>(o_cu), ws.rsws, st,
-                  ap.at<uint32_t>(o_mg));
-        } else {
-          mask_mul(ctx, Bn, nl1, ap.at<const uint64_t*>(o_mi), ap.at<uint32_t>(o_mg), ap.at<uint64_t*>(o_mo), st);
-          rescale(ctx, Bn, 2, nl1, ap.at<const uint64_t*>(o_ri), ap.at<uint64_t*>(o_cu), ws.rsws, st);
-        }
-      });
-      for (int t = 0; t < p.rot_digits; ++t) {
-        std::vector<const uint64_t*> src;
-        std::vector<uint32_t> st_amt;
-        std::vector<uint64_t*> out;
-        for (size_t k = 0; k < nb; ++k) {
-          const uint32_t r = plan.pairs[pairs[q0 + k]].rot;
-          const uint32_t rt_ = (r >> (rbits * t)) & rmask;
-          if (!rt_) continue;
-          uint64_t* dst = fused_mask ? (where[k] == cur[k] ? alt[k] : cur[k]) : cur[k];
-          src.push_back(where[k]);
-          st_amt.push_back(rt_ << (rbits * t));
-          out.push_back(dst);
-          where[k] = dst;
-        }
-        enqueue_rotation(ctx, ap, ops, nl2, src, st_amt, out, ws, st, fused_mask);
-      }
-      std::vector<uint32_t> seg;
-      for (size_t k = 0; k < nb;) {
-        const int32_t ch = plan.pairs[pairs[q0 + k]].chunk;
-        size_t k2 = k;
-        while (k2 < nb && plan.pairs[pairs[q0 + k2]].chunk == ch) ++k2;
-        seg.push_back((uint32_t)ch);
-        seg.push_back((uint32_t)k);
-        seg.push_back((uint32_t)k2);
-        k = k2;
-      }
-      const size_t o_sg = ap.push(seg);
-      const uint32_t nseg = (uint32_t)(seg.size() / 3);
-      uint64_t* const* res = (uint64_t* const*)result_dev.get();
-      const uint32_t ncontrib = (uint32_t)nb;
-      ops.push_back([=, &ap] { accumulate(ctx, nseg, ncontrib, nl2, ap.at<uint32_t>(o_sg), ws.cur, res, st); });
+      enqueue_tail(ctx, ap, ops, items, true, ws, res, st);
     }
     ap.upload(st);
     for (auto& op : ops) op();

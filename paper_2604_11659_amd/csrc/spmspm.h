@@ -50,7 +50,10 @@ struct Job {
 // Executes one or many matmuls as a single stream of batched launches: the products and pairs of all
 // jobs are merged, so small matmuls share launches and pairs with equal rotation keys sit together.
 // Each job's C receives its dense result chunks (two levels below the top).
-void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st);
+// grouped: the pairs of a job sharing (result chunk, target rotation) are summed after their masks
+// and go through one second rescale and one target rotation (different ciphertext bits from the
+// per-pair form, same decryption up to noise).
+void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool grouped = false);
 
 // Resumable execution: prepare_result validates keys/operands and zeroes C; execute_slices runs the
 // products [lo, hi) of several prepared jobs (and all their pairs) as one merged launch stream,
@@ -60,9 +63,12 @@ struct Slice {
   int32_t lo, hi;
 };
 void prepare_result(fhe_ctx* ctx, Job& J, hipStream_t st);
-void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st);
+void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bool grouped = false);
 
 // Counts of key-switch work in the plan: [F, products, align KS, relin KS, target KS, result chunks].
 void plan_counts(const Params& p, const Plan& plan, int64_t out[6]);
+
+// Grouped form: [groups (distinct result chunk, target rotation), target key switches].
+void plan_group_counts(const Params& p, const Plan& plan, int64_t out[2]);
 
 }  // namespace fhe

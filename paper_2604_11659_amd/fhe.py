@@ -63,6 +63,8 @@ _SIGS = {
     "fhe_spmspm_batch": ([c_vp, c_sz, PP, PP, c_vp, PP], c_i32),
     "fhe_spmspm_batch_pairs": ([c_vp, c_sz, PP, PP, P_i64, P_i64, c_vp, PP], c_i32),
     "fhe_plan_stats": ([c_vp, c_vp, c_vp, P_i64], c_i32),
+    "fhe_spmspm_plan": ([c_vp, c_sz, PP, PP, P_i64, P_i64, c_i32, c_vp, PP], c_i32),
+    "fhe_plan_groups": ([c_vp, c_vp, c_vp, P_i64], c_i32),
     "fhe_autotune": ([c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_dbl),
                       ctypes.POINTER(c_i32), P_i32, P_dbl, c_i32], c_i32),
     "fhe_plan_pattern": ([c_i32, c_i32, c_i32, c_i32, c_i32, P_i32, P_i32, P_i32, P_i32, P_i64], c_i32),
@@ -287,33 +289,39 @@ class Context(_Handle):
     def encrypt_csc(self, sk, rows, cols, indptr, indices, values, seed, stream=None) -> Matrix:
         return self._encrypt(_lib.fhe_encrypt_csc, sk, rows, cols, indptr, indices, values, seed, stream)
 
-    def spmspm(self, A: Matrix, B: Matrix, stream=None) -> Matrix:
+    def spmspm(self, A: Matrix, B: Matrix, stream=None, grouped: bool = False) -> Matrix:
+        """C = A B. grouped: pairs sharing (result chunk, target rotation) share one second rescale
+        and one target rotation (FHE_PLAN_GROUPED)."""
+        if grouped:
+            return self.spmspm_batch([A], [B], stream, grouped=True)[0]
         out = c_vp()
         _check(_lib.fhe_spmspm(self._ptr, A._ptr, B._ptr, _stream(stream), ctypes.byref(out)))
         return Matrix(out.value, self)
 
-    def spmspm_batch(self, As, Bs, stream=None, pair_ranges=None) -> list:
+    def spmspm_batch(self, As, Bs, stream=None, pair_ranges=None, grouped: bool = False) -> list:
         """[A_i B_i] in one merged launch stream (bit-identical to one-at-a-time spmspm).
 
-        pair_ranges: optional [(begin, end)] per matmul, restricting each to those matched pairs."""
+        pair_ranges: optional [(begin, end)] per matmul, restricting each to those matched pairs.
+        grouped: the grouped plan mode (FHE_PLAN_GROUPED)."""
         n = len(As)
         assert len(Bs) == n
         pa = (c_vp * max(1, n))(*[a._ptr for a in As])
         pb = (c_vp * max(1, n))(*[b._ptr for b in Bs])
         out = (c_vp * max(1, n))()
         if pair_ranges is None:
-            _check(_lib.fhe_spmspm_batch(self._ptr, n, ctypes.cast(pa, PP), ctypes.cast(pb, PP), _stream(stream),
-                                         ctypes.cast(out, PP)))
+            lo = hi = None
         else:
             assert len(pair_ranges) == n
             lo = np.asarray([r[0] for r in pair_ranges] or [0], np.int64)
             hi = np.asarray([r[1] for r in pair_ranges] or [0], np.int64)
-            _check(_lib.fhe_spmspm_batch_pairs(self._ptr, n, ctypes.cast(pa, PP), ctypes.cast(pb, PP),
-                                               _ptr(lo, c_i64), _ptr(hi, c_i64), _stream(stream),
-                                               ctypes.cast(out, PP)))
+        _check(_lib.fhe_spmspm_plan(self._ptr, n, ctypes.cast(pa, PP), ctypes.cast(pb, PP),
+                                    None if lo is None else _ptr(lo, c_i64), None if hi is None else _ptr(hi, c_i64),
+                                    1 if grouped else 0, _stream(stream), ctypes.cast(out, PP)))
         return [Matrix(out[i], self) for i in range(n)]
 
-    def spmspm_pairs(self, A: Matrix, B: Matrix, begin: int, end: int, stream=None) -> Matrix:
+    def spmspm_pairs(self, A: Matrix, B: Matrix, begin: int, end: int, stream=None, grouped: bool = False) -> Matrix:
+        if grouped:
+            return self.spmspm_batch([A], [B], stream, pair_ranges=[(begin, end)], grouped=True)[0]
         out = c_vp()
         _check(_lib.fhe_spmspm_pairs(self._ptr, A._ptr, B._ptr, begin, end, _stream(stream), ctypes.byref(out)))
         return Matrix(out.value, self)
@@ -340,6 +348,12 @@ class Context(_Handle):
         c = np.zeros(6, np.int64)
         _check(_lib.fhe_plan_stats(self._ptr, A._ptr, B._ptr, _ptr(c, c_i64)))
         return PlanStats(*[int(x) for x in c])
+
+    def plan_groups(self, A: Matrix, B: Matrix) -> tuple:
+        """(groups, target-rotation key switches) of the grouped plan of A B."""
+        c = np.zeros(2, np.int64)
+        _check(_lib.fhe_plan_groups(self._ptr, A._ptr, B._ptr, _ptr(c, c_i64)))
+        return int(c[0]), int(c[1])
 
     def plan_rotations(self, A: Matrix, B: Matrix):
         n = c_sz()

@@ -78,3 +78,38 @@ def test_dnn_layer_full_fp64_and_sampled_bit_exact():
         _say(f"[full] dnn pairs [{lo}, {hi}) oracle")
         ref = spmspm.spmspm(op, keys, OA, OB, workers=WORKERS, pairs=pairs[lo:hi])
         assert (ctx.export(Cs, 0) == ref[0].data).all(), (lo, hi)
+
+
+def _merged_window(op, pairs, n, width):
+    """The traversal window of `width` pairs whose grouped plan merges the most pairs (host only)."""
+    best = (0, 0)
+    for lo in range(0, max(1, len(pairs) - width), 997):
+        merged = width - len(spmspm.target_groups(op, pairs[lo:lo + width], n))
+        best = max(best, (merged, lo))
+    return best[1], best[1] + width
+
+
+@pytest.mark.timeout(1200)
+def test_dnn_layer_grouped_full_fp64_and_sampled_bit_exact():
+    """Grouped plan at the DNN layer's full size: decrypts within 1e-5 of FP64; a traversal window
+    in which several pairs share groups is bit-exact against the oracle's grouped form."""
+    w = synth.WORKLOADS["dnn"]
+    _say("[full] dnn grouped setup")
+    a, b, ctx, sk, A, B, op, keys, OA, OB = _prepare(w)
+    groups, gks = ctx.plan_groups(A, B)
+    _say(f"[full] dnn grouped gpu spmspm: {groups} groups, {gks} target key switches")
+    C = ctx.spmspm(A, B, grouped=True)
+    err = np.abs(ctx.decrypt_decode(sk, C) - a @ b).max()
+    _say(f"[full] dnn grouped max-abs error {err:.3e}")
+    assert err < 1e-5
+    C.close()
+    pairs = spmspm.matched_pairs(w.m, w.n, OA.indptr, OA.indices, OB.indptr, OB.indices)
+    assert groups == len(spmspm.target_groups(op, pairs, w.n))
+    lo, hi = _merged_window(op, pairs, w.n, 24)
+    ng = len(spmspm.target_groups(op, pairs[lo:hi], w.n))
+    assert ng < hi - lo
+    _say(f"[full] dnn grouped pairs [{lo}, {hi}) ({ng} groups) gpu")
+    Cs = ctx.spmspm_pairs(A, B, lo, hi, grouped=True)
+    _say(f"[full] dnn grouped pairs [{lo}, {hi}) oracle")
+    ref = spmspm.spmspm(op, keys, OA, OB, workers=WORKERS, pairs=pairs[lo:hi], grouped=True)
+    assert (ctx.export(Cs, 0) == ref[0].data).all(), (lo, hi)
