@@ -35,6 +35,8 @@ Allocator current_allocator();
 int prof_begin(const char* name, hipStream_t st);
 void prof_end(int tok, hipStream_t st, double algorithmic_bytes);
 void prof_enable(bool on);
+// Adds n to the work counter `name` while timing is on (reported as "count:<name>" with n launches).
+void prof_count(const char* name, int64_t n);
 std::vector<std::tuple<std::string, int64_t, double, double>> prof_summary();
 
 // Owning device buffer, allocated and released through the registered allocator.

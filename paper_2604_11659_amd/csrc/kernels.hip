@@ -1422,6 +1422,7 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
   const Params& p = ctx->p;
   if (p.alpha > kMaxAlpha || p.np > kMaxK) fail(FHE_EINVAL, "alpha or n_p above kernel limits");
   if (nl < 1 || nl > (uint32_t)p.nq) fail(FHE_ESHAPE, "key switch level out of range");
+  prof_count("keyswitch", B);
   const uint32_t N = p.N, K = p.np, next = nl + K, beta = p.beta(nl), alpha = p.alpha;
   const uint32_t R = modup_rows(p, nl), cnt_last = nl - (beta - 1) * alpha;
   const uint32_t beta_full = cnt_last == alpha ? beta : beta - 1;
@@ -1559,6 +1560,7 @@ void rescale(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const 
   if (!B) return;
   const Params& p = ctx->p;
   if (nl < 2 || nl > (uint32_t)p.nq) fail(FHE_ELEVEL, "rescale needs at least two limbs");
+  prof_count("rescale", B);
   if (mask_galois && (!rescale_fuses_mask(ctx) || nl > (uint32_t)p.nq - 1))
     fail(FHE_EINVAL, "mask-fused rescale needs the fused column kernels and a level below the top");
   const uint32_t N = p.N, BC = B * ncomp;

@@ -87,6 +87,7 @@ struct KernelTimer {
   bool on = false;
   std::vector<TimerRec> recs;
   std::vector<hipEvent_t> pool;
+  std::map<std::string, int64_t> counts;  // work counters (no timing), e.g. key switches issued
 };
 KernelTimer& timer() {
   static KernelTimer* t = new KernelTimer();
@@ -123,6 +124,12 @@ void prof_end(int tok, hipStream_t st, double bytes) {
   HIPCHECK(hipEventRecord(t.recs[tok].b, st));
 }
 
+void prof_count(const char* name, int64_t n) {
+  KernelTimer& t = timer();
+  std::lock_guard<std::mutex> lk(t.mu);
+  if (t.on) t.counts[name] += n;
+}
+
 void prof_enable(bool on) {
   KernelTimer& t = timer();
   std::lock_guard<std::mutex> lk(t.mu);
@@ -133,6 +140,7 @@ void prof_enable(bool on) {
       t.pool.push_back(r.b);
     }
     t.recs.clear();
+    t.counts.clear();
   }
   t.on = on;
 }
@@ -153,6 +161,7 @@ std::vector<std::tuple<std::string, int64_t, double, double>> prof_summary() {
   }
   std::vector<std::tuple<std::string, int64_t, double, double>> out;
   for (auto& kv : agg) out.emplace_back(kv.first, std::get<0>(kv.second), std::get<1>(kv.second), std::get<2>(kv.second));
+  for (auto& kv : t.counts) out.emplace_back("count:" + kv.first, kv.second, 0.0, 0.0);
   return out;
 }
 

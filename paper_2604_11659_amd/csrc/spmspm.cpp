@@ -79,6 +79,38 @@ Plan build_plan(const Params& p, const fhe_mat* A, const fhe_mat* B, int64_t beg
     }
   }
   plan.matched = idx;
+  // Order the products by the ciphertext their alignment rotates and by its rotation digits, low
+  // digit first: products whose rotations start with the same steps become neighbours, so a batch of
+  // products computes each shared intermediate rotation once (the executor keys rotation states by
+  // source and amount prefix). Bits are unaffected: every product still sees its own sequence.
+  const uint32_t rb = (uint32_t)p.rot_bits, rm = (1u << rb) - 1;
+  auto skey = [&](const PlanProduct& pr, int t) -> int64_t {
+    const uint32_t a = (uint32_t)(pr.d > 0 ? pr.d : -pr.d);
+    return (int64_t)((a >> (rb * t)) & rm);
+  };
+  std::vector<int32_t> order(plan.prods.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+  std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    const PlanProduct &a = plan.prods[x], &b = plan.prods[y];
+    const int ka = a.d > 0 ? 1 : (a.d < 0 ? 0 : 2), kb = b.d > 0 ? 1 : (b.d < 0 ? 0 : 2);
+    if (ka != kb) return ka < kb;
+    const int32_t ca = a.d > 0 ? a.cb : a.ca, cb = b.d > 0 ? b.cb : b.ca;
+    if (ca != cb) return ca < cb;
+    for (int t = 0; t < p.rot_digits; ++t) {
+      const int64_t da = skey(a, t), db = skey(b, t);
+      if (da != db) return da < db;
+    }
+    if (a.ca != b.ca) return a.ca < b.ca;
+    return a.cb < b.cb;
+  });
+  std::vector<int32_t> rank(order.size());
+  std::vector<PlanProduct> sorted(order.size());
+  for (size_t r = 0; r < order.size(); ++r) {
+    rank[order[r]] = (int32_t)r;
+    sorted[r] = plan.prods[order[r]];
+  }
+  plan.prods.swap(sorted);
+  for (auto& pa : plan.pairs) pa.prod = rank[pa.prod];
   return plan;
 }
 
@@ -220,37 +252,63 @@ void enqueue_products(fhe_ctx* ctx, ArgPack& ap, Ops& ops, const Plan& plan, con
                       const int32_t* ids, size_t npb, const Workspace& ws, hipStream_t st) {
   const Params& p = ctx->p;
   const uint32_t N = p.N, nq = p.nq, nl1 = nq - 1;
-  // (1) Alignment rotations (Algorithm 1): rotate the operand whose value sits at the later slot.
-  // Rotation steps alternate between two scratch buffers per product (align, then the relinearised
-  // product's buffer, free until step (2) writes it), so every key switch reads its input through
-  // the automorphism without an in-place hazard.
-  std::vector<const uint64_t*> cur_src(npb), opa(npb), opb(npb);
+  // (1) Alignment rotations (Algorithm 1): rotate the operand whose value sits at the later slot, by
+  // the slot difference, one key switch per nonzero rotation digit (low digit first). A rotation
+  // state is (source ciphertext, amount applied so far); products of the batch that reach the same
+  // state share its buffer, so each distinct intermediate rotation is computed once. States live in
+  // 2 npb slots (the align buffers and the relinearised products' buffers, free until step (2)
+  // writes them); a step's outputs take slots no live state holds, so no key switch writes a buffer
+  // another one of the same launch reads.
+  const uint32_t rbits = (uint32_t)p.rot_bits, rmask = (1u << rbits) - 1;
+  std::vector<const uint64_t*> cur_src(npb), opa(npb), opb(npb), base(npb);
+  std::vector<uint32_t> amt(npb, 0);
+  std::vector<int32_t> slot_of(npb, -1);  // -1: the state is the source operand itself
+  std::vector<int32_t> refs(2 * npb, 0);
+  auto slot_ptr = [&](int32_t sl) -> uint64_t* {
+    return sl < (int32_t)npb ? ws.align + (size_t)sl * 2 * nq * N : ws.pfull + (size_t)(sl - npb) * 2 * nq * N;
+  };
   for (size_t k = 0; k < npb; ++k) {
     const PlanProduct& pr = plan.prods[ids[k]];
     opa[k] = job_of[pr.job]->A->chunk(pr.ca, N);
     opb[k] = job_of[pr.job]->B->chunk(pr.cb, N);
-    cur_src[k] = pr.d > 0 ? opb[k] : opa[k];
+    cur_src[k] = base[k] = pr.d > 0 ? opb[k] : opa[k];
+    amt[k] = pr.d == 0 ? 0u : (uint32_t)((pr.d > 0 ? pr.d : -pr.d) % (int32_t)p.S);
   }
   for (int t = 0; t < p.rot_digits; ++t) {
     std::vector<const uint64_t*> src;
     std::vector<uint32_t> st_amt;
     std::vector<uint64_t*> out;
-    const uint32_t b = p.rot_bits, mask = (1u << b) - 1;
+    std::vector<char> taken(2 * npb, 0);
+    std::unordered_map<uint64_t, int32_t> made;  // (source index, prefix) -> output slot of this step
+    std::unordered_map<const uint64_t*, uint32_t> src_id;
+    std::vector<int32_t> new_slot(npb, -2);
+    int32_t next_free = 0;
     for (size_t k = 0; k < npb; ++k) {
-      const PlanProduct& pr = plan.prods[ids[k]];
-      if (pr.d == 0) continue;
-      const uint32_t amt = (uint32_t)((pr.d > 0 ? pr.d : -pr.d) % (int32_t)p.S);
-      const uint32_t rt_ = (amt >> (b * t)) & mask;
+      const uint32_t rt_ = (amt[k] >> (rbits * t)) & rmask;
       if (!rt_) continue;
-      uint64_t* al = ws.align + k * 2 * nq * N;
-      uint64_t* pf = ws.pfull + k * 2 * nq * N;
-      uint64_t* dst = cur_src[k] == al ? pf : al;
-      src.push_back(cur_src[k]);
-      st_amt.push_back(rt_ << (b * t));
-      out.push_back(dst);
-      cur_src[k] = dst;
+      const uint32_t sid = src_id.emplace(base[k], (uint32_t)src_id.size()).first->second;
+      const uint32_t prefix = amt[k] & (uint32_t)((rbits * (t + 1) >= 32) ? ~0u : ((1u << (rbits * (t + 1))) - 1));
+      const uint64_t key = ((uint64_t)sid << 32) | prefix;
+      auto it = made.find(key);
+      if (it == made.end()) {
+        while (next_free < (int32_t)(2 * npb) && (refs[next_free] > 0 || taken[next_free])) ++next_free;
+        if (next_free >= (int32_t)(2 * npb)) fail(FHE_EINVAL, "internal: no free rotation-state slot");
+        taken[next_free] = 1;
+        it = made.emplace(key, next_free).first;
+        src.push_back(cur_src[k]);
+        st_amt.push_back(rt_ << (rbits * t));
+        out.push_back(slot_ptr(next_free));
+      }
+      new_slot[k] = it->second;
     }
     enqueue_rotation(ctx, ap, ops, nq, src, st_amt, out, ws, st, true);
+    for (size_t k = 0; k < npb; ++k) {
+      if (new_slot[k] == -2) continue;
+      if (slot_of[k] >= 0) --refs[slot_of[k]];
+      slot_of[k] = new_slot[k];
+      ++refs[slot_of[k]];
+      cur_src[k] = slot_ptr(slot_of[k]);
+    }
   }
   for (size_t k = 0; k < npb; ++k) {
     const PlanProduct& pr = plan.prods[ids[k]];
