@@ -252,6 +252,29 @@ def run_serve(args) -> dict:
     }
 
 
+def run_graph(ctx, A, B, steps: int) -> dict:
+    """The per-pair plan recorded once as a HIP graph (FHE_PLAN_GRAPH) and replayed: one launch per
+    matmul instead of one per kernel; the limbs are those of the eager form."""
+    import torch
+    t0 = time.perf_counter()
+    C = ctx.spmspm(A, B, graph=True)  # records the graph, then launches it
+    torch.cuda.synchronize()
+    rec = time.perf_counter() - t0
+    C.close()
+    t0 = time.perf_counter()
+    C = None
+    for _ in range(steps):
+        if C is not None:
+            C.close()
+        C = ctx.spmspm(A, B, graph=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    C.close()
+    log(f"graph: record + first launch {1000 * rec:.1f} ms, replay {1000 * dt / steps:.2f} ms/step")
+    return {"plan": "per-pair, HIP graph replay", "value": round(steps / dt, 6), "unit": "SpMSpM/s",
+            "steps": steps, "ms_per_step": round(1000 * dt / steps, 3), "record_and_first_ms": round(1000 * rec, 1)}
+
+
 def run_grouped(ctx, sk, A, B, st, ref, steps: int) -> dict:
     """The grouped plan on the same operands: masked products sharing (result chunk, target rotation)
     summed, then one rescale and one rotation per group. Different ciphertext bits from the per-pair
@@ -273,7 +296,9 @@ def run_grouped(ctx, sk, A, B, st, ref, steps: int) -> dict:
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     fhe.profile_enable(False)
-    ks = fhe.profile_read().get("count:keyswitch", {}).get("launches", 0) / steps
+    prof = fhe.profile_read()
+    ks = prof.get("count:keyswitch", {}).get("launches", 0) / steps
+    _, kernels = roofline(prof)
     dec = ctx.decrypt_decode(sk, C)
     C.close()
     v = steps / dt
@@ -282,7 +307,7 @@ def run_grouped(ctx, sk, A, B, st, ref, steps: int) -> dict:
             "ms_per_step": round(1000 * dt / steps, 2), "groups": groups, "target_keyswitches": gks,
             "keyswitches_executed": ks, "matched_pairs_per_s": round(st.matched_pairs * v, 1),
             "keyswitch_per_s": round(ks * v, 1), "max_abs_err": float(np.abs(dec - ref).max()),
-            "frobenius_err": float(np.sqrt(((dec - ref) ** 2).sum()))}
+            "frobenius_err": float(np.sqrt(((dec - ref) ** 2).sum()))}, kernels
 
 
 def main():
@@ -304,6 +329,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=int, default=16)
     ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle pairs to time (0 = skip, -1 = one per core)")
     ap.add_argument("--kernels-out", default=None, help="write per-kernel timings (JSON) here")
+    ap.add_argument("--graph-steps", type=int, default=2,
+                    help="also time this many replays of the per-pair plan recorded as one HIP graph (0 = skip)")
     ap.add_argument("--grouped-steps", type=int, default=2,
                     help="also time this many steps of the grouped plan (one rescale and rotation per result "
                          "chunk and target rotation; 0 = skip), after one warm-up step")
@@ -399,11 +426,14 @@ def main():
         "max_abs_err": err, "frobenius_err": frob, "setup_s": round(setup_s, 2),
         "roofline": roof, "cpu_baseline": cpu,
     }
+    gkernels = None
+    if args.graph_steps > 0:
+        line["graph"] = run_graph(ctx, A, B, args.graph_steps)
     if args.grouped_steps > 0:
-        line["grouped"] = run_grouped(ctx, sk, A, B, st, ref, args.grouped_steps)
+        line["grouped"], gkernels = run_grouped(ctx, sk, A, B, st, ref, args.grouped_steps)
     if args.kernels_out:
         with open(args.kernels_out, "w") as f:
-            json.dump({"kernels": kernels, "plan": st.__dict__}, f, indent=1)
+            json.dump({"kernels": kernels, "grouped_kernels": gkernels, "plan": st.__dict__}, f, indent=1)
     print(json.dumps(line), flush=True)
 
 

@@ -146,6 +146,7 @@ int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, co
 /* Plan modes of fhe_spmspm_plan. */
 #define FHE_PLAN_PER_PAIR 0 /* Algorithm 2 per matched pair (the form of fhe_spmspm) */
 #define FHE_PLAN_GROUPED 1  /* grouped target rotations, see fhe_spmspm_plan */
+#define FHE_PLAN_GRAPH 256  /* flag: record the launch stream as a HIP graph and replay it, see below */
 
 /* General form of the matmul calls: C_out[i] = A[i] B[i] for i < cnt as one merged launch stream,
  * each restricted to the matched pairs with traversal index in [pair_begin[i], pair_end[i]) (both
@@ -156,10 +157,18 @@ int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, co
  * through one second rescale and one target rotation. The groups are formed over the pairs of the
  * call's range. Decrypted results equal the per-pair form's up to noise (lower: fewer roundings
  * and key switches); the ciphertext limbs are those of that grouped sequence, not the per-pair
- * ones. The grouped form keeps one accumulator of 2 (n_q - 1) N words per group in device memory,
- * up to FHE_GROUP_MB (environment, default 49152 MiB); beyond that it runs the groups in passes and
- * each pass recomputes the products its pairs use. Errors as fhe_spmspm_batch_pairs, FHE_EINVAL for
- * an unknown mode; on error all C_out[i] are NULL. */
+ * ones. The grouped form keeps the products (2 (n_q - 1) N words each) its groups use resident in
+ * device memory, up to FHE_GROUP_MB (environment, default 49152 MiB, raised to the largest group's
+ * products if needed); beyond that it runs the groups in passes and each pass recomputes the
+ * products its pairs use. Errors as fhe_spmspm_batch_pairs, FHE_EINVAL for
+ * an unknown mode; on error all C_out[i] are NULL.
+ * With FHE_PLAN_GRAPH or-ed into mode, the first call records the call's whole launch stream as one
+ * HIP graph (on a stream of the context's own) and keeps it on the context, together with the pointer
+ * tables and scratch its kernels read; later calls with the same operand handles, ranges, plan mode
+ * and NTT split replay it with a single launch on `stream`. Results are bit-identical to the eager
+ * form. A context keeps at most two graphs (the oldest is dropped) and drops them all when its
+ * scratch has to grow. Graph calls are not timed per kernel by fhe_profile_* (one "graph_replay"
+ * record per call). */
 int fhe_spmspm_plan(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B,
                     const int64_t* pair_begin, const int64_t* pair_end, int32_t mode, void* stream, fhe_mat** C_out);
 

@@ -182,7 +182,8 @@ int fhe_spmspm_plan(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe
       need(B, "B");
     }
     for (size_t i = 0; i < cnt; ++i) C_out[i] = nullptr;
-    if (mode != FHE_PLAN_PER_PAIR && mode != FHE_PLAN_GROUPED) fail(FHE_EINVAL, "unknown plan mode");
+    const int32_t plan_mode = mode & ~FHE_PLAN_GRAPH;
+    if (plan_mode != FHE_PLAN_PER_PAIR && plan_mode != FHE_PLAN_GROUPED) fail(FHE_EINVAL, "unknown plan mode");
     if ((pair_begin == nullptr) != (pair_end == nullptr)) fail(FHE_EINVAL, "pair_begin and pair_end go together");
     for (size_t i = 0; i < cnt; ++i) {
       check_operands(A[i], B[i]);
@@ -194,9 +195,9 @@ int fhe_spmspm_plan(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe
     for (size_t i = 0; i < cnt; ++i) {
       Cs[i].reset(new fhe_mat());
       const int64_t lo = pair_begin ? pair_begin[i] : 0, hi = pair_end ? pair_end[i] : INT64_MAX;
-      jobs[i] = Job{A[i], B[i], build_plan(ctx->p, A[i], B[i], lo, hi), Cs[i].get()};
+      jobs[i] = Job{A[i], B[i], build_plan(ctx->p, A[i], B[i], lo, hi), Cs[i].get(), lo, hi};
     }
-    execute_jobs(ctx, jobs, as_stream(stream), mode == FHE_PLAN_GROUPED);
+    execute_jobs(ctx, jobs, as_stream(stream), plan_mode == FHE_PLAN_GROUPED, (mode & FHE_PLAN_GRAPH) != 0);
     for (size_t i = 0; i < cnt; ++i) C_out[i] = Cs[i].release();
   });
 }

@@ -228,6 +228,8 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
   ctx->t.mask = DevBuf((size_t)nml * N * 8, st);
   signed_to_limbs(ctx, (const int64_t*)mint.get(), nml, nml, 0, ctx->t.mask.u64(), st);
   ntt_forward(ctx, LimbBatch{ctx->t.mask.u64(), nml, 1, (uint64_t)nml * N, nml, 0}, st);
+  ctx->t.mask_f = DevBuf((size_t)nml * N * 8, st);
+  to_f64_bits(ctx, (uint64_t)nml * N, ctx->t.mask.u64(), ctx->t.mask_f.u64(), st);
   to_montgomery(ctx, ctx->t.mask.u64(), nml, nml, 0, st);
   sync(st);
 }

@@ -37,6 +37,13 @@ void prof_end(int tok, hipStream_t st, double algorithmic_bytes);
 void prof_enable(bool on);
 // Adds n to the work counter `name` while timing is on (reported as "count:<name>" with n launches).
 void prof_count(const char* name, int64_t n);
+// While alive, launches on this thread are not timed (they are being captured into a graph).
+// prof_count adds to the scope's own counters instead.
+struct CaptureScope {
+  CaptureScope();
+  ~CaptureScope();
+  int64_t count(const char* name) const;
+};
 std::vector<std::tuple<std::string, int64_t, double, double>> prof_summary();
 
 // Owning device buffer, allocated and released through the registered allocator.
@@ -91,6 +98,7 @@ struct Tables {
   DevBuf moddown_f;  // doubles [K][nq][4]: c0 = phat mod q_i, c0 / q_i, c1 = c0 2^30 mod q_i, c1 / q_i
   DevBuf rescale;  // ql_inv[l][i][2] = (q_l^-1 mod q_i, shoup), l < nq, i < l
   DevBuf mask;     // NTT of the base mask on limbs 0..nq-2, Montgomery form: [nq-1][N]
+  DevBuf mask_f;   // the same residues in [0, q) as the bits of doubles (FP64 products)
   std::vector<size_t> modup_offset;  // index nl (1..nq): offset (uint64 units) of the nl block
   std::vector<int64_t> base_mask;    // coefficient-domain base mask (host copy)
 };
@@ -99,6 +107,17 @@ struct SwitchKey {
   DevBuf buf;  // [beta_top][2][nq+np][N], NTT domain; Q limbs as doubles' bits, P limbs in Montgomery form
 };
 
+}  // namespace fhe
+
+namespace fhe {
+struct GraphEntry;  // a captured matmul launch stream (spmspm.cpp)
+uint64_t next_handle_id();
+// Stream created on first use (default priority), destroyed with its owner.
+struct OwnedStream {
+  hipStream_t s = nullptr;
+  hipStream_t get();
+  ~OwnedStream();
+};
 }  // namespace fhe
 
 struct fhe_ctx {
@@ -111,6 +130,8 @@ struct fhe_ctx {
   std::recursive_mutex exec_mu;  // one matmul execution at a time per context (shared scratch); the
                                  // autotuner holds it across the matmuls it times
   fhe::DevBuf ws_cache;  // executor scratch, grown on demand
+  fhe::OwnedStream capture_stream;  // stream the executor captures HIP graphs on
+  std::vector<std::shared_ptr<fhe::GraphEntry>> graphs;  // captured matmuls, most recent last
 };
 
 struct fhe_sk {
@@ -126,6 +147,7 @@ struct fhe_ct {
 };
 
 struct fhe_mat {
+  uint64_t id = fhe::next_handle_id();  // unique per handle in the process (keys captured graphs)
   int kind = 0;  // 0 CSR operand, 1 CSC operand, 2 dense result
   int rows = 0, cols = 0;
   std::vector<int32_t> indptr, indices;  // public pattern (operands)

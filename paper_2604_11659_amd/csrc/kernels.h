@@ -73,6 +73,9 @@ void mask_mul(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* const
 void mask_sum(const fhe_ctx* ctx, uint32_t nseg, uint32_t nentries, uint32_t nl, const uint32_t* seg,
               const uint64_t* const* in, const uint32_t* galois, uint64_t* acc, hipStream_t st);
 
+// out[i] = the bits of in[i] as a double (values below 2^53), i < n.
+void to_f64_bits(const fhe_ctx* ctx, uint64_t n, const uint64_t* in, uint64_t* out, hipStream_t st);
+
 // results[seg[3s]] += sum of contrib[b] for b in [seg[3s+1], seg[3s+2]); [2][nl][N] each; `results` is
 // a device array of result-chunk pointers. ncontrib (the number of contributions the segments cover)
 // only sizes the launch's traffic figure for the kernel timer.

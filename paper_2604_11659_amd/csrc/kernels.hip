@@ -1055,11 +1055,13 @@ __global__ __launch_bounds__(kThreads) void k_mask_mul(uint32_t B, uint32_t nl, 
 // Grouped masked sums. Segment s: accumulator seg[4s] (at acc + seg[4s] * 2 nl N), entries
 // [seg[4s+1], seg[4s+2]), and seg[4s+3] = 1 to overwrite the accumulator (first products of its
 // group), 0 to add to it. acc[c][i][k] (+)= sum over the entries e of in[e][c][i][k] times the one-hot
-// mask tau_(galois[e])(base mask) at limb i, coefficient k (NTT domain, mask in Montgomery form).
+// mask tau_(galois[e])(base mask) at limb i, coefficient k (NTT domain). All limbs are Q limbs
+// (q < 2^50): the products are exact FP64 (FpArith::kacc, the mask as doubles, every term below
+// 0.875 q) and the sums are reduced every four entries; the stored result is the residue in [0, q).
 // One thread per (segment, limb, coefficient): both components share the mask word.
 __global__ __launch_bounds__(kThreads) void k_mask_sum(uint32_t nseg, uint32_t nl, uint32_t logN,
                                                       const ModInfo* __restrict__ mods,
-                                                      const uint64_t* __restrict__ maskm,
+                                                      const uint64_t* __restrict__ maskf,
                                                       const uint32_t* __restrict__ seg,
                                                       const uint64_t* const* __restrict__ in,
                                                       const uint32_t* __restrict__ galois,
@@ -1071,24 +1073,51 @@ __global__ __launch_bounds__(kThreads) void k_mask_sum(uint32_t nseg, uint32_t n
     const uint32_t s = (uint32_t)(t / per);
     const uint64_t off = t - (uint64_t)s * per;
     const uint32_t i = (uint32_t)(off >> logN), k = (uint32_t)off & (N - 1);
-    const ModInfo m = mods[i];
+    FpArith ar;
+    ar.init(mods[i]);
     const uint32_t e0 = seg[4 * s + 1], e1 = seg[4 * s + 2];
     uint64_t* a = acc + (uint64_t)seg[4 * s] * 2 * per + off;
-    uint64_t v0 = 0, v1 = 0;
+    double v0 = 0.0, v1 = 0.0;
     if (!seg[4 * s + 3]) {
-      v0 = a[0];
-      v1 = a[per];
+      v0 = (double)a[0];
+      v1 = (double)a[per];
     }
-    const uint64_t* mrow = maskm + ((uint64_t)i << logN);
-    for (uint32_t e = e0; e < e1; ++e) {
+    const uint64_t* mrow = maskf + ((uint64_t)i << logN);
+    uint32_t e = e0;
+    // four entries per round (|sum| stays below q + 4 * 0.875 q < 2^53), loads issued first
+    for (; e + 4 <= e1; e += 4) {
+      uint64_t mk[4], x0[4], x1[4];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j) {
+        const uint64_t* x = in[e + j] + off;
+        mk[j] = mrow[automorph_src(k, galois[e + j], logN)];
+        x0[j] = x[0];
+        x1[j] = x[per];
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j) {
+        v0 = ar.kacc(v0, (double)x0[j], mk[j]);
+        v1 = ar.kacc(v1, (double)x1[j], mk[j]);
+      }
+      ar.kred(v0);
+      ar.kred(v1);
+    }
+    for (; e < e1; ++e) {
       const uint64_t mk = mrow[automorph_src(k, galois[e], logN)];
       const uint64_t* x = in[e] + off;
-      v0 = add_mod(v0, mont_mul(x[0], mk, m.q, m.qinv), m.q);
-      v1 = add_mod(v1, mont_mul(x[per], mk, m.q, m.qinv), m.q);
+      v0 = ar.kacc(v0, (double)x[0], mk);
+      v1 = ar.kacc(v1, (double)x[per], mk);
     }
-    a[0] = v0;
-    a[per] = v1;
+    a[0] = ar.kfinal(v0);
+    a[per] = ar.kfinal(v1);
   }
+}
+
+// out[i] = the bits of (double)in[i] (residues below 2^53), i < n.
+__global__ __launch_bounds__(kThreads) void k_to_f64_bits(uint64_t n, const uint64_t* __restrict__ in,
+                                                         uint64_t* __restrict__ out) {
+  for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kThreads)
+    out[t] = (uint64_t)__double_as_longlong((double)in[t]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_accumulate(uint32_t nseg, uint32_t nl, uint32_t logN,
@@ -1630,7 +1659,11 @@ void mask_sum(const fhe_ctx* ctx, uint32_t nseg, uint32_t nentries, uint32_t nl,
   // when it already holds a partial sum; counted as written only)
   const double bytes = 8.0 * nl * ctx->p.N * (3.0 * nentries + 2.0 * nseg);
   FHE_LAUNCH("mask_sum", bytes, k_mask_sum, grid_for((uint64_t)nseg * nl << ctx->p.logN), 0, st, nseg, nl,
-             ctx->p.logN, mods_of(ctx), ctx->t.mask.u64(), seg, in, galois, acc);
+             ctx->p.logN, mods_of(ctx), ctx->t.mask_f.u64(), seg, in, galois, acc);
+}
+
+void to_f64_bits(const fhe_ctx* ctx, uint64_t n, const uint64_t* in, uint64_t* out, hipStream_t st) {
+  FHE_LAUNCH("to_f64_bits", 16.0 * n, k_to_f64_bits, grid_for(n), 0, st, n, in, out);
 }
 
 void accumulate(const fhe_ctx* ctx, uint32_t nseg, uint32_t ncontrib, uint32_t nl, const uint32_t* seg,

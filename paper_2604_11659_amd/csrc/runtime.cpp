@@ -1,4 +1,5 @@
 // Errors, the device allocator hook and owning device buffers.
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -105,7 +106,38 @@ hipEvent_t take_event(KernelTimer& t) {
 }
 }  // namespace
 
+namespace {
+thread_local int g_capturing = 0;
+thread_local std::map<std::string, int64_t>* g_capture_counts = nullptr;
+std::atomic<uint64_t> g_handle_id{1};
+}  // namespace
+
+CaptureScope::CaptureScope() {
+  if (!g_capturing++) g_capture_counts = new std::map<std::string, int64_t>();
+}
+CaptureScope::~CaptureScope() {
+  if (!--g_capturing) {
+    delete g_capture_counts;
+    g_capture_counts = nullptr;
+  }
+}
+int64_t CaptureScope::count(const char* name) const {
+  auto it = g_capture_counts->find(name);
+  return it == g_capture_counts->end() ? 0 : it->second;
+}
+
+uint64_t next_handle_id() { return g_handle_id.fetch_add(1); }
+
+hipStream_t OwnedStream::get() {
+  if (!s) HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  return s;
+}
+OwnedStream::~OwnedStream() {
+  if (s) (void)hipStreamDestroy(s);
+}
+
 int prof_begin(const char* name, hipStream_t st) {
+  if (g_capturing) return -1;
   KernelTimer& t = timer();
   std::lock_guard<std::mutex> lk(t.mu);
   if (!t.on) return -1;
@@ -125,6 +157,10 @@ void prof_end(int tok, hipStream_t st, double bytes) {
 }
 
 void prof_count(const char* name, int64_t n) {
+  if (g_capturing) {
+    (*g_capture_counts)[name] += n;
+    return;
+  }
   KernelTimer& t = timer();
   std::lock_guard<std::mutex> lk(t.mu);
   if (t.on) t.counts[name] += n;

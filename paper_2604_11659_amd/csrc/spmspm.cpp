@@ -224,13 +224,17 @@ void prepare_result(fhe_ctx* ctx, Job& J, hipStream_t st) {
   HIPCHECK(hipMemsetAsync(C->data.get(), 0, (size_t)J.plan.nres * chunk_elems * 8, st));
 }
 
-void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool grouped) {
+void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool grouped, bool graph) {
   std::vector<Slice> slices;
   for (auto& J : jobs) {
     prepare_result(ctx, J, st);
     slices.push_back(Slice{&J, 0, (int32_t)J.plan.prods.size()});
   }
-  execute_slices(ctx, slices, st, grouped);
+  execute_slices(ctx, slices, st, grouped, graph);
+}
+
+GraphEntry::~GraphEntry() {
+  if (exec) (void)hipGraphExecDestroy(exec);
 }
 
 namespace {
@@ -246,10 +250,32 @@ struct TailItem {
 
 using Ops = std::vector<std::function<void()>>;
 
+// Runs batches of launches: each batch's pointer tables are uploaded on `ls`, then its launches run
+// at once (eager) or are kept for a graph capture (deferred).
+struct Runner {
+  hipStream_t ls;
+  bool defer;
+  std::vector<std::unique_ptr<ArgPack>>& packs;
+  std::vector<Ops> pending;
+  ArgPack& pack() {
+    packs.emplace_back(new ArgPack());
+    return *packs.back();
+  }
+  void submit(ArgPack& ap, Ops& ops) {
+    ap.upload(ls);
+    if (defer) {
+      pending.push_back(std::move(ops));
+    } else {
+      for (auto& op : ops) op();
+    }
+  }
+};
+
 // EvalMult -> Relinearize -> Rescale of the products ids[k] (after their alignment rotations) into
 // ws.prod slot k, [2][nq - 1][N] each.
 void enqueue_products(fhe_ctx* ctx, ArgPack& ap, Ops& ops, const Plan& plan, const std::vector<const Job*>& job_of,
-                      const int32_t* ids, size_t npb, const Workspace& ws, hipStream_t st) {
+                      const int32_t* ids, size_t npb, const Workspace& ws, hipStream_t st,
+                      uint64_t* const* dest = nullptr) {
   const Params& p = ctx->p;
   const uint32_t N = p.N, nq = p.nq, nl1 = nq - 1;
   // (1) Alignment rotations (Algorithm 1): rotate the operand whose value sits at the later slot, by
@@ -323,7 +349,7 @@ void enqueue_products(fhe_ctx* ctx, ArgPack& ap, Ops& ops, const Plan& plan, con
     add[2 * k + 1] = ws.tens + k * 3 * nq * N + (size_t)nq * N;
     pout[k] = ws.pfull + k * 2 * nq * N;
     pin[k] = pout[k];
-    rout[k] = ws.prod + k * 2 * nl1 * N;
+    rout[k] = dest ? dest[k] : ws.prod + k * 2 * nl1 * N;
   }
   const size_t o_a = ap.push(opa), o_b = ap.push(opb), o_k = ap.push(keys), o_ad = ap.push(add),
                o_po = ap.push(pout), o_pi = ap.push(pin), o_ro = ap.push(rout);
@@ -339,13 +365,14 @@ void enqueue_products(fhe_ctx* ctx, ArgPack& ap, Ops& ops, const Plan& plan, con
 // The tail of Algorithm 2 for up to BB items at level top - 1 (sorted by result chunk, then
 // rotation): (masked) rescale, target rotation, accumulation into the result chunks.
 void enqueue_tail(fhe_ctx* ctx, ArgPack& ap, Ops& ops, const std::vector<TailItem>& items, bool masked,
-                  const Workspace& ws, uint64_t* const* res, hipStream_t st) {
+                  const Workspace& ws, uint64_t* const* res, hipStream_t st, uint64_t* alt_base = nullptr) {
   const Params& p = ctx->p;
   const uint32_t N = p.N, nl1 = p.nq - 1, nl2 = p.nq - 2;
   const size_t nb = items.size();
   if (!nb) return;
   // Without a separate mask multiply the mask buffer is free: the target rotation steps alternate
-  // between it and cur, starting where an even number of steps ends in cur.
+  // between it (or alt_base, [nb][2][nl1][N], when the inputs live in the mask buffer) and cur,
+  // starting where an even number of steps ends in cur.
   const bool pingpong = !masked || rescale_fuses_mask(ctx);
   const uint32_t rbits = p.rot_bits, rmask = (1u << rbits) - 1;
   std::vector<const uint64_t*> min_(nb), rin(nb);
@@ -358,7 +385,7 @@ void enqueue_tail(fhe_ctx* ctx, ArgPack& ap, Ops& ops, const std::vector<TailIte
     mout[k] = ws.msk + k * 2 * nl1 * N;
     rin[k] = mout[k];
     cur[k] = ws.cur + k * 2 * nl2 * N;
-    alt[k] = ws.msk + k * 2 * nl1 * N;
+    alt[k] = (alt_base ? alt_base : ws.msk) + k * 2 * nl1 * N;
     int nz = 0;
     for (int t = 0; t < p.rot_digits; ++t) nz += ((it.rot >> (rbits * t)) & rmask) != 0;
     where[k] = (pingpong && (nz & 1)) ? alt[k] : cur[k];
@@ -416,12 +443,14 @@ size_t group_budget_bytes() {
 }
 
 // Grouped tail: the masked products of all pairs sharing (result chunk, target rotation) are summed
-// into one accumulator per group (exact, mod q), then each group is rescaled, rotated and
-// accumulated once. Accumulators for all groups are kept when they fit the group budget; otherwise
-// the groups are processed in passes and each pass recomputes the products its pairs use.
+// (exact, mod q) into one ciphertext per group, which is rescaled, rotated and accumulated once.
+// The products a pass of groups uses are computed first and kept resident (a product serves about
+// ten pairs in different groups); each batch of groups then builds its sums with one k_mask_sum
+// launch straight into the tail's input buffer. When all products do not fit the group budget, the
+// groups run in passes, each recomputing the products its pairs use.
 void execute_grouped(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job*>& job_of, const Workspace& ws,
-                     size_t PB, size_t BB, uint64_t* const* res, std::vector<std::unique_ptr<ArgPack>>& packs,
-                     DevBuf& gacc, hipStream_t st) {
+                     size_t PB, size_t BB, uint64_t* const* res, Runner& run, DevBuf& gbuf) {
+  const hipStream_t st = run.ls;
   const Params& p = ctx->p;
   const uint32_t N = p.N, nl1 = p.nq - 1;
   const size_t npairs = plan.pairs.size(), nprod = plan.prods.size();
@@ -443,81 +472,117 @@ void execute_grouped(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job
     std::vector<size_t> fill(gfirst.begin(), gfirst.end() - 1);
     for (size_t k = 0; k < npairs; ++k) gpair[fill[pg[k]]++] = (uint32_t)k;
   }
-  const size_t acc_elems = (size_t)2 * nl1 * N;
-  const size_t GA = std::max<size_t>(1, std::min<size_t>(ng, group_budget_bytes() / (acc_elems * 8)));
-  if (gacc.bytes() < GA * acc_elems * 8) {
-    gacc.reset();
-    gacc = DevBuf(GA * acc_elems * 8, st);
-  }
-  uint64_t* acc = gacc.u64();
-  std::vector<int32_t> slot(nprod, -1);
-  std::vector<char> used(nprod, 0);
-  for (size_t g0 = 0; g0 < ng; g0 += GA) {
-    const size_t g1 = std::min(ng, g0 + GA);
-    std::vector<int32_t> need;
-    for (size_t k = gfirst[g0]; k < gfirst[g1]; ++k) {
-      const int32_t pid = plan.pairs[gpair[k]].prod;
-      if (!used[pid]) {
-        used[pid] = 1;
-        need.push_back(pid);
+  // resident products (at most PS) plus the tail's second ping-pong buffers
+  const size_t pe = (size_t)2 * nl1 * N;
+  const size_t budget = group_budget_bytes() / 8;
+  const size_t alt_elems = BB * pe;
+  // store size: the budget, but never less than the largest group's distinct products
+  size_t gmax = 1;
+  {
+    std::vector<char> seen(nprod, 0);
+    for (size_t g = 0; g < ng; ++g) {
+      size_t c = 0;
+      for (size_t k = gfirst[g]; k < gfirst[g + 1]; ++k) {
+        const int32_t pid = plan.pairs[gpair[k]].prod;
+        if (!seen[pid]) {
+          seen[pid] = 1;
+          ++c;
+        }
       }
+      for (size_t k = gfirst[g]; k < gfirst[g + 1]; ++k) seen[plan.pairs[gpair[k]].prod] = 0;
+      gmax = std::max(gmax, c);
     }
-    std::sort(need.begin(), need.end());
-    for (int32_t pid : need) used[pid] = 0;
-    std::vector<char> touched(g1 - g0, 0);
-    for (size_t b0 = 0; b0 < need.size(); b0 += PB) {
-      const size_t b1 = std::min(need.size(), b0 + PB), npb = b1 - b0;
-      packs.emplace_back(new ArgPack());
-      ArgPack& ap = *packs.back();
+  }
+  const size_t PS = std::min<size_t>(nprod, std::max<size_t>(gmax, budget / pe));
+  if (gbuf.bytes() < (PS * pe + alt_elems) * 8) {
+    gbuf.reset();
+    gbuf = DevBuf((PS * pe + alt_elems) * 8, st);
+  }
+  uint64_t* store = gbuf.u64();
+  uint64_t* alt = store + PS * pe;
+  std::vector<int32_t> slot(nprod, -1);
+  size_t g0 = 0;
+  while (g0 < ng) {
+    // the pass: groups [g0, g1) whose products fit in the store (at least one group)
+    std::vector<int32_t> need;
+    size_t g1 = g0;
+    while (g1 < ng) {
+      size_t add = 0;
+      for (size_t k = gfirst[g1]; k < gfirst[g1 + 1]; ++k) {
+        const int32_t pid = plan.pairs[gpair[k]].prod;
+        if (slot[pid] == -1) {
+          slot[pid] = -2;  // counted for this group
+          ++add;
+        }
+      }
+      for (size_t k = gfirst[g1]; k < gfirst[g1 + 1]; ++k) {
+        const int32_t pid = plan.pairs[gpair[k]].prod;
+        if (slot[pid] == -2) slot[pid] = -1;
+      }
+      if (g1 > g0 && need.size() + add > PS) break;
+      for (size_t k = gfirst[g1]; k < gfirst[g1 + 1]; ++k) {
+        const int32_t pid = plan.pairs[gpair[k]].prod;
+        if (slot[pid] == -1) {
+          slot[pid] = (int32_t)need.size();
+          need.push_back(pid);
+        }
+      }
+      ++g1;
+    }
+    // products of the pass, in product order (shared alignment prefixes sit together)
+    std::vector<int32_t> order(need);
+    std::sort(order.begin(), order.end());
+    for (size_t b0 = 0; b0 < order.size(); b0 += PB) {
+      const size_t npb = std::min(order.size(), b0 + PB) - b0;
+      std::vector<uint64_t*> dest(npb);
+      for (size_t k = 0; k < npb; ++k) dest[k] = store + (size_t)slot[order[b0 + k]] * pe;
+      ArgPack& ap = run.pack();
       Ops ops;
-      enqueue_products(ctx, ap, ops, plan, job_of, need.data() + b0, npb, ws, st);
-      for (size_t k = 0; k < npb; ++k) slot[need[b0 + k]] = (int32_t)k;
-      // masked products of this batch into their groups' accumulators
+      enqueue_products(ctx, ap, ops, plan, job_of, order.data() + b0, npb, ws, st, dest.data());
+      run.submit(ap, ops);
+    }
+    // groups of the pass in tail batches: masked sums into the mask buffer, then the tail
+    for (size_t t0 = g0; t0 < g1; t0 += BB) {
+      const size_t t1 = std::min(g1, t0 + BB);
       std::vector<uint32_t> seg, gal;
       std::vector<const uint64_t*> in;
-      for (size_t g = g0; g < g1; ++g) {
+      std::vector<TailItem> items;
+      for (size_t g = t0; g < t1; ++g) {
         const size_t e0 = in.size();
         for (size_t k = gfirst[g]; k < gfirst[g + 1]; ++k) {
           const PlanPair& pa = plan.pairs[gpair[k]];
-          if (slot[pa.prod] < 0) continue;
-          in.push_back(ws.prod + (size_t)slot[pa.prod] * acc_elems);
+          in.push_back(store + (size_t)slot[pa.prod] * pe);
           gal.push_back(mask_galois(p, pa.min_pos));
         }
-        if (in.size() == e0) continue;
-        seg.push_back((uint32_t)(g - g0));
+        seg.push_back((uint32_t)(g - t0));
         seg.push_back((uint32_t)e0);
         seg.push_back((uint32_t)in.size());
-        seg.push_back(touched[g - g0] ? 0u : 1u);
-        touched[g - g0] = 1;
+        seg.push_back(1u);
+        items.push_back(TailItem{ws.msk + (g - t0) * pe, 0u, (int32_t)(gkeys[g] >> 32), (uint32_t)gkeys[g]});
       }
-      for (size_t k = 0; k < npb; ++k) slot[need[b0 + k]] = -1;
+      ArgPack& ap = run.pack();
+      Ops ops;
       const size_t o_sg = ap.push(seg), o_in = ap.push(in), o_ga = ap.push(gal);
       const uint32_t nseg = (uint32_t)(seg.size() / 4), nent = (uint32_t)in.size();
+      uint64_t* msk = ws.msk;
       ops.push_back([=, &ap] {
-        mask_sum(ctx, nseg, nent, nl1, ap.at<uint32_t>(o_sg), ap.at<const uint64_t*>(o_in), ap.at<uint32_t>(o_ga), acc,
+        mask_sum(ctx, nseg, nent, nl1, ap.at<uint32_t>(o_sg), ap.at<const uint64_t*>(o_in), ap.at<uint32_t>(o_ga), msk,
                  st);
       });
-      ap.upload(st);
-      for (auto& op : ops) op();
+      enqueue_tail(ctx, ap, ops, items, false, ws, res, st, alt);
+      run.submit(ap, ops);
     }
-    for (size_t t0 = g0; t0 < g1; t0 += BB) {
-      const size_t t1 = std::min(g1, t0 + BB);
-      std::vector<TailItem> items;
-      for (size_t g = t0; g < t1; ++g)
-        items.push_back(TailItem{acc + (g - g0) * acc_elems, 0u, (int32_t)(gkeys[g] >> 32), (uint32_t)gkeys[g]});
-      packs.emplace_back(new ArgPack());
-      ArgPack& ap = *packs.back();
-      Ops ops;
-      enqueue_tail(ctx, ap, ops, items, false, ws, res, st);
-      ap.upload(st);
-      for (auto& op : ops) op();
-    }
+    for (int32_t pid : need) slot[pid] = -1;
+    g0 = g1;
   }
 }
 
+void run_per_pair(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job*>& job_of, const Workspace& ws,
+                  size_t PB, size_t BB, uint64_t* const* res, Runner& run);
+
 }  // namespace
 
-void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bool grouped) {
+void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bool grouped, bool graph) {
   const Params& p = ctx->p;
   const uint32_t N = p.N, nq = p.nq, nl1 = nq - 1, nl2 = nq - 2;
   std::lock_guard<std::recursive_mutex> exec_lock(ctx->exec_mu);
@@ -547,11 +612,34 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bo
     HIPCHECK(hipStreamSynchronize(st));
     return;
   }
-  DevBuf result_dev = upload(result_ptr, st);
+  // A captured launch stream for these operands, ranges, plan mode and NTT split, on this scratch.
+  std::vector<uint64_t> key{grouped ? 1u : 0u, p.k1, slices.size()};
+  for (auto& sl : slices)
+    for (uint64_t v : {sl.job->A->id, sl.job->B->id, (uint64_t)sl.job->pair_lo, (uint64_t)sl.job->pair_hi,
+                       (uint64_t)sl.lo, (uint64_t)sl.hi})
+      key.push_back(v);
+  if (graph) {
+    for (auto& g : ctx->graphs) {
+      if (g->key != key || g->ws_base != ctx->ws_cache.get() || g->ws_bytes != ctx->ws_cache.bytes() ||
+          g->nres != result_ptr.size())
+        continue;
+      HIPCHECK(hipMemcpyAsync(g->result_dev.get(), result_ptr.data(), result_ptr.size() * 8, hipMemcpyHostToDevice,
+                              st));
+      const int tok = prof_begin("graph_replay", st);
+      HIPCHECK(hipGraphLaunch(g->exec, st));
+      prof_end(tok, st, 0.0);
+      prof_count("keyswitch", g->n_ks);
+      prof_count("rescale", g->n_rescale);
+      HIPCHECK(hipStreamSynchronize(st));
+      return;
+    }
+  }
+  // Launch stream: the caller's, or the context's capture stream when recording a graph.
+  const hipStream_t ls = graph ? ctx->capture_stream.get() : st;
+  std::shared_ptr<GraphEntry> entry = graph ? std::make_shared<GraphEntry>() : nullptr;
+  DevBuf result_local = upload(result_ptr, ls);
   index_plan(plan);
   const size_t nprod = plan.prods.size();
-  const std::vector<size_t>& first = plan.first;
-  const std::vector<uint32_t>& by_prod = plan.by_prod;
 
   // Batch sizes from the workspace budget.
   const size_t e = 8ull * N;
@@ -574,6 +662,8 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bo
       std::max(rescale_ws_elems(ctx, (uint32_t)PB, 2, nq), rescale_ws_elems(ctx, (uint32_t)BB, 2, nl1));
   const size_t total = sz_align + rt + sz_tens + sz_pfull + sz_prod + sz_msk + sz_cur + sz_ks + sz_rs;
   if (ctx->ws_cache.bytes() < total * 8) {  // grow-only scratch kept by the context between calls
+    HIPCHECK(hipStreamSynchronize(st));      // earlier work on the old scratch has finished
+    ctx->graphs.clear();                      // graphs captured on the old scratch are stale
     ctx->ws_cache.reset();
     ctx->ws_cache = DevBuf(total * 8, st);
   }
@@ -588,20 +678,76 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bo
   ws.ksws = w; w += sz_ks;
   ws.rsws = w;
 
-  uint64_t* const* res = (uint64_t* const*)result_dev.get();
-  std::vector<std::unique_ptr<ArgPack>> packs;
-  DevBuf gacc;  // group accumulators (grouped form), released after the final synchronisation
+  uint64_t* const* res = (uint64_t* const*)result_local.get();
+  std::vector<std::unique_ptr<ArgPack>> local_packs;
+  DevBuf local_gbuf;  // grouped form: resident products, released after the final synchronisation
+  Runner run{ls, graph, graph ? entry->packs : local_packs, {}};
+  DevBuf& gbuf = graph ? entry->gbuf : local_gbuf;
   if (grouped) {
-    execute_grouped(ctx, plan, job_of, ws, PB, BB, res, packs, gacc, st);
+    execute_grouped(ctx, plan, job_of, ws, PB, BB, res, run, gbuf);
+  } else {
+    run_per_pair(ctx, plan, job_of, ws, PB, BB, res, run);
+  }
+  if (!graph) {
     HIPCHECK(hipStreamSynchronize(st));
     return;
   }
+  // Record the deferred launches as one graph, keep it on the context, launch it on the caller's
+  // stream. The pointer tables were uploaded on the capture stream before recording.
+  HIPCHECK(hipStreamSynchronize(ls));
+  hipGraph_t g = nullptr;
+  int64_t n_ks = 0, n_rs = 0;
+  HIPCHECK(hipStreamBeginCapture(ls, hipStreamCaptureModeRelaxed));
+  try {
+    CaptureScope cs;
+    for (auto& ops : run.pending)
+      for (auto& op : ops) op();
+    n_ks = cs.count("keyswitch");
+    n_rs = cs.count("rescale");
+  } catch (...) {
+    hipGraph_t junk = nullptr;
+    (void)hipStreamEndCapture(ls, &junk);
+    if (junk) (void)hipGraphDestroy(junk);
+    throw;
+  }
+  HIPCHECK(hipStreamEndCapture(ls, &g));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHECK(ie);
+  entry->exec = ex;
+  entry->key = key;
+  entry->result_dev = std::move(result_local);
+  entry->nres = result_ptr.size();
+  entry->ws_base = ctx->ws_cache.get();
+  entry->ws_bytes = ctx->ws_cache.bytes();
+  entry->n_ks = n_ks;
+  entry->n_rescale = n_rs;
+  if (ctx->graphs.size() >= 2) ctx->graphs.erase(ctx->graphs.begin());
+  ctx->graphs.push_back(entry);
+  const int tok = prof_begin("graph_replay", st);
+  HIPCHECK(hipGraphLaunch(ex, st));
+  prof_end(tok, st, 0.0);
+  prof_count("keyswitch", n_ks);
+  prof_count("rescale", n_rs);
+  HIPCHECK(hipStreamSynchronize(st));
+}
+
+namespace {
+
+void run_per_pair(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job*>& job_of, const Workspace& ws,
+                  size_t PB, size_t BB, uint64_t* const* res, Runner& run) {
+  const Params& p = ctx->p;
+  const uint32_t N = p.N, nl1 = p.nq - 1;
+  const hipStream_t st = run.ls;
+  const size_t nprod = plan.prods.size();
+  const std::vector<size_t>& first = plan.first;
+  const std::vector<uint32_t>& by_prod = plan.by_prod;
   std::vector<int32_t> ids(nprod);
   for (size_t i = 0; i < nprod; ++i) ids[i] = (int32_t)i;
   for (size_t p0 = 0; p0 < nprod; p0 += PB) {
     const size_t p1 = std::min(nprod, p0 + PB), npb = p1 - p0;
-    packs.emplace_back(new ArgPack());
-    ArgPack& ap = *packs.back();
+    ArgPack& ap = run.pack();
     Ops ops;
     enqueue_products(ctx, ap, ops, plan, job_of, ids.data() + p0, npb, ws, st);
     // (3) Pairs of these products: mask, rescale, target rotation, accumulate.
@@ -621,10 +767,10 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bo
       }
       enqueue_tail(ctx, ap, ops, items, true, ws, res, st);
     }
-    ap.upload(st);
-    for (auto& op : ops) op();
+    run.submit(ap, ops);
   }
-  HIPCHECK(hipStreamSynchronize(st));
 }
+
+}  // namespace
 
 }  // namespace fhe

@@ -45,6 +45,7 @@ struct Job {
   const fhe_mat* B;
   Plan plan;
   fhe_mat* C;
+  int64_t pair_lo = 0, pair_hi = INT64_MAX;  // the traversal range the plan was built for
 };
 
 // Executes one or many matmuls as a single stream of batched launches: the products and pairs of all
@@ -53,7 +54,25 @@ struct Job {
 // grouped: the pairs of a job sharing (result chunk, target rotation) are summed after their masks
 // and go through one second rescale and one target rotation (different ciphertext bits from the
 // per-pair form, same decryption up to noise).
-void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool grouped = false);
+// graph: capture the launch stream in a HIP graph kept on the context (at most two, most recent
+// kept) and replay it when the same operand handles, ranges, plan mode and NTT split come again;
+// results are bit-identical to the eager launches. Only the result-chunk pointer table changes
+// between replays (rewritten before each launch, outside the graph).
+void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool grouped = false, bool graph = false);
+
+// A captured matmul launch stream and everything its kernels read that is not an operand or key.
+struct GraphEntry {
+  std::vector<uint64_t> key;
+  hipGraphExec_t exec = nullptr;
+  std::vector<std::unique_ptr<ArgPack>> packs;  // device pointer tables the kernels read
+  DevBuf result_dev;                            // result-chunk pointers, rewritten per replay
+  size_t nres = 0;
+  DevBuf gbuf;                                  // grouped form: resident products
+  const void* ws_base = nullptr;                // executor scratch the graph was captured on
+  size_t ws_bytes = 0;
+  int64_t n_ks = 0, n_rescale = 0;              // work per replay (profiler counters)
+  ~GraphEntry();
+};
 
 // Resumable execution: prepare_result validates keys/operands and zeroes C; execute_slices runs the
 // products [lo, hi) of several prepared jobs (and all their pairs) as one merged launch stream,
@@ -63,7 +82,8 @@ struct Slice {
   int32_t lo, hi;
 };
 void prepare_result(fhe_ctx* ctx, Job& J, hipStream_t st);
-void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bool grouped = false);
+void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bool grouped = false,
+                    bool graph = false);
 
 // Counts of key-switch work in the plan: [F, products, align KS, relin KS, target KS, result chunks].
 void plan_counts(const Params& p, const Plan& plan, int64_t out[6]);

@@ -289,20 +289,22 @@ class Context(_Handle):
     def encrypt_csc(self, sk, rows, cols, indptr, indices, values, seed, stream=None) -> Matrix:
         return self._encrypt(_lib.fhe_encrypt_csc, sk, rows, cols, indptr, indices, values, seed, stream)
 
-    def spmspm(self, A: Matrix, B: Matrix, stream=None, grouped: bool = False) -> Matrix:
+    def spmspm(self, A: Matrix, B: Matrix, stream=None, grouped: bool = False, graph: bool = False) -> Matrix:
         """C = A B. grouped: pairs sharing (result chunk, target rotation) share one second rescale
-        and one target rotation (FHE_PLAN_GROUPED)."""
-        if grouped:
-            return self.spmspm_batch([A], [B], stream, grouped=True)[0]
+        and one target rotation (FHE_PLAN_GROUPED). graph: record / replay the call as a HIP graph."""
+        if grouped or graph:
+            return self.spmspm_batch([A], [B], stream, grouped=grouped, graph=graph)[0]
         out = c_vp()
         _check(_lib.fhe_spmspm(self._ptr, A._ptr, B._ptr, _stream(stream), ctypes.byref(out)))
         return Matrix(out.value, self)
 
-    def spmspm_batch(self, As, Bs, stream=None, pair_ranges=None, grouped: bool = False) -> list:
+    def spmspm_batch(self, As, Bs, stream=None, pair_ranges=None, grouped: bool = False,
+                     graph: bool = False) -> list:
         """[A_i B_i] in one merged launch stream (bit-identical to one-at-a-time spmspm).
 
         pair_ranges: optional [(begin, end)] per matmul, restricting each to those matched pairs.
-        grouped: the grouped plan mode (FHE_PLAN_GROUPED)."""
+        grouped: the grouped plan mode (FHE_PLAN_GROUPED). graph: FHE_PLAN_GRAPH (record the launch
+        stream as a HIP graph on first use, replay it on later calls with the same operands)."""
         n = len(As)
         assert len(Bs) == n
         pa = (c_vp * max(1, n))(*[a._ptr for a in As])
@@ -316,7 +318,8 @@ class Context(_Handle):
             hi = np.asarray([r[1] for r in pair_ranges] or [0], np.int64)
         _check(_lib.fhe_spmspm_plan(self._ptr, n, ctypes.cast(pa, PP), ctypes.cast(pb, PP),
                                     None if lo is None else _ptr(lo, c_i64), None if hi is None else _ptr(hi, c_i64),
-                                    1 if grouped else 0, _stream(stream), ctypes.cast(out, PP)))
+                                    (1 if grouped else 0) | (256 if graph else 0), _stream(stream),
+                                    ctypes.cast(out, PP)))
         return [Matrix(out[i], self) for i in range(n)]
 
     def spmspm_pairs(self, A: Matrix, B: Matrix, begin: int, end: int, stream=None, grouped: bool = False) -> Matrix:

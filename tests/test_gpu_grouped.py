@@ -78,7 +78,8 @@ def test_grouped_parity_small(fhe, prm):
 
 def test_grouped_two_result_chunks_and_passes(fhe, monkeypatch):
     """64 x 40 result over two S-slot chunks; then the same with a group budget of 1 MiB (four
-    accumulators per pass, every pass recomputing its products): identical limbs."""
+    resident products per pass, so the groups run in many passes, each recomputing the products it
+    uses): identical limbs."""
     prm = PRM[0]
     a = synth.sparse_dense(64, 2, 0.85, "uniform", 10, 12)
     b = synth.sparse_dense(2, 40, 0.5, "uniform", 11, 13)
