@@ -281,7 +281,7 @@ def run_grouped(ctx, sk, A, B, st, ref, steps: int) -> dict:
     plan (its own oracle mode), same decryption up to noise."""
     import torch
     groups, gks = ctx.plan_groups(A, B)
-    C = ctx.spmspm(A, B, grouped=True)  # warm-up (allocates the group accumulators)
+    C = ctx.spmspm(A, B, grouped=True)  # warm-up (allocates the resident products)
     C.close()
     torch.cuda.synchronize()
     log(f"grouped warm-up done: {groups} groups, {gks} target key switches")
@@ -329,6 +329,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=int, default=16)
     ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle pairs to time (0 = skip, -1 = one per core)")
     ap.add_argument("--kernels-out", default=None, help="write per-kernel timings (JSON) here")
+    ap.add_argument("--plan", default="per_pair", choices=["per_pair", "grouped"],
+                    help="plan of the timed steps: Algorithm 2 per matched pair, or grouped target rotations "
+                         "(then the grouped and graph legs are skipped)")
     ap.add_argument("--graph-steps", type=int, default=2,
                     help="also time this many replays of the per-pair plan recorded as one HIP graph (0 = skip)")
     ap.add_argument("--grouped-steps", type=int, default=2,
@@ -384,9 +387,12 @@ def main():
     st = ctx.plan_stats(A, B)
     log(f"setup {setup_s:.1f} s; plan {st}")
 
+    grouped = args.plan == "grouped"
+    if grouped:
+        args.graph_steps = args.grouped_steps = 0
     C = None
     for _ in range(args.warmup):
-        C = ctx.spmspm(A, B)
+        C = ctx.spmspm(A, B, grouped=grouped)
         C.close()
         log("warmup step done")
     torch.cuda.synchronize()
@@ -395,7 +401,7 @@ def main():
     for _ in range(args.steps):
         if C is not None:
             C.close()
-        C = ctx.spmspm(A, B)
+        C = ctx.spmspm(A, B, grouped=grouped)
         log(f"timed step done at {time.perf_counter() - t0:.2f} s")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -416,7 +422,8 @@ def main():
         "metric": METRIC, "value": round(value, 6), "unit": "SpMSpM/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1000 * dt / args.steps, 2), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": describe(w), "matched_pairs": st.matched_pairs, "products": st.products,
+        "config": {"workload": describe(w), "plan": "grouped target rotations" if grouped else "per matched pair",
+                   "matched_pairs": st.matched_pairs, "products": st.products,
                    "keyswitches": st.keyswitches, "parallelism": "single GPU, batched launches",
                    "ntt_split_autotuned": tuned},
         "matched_pairs_per_s": round(st.matched_pairs * value, 1),
