@@ -166,6 +166,48 @@ def result_chunks(params: Params, m: int, n: int) -> int:
     return max(1, -(-(m * n) // params.S))
 
 
+def digit_tree_level0(params: Params, keys: Keys, A: EncSparse, B: EncSparse, groups: list) -> dict:
+    """First level of the digit tree: each group's masked sum is rescaled once and rotated by the
+    lowest rotation digit of its target rotation only; the results are added per (result chunk,
+    remaining digits). {(chunk, rot >> b): ciphertext data}."""
+    b = params.rot_step_bits()
+    low = (1 << b) - 1
+    out = {}
+    for ((cr, rot), members) in groups:
+        acc = None
+        for (_, _, a_pos, b_pos) in members:
+            d = masked_product(params, keys, A, B, a_pos, b_pos)
+            acc = d if acc is None else ckks.add(params, acc, d)
+        acc = ckks.rescale(params, acc)
+        if rot & low:
+            acc = ckks.rotate_single(params, keys, acc, rot & low)
+        key = (cr, rot >> b)
+        out[key] = acc if key not in out else ckks.add(params, out[key], acc)
+    return {k: v.data for k, v in out.items()}
+
+
+def digit_tree_finish(params: Params, keys: Keys, level: dict, nres: int) -> list:
+    """Remaining levels of the digit tree: at level t every partial sum is rotated by its digit t
+    (r_t 2^(b t), one key switch unless the digit is 0) and added into the partial sum of (chunk,
+    digits above t); after the last digit one sum per result chunk is left."""
+    b = params.rot_step_bits()
+    low = (1 << b) - 1
+    level = {k: Ct(v, params.delta_out) for k, v in level.items()}
+    for t in range(1, params.rot_digits):
+        nxt = {}
+        for (cr, rest), ct in sorted(level.items()):
+            if rest & low:
+                ct = ckks.rotate_single(params, keys, ct, (rest & low) << (b * t))
+            key = (cr, rest >> b)
+            nxt[key] = ct if key not in nxt else ckks.add(params, nxt[key], ct)
+        level = nxt
+    res = [None] * nres
+    for (cr, rest), ct in level.items():
+        assert rest == 0
+        res[cr] = ct.data
+    return res
+
+
 def _accumulate(params: Params, keys: Keys, A: EncSparse, B: EncSparse, pairs: list) -> list:
     res = [None] * result_chunks(params, A.rows, B.cols)
     for (i, j, a_pos, b_pos) in pairs:
@@ -187,6 +229,8 @@ _G = {}
 
 def _worker(idx):
     g = _G
+    if g["tree"]:
+        return digit_tree_level0(g["params"], g["keys"], g["A"], g["B"], g["parts"][idx])
     if g["grouped"]:
         return _accumulate_groups(g["params"], g["keys"], g["A"], g["B"], g["parts"][idx])
     return _accumulate(g["params"], g["keys"], g["A"], g["B"], g["parts"][idx])
@@ -209,26 +253,52 @@ def rotation_elements(params: Params, A: EncSparse, B: EncSparse, pairs: list) -
 
 
 def spmspm(params: Params, keys: Keys, A: EncSparse, B: EncSparse, workers: int = 1, pairs: list | None = None,
-           grouped: bool = False) -> list:
+           grouped: bool = False, tree: bool = False) -> list:
     """Encrypted C = A B as a list of result-chunk ciphertexts (row-major slots).
 
     ``pairs`` restricts the sum to a subset of matched pairs (default: all).
     ``grouped``: pairs sharing (result chunk, target rotation) go through one second rescale and one
     target rotation together (``group_contribution``); groups are formed over ``pairs``.
+    ``tree`` (implies grouped): the groups' target rotations are further shared digit by digit
+    (``digit_tree_level0``, ``digit_tree_finish``): a rotation by r = sum_t r_t 2^(b t) is the
+    product of its digit steps, and rotation is linear, so the groups whose rotations agree above
+    digit t are added before their common digit-t step.
     With workers > 1 the pairs (or groups) are split across processes and the partial results are
     added; addition mod q is exact, so the result does not depend on the split."""
     assert A.cols == B.rows
+    grouped = grouped or tree
     if pairs is None:
         pairs = matched_pairs(A.rows, B.cols, A.indptr, A.indices, B.indptr, B.indices)
     units = target_groups(params, pairs, B.cols) if grouped else pairs
     out_nl = params.n_q - 2
     nres = result_chunks(params, A.rows, B.cols)
-    if workers <= 1 or len(units) < 2:
+    if tree:
+        if workers <= 1 or len(units) < 2:
+            levels = [digit_tree_level0(params, keys, A, B, units)]
+        else:
+            gs = sorted(rotation_elements(params, A, B, pairs) - set(keys._rot))
+            ctx = mp.get_context("fork")
+            _G.update(params=params, keys=keys, A=A, B=B, grouped=True, tree=True)
+            if gs:
+                with ctx.Pool(workers) as pool:
+                    for gval, key in pool.imap_unordered(_keygen_worker, gs):
+                        keys._rot[gval] = key
+            _G["parts"] = [units[w::workers] for w in range(workers)]
+            with ctx.Pool(workers) as pool:
+                levels = pool.map(_worker, range(workers))
+            _G.clear()
+        level = {}
+        for part in levels:
+            for k, v in part.items():
+                level[k] = v if k not in level else ckks.add(params, Ct(level[k], params.delta_out),
+                                                            Ct(v, params.delta_out)).data
+        parts = [digit_tree_finish(params, keys, level, nres)]
+    elif workers <= 1 or len(units) < 2:
         parts = [_accumulate_groups(params, keys, A, B, units) if grouped else _accumulate(params, keys, A, B, units)]
     else:
         gs = sorted(rotation_elements(params, A, B, pairs) - set(keys._rot))
         ctx = mp.get_context("fork")
-        _G.update(params=params, keys=keys, A=A, B=B, grouped=grouped)
+        _G.update(params=params, keys=keys, A=A, B=B, grouped=grouped, tree=False)
         if gs:
             with ctx.Pool(workers) as pool:
                 for gval, key in pool.imap_unordered(_keygen_worker, gs):
