@@ -166,9 +166,41 @@ def result_chunks(params: Params, m: int, n: int) -> int:
     return max(1, -(-(m * n) // params.S))
 
 
+def digit_tree_sum(params, items: list, nres: int, rotate, add) -> list:
+    """Sum of Rot_rot(x) over items (chunk, rot, x) per result chunk, sharing rotations digit by digit.
+
+    A rotation by r = sum_t r_t 2^(b t) is the composition of its digit steps (t ascending, zero
+    digits skipped, as for every rotation here). Level 0 rotates each x by its lowest digit and adds
+    the results of equal (chunk, r >> b); level t rotates each partial sum by its digit t and adds
+    those of equal (chunk, digits above t). After the last digit one sum per chunk is left.
+    ``rotate(x, step)`` and ``add(x, y)`` are the ring operations (ciphertexts here; plaintext slot
+    vectors in the tests). Returns [sum or None per chunk]."""
+    b = params.rot_step_bits()
+    low = (1 << b) - 1
+    level = {}
+    for (cr, rot, x) in items:
+        if rot & low:
+            x = rotate(x, rot & low)
+        key = (cr, rot >> b)
+        level[key] = x if key not in level else add(level[key], x)
+    for t in range(1, params.rot_digits):
+        nxt = {}
+        for (cr, rest), x in sorted(level.items(), key=lambda kv: kv[0]):
+            if rest & low:
+                x = rotate(x, (rest & low) << (b * t))
+            key = (cr, rest >> b)
+            nxt[key] = x if key not in nxt else add(nxt[key], x)
+        level = nxt
+    res = [None] * nres
+    for (cr, rest), x in level.items():
+        assert rest == 0
+        res[cr] = x
+    return res
+
+
 def digit_tree_level0(params: Params, keys: Keys, A: EncSparse, B: EncSparse, groups: list) -> dict:
-    """First level of the digit tree: each group's masked sum is rescaled once and rotated by the
-    lowest rotation digit of its target rotation only; the results are added per (result chunk,
+    """First level of the digit tree on ciphertexts: each group's masked sum is rescaled once and
+    rotated by the lowest digit of its target rotation; the results are added per (result chunk,
     remaining digits). {(chunk, rot >> b): ciphertext data}."""
     b = params.rot_step_bits()
     low = (1 << b) - 1
@@ -187,25 +219,12 @@ def digit_tree_level0(params: Params, keys: Keys, A: EncSparse, B: EncSparse, gr
 
 
 def digit_tree_finish(params: Params, keys: Keys, level: dict, nres: int) -> list:
-    """Remaining levels of the digit tree: at level t every partial sum is rotated by its digit t
-    (r_t 2^(b t), one key switch unless the digit is 0) and added into the partial sum of (chunk,
-    digits above t); after the last digit one sum per result chunk is left."""
+    """The remaining levels (digits 1 and up) of ``digit_tree_sum`` on the level-0 partial sums."""
     b = params.rot_step_bits()
-    low = (1 << b) - 1
-    level = {k: Ct(v, params.delta_out) for k, v in level.items()}
-    for t in range(1, params.rot_digits):
-        nxt = {}
-        for (cr, rest), ct in sorted(level.items()):
-            if rest & low:
-                ct = ckks.rotate_single(params, keys, ct, (rest & low) << (b * t))
-            key = (cr, rest >> b)
-            nxt[key] = ct if key not in nxt else ckks.add(params, nxt[key], ct)
-        level = nxt
-    res = [None] * nres
-    for (cr, rest), ct in level.items():
-        assert rest == 0
-        res[cr] = ct.data
-    return res
+    items = [(cr, rest << b, Ct(v, params.delta_out)) for (cr, rest), v in level.items()]
+    out = digit_tree_sum(params, items, nres, lambda x, r: ckks.rotate_single(params, keys, x, r),
+                         lambda x, y: ckks.add(params, x, y))
+    return [None if x is None else x.data for x in out]
 
 
 def _accumulate(params: Params, keys: Keys, A: EncSparse, B: EncSparse, pairs: list) -> list:
