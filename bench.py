@@ -275,13 +275,15 @@ def run_graph(ctx, A, B, steps: int) -> dict:
             "steps": steps, "ms_per_step": round(1000 * dt / steps, 3), "record_and_first_ms": round(1000 * rec, 1)}
 
 
-def run_grouped(ctx, sk, A, B, st, ref, steps: int) -> dict:
+def run_grouped(ctx, sk, A, B, st, ref, steps: int, tree: bool = False) -> dict:
     """The grouped plan on the same operands: masked products sharing (result chunk, target rotation)
     summed, then one rescale and one rotation per group. Different ciphertext bits from the per-pair
     plan (its own oracle mode), same decryption up to noise."""
     import torch
-    groups, gks = ctx.plan_groups(A, B)
-    C = ctx.spmspm(A, B, grouped=True)  # warm-up (allocates the resident products)
+    groups, gks, tks = ctx.plan_groups(A, B)
+    if tree:
+        gks = tks
+    C = ctx.spmspm(A, B, grouped=True, tree=tree)  # warm-up (allocates the resident products)
     C.close()
     torch.cuda.synchronize()
     log(f"grouped warm-up done: {groups} groups, {gks} target key switches")
@@ -292,7 +294,7 @@ def run_grouped(ctx, sk, A, B, st, ref, steps: int) -> dict:
     for _ in range(steps):
         if C is not None:
             C.close()
-        C = ctx.spmspm(A, B, grouped=True)
+        C = ctx.spmspm(A, B, grouped=True, tree=tree)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     fhe.profile_enable(False)
@@ -302,8 +304,8 @@ def run_grouped(ctx, sk, A, B, st, ref, steps: int) -> dict:
     dec = ctx.decrypt_decode(sk, C)
     C.close()
     v = steps / dt
-    log(f"grouped: {1000 * dt / steps:.1f} ms/step")
-    return {"plan": "grouped target rotations", "value": round(v, 6), "unit": "SpMSpM/s", "steps": steps,
+    log(f"{'tree' if tree else 'grouped'}: {1000 * dt / steps:.1f} ms/step")
+    return {"plan": "grouped target rotations" + (", shared digit by digit" if tree else ""), "value": round(v, 6), "unit": "SpMSpM/s", "steps": steps,
             "ms_per_step": round(1000 * dt / steps, 2), "groups": groups, "target_keyswitches": gks,
             "keyswitches_executed": ks, "matched_pairs_per_s": round(st.matched_pairs * v, 1),
             "keyswitch_per_s": round(ks * v, 1), "max_abs_err": float(np.abs(dec - ref).max()),
@@ -329,11 +331,14 @@ def main():
     ap.add_argument("--serve-budget-gb", type=int, default=16)
     ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle pairs to time (0 = skip, -1 = one per core)")
     ap.add_argument("--kernels-out", default=None, help="write per-kernel timings (JSON) here")
-    ap.add_argument("--plan", default="per_pair", choices=["per_pair", "grouped"],
-                    help="plan of the timed steps: Algorithm 2 per matched pair, or grouped target rotations "
-                         "(then the grouped and graph legs are skipped)")
+    ap.add_argument("--plan", default="per_pair", choices=["per_pair", "grouped", "tree"],
+                    help="plan of the timed steps: Algorithm 2 per matched pair, grouped target rotations, or "
+                         "grouped with digit-shared rotations (then the other legs are skipped)")
     ap.add_argument("--graph-steps", type=int, default=2,
                     help="also time this many replays of the per-pair plan recorded as one HIP graph (0 = skip)")
+    ap.add_argument("--tree-steps", type=int, default=2,
+                    help="also time this many steps of the grouped plan with its target rotations shared digit "
+                         "by digit (0 = skip)")
     ap.add_argument("--grouped-steps", type=int, default=2,
                     help="also time this many steps of the grouped plan (one rescale and rotation per result "
                          "chunk and target rotation; 0 = skip), after one warm-up step")
@@ -387,12 +392,12 @@ def main():
     st = ctx.plan_stats(A, B)
     log(f"setup {setup_s:.1f} s; plan {st}")
 
-    grouped = args.plan == "grouped"
+    grouped, tree = args.plan in ("grouped", "tree"), args.plan == "tree"
     if grouped:
-        args.graph_steps = args.grouped_steps = 0
+        args.graph_steps = args.grouped_steps = args.tree_steps = 0
     C = None
     for _ in range(args.warmup):
-        C = ctx.spmspm(A, B, grouped=grouped)
+        C = ctx.spmspm(A, B, grouped=grouped, tree=tree)
         C.close()
         log("warmup step done")
     torch.cuda.synchronize()
@@ -401,7 +406,7 @@ def main():
     for _ in range(args.steps):
         if C is not None:
             C.close()
-        C = ctx.spmspm(A, B, grouped=grouped)
+        C = ctx.spmspm(A, B, grouped=grouped, tree=tree)
         log(f"timed step done at {time.perf_counter() - t0:.2f} s")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -422,7 +427,9 @@ def main():
         "metric": METRIC, "value": round(value, 6), "unit": "SpMSpM/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1000 * dt / args.steps, 2), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": describe(w), "plan": "grouped target rotations" if grouped else "per matched pair",
+        "config": {"workload": describe(w),
+                   "plan": ("grouped target rotations, shared digit by digit" if tree else
+                            "grouped target rotations" if grouped else "per matched pair"),
                    "matched_pairs": st.matched_pairs, "products": st.products,
                    "keyswitches": st.keyswitches, "parallelism": "single GPU, batched launches",
                    "ntt_split_autotuned": tuned},
@@ -438,6 +445,8 @@ def main():
         line["graph"] = run_graph(ctx, A, B, args.graph_steps)
     if args.grouped_steps > 0:
         line["grouped"], gkernels = run_grouped(ctx, sk, A, B, st, ref, args.grouped_steps)
+    if args.tree_steps > 0:
+        line["tree"], _ = run_grouped(ctx, sk, A, B, st, ref, args.tree_steps, tree=True)
     if args.kernels_out:
         with open(args.kernels_out, "w") as f:
             json.dump({"kernels": kernels, "grouped_kernels": gkernels, "plan": st.__dict__}, f, indent=1)

@@ -146,6 +146,7 @@ int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, co
 /* Plan modes of fhe_spmspm_plan. */
 #define FHE_PLAN_PER_PAIR 0 /* Algorithm 2 per matched pair (the form of fhe_spmspm) */
 #define FHE_PLAN_GROUPED 1  /* grouped target rotations, see fhe_spmspm_plan */
+#define FHE_PLAN_TREE 2     /* grouped, with the target rotations shared digit by digit */
 #define FHE_PLAN_GRAPH 256  /* flag: record the launch stream as a HIP graph and replay it, see below */
 
 /* General form of the matmul calls: C_out[i] = A[i] B[i] for i < cnt as one merged launch stream,
@@ -162,6 +163,13 @@ int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, co
  * products if needed); beyond that it runs the groups in passes and each pass recomputes the
  * products its pairs use. Errors as fhe_spmspm_batch_pairs, FHE_EINVAL for
  * an unknown mode; on error all C_out[i] are NULL.
+ * FHE_PLAN_TREE is the grouped plan with its target rotations shared further: a rotation by
+ * r = sum_t r_t 2^(b t) is the composition of its digit steps, so each group is rotated by its low
+ * digit only and added to the partial sum of its (result chunk, higher digits); each partial sum is
+ * then rotated by its next digit and added into the next level's, and so on. One key switch per
+ * group with a nonzero low digit plus one per distinct nonzero higher-digit key. Same decryption up
+ * to noise; the limbs are those of that sequence. Its partial sums (one ciphertext per distinct key
+ * per level) are kept in device memory besides the resident products.
  * With FHE_PLAN_GRAPH or-ed into mode, the first call records the call's whole launch stream as one
  * HIP graph (on a stream of the context's own) and keeps it on the context, together with the pointer
  * tables and scratch its kernels read; later calls with the same operand handles, ranges, plan mode
@@ -191,9 +199,9 @@ int fhe_autotune(fhe_ctx* ctx, void* stream, const fhe_mat* A, const fhe_mat* B,
 int fhe_plan_stats(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t counts[6]);
 
 /* Grouped-plan statistics of A B: counts[0] = groups (distinct result chunk and target rotation),
- * counts[1] = their target-rotation key switches (the other counts are those of fhe_plan_stats).
- * Errors as fhe_spmspm. */
-int fhe_plan_groups(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t counts[2]);
+ * counts[1] = their target-rotation key switches, counts[2] = the target-rotation key switches of
+ * the digit tree (FHE_PLAN_TREE); the other counts are those of fhe_plan_stats. Errors as fhe_spmspm. */
+int fhe_plan_groups(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t counts[3]);
 
 /* Host-only planning from the public patterns (no context, no device): the same counts as
  * fhe_plan_stats for A (m x k, CSR pattern) times B (k x n, CSC pattern) at ring dimension 2^log_n

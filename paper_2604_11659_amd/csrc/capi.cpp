@@ -183,7 +183,8 @@ int fhe_spmspm_plan(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe
     }
     for (size_t i = 0; i < cnt; ++i) C_out[i] = nullptr;
     const int32_t plan_mode = mode & ~FHE_PLAN_GRAPH;
-    if (plan_mode != FHE_PLAN_PER_PAIR && plan_mode != FHE_PLAN_GROUPED) fail(FHE_EINVAL, "unknown plan mode");
+    if (plan_mode != FHE_PLAN_PER_PAIR && plan_mode != FHE_PLAN_GROUPED && plan_mode != FHE_PLAN_TREE)
+      fail(FHE_EINVAL, "unknown plan mode");
     if ((pair_begin == nullptr) != (pair_end == nullptr)) fail(FHE_EINVAL, "pair_begin and pair_end go together");
     for (size_t i = 0; i < cnt; ++i) {
       check_operands(A[i], B[i]);
@@ -197,7 +198,8 @@ int fhe_spmspm_plan(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe
       const int64_t lo = pair_begin ? pair_begin[i] : 0, hi = pair_end ? pair_end[i] : INT64_MAX;
       jobs[i] = Job{A[i], B[i], build_plan(ctx->p, A[i], B[i], lo, hi), Cs[i].get(), lo, hi};
     }
-    execute_jobs(ctx, jobs, as_stream(stream), plan_mode == FHE_PLAN_GROUPED, (mode & FHE_PLAN_GRAPH) != 0);
+    execute_jobs(ctx, jobs, as_stream(stream), plan_mode == FHE_PLAN_GROUPED, (mode & FHE_PLAN_GRAPH) != 0,
+                 plan_mode == FHE_PLAN_TREE);
     for (size_t i = 0; i < cnt; ++i) C_out[i] = Cs[i].release();
   });
 }
@@ -252,7 +254,7 @@ int fhe_plan_stats(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t cou
   });
 }
 
-int fhe_plan_groups(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t counts[2]) {
+int fhe_plan_groups(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t counts[3]) {
   return guarded([&] {
     need(ctx, "ctx");
     need(counts, "counts");

@@ -73,6 +73,13 @@ void mask_mul(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* const
 void mask_sum(const fhe_ctx* ctx, uint32_t nseg, uint32_t nentries, uint32_t nl, const uint32_t* seg,
               const uint64_t* const* in, const uint32_t* galois, uint64_t* acc, hipStream_t st);
 
+// As accumulate, with the contributions given by a device array of pointers.
+void accumulate_ptr(const fhe_ctx* ctx, uint32_t nseg, uint32_t ncontrib, uint32_t nl, const uint32_t* seg,
+                    const uint64_t* const* contrib, uint64_t* const* results, hipStream_t st);
+
+// x[i] = 0 for i < n (a kernel launch: usable inside a recorded graph).
+void fill_zero(const fhe_ctx* ctx, uint64_t n, uint64_t* x, hipStream_t st);
+
 // out[i] = the bits of in[i] as a double (values below 2^53), i < n.
 void to_f64_bits(const fhe_ctx* ctx, uint64_t n, const uint64_t* in, uint64_t* out, hipStream_t st);
 

@@ -1113,6 +1113,32 @@ __global__ __launch_bounds__(kThreads) void k_mask_sum(uint32_t nseg, uint32_t n
   }
 }
 
+// results[seg[3s]] += sum of contrib[b] for b in [seg[3s+1], seg[3s+2]), contributions given by
+// pointer ([2][nl][N] each).
+__global__ __launch_bounds__(kThreads) void k_accumulate_ptr(uint32_t nseg, uint32_t nl, uint32_t logN,
+                                                            const ModInfo* __restrict__ mods,
+                                                            const uint32_t* __restrict__ seg,
+                                                            const uint64_t* const* __restrict__ contrib,
+                                                            uint64_t* const* __restrict__ results) {
+  const uint64_t per = (uint64_t)2 * nl << logN;
+  const uint64_t total = (uint64_t)nseg * per;
+  for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < total; t += (uint64_t)gridDim.x * kThreads) {
+    const uint32_t s = (uint32_t)(t / per);
+    const uint64_t off = t - (uint64_t)s * per;
+    const uint64_t q = mods[(uint32_t)((off >> logN) % nl)].q;
+    const uint32_t b0 = seg[3 * s + 1], b1 = seg[3 * s + 2];
+    uint64_t* res = results[seg[3 * s]];
+    uint64_t acc = res[off];
+    for (uint32_t b = b0; b < b1; ++b) acc = add_mod(acc, contrib[b][off], q);
+    res[off] = acc;
+  }
+}
+
+// x[i] = 0 for i < n (a kernel, so that it can be recorded in a graph).
+__global__ __launch_bounds__(kThreads) void k_fill_zero(uint64_t n, uint64_t* __restrict__ x) {
+  for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kThreads) x[t] = 0;
+}
+
 // out[i] = the bits of (double)in[i] (residues below 2^53), i < n.
 __global__ __launch_bounds__(kThreads) void k_to_f64_bits(uint64_t n, const uint64_t* __restrict__ in,
                                                          uint64_t* __restrict__ out) {
@@ -1660,6 +1686,19 @@ void mask_sum(const fhe_ctx* ctx, uint32_t nseg, uint32_t nentries, uint32_t nl,
   const double bytes = 8.0 * nl * ctx->p.N * (3.0 * nentries + 2.0 * nseg);
   FHE_LAUNCH("mask_sum", bytes, k_mask_sum, grid_for((uint64_t)nseg * nl << ctx->p.logN), 0, st, nseg, nl,
              ctx->p.logN, mods_of(ctx), ctx->t.mask_f.u64(), seg, in, galois, acc);
+}
+
+void accumulate_ptr(const fhe_ctx* ctx, uint32_t nseg, uint32_t ncontrib, uint32_t nl, const uint32_t* seg,
+                    const uint64_t* const* contrib, uint64_t* const* results, hipStream_t st) {
+  if (!nseg) return;
+  const double bytes = 8.0 * 2 * nl * ctx->p.N * ((double)ncontrib + 2.0 * nseg);
+  FHE_LAUNCH("accumulate", bytes, k_accumulate_ptr, grid_for((uint64_t)nseg * 2 * nl << ctx->p.logN), 0, st, nseg,
+             nl, ctx->p.logN, mods_of(ctx), seg, contrib, results);
+}
+
+void fill_zero(const fhe_ctx* ctx, uint64_t n, uint64_t* x, hipStream_t st) {
+  if (!n) return;
+  FHE_LAUNCH("fill_zero", 8.0 * n, k_fill_zero, grid_for(n), 0, st, n, x);
 }
 
 void to_f64_bits(const fhe_ctx* ctx, uint64_t n, const uint64_t* in, uint64_t* out, hipStream_t st) {

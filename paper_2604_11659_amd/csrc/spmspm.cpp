@@ -126,7 +126,7 @@ void plan_counts(const Params& p, const Plan& plan, int64_t out[6]) {
   out[5] = plan.nres;
 }
 
-void plan_group_counts(const Params& p, const Plan& plan, int64_t out[2]) {
+void plan_group_counts(const Params& p, const Plan& plan, int64_t out[3]) {
   std::vector<uint64_t> keys;
   keys.reserve(plan.pairs.size());
   for (const auto& pa : plan.pairs) keys.push_back(((uint64_t)(uint32_t)pa.chunk << 32) | pa.rot);
@@ -136,6 +136,19 @@ void plan_group_counts(const Params& p, const Plan& plan, int64_t out[2]) {
   for (uint64_t k : keys) target += (int64_t)rotation_steps(p, (uint32_t)k).size();
   out[0] = (int64_t)keys.size();
   out[1] = target;
+  // digit tree: one key switch per distinct nonzero (chunk, digits from t up) with digit t nonzero
+  const uint32_t rb = (uint32_t)p.rot_bits, rlow = (1u << rb) - 1;
+  int64_t tree = 0;
+  for (int t = 0; t < p.rot_digits; ++t) {
+    std::vector<uint64_t> lk;
+    for (uint64_t k : keys) {
+      const uint32_t rest = (uint32_t)k >> (rb * t);
+      if (rest & rlow) lk.push_back((k & ~0xffffffffull) | rest);
+    }
+    std::sort(lk.begin(), lk.end());
+    tree += (int64_t)(std::unique(lk.begin(), lk.end()) - lk.begin());
+  }
+  out[2] = tree;
 }
 
 namespace {
@@ -224,13 +237,13 @@ void prepare_result(fhe_ctx* ctx, Job& J, hipStream_t st) {
   HIPCHECK(hipMemsetAsync(C->data.get(), 0, (size_t)J.plan.nres * chunk_elems * 8, st));
 }
 
-void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool grouped, bool graph) {
+void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool grouped, bool graph, bool tree) {
   std::vector<Slice> slices;
   for (auto& J : jobs) {
     prepare_result(ctx, J, st);
     slices.push_back(Slice{&J, 0, (int32_t)J.plan.prods.size()});
   }
-  execute_slices(ctx, slices, st, grouped, graph);
+  execute_slices(ctx, slices, st, grouped, graph, tree);
 }
 
 GraphEntry::~GraphEntry() {
@@ -449,7 +462,7 @@ size_t group_budget_bytes() {
 // launch straight into the tail's input buffer. When all products do not fit the group budget, the
 // groups run in passes, each recomputing the products its pairs use.
 void execute_grouped(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job*>& job_of, const Workspace& ws,
-                     size_t PB, size_t BB, uint64_t* const* res, Runner& run, DevBuf& gbuf) {
+                     size_t PB, size_t BB, uint64_t* const* res, Runner& run, DevBuf& gbuf, bool tree) {
   const hipStream_t st = run.ls;
   const Params& p = ctx->p;
   const uint32_t N = p.N, nl1 = p.nq - 1;
@@ -494,12 +507,44 @@ void execute_grouped(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job
     }
   }
   const size_t PS = std::min<size_t>(nprod, std::max<size_t>(gmax, budget / pe));
-  if (gbuf.bytes() < (PS * pe + alt_elems) * 8) {
+  // Digit tree: partial sums of level t = 1 .. D-1 keyed (chunk, rotation >> (b t)), sorted, so
+  // that the keys of one level that feed the same key of the next are contiguous.
+  const uint32_t rb = (uint32_t)p.rot_bits, rlow = (1u << rb) - 1;
+  const size_t ce = (size_t)2 * (p.nq - 2) * N;  // a ciphertext two levels below the top
+  std::vector<std::vector<uint64_t>> lkeys(tree ? (size_t)p.rot_digits : 0);
+  std::vector<size_t> lbase(lkeys.size(), 0);
+  size_t nlev = 0;
+  for (size_t t = 1; t < lkeys.size(); ++t) {
+    for (uint64_t gk : gkeys) lkeys[t].push_back((gk & ~0xffffffffull) | ((gk & 0xffffffffull) >> (rb * t)));
+    std::sort(lkeys[t].begin(), lkeys[t].end());
+    lkeys[t].erase(std::unique(lkeys[t].begin(), lkeys[t].end()), lkeys[t].end());
+    lbase[t] = nlev;
+    nlev += lkeys[t].size();
+  }
+  const size_t gwords = PS * pe + alt_elems + nlev * ce;
+  if (gbuf.bytes() < gwords * 8) {
     gbuf.reset();
-    gbuf = DevBuf((PS * pe + alt_elems) * 8, st);
+    gbuf = DevBuf(gwords * 8, st);
   }
   uint64_t* store = gbuf.u64();
   uint64_t* alt = store + PS * pe;
+  uint64_t* lev = alt + alt_elems;
+  auto lev_index = [&](size_t t, uint64_t key) -> size_t {
+    return lbase[t] + (size_t)(std::lower_bound(lkeys[t].begin(), lkeys[t].end(), key) - lkeys[t].begin());
+  };
+  uint64_t* const* lev1_ptrs = nullptr;  // device table of the level-1 partial sums
+  if (nlev) {
+    std::vector<uint64_t*> ptrs(nlev);
+    for (size_t i = 0; i < nlev; ++i) ptrs[i] = lev + i * ce;
+    ArgPack& ap = run.pack();
+    Ops ops;
+    const size_t o_p = ap.push(ptrs);
+    uint64_t* lz = lev;
+    const uint64_t nz = (uint64_t)nlev * ce;
+    ops.push_back([=] { fill_zero(ctx, nz, lz, st); });
+    run.submit(ap, ops);
+    lev1_ptrs = ap.at<uint64_t*>(o_p);
+  }
   std::vector<int32_t> slot(nprod, -1);
   size_t g0 = 0;
   while (g0 < ng) {
@@ -558,7 +603,12 @@ void execute_grouped(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job
         seg.push_back((uint32_t)e0);
         seg.push_back((uint32_t)in.size());
         seg.push_back(1u);
-        items.push_back(TailItem{ws.msk + (g - t0) * pe, 0u, (int32_t)(gkeys[g] >> 32), (uint32_t)gkeys[g]});
+        if (nlev) {  // level 0 of the tree: the low digit only, into the level-1 partial sum
+          const uint64_t k1 = (gkeys[g] & ~0xffffffffull) | ((gkeys[g] & 0xffffffffull) >> rb);
+          items.push_back(TailItem{ws.msk + (g - t0) * pe, 0u, (int32_t)lev_index(1, k1), (uint32_t)gkeys[g] & rlow});
+        } else {
+          items.push_back(TailItem{ws.msk + (g - t0) * pe, 0u, (int32_t)(gkeys[g] >> 32), (uint32_t)gkeys[g]});
+        }
       }
       ArgPack& ap = run.pack();
       Ops ops;
@@ -569,11 +619,62 @@ void execute_grouped(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job
         mask_sum(ctx, nseg, nent, nl1, ap.at<uint32_t>(o_sg), ap.at<const uint64_t*>(o_in), ap.at<uint32_t>(o_ga), msk,
                  st);
       });
-      enqueue_tail(ctx, ap, ops, items, false, ws, res, st, alt);
+      enqueue_tail(ctx, ap, ops, items, false, ws, nlev ? lev1_ptrs : res, st, alt);
       run.submit(ap, ops);
     }
     for (int32_t pid : need) slot[pid] = -1;
     g0 = g1;
+  }
+  // Levels 1 .. D-1 of the tree: rotate each partial sum by its digit t (one key switch, none for a
+  // zero digit) and add it into the partial sum of the next level (the result chunk after the last).
+  for (size_t t = 1; t < lkeys.size(); ++t) {
+    const bool last = t + 1 == lkeys.size();
+    std::vector<uint64_t*> next_ptrs;
+    if (!last) {
+      next_ptrs.resize(lkeys[t + 1].size());
+      for (size_t i = 0; i < next_ptrs.size(); ++i) next_ptrs[i] = lev + (lbase[t + 1] + i) * ce;
+    }
+    const std::vector<uint64_t>& K = lkeys[t];
+    for (size_t t0 = 0; t0 < K.size(); t0 += BB) {
+      const size_t t1 = std::min(K.size(), t0 + BB);
+      std::vector<const uint64_t*> src, contrib;
+      std::vector<uint32_t> steps, seg;
+      std::vector<uint64_t*> out;
+      int64_t cur_target = -1;
+      for (size_t i = t0; i < t1; ++i) {
+        const uint32_t rest = (uint32_t)(K[i] & 0xffffffffull), digit = rest & rlow;
+        const uint64_t* acc = lev + (lbase[t] + i) * ce;
+        if (digit) {
+          uint64_t* o = ws.cur + (i - t0) * ce;
+          src.push_back(acc);
+          steps.push_back(digit << (rb * t));
+          out.push_back(o);
+          contrib.push_back(o);
+        } else {
+          contrib.push_back(acc);
+        }
+        const uint64_t nk = (K[i] & ~0xffffffffull) | (rest >> rb);
+        const int64_t target = last ? (int64_t)(K[i] >> 32) : (int64_t)(lev_index(t + 1, nk) - lbase[t + 1]);
+        if (target != cur_target) {
+          if (cur_target >= 0) seg.push_back((uint32_t)contrib.size() - 1);
+          seg.push_back((uint32_t)target);
+          seg.push_back((uint32_t)contrib.size() - 1);
+          cur_target = target;
+        }
+      }
+      seg.push_back((uint32_t)contrib.size());
+      ArgPack& ap = run.pack();
+      Ops ops;
+      enqueue_rotation(ctx, ap, ops, p.nq - 2, src, steps, out, ws, st, true);
+      const size_t o_c = ap.push(contrib), o_s = ap.push(seg);
+      const size_t o_n = last ? 0 : ap.push(next_ptrs);
+      const uint32_t nseg = (uint32_t)(seg.size() / 3), ncon = (uint32_t)contrib.size();
+      ops.push_back([=, &ap] {
+        accumulate_ptr(ctx, nseg, ncon, p.nq - 2, ap.at<uint32_t>(o_s), ap.at<const uint64_t*>(o_c),
+                       last ? res : ap.at<uint64_t*>(o_n), st);
+      });
+      run.submit(ap, ops);
+    }
   }
 }
 
@@ -582,7 +683,8 @@ void run_per_pair(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job*>&
 
 }  // namespace
 
-void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bool grouped, bool graph) {
+void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bool grouped, bool graph, bool tree) {
+  grouped = grouped || tree;
   const Params& p = ctx->p;
   const uint32_t N = p.N, nq = p.nq, nl1 = nq - 1, nl2 = nq - 2;
   std::lock_guard<std::recursive_mutex> exec_lock(ctx->exec_mu);
@@ -613,7 +715,7 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bo
     return;
   }
   // A captured launch stream for these operands, ranges, plan mode and NTT split, on this scratch.
-  std::vector<uint64_t> key{grouped ? 1u : 0u, p.k1, slices.size()};
+  std::vector<uint64_t> key{tree ? 2u : grouped ? 1u : 0u, p.k1, slices.size()};
   for (auto& sl : slices)
     for (uint64_t v : {sl.job->A->id, sl.job->B->id, (uint64_t)sl.job->pair_lo, (uint64_t)sl.job->pair_hi,
                        (uint64_t)sl.lo, (uint64_t)sl.hi})
@@ -684,7 +786,7 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bo
   Runner run{ls, graph, graph ? entry->packs : local_packs, {}};
   DevBuf& gbuf = graph ? entry->gbuf : local_gbuf;
   if (grouped) {
-    execute_grouped(ctx, plan, job_of, ws, PB, BB, res, run, gbuf);
+    execute_grouped(ctx, plan, job_of, ws, PB, BB, res, run, gbuf, tree);
   } else {
     run_per_pair(ctx, plan, job_of, ws, PB, BB, res, run);
   }

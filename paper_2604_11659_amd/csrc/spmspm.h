@@ -58,7 +58,10 @@ struct Job {
 // kept) and replay it when the same operand handles, ranges, plan mode and NTT split come again;
 // results are bit-identical to the eager launches. Only the result-chunk pointer table changes
 // between replays (rewritten before each launch, outside the graph).
-void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool grouped = false, bool graph = false);
+// tree (implies grouped): the groups' target rotations are shared digit by digit (level t rotates
+// the partial sums of equal (chunk, digits above t) once by digit t).
+void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool grouped = false, bool graph = false,
+                  bool tree = false);
 
 // A captured matmul launch stream and everything its kernels read that is not an operand or key.
 struct GraphEntry {
@@ -83,12 +86,13 @@ struct Slice {
 };
 void prepare_result(fhe_ctx* ctx, Job& J, hipStream_t st);
 void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bool grouped = false,
-                    bool graph = false);
+                    bool graph = false, bool tree = false);
 
 // Counts of key-switch work in the plan: [F, products, align KS, relin KS, target KS, result chunks].
 void plan_counts(const Params& p, const Plan& plan, int64_t out[6]);
 
-// Grouped form: [groups (distinct result chunk, target rotation), target key switches].
-void plan_group_counts(const Params& p, const Plan& plan, int64_t out[2]);
+// Grouped form: [groups (distinct result chunk, target rotation), their target key switches, the
+// target key switches of the digit tree].
+void plan_group_counts(const Params& p, const Plan& plan, int64_t out[3]);
 
 }  // namespace fhe

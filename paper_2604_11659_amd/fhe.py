@@ -289,17 +289,19 @@ class Context(_Handle):
     def encrypt_csc(self, sk, rows, cols, indptr, indices, values, seed, stream=None) -> Matrix:
         return self._encrypt(_lib.fhe_encrypt_csc, sk, rows, cols, indptr, indices, values, seed, stream)
 
-    def spmspm(self, A: Matrix, B: Matrix, stream=None, grouped: bool = False, graph: bool = False) -> Matrix:
+    def spmspm(self, A: Matrix, B: Matrix, stream=None, grouped: bool = False, graph: bool = False,
+               tree: bool = False) -> Matrix:
         """C = A B. grouped: pairs sharing (result chunk, target rotation) share one second rescale
-        and one target rotation (FHE_PLAN_GROUPED). graph: record / replay the call as a HIP graph."""
-        if grouped or graph:
-            return self.spmspm_batch([A], [B], stream, grouped=grouped, graph=graph)[0]
+        and one target rotation (FHE_PLAN_GROUPED); tree: grouped, with the target rotations shared
+        digit by digit (FHE_PLAN_TREE). graph: record / replay the call as a HIP graph."""
+        if grouped or graph or tree:
+            return self.spmspm_batch([A], [B], stream, grouped=grouped, graph=graph, tree=tree)[0]
         out = c_vp()
         _check(_lib.fhe_spmspm(self._ptr, A._ptr, B._ptr, _stream(stream), ctypes.byref(out)))
         return Matrix(out.value, self)
 
     def spmspm_batch(self, As, Bs, stream=None, pair_ranges=None, grouped: bool = False,
-                     graph: bool = False) -> list:
+                     graph: bool = False, tree: bool = False) -> list:
         """[A_i B_i] in one merged launch stream (bit-identical to one-at-a-time spmspm).
 
         pair_ranges: optional [(begin, end)] per matmul, restricting each to those matched pairs.
@@ -318,13 +320,14 @@ class Context(_Handle):
             hi = np.asarray([r[1] for r in pair_ranges] or [0], np.int64)
         _check(_lib.fhe_spmspm_plan(self._ptr, n, ctypes.cast(pa, PP), ctypes.cast(pb, PP),
                                     None if lo is None else _ptr(lo, c_i64), None if hi is None else _ptr(hi, c_i64),
-                                    (1 if grouped else 0) | (256 if graph else 0), _stream(stream),
+                                    (2 if tree else 1 if grouped else 0) | (256 if graph else 0), _stream(stream),
                                     ctypes.cast(out, PP)))
         return [Matrix(out[i], self) for i in range(n)]
 
-    def spmspm_pairs(self, A: Matrix, B: Matrix, begin: int, end: int, stream=None, grouped: bool = False) -> Matrix:
-        if grouped:
-            return self.spmspm_batch([A], [B], stream, pair_ranges=[(begin, end)], grouped=True)[0]
+    def spmspm_pairs(self, A: Matrix, B: Matrix, begin: int, end: int, stream=None, grouped: bool = False,
+                     tree: bool = False) -> Matrix:
+        if grouped or tree:
+            return self.spmspm_batch([A], [B], stream, pair_ranges=[(begin, end)], grouped=grouped, tree=tree)[0]
         out = c_vp()
         _check(_lib.fhe_spmspm_pairs(self._ptr, A._ptr, B._ptr, begin, end, _stream(stream), ctypes.byref(out)))
         return Matrix(out.value, self)
@@ -353,10 +356,10 @@ class Context(_Handle):
         return PlanStats(*[int(x) for x in c])
 
     def plan_groups(self, A: Matrix, B: Matrix) -> tuple:
-        """(groups, target-rotation key switches) of the grouped plan of A B."""
-        c = np.zeros(2, np.int64)
+        """(groups, target-rotation key switches grouped, same with the digit tree) of A B."""
+        c = np.zeros(3, np.int64)
         _check(_lib.fhe_plan_groups(self._ptr, A._ptr, B._ptr, _ptr(c, c_i64)))
-        return int(c[0]), int(c[1])
+        return int(c[0]), int(c[1]), int(c[2])
 
     def plan_rotations(self, A: Matrix, B: Matrix):
         n = c_sz()

@@ -96,7 +96,7 @@ def test_dnn_layer_grouped_full_fp64_and_sampled_bit_exact():
     w = synth.WORKLOADS["dnn"]
     _say("[full] dnn grouped setup")
     a, b, ctx, sk, A, B, op, keys, OA, OB = _prepare(w)
-    groups, gks = ctx.plan_groups(A, B)
+    groups, gks, _ = ctx.plan_groups(A, B)
     _say(f"[full] dnn grouped gpu spmspm: {groups} groups, {gks} target key switches")
     C = ctx.spmspm(A, B, grouped=True)
     err = np.abs(ctx.decrypt_decode(sk, C) - a @ b).max()
@@ -112,4 +112,27 @@ def test_dnn_layer_grouped_full_fp64_and_sampled_bit_exact():
     Cs = ctx.spmspm_pairs(A, B, lo, hi, grouped=True)
     _say(f"[full] dnn grouped pairs [{lo}, {hi}) oracle")
     ref = spmspm.spmspm(op, keys, OA, OB, workers=WORKERS, pairs=pairs[lo:hi], grouped=True)
+    assert (ctx.export(Cs, 0) == ref[0].data).all(), (lo, hi)
+
+
+@pytest.mark.timeout(1200)
+def test_dnn_layer_tree_full_fp64_and_sampled_bit_exact():
+    """Digit-tree plan at the DNN layer's full size: decrypts within 1e-5 of FP64; a traversal window
+    whose groups merge is bit-exact against the oracle's tree mode."""
+    w = synth.WORKLOADS["dnn"]
+    _say("[full] dnn tree setup")
+    a, b, ctx, sk, A, B, op, keys, OA, OB = _prepare(w)
+    groups, gks, tks = ctx.plan_groups(A, B)
+    _say(f"[full] dnn tree gpu spmspm: {groups} groups, {gks} -> {tks} target key switches")
+    C = ctx.spmspm(A, B, tree=True)
+    err = np.abs(ctx.decrypt_decode(sk, C) - a @ b).max()
+    _say(f"[full] dnn tree max-abs error {err:.3e}")
+    assert err < 1e-5
+    C.close()
+    pairs = spmspm.matched_pairs(w.m, w.n, OA.indptr, OA.indices, OB.indptr, OB.indices)
+    lo, hi = _merged_window(op, pairs, w.n, 24)
+    _say(f"[full] dnn tree pairs [{lo}, {hi}) gpu")
+    Cs = ctx.spmspm_pairs(A, B, lo, hi, tree=True)
+    _say(f"[full] dnn tree pairs [{lo}, {hi}) oracle")
+    ref = spmspm.spmspm(op, keys, OA, OB, workers=WORKERS, pairs=pairs[lo:hi], tree=True)
     assert (ctx.export(Cs, 0) == ref[0].data).all(), (lo, hi)

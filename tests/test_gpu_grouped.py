@@ -60,7 +60,7 @@ def test_grouped_parity_small(fhe, prm):
     a = synth.sparse_dense(6, 7, 0.4, "uniform", 0, 2)
     b = synth.sparse_dense(7, 5, 0.4, "uniform", 1, 3)
     op, okeys, ctx, sk, A, B, OA, OB = _operands(fhe, prm, a, b)
-    groups, gks = ctx.plan_groups(A, B)
+    groups, gks, _ = ctx.plan_groups(A, B)
     st = ctx.plan_stats(A, B)
     _say(f"[grouped] {prm} 6x7x5: {st.matched_pairs} pairs, {groups} groups, gpu")
     C = ctx.spmspm(A, B, grouped=True)
@@ -136,3 +136,44 @@ def test_grouped_full_sparsity_is_zero(fhe):
     C = ctx.spmspm(ctx.encrypt_csr(sk, 4, 4, ip, ix, v, seed=43), ctx.encrypt_csc(sk, 4, 4, ip, ix, v, seed=44),
                    grouped=True)
     assert (ctx.export(C, 0) == 0).all()
+
+
+@pytest.mark.parametrize("prm", PRM)
+def test_tree_parity_small(fhe, prm):
+    """Grouped plan with its target rotations shared digit by digit (FHE_PLAN_TREE) against the
+    oracle's tree mode; with one rotation digit it equals the grouped plan."""
+    a = synth.sparse_dense(6, 7, 0.4, "uniform", 0, 2)
+    b = synth.sparse_dense(7, 5, 0.4, "uniform", 1, 3)
+    op, okeys, ctx, sk, A, B, OA, OB = _operands(fhe, prm, a, b)
+    groups, gks, tks = ctx.plan_groups(A, B)
+    _say(f"[tree] {prm}: {groups} groups, {gks} -> {tks} target key switches, gpu")
+    C = ctx.spmspm(A, B, tree=True)
+    _say(f"[tree] {prm} oracle")
+    ref = spmspm.spmspm(op, okeys, OA, OB, tree=True, workers=4)
+    assert _same(ctx, C, ref)
+    assert np.abs(ctx.decrypt_decode(sk, C) - a @ b).max() < 1e-5
+    if op.rot_digits == 1:
+        assert tks == gks
+        assert _same(ctx, C, spmspm.spmspm(op, okeys, OA, OB, grouped=True, workers=4))
+    else:
+        assert tks < gks
+
+
+def test_tree_two_result_chunks_passes_and_graph(fhe, monkeypatch):
+    prm = PRM[0]
+    a = synth.sparse_dense(64, 2, 0.85, "uniform", 10, 12)
+    b = synth.sparse_dense(2, 40, 0.5, "uniform", 11, 13)
+    op, okeys, ctx, sk, A, B, OA, OB = _operands(fhe, prm, a, b, seeds=(53, 54))
+    _say(f"[tree] two chunks: {ctx.plan_groups(A, B)}, gpu")
+    C = ctx.spmspm(A, B, tree=True)
+    _say("[tree] two chunks oracle")
+    ref = spmspm.spmspm(op, okeys, OA, OB, tree=True, workers=8)
+    assert _same(ctx, C, ref)
+    assert np.abs(ctx.decrypt_decode(sk, C) - a @ b).max() < 1e-5
+    monkeypatch.setenv("FHE_GROUP_MB", "1")
+    _say("[tree] two chunks, 1 MiB group budget")
+    assert _same(ctx, ctx.spmspm(A, B, tree=True), ref)
+    monkeypatch.delenv("FHE_GROUP_MB")
+    for rep in range(3):
+        _say(f"[tree] graph call {rep}")
+        assert _same(ctx, ctx.spmspm(A, B, tree=True, graph=True), ref)
