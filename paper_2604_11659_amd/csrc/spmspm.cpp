@@ -170,11 +170,25 @@ size_t workspace_budget_bytes() {
 // component 0 is read through it by the final combine, so out[b] must be disjoint from src[b].
 // Otherwise both components go to scratch first, and out[b] may equal src[b].
 void enqueue_rotation(fhe_ctx* ctx, ArgPack& ap, std::vector<std::function<void()>>& ops, uint32_t nl,
-                      const std::vector<const uint64_t*>& src, const std::vector<uint32_t>& steps,
-                      const std::vector<uint64_t*>& out, const Workspace& ws, hipStream_t st, bool gather) {
+                      const std::vector<const uint64_t*>& src_in, const std::vector<uint32_t>& steps_in,
+                      const std::vector<uint64_t*>& out_in, const Workspace& ws, hipStream_t st, bool gather) {
   const Params& p = ctx->p;
-  const uint32_t N = p.N, B = (uint32_t)src.size();
+  const uint32_t N = p.N, B = (uint32_t)src_in.size();
   if (!B) return;
+  // Items that use the same rotation key become neighbours in the launch (key-stationary): the
+  // inner-product kernel visits item after item for each (limb, tile), so their key tiles are
+  // fetched from HBM once and served from L2 / MALL for the neighbours. The items are independent.
+  std::vector<uint32_t> ord(B);
+  for (uint32_t b = 0; b < B; ++b) ord[b] = b;
+  std::stable_sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) { return steps_in[x] < steps_in[y]; });
+  std::vector<const uint64_t*> src(B);
+  std::vector<uint32_t> steps(B);
+  std::vector<uint64_t*> out(B);
+  for (uint32_t b = 0; b < B; ++b) {
+    src[b] = src_in[ord[b]];
+    steps[b] = steps_in[ord[b]];
+    out[b] = out_in[ord[b]];
+  }
   std::vector<uint32_t> gal(B);
   std::vector<const uint64_t*> keys(B), add(2 * B), src1(B);
   for (uint32_t b = 0; b < B; ++b) {
