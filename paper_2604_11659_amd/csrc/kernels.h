@@ -26,6 +26,11 @@ struct LimbBatch {
   // limbs are unaffected. Only for forward transforms and the row phase of inverse ones, whose
   // consumers are the fused key-switch / rescale kernels.
   uint32_t raw_out = 0;
+  // Optional, for the phase that reads `src` in a row-phase (phase 2) launch: poly p is read from
+  // src_ptr[p] ([limbs][N]) through the automorphism tau_(src_gal[p]) (device arrays).
+  const uint64_t* const* src_ptr = nullptr;
+  const uint32_t* src_gal = nullptr;
+  uint32_t src_ptr_limb0 = 0;  // limb of src_ptr[p] that this batch's limb 0 reads
 };
 
 // Negacyclic NTT, in place. Forward: coefficients -> evaluations at psi^(2 brv(i) + 1) (bit-reversed
@@ -47,11 +52,14 @@ void tensor(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* const* 
 // output component c. out[b]: [2][nl][N]. ws: keyswitch_ws_elems(ctx, B, nl) uint64 of workspace.
 // With galois (device array of B Galois elements), add[2b] (component 0) is read through the
 // automorphism tau_(galois[b]) (NTT domain): a rotation then needs tau of component 1 only; out[b]
-// must not overlap add[2b] in that case.
+// must not overlap add[2b] in that case. With galois and in_ptrs (device array of B pointers to
+// [nl][N]), input item b is tau_(galois[b])(in_ptrs[b]), read through the automorphism by the
+// kernels themselves (`in` and in_stride are unused): a rotation then runs no separate
+// automorphism launch at all.
 size_t keyswitch_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t nl);
 void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, uint64_t in_stride,
                const uint64_t* const* keys, const uint64_t* const* add, uint64_t* const* out, uint64_t* ws,
-               hipStream_t st, const uint32_t* galois = nullptr);
+               hipStream_t st, const uint32_t* galois = nullptr, const uint64_t* const* in_ptrs = nullptr);
 
 // Rescale of B ciphertexts [ncomp][nl][N] -> [ncomp][nl-1][N] (nearest rounding of the dropped limb).
 // With mask_galois (device array of B Galois elements, needs rescale_fuses_mask and nl <= nq - 1),

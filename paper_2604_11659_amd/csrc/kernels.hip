@@ -318,7 +318,8 @@ __device__ __forceinline__ void ntt_rounds(uint64_t* lds, const A& ar, const typ
   }
 }
 
-template <bool kInv, int kPhase, class A, int NT>
+// kSrcPtr: the first phase reads its input through lb.src_ptr / lb.src_gal (automorphism gather).
+template <bool kInv, int kPhase, class A, int NT, bool kSrcPtr = false>
 __global__ __launch_bounds__(NT) void k_ntt(LimbBatch lb, const ModInfo* __restrict__ mods,
                                                  const typename A::W* __restrict__ tw, uint32_t logN, uint32_t k1,
                                                  bool from_src) {
@@ -328,7 +329,7 @@ __global__ __launch_bounds__(NT) void k_ntt(LimbBatch lb, const ModInfo* __restr
   const uint32_t limb = blockIdx.x / tiles, tile = blockIdx.x - limb * tiles;
   const uint32_t poly = limb / lb.limbs, e = limb - poly * lb.limbs;
   uint64_t* a = lb.base + (uint64_t)poly * lb.poly_stride + (uint64_t)e * N;
-  const uint64_t* in = from_src ? lb.src + (uint64_t)poly * lb.src_stride + (uint64_t)e * N : a;
+  const uint64_t* in = from_src && lb.src ? lb.src + (uint64_t)poly * lb.src_stride + (uint64_t)e * N : a;
   const uint32_t mi = mod_index(lb, poly, e);
   const ModInfo m = mods[mi];
   A ar;
@@ -340,10 +341,21 @@ __global__ __launch_bounds__(NT) void k_ntt(LimbBatch lb, const ModInfo* __restr
   if (kPhase == 2) {
     // rows are contiguous: every wavefront loads, transforms and stores its own rows
     const uint32_t wb = (threadIdx.x >> 6) * (kNttE / (NT / 64)), lane = threadIdx.x & 63;
+    if (kSrcPtr) {
+      // read through the automorphism: a wavefront's 64 indices map into one aligned 64-word block
+      const uint64_t* sp = lb.src_ptr[poly] + (uint64_t)(lb.src_ptr_limb0 + e) * N;
+      const uint32_t g = lb.src_gal[poly];
 #pragma unroll
-    for (uint32_t r_ = 0; r_ < kPer; ++r_) {
-      const uint32_t idx = wb + lane + r_ * 64;
-      lds[pad_idx(idx)] = ar.lds_in(in[j0 + idx]);
+      for (uint32_t r_ = 0; r_ < kPer; ++r_) {
+        const uint32_t idx = wb + lane + r_ * 64;
+        lds[pad_idx(idx)] = ar.lds_in(sp[automorph_src(j0 + idx, g, logN)]);
+      }
+    } else {
+#pragma unroll
+      for (uint32_t r_ = 0; r_ < kPer; ++r_) {
+        const uint32_t idx = wb + lane + r_ * 64;
+        lds[pad_idx(idx)] = ar.lds_in(in[j0 + idx]);
+      }
     }
     wave_sync();
     ntt_rounds<kInv, 2, A, kPer, NT, true>(lds, ar, tw + toff, k, logC, k1, j0);
@@ -381,11 +393,12 @@ __global__ __launch_bounds__(NT) void k_ntt(LimbBatch lb, const ModInfo* __restr
 // directly. Only u = sum_j ext_j * key_j (both components) is written, so the transformed digits
 // never return to HBM.
 constexpr int kInnerThreads = 512;
-template <class A>
+template <class A, bool kSrcPtr>
 __device__ __forceinline__ void ntt_p2_inner_body(
     uint32_t B, uint32_t nl, uint32_t K, uint32_t nq, uint32_t alpha, uint32_t R, uint32_t e0, uint32_t ne,
     uint32_t logN, uint32_t k1, const ModInfo* __restrict__ mods, const typename A::W* __restrict__ tw,
-    const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __restrict__ ext,
+    const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* const* __restrict__ in_ptr,
+    const uint32_t* __restrict__ in_gal, const uint64_t* __restrict__ ext,
     const uint64_t* const* __restrict__ keys, uint64_t* __restrict__ u) {
   extern __shared__ uint64_t lds[];
   constexpr uint32_t kPer = kNttE / kInnerThreads;
@@ -411,14 +424,26 @@ __device__ __forceinline__ void ntt_p2_inner_body(
     const uint32_t lo = j * alpha, cnt = min(alpha, nl - lo);
     const uint64_t* kb = key + ((uint64_t)(j * 2 + 0) * nall + mi) * N + j0;
     const uint64_t* ka = key + ((uint64_t)(j * 2 + 1) * nall + mi) * N + j0;
-    if (e >= lo && e < lo + cnt) {
-      const uint64_t* x = in + (uint64_t)b * in_stride + (uint64_t)e * N + j0;
+    if (e >= lo && e < lo + cnt) {  // the digit's own limbs (Q limbs only)
+      if (kSrcPtr) {  // the input read through its automorphism (rotation without a separate pass)
+        const uint64_t* x = in_ptr[b] + (uint64_t)e * N;
+        const uint32_t g = in_gal[b];
 #pragma unroll
-      for (uint32_t r = 0; r < kPer; ++r) {
-        const uint32_t idx = wb + lane + r * 64;
-        const typename A::T xv = ar.from_u64(x[idx]);
-        acc0[r] = ar.kacc(acc0[r], xv, kb[idx]);
-        acc1[r] = ar.kacc(acc1[r], xv, ka[idx]);
+        for (uint32_t r = 0; r < kPer; ++r) {
+          const uint32_t idx = wb + lane + r * 64;
+          const typename A::T xv = ar.from_u64(x[automorph_src((uint32_t)j0 + idx, g, logN)]);
+          acc0[r] = ar.kacc(acc0[r], xv, kb[idx]);
+          acc1[r] = ar.kacc(acc1[r], xv, ka[idx]);
+        }
+      } else {
+        const uint64_t* x = in + (uint64_t)b * in_stride + (uint64_t)e * N + j0;
+#pragma unroll
+        for (uint32_t r = 0; r < kPer; ++r) {
+          const uint32_t idx = wb + lane + r * 64;
+          const typename A::T xv = ar.from_u64(x[idx]);
+          acc0[r] = ar.kacc(acc0[r], xv, kb[idx]);
+          acc1[r] = ar.kacc(acc1[r], xv, ka[idx]);
+        }
       }
     } else {
       const uint32_t row = e < lo ? e : e - cnt;
@@ -458,13 +483,17 @@ __device__ __forceinline__ void ntt_p2_inner_body(
   }
 }
 
-template <class A>
+// kSrcPtr: the input items are read through their automorphisms (in_ptr, in_gal; only the FP64
+// instantiation reads the input at all).
+template <class A, bool kSrcPtr>
 __global__ __launch_bounds__(kInnerThreads) void k_ntt_p2_inner(
     uint32_t B, uint32_t nl, uint32_t K, uint32_t nq, uint32_t alpha, uint32_t R, uint32_t e0, uint32_t ne,
     uint32_t logN, uint32_t k1, const ModInfo* __restrict__ mods, const typename A::W* __restrict__ tw,
-    const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __restrict__ ext,
+    const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* const* __restrict__ in_ptr,
+    const uint32_t* __restrict__ in_gal, const uint64_t* __restrict__ ext,
     const uint64_t* const* __restrict__ keys, uint64_t* __restrict__ u) {
-  ntt_p2_inner_body<A>(B, nl, K, nq, alpha, R, e0, ne, logN, k1, mods, tw, in, in_stride, ext, keys, u);
+  ntt_p2_inner_body<A, kSrcPtr>(B, nl, K, nq, alpha, R, e0, ne, logN, k1, mods, tw, in, in_stride, in_ptr, in_gal,
+                                ext, keys, u);
 }
 
 // Row phase of the forward NTT of the ModDown conversion fused with the final combine:
@@ -1342,6 +1371,7 @@ static void ntt_phase(const fhe_ctx* ctx, const LimbBatch& lb, const char* name_
     LimbBatch sub = lb;
     sub.base = lb.base + (uint64_t)r.lo * p.N;
     if (sub.src) sub.src = lb.src + (uint64_t)r.lo * p.N;
+    if (sub.src_ptr) sub.src_ptr_limb0 = lb.src_ptr_limb0 + r.lo;
     sub.limbs = r.hi - r.lo;
     if (part == 0) {
       sub.n_first = sub.limbs;
@@ -1353,7 +1383,14 @@ static void ntt_phase(const fhe_ctx* ctx, const LimbBatch& lb, const char* name_
     const uint32_t blocks = ntt_blocks(ctx, sub);
     const double bytes = 16.0 * p.N * sub.limbs * sub.npoly;
     // row phase: the 512-thread variant (see rows_nt); column phase: 256 threads x 16 elements
-    if (kPhase == 2 && rows_nt() == 512) {
+    if (kPhase == 2 && from_src && sub.src_ptr) {
+      if (r.q)
+        FHE_LAUNCH_T(name_q, bytes, (k_ntt<kInv, kPhase, FpArith, 512, true>), blocks, 512, lds, st, sub, mods_of(ctx),
+                     twf, p.logN, p.k1, from_src);
+      else
+        FHE_LAUNCH_T(name_p, bytes, (k_ntt<kInv, kPhase, IntArith, 512, true>), blocks, 512, lds, st, sub,
+                     mods_of(ctx), ctx->t.tw.u64(), p.logN, p.k1, from_src);
+    } else if (kPhase == 2 && rows_nt() == 512) {
       if (r.q)
         FHE_LAUNCH_T(name_q, bytes, (k_ntt<kInv, kPhase, FpArith, 512>), blocks, 512, lds, st, sub, mods_of(ctx), twf,
                      p.logN, p.k1, from_src);
@@ -1378,6 +1415,7 @@ static void check_holes(const fhe_ctx* ctx, const LimbBatch& lb) {
 
 static void ntt_forward_cols(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st) {
   if (lb.limbs == 0 || lb.npoly == 0) return;
+  if (lb.src_ptr) fail(FHE_EINVAL, "automorphism reads are only for row phases");
   check_batch(ctx, lb);
   check_holes(ctx, lb);
   ntt_phase<false, 1>(ctx, lb, "ntt_fwd_p1_q", "ntt_fwd_p1_p", lb.src != nullptr, st);
@@ -1385,6 +1423,7 @@ static void ntt_forward_cols(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_
 
 void ntt_forward(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st) {
   if (lb.limbs == 0 || lb.npoly == 0) return;
+  if (lb.src_ptr) fail(FHE_EINVAL, "automorphism reads are only for row phases");
   check_batch(ctx, lb);
   check_holes(ctx, lb);
   ntt_phase<false, 1>(ctx, lb, "ntt_fwd_p1_q", "ntt_fwd_p1_p", lb.src != nullptr, st);
@@ -1396,7 +1435,7 @@ static void ntt_inverse_rows(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_
   if (lb.limbs == 0 || lb.npoly == 0) return;
   check_batch(ctx, lb);
   check_holes(ctx, lb);
-  ntt_phase<true, 2>(ctx, lb, "ntt_inv_p2_q", "ntt_inv_p2_p", lb.src != nullptr, st);
+  ntt_phase<true, 2>(ctx, lb, "ntt_inv_p2_q", "ntt_inv_p2_p", lb.src != nullptr || lb.src_ptr != nullptr, st);
 }
 
 void ntt_inverse(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st) {
@@ -1404,8 +1443,10 @@ void ntt_inverse(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st) {
   if (lb.raw_out) fail(FHE_EINVAL, "internal-form output is only for row phases of inverse transforms");
   check_batch(ctx, lb);
   check_holes(ctx, lb);
-  ntt_phase<true, 2>(ctx, lb, "ntt_inv_p2_q", "ntt_inv_p2_p", lb.src != nullptr, st);
-  ntt_phase<true, 1>(ctx, lb, "ntt_inv_p1_q", "ntt_inv_p1_p", false, st);
+  ntt_phase<true, 2>(ctx, lb, "ntt_inv_p2_q", "ntt_inv_p2_p", lb.src != nullptr || lb.src_ptr != nullptr, st);
+  LimbBatch cols = lb;  // the column phase works in place on the row phase's output
+  cols.src_ptr = nullptr;
+  ntt_phase<true, 1>(ctx, cols, "ntt_inv_p1_q", "ntt_inv_p1_p", false, st);
 }
 
 void automorph(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const uint64_t* const* src,
@@ -1472,8 +1513,9 @@ size_t keyswitch_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t nl) {
 
 void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, uint64_t in_stride,
                const uint64_t* const* keys, const uint64_t* const* add, uint64_t* const* out, uint64_t* ws,
-               hipStream_t st, const uint32_t* galois) {
+               hipStream_t st, const uint32_t* galois, const uint64_t* const* in_ptrs) {
   if (!B) return;
+  if (in_ptrs && !galois) fail(FHE_EINVAL, "key switch input pointers need their Galois elements");
   const Params& p = ctx->p;
   if (p.alpha > kMaxAlpha || p.np > kMaxK) fail(FHE_EINVAL, "alpha or n_p above kernel limits");
   if (nl < 1 || nl > (uint32_t)p.nq) fail(FHE_ESHAPE, "key switch level out of range");
@@ -1490,6 +1532,10 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
   LimbBatch lb_in{dcoef, nl, B, (uint64_t)nl * N, nl, 0};
   lb_in.src = in;
   lb_in.src_stride = in_stride;
+  if (in_ptrs) {
+    lb_in.src_ptr = in_ptrs;
+    lb_in.src_gal = galois;
+  }
   if (cols_fusable(ctx, alpha)) {
     // 1-3 fused: row phase of the INTT here, then one kernel for the column phases and ModUp.
     LimbBatch lb_rows = lb_in;
@@ -1553,12 +1599,18 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
   const double* twf = (const double*)ctx->t.twf.get();
   // per extended limb: beta digit words (input or ModUp row), 2 beta key words, 2 output words
   const double ib = 8.0 * N * (double)B * (3.0 * beta + 2.0);
-  FHE_LAUNCH_T("ntt_p2_inner_q", ib * nl, k_ntt_p2_inner<FpArith>, (uint64_t)B * nl * tiles, kInnerThreads, lds, st,
-               B, nl, K, (uint32_t)p.nq, alpha, R, 0u, nl, p.logN, p.k1, mods_of(ctx), twf, in, in_stride, ext, keys,
-               u);
-  FHE_LAUNCH_T("ntt_p2_inner_p", ib * K, k_ntt_p2_inner<IntArith>, (uint64_t)B * K * tiles, kInnerThreads, lds, st, B, nl, K,
-             (uint32_t)p.nq, alpha, R, nl, K, p.logN, p.k1, mods_of(ctx), ctx->t.tw.u64(), in, in_stride, ext, keys,
-             u);
+  const uint32_t* in_gal = in_ptrs ? galois : nullptr;
+  if (in_ptrs)
+    FHE_LAUNCH_T("ntt_p2_inner_q", ib * nl, (k_ntt_p2_inner<FpArith, true>), (uint64_t)B * nl * tiles, kInnerThreads,
+                 lds, st, B, nl, K, (uint32_t)p.nq, alpha, R, 0u, nl, p.logN, p.k1, mods_of(ctx), twf, in, in_stride,
+                 in_ptrs, in_gal, ext, keys, u);
+  else
+    FHE_LAUNCH_T("ntt_p2_inner_q", ib * nl, (k_ntt_p2_inner<FpArith, false>), (uint64_t)B * nl * tiles, kInnerThreads,
+                 lds, st, B, nl, K, (uint32_t)p.nq, alpha, R, 0u, nl, p.logN, p.k1, mods_of(ctx), twf, in, in_stride,
+                 in_ptrs, in_gal, ext, keys, u);
+  FHE_LAUNCH_T("ntt_p2_inner_p", ib * K, (k_ntt_p2_inner<IntArith, false>), (uint64_t)B * K * tiles, kInnerThreads, lds,
+               st, B, nl, K, (uint32_t)p.nq, alpha, R, nl, K, p.logN, p.k1, mods_of(ctx), ctx->t.tw.u64(), in,
+               in_stride, nullptr, nullptr, ext, keys, u);
   // 5. ModDown: INTT of the P limbs, conversion to Q_l, column phase, row phase fused with the combine.
   const LimbBatch lb_up{u + (size_t)nl * N, K, 2 * B, (uint64_t)next * N, 0, (uint32_t)p.nq};
   if (cols_fusable(ctx, K)) {

@@ -166,8 +166,8 @@ size_t workspace_budget_bytes() {
 }
 
 // One batched rotation step over `items`: src[b] -> out[b] rotated left by steps[b] (one key switch).
-// gather: only component 1 goes through the automorphism into scratch (the key switch input);
-// component 0 is read through it by the final combine, so out[b] must be disjoint from src[b].
+// gather: no automorphism pass; the key switch reads component 1 through the automorphism and its
+// final combine reads component 0 through it, so out[b] must be disjoint from src[b].
 // Otherwise both components go to scratch first, and out[b] may equal src[b].
 void enqueue_rotation(fhe_ctx* ctx, ArgPack& ap, std::vector<std::function<void()>>& ops, uint32_t nl,
                       const std::vector<const uint64_t*>& src_in, const std::vector<uint32_t>& steps_in,
@@ -202,10 +202,10 @@ void enqueue_rotation(fhe_ctx* ctx, ArgPack& ap, std::vector<std::function<void(
   const size_t o_src = ap.push(src), o_s1 = ap.push(src1), o_g = ap.push(gal), o_k = ap.push(keys),
                o_a = ap.push(add), o_o = ap.push(out);
   if (gather) {
+    // the key switch reads component 1 through the automorphism, the final combine component 0
     ops.push_back([=, &ap] {
-      automorph(ctx, B, 1, nl, ap.at<const uint64_t*>(o_s1), ap.at<uint32_t>(o_g), ws.rtmp, st);
-      keyswitch(ctx, B, nl, ws.rtmp, (uint64_t)nl * N, ap.at<const uint64_t*>(o_k), ap.at<const uint64_t*>(o_a),
-                ap.at<uint64_t*>(o_o), ws.ksws, st, ap.at<uint32_t>(o_g));
+      keyswitch(ctx, B, nl, nullptr, 0, ap.at<const uint64_t*>(o_k), ap.at<const uint64_t*>(o_a),
+                ap.at<uint64_t*>(o_o), ws.ksws, st, ap.at<uint32_t>(o_g), ap.at<const uint64_t*>(o_s1));
     });
     return;
   }
