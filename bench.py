@@ -173,6 +173,57 @@ def run_batch(args) -> dict:
     }
 
 
+def run_sweep(args) -> dict:
+    """Runtime against sparsity on the 16x16 workload (the shape of the paper's Table 1 / Fig. 4a):
+    for sparsity 0 %, 10 %, ..., 100 % in both operands, the CSR x CSC plan (per pair, and replayed
+    as a HIP graph) and the naive dense plan (every entry stored, zeros included, so all m k n
+    products run) on the same values; time per matmul, matched pairs and max-abs error."""
+    import torch
+    from paper_2604_11659_amd import fhe
+    w = synth.WORKLOADS["plain"]
+    ctx = fhe.Context(w.log_n, w.n_q, w.n_p, w.alpha, w.rot_digits)
+    sk = ctx.keygen(42)
+    reps = max(1, args.steps)
+
+    def timed(fn):
+        C = fn()  # warm-up (and graph recording)
+        torch.cuda.synchronize()
+        C.close()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            C.close()
+            C = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, C
+
+    rows = []
+    for pct in range(0, 101, 10):
+        s = pct / 100
+        a = synth.sparse_dense(w.m, w.k, s, "uniform", 0, 2)
+        b = synth.sparse_dense(w.k, w.n, s, "uniform", 1, 3)
+        A = ctx.encrypt_csr(sk, w.m, w.k, *synth.to_csr(a), seed=43)
+        B = ctx.encrypt_csc(sk, w.k, w.n, *synth.to_csc(b), seed=44)
+        Ad = ctx.encrypt_csr(sk, w.m, w.k, *synth.full_csr(a), seed=45)
+        Bd = ctx.encrypt_csc(sk, w.k, w.n, *synth.full_csc(b), seed=46)
+        ctx.keygen_rotations(sk, sorted(set(ctx.plan_rotations(A, B)) | set(ctx.plan_rotations(Ad, Bd))))
+        F, Fd = ctx.plan_stats(A, B).matched_pairs, ctx.plan_stats(Ad, Bd).matched_pairs
+        t_s, C = timed(lambda: ctx.spmspm(A, B))
+        e_s = float(np.abs(ctx.decrypt_decode(sk, C) - a @ b).max())
+        t_g, C = timed(lambda: ctx.spmspm(A, B, graph=True))
+        t_d, Cd = timed(lambda: ctx.spmspm(Ad, Bd))
+        e_d = float(np.abs(ctx.decrypt_decode(sk, Cd) - a @ b).max())
+        C.close()
+        Cd.close()
+        rows.append({"sparsity": s, "matched_pairs": F, "dense_pairs": Fd, "csr_ms": round(1000 * t_s, 3),
+                     "csr_graph_ms": round(1000 * t_g, 3), "dense_ms": round(1000 * t_d, 3),
+                     "speedup_vs_dense": round(t_d / t_s, 2), "csr_max_abs_err": e_s, "dense_max_abs_err": e_d})
+        log(f"sparsity {pct}%: F={F} csr {1000 * t_s:.2f} ms (graph {1000 * t_g:.2f}), dense {1000 * t_d:.2f} ms")
+    return {"metric": "encrypted 16x16 SpMSpM time vs sparsity (CSR x CSC plan vs naive dense plan)",
+            "unit": "ms per matmul", "n_gpus": 1, "higher_is_better": False, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": describe(w) + "; both operands at the same sparsity, seeds 0-3",
+                       "repetitions": reps}, "rows": rows}
+
+
 SERVE_PARAMS = [(16, 24, 3, 3, 3), (17, 35, 3, 3, 4)]  # (log_n, n_q, n_p, alpha, rotation digits)
 
 
@@ -343,6 +394,8 @@ def main():
     ap.add_argument("--autotune", type=int, default=1, help="1: pick the NTT split by timing (untimed set-up)")
     ap.add_argument("--autotune-pairs", type=int, default=4000, help="matched pairs timed per candidate split")
     ap.add_argument("--serve", action="store_true", help="run the request-loop benchmark instead")
+    ap.add_argument("--sweep", action="store_true",
+                    help="run the 16x16 sparsity sweep (CSR x CSC plan vs naive dense plan) instead")
     ap.add_argument("--serve-mix", type=int, default=1, help="1: N=2^16 and N=2^17 parameter sets, 0: N=2^16 only")
     ap.add_argument("--serve-sizes", default="16,32")
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered load as a fraction of capacity")
@@ -373,6 +426,9 @@ def main():
 
     if args.serve:
         print(json.dumps(run_serve(args)), flush=True)
+        return
+    if args.sweep:
+        print(json.dumps(run_sweep(args)), flush=True)
         return
     if args.workload in synth.BATCH_WORKLOADS:
         print(json.dumps(run_batch(args)), flush=True)

@@ -48,6 +48,19 @@ def to_csc(d: np.ndarray):
     return to_csr(np.ascontiguousarray(d.T))
 
 
+def full_csr(d: np.ndarray):
+    """The CSR arrays of d with every entry stored, zeros included (the naive dense plan: every
+    (i, k, j) product is computed whatever the values)."""
+    rows, cols = d.shape
+    indptr = (np.arange(rows + 1, dtype=np.int32) * cols).astype(np.int32)
+    indices = np.tile(np.arange(cols, dtype=np.int32), rows)
+    return indptr, indices, np.ascontiguousarray(d, dtype=np.float64).reshape(-1)
+
+
+def full_csc(d: np.ndarray):
+    return full_csr(np.ascontiguousarray(d.T))
+
+
 @dataclass(frozen=True)
 class Workload:
     name: str
