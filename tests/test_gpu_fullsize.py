@@ -136,3 +136,65 @@ def test_dnn_layer_tree_full_fp64_and_sampled_bit_exact():
     _say(f"[full] dnn tree pairs [{lo}, {hi}) oracle")
     ref = spmspm.spmspm(op, keys, OA, OB, workers=WORKERS, pairs=pairs[lo:hi], tree=True)
     assert (ctx.export(Cs, 0) == ref[0].data).all(), (lo, hi)
+
+
+# ---- the larger parameter sets (N = 2^16 with 24 Q + 3 P primes, N = 2^17 with 35 Q + 3 P) ----
+
+def _ctx_pair(prm):
+    from paper_2604_11659_amd import fhe
+    log_n, n_q, n_p, alpha, D = prm
+    ctx = fhe.Context(log_n, n_q, n_p, alpha, D)
+    sk = ctx.keygen(42)
+    op = ckks.Params(log_n=log_n, n_q=n_q, n_p=n_p, alpha=alpha, rot_digits=D)
+    return ctx, sk, op, ckks.Keys(op, 42)
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("prm,a,b", [
+    # alignment rotations of A and B, a target rotation by S - 1 (three digit steps), shared products
+    ((16, 24, 3, 3, 3), np.array([[0.5, -0.25, 0.75]]), np.array([[0.0, 0.3], [0.0, -0.6], [0.9, 0.0]])),
+    # one product, one target rotation by 1: every key-switch kernel at alpha = K = 3, N = 2^17
+    ((17, 35, 3, 3, 4), np.array([[0.5, -0.25]]), np.array([[0.75], [0.3]])),
+])
+def test_large_parameter_sets_bit_exact(prm, a, b):
+    """The parameter sets of the large, batching and serving workloads (three primes per digit,
+    three special primes, NTT splits 2^7 x 2^9 and 2^8 x 2^9): a small matmul bit-exact against the
+    oracle in every limb."""
+    _say(f"[large] {prm} setup")
+    ctx, sk, op, keys = _ctx_pair(prm)
+    (m, k), n = a.shape, b.shape[1]
+    A = ctx.encrypt_csr(sk, m, k, *synth.to_csr(a), seed=43)
+    B = ctx.encrypt_csc(sk, k, n, *synth.to_csc(b), seed=44)
+    _say(f"[large] {prm} gpu {ctx.plan_stats(A, B)}")
+    C = ctx.spmspm(A, B)
+    _say(f"[large] {prm} oracle")
+    ref = spmspm.spmspm(op, keys, spmspm.encrypt_csr(op, keys, m, k, *synth.to_csr(a), seed=43),
+                        spmspm.encrypt_csc(op, keys, k, n, *synth.to_csc(b), seed=44), workers=WORKERS)
+    assert (ctx.export(C, 0) == ref[0].data).all()
+    assert np.abs(ctx.decrypt_decode(sk, C) - a @ b).max() < 1e-5
+    C.close()
+    ctx.close()
+
+
+@pytest.mark.timeout(1200)
+def test_large_workload_sampled_pairs_bit_exact():
+    """The 512 x 512 workload at N = 2^16 (B over four operand chunks, C over eight result chunks):
+    pair ranges at the start, middle and end of Algorithm 1's traversal are bit-exact against the
+    oracle on the same pairs."""
+    w = synth.WORKLOADS["large"]
+    _say("[full] large setup")
+    a, b, ctx, sk, A, B, op, keys, OA, OB = _prepare(w)
+    st = ctx.plan_stats(A, B)
+    assert st.result_chunks == 8 and B.info()["chunks"] == 4
+    F = st.matched_pairs
+    pairs = spmspm.matched_pairs(w.m, w.n, OA.indptr, OA.indices, OB.indptr, OB.indices)
+    assert len(pairs) == F
+    for lo, hi in [(0, 2), (F // 2, F // 2 + 2), (F - 2, F)]:
+        _say(f"[full] large pairs [{lo}, {hi}) gpu")
+        Cs = ctx.spmspm_pairs(A, B, lo, hi)
+        _say(f"[full] large pairs [{lo}, {hi}) oracle")
+        ref = spmspm.spmspm(op, keys, OA, OB, workers=WORKERS, pairs=pairs[lo:hi])
+        for c, r in enumerate(ref):
+            assert (ctx.export(Cs, c) == r.data).all(), (lo, hi, c)
+        Cs.close()
+    ctx.close()
