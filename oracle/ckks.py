@@ -277,6 +277,77 @@ def rotate_single(params: Params, keys: Keys, ct: Ct, r: int) -> Ct:
     return Ct(np.stack([c0, u[1]]), ct.scale)
 
 
+def ext_moduli(params: Params, nl: int) -> np.ndarray:
+    """Moduli of the extended basis at nl limbs: q_0 .. q_(nl-1), then p_0 .. p_(K-1)."""
+    return np.ascontiguousarray(np.concatenate([params.primes[:nl], params.primes[params.n_q:]]))
+
+
+def modup_digits(params: Params, d: np.ndarray) -> list:
+    """ModUp of every digit of d ([nl][N], coefficient domain): the list over digits j of the
+    extended polynomials ([nl + K][N]) that the key switch multiplies by the key's digit j."""
+    nl = d.shape[0]
+    d = np.ascontiguousarray(d, dtype=np.uint64)
+    em = ext_moduli(params, nl)
+    out = []
+    for j in range(-(-nl // params.alpha)):
+        lo, hi = j * params.alpha, min((j + 1) * params.alpha, nl)
+        ext = _u64((nl + params.n_p, params.N))
+        lib().or_modup(P(d), nl, lo, hi, P(em), params.n_p, params.N, P(ext))
+        out.append(ext)
+    return out
+
+
+def keyswitch_digits(params: Params, exts: list, key: np.ndarray, nl: int, g: int = 1) -> np.ndarray:
+    """Inner product and ModDown from given extended digits, each first mapped by tau_g (applied limb
+    by limb over the extended basis): u_c = sum_j tau_g(ext_j) (*) key_(j,c); out_c = ModDown(u_c).
+    With g = 1 and exts = modup_digits(d) this is keyswitch(d). -> [2][nl][N]."""
+    N, nk = params.N, params.n_p
+    nxt = nl + nk
+    em = ext_moduli(params, nl)
+    u = np.zeros((2, nxt, N), dtype=np.uint64)
+    prod = _u64(N)
+    for j, ext in enumerate(exts):
+        if g != 1:
+            eg = _u64((nxt, N))
+            lib().or_automorph(P(np.ascontiguousarray(ext)), P(eg), N, g, P(em), nxt)
+        else:
+            eg = ext
+        for c in range(2):
+            for e in range(nxt):
+                limb = e if e < nl else params.n_q + (e - nl)
+                lib().or_poly_mul(P(np.ascontiguousarray(eg[e])), P(np.ascontiguousarray(key[j, c, limb])), P(prod),
+                                  N, int(em[e]))
+                u[c, e] = (u[c, e] + prod) % em[e]
+    out = _u64((2, nl, N))
+    for c in range(2):
+        o = _u64((nl, N))
+        lib().or_moddown(P(np.ascontiguousarray(u[c])), nl, P(em), nk, N, P(o))
+        out[c] = o
+    return out
+
+
+def rotate_single_hoisted(params: Params, keys: Keys, ct: Ct, r: int, exts: list | None = None) -> Ct:
+    """Left rotation by r with the automorphism moved past ModUp (hoisting): the key switch uses
+    tau_g(ModUp_j(c1)), which agrees with ModUp_j(tau_g(c1)) modulo each digit's modulus (tau_g is a
+    ring automorphism modulo every prime), so the result decrypts to the same rotation; ModUp of c1
+    depends on ct alone and can serve every rotation of ct. `exts` = modup_digits(ct's c1) if known."""
+    g = pow(5, r, 2 * params.N)
+    nl = ct.data.shape[1]
+    if exts is None:
+        exts = modup_digits(params, ct.data[1])
+    u = keyswitch_digits(params, exts, keys.rot_key(g), nl, g)
+    t0 = automorph(params, Ct(ct.data[0:1].copy(), ct.scale), g)
+    c0 = add(params, t0, Ct(u[0:1].copy(), ct.scale)).data[0]
+    return Ct(np.stack([c0, u[1]]), ct.scale)
+
+
+def rotate_hoisted(params: Params, keys: Keys, ct: Ct, r: int) -> Ct:
+    """Rotation by r as its digit steps (as rotate), each step hoisted."""
+    for step in rotation_steps(params, r):
+        ct = rotate_single_hoisted(params, keys, ct, step)
+    return ct
+
+
 def rotation_steps(params: Params, r: int) -> list[int]:
     """Decomposition of a left rotation by r into key-switched steps r_t * 2^(b t), t ascending."""
     S = params.S

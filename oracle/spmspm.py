@@ -110,15 +110,20 @@ def target(params: Params, i: int, j: int, n: int, min_pos: int):
     return cr, (min_pos - lt) % params.S
 
 
+_HOIST = {"on": False}
+
+
 def masked_product(params: Params, keys: Keys, A: EncSparse, B: EncSparse, a_pos: int, b_pos: int) -> Ct:
     """Algorithm 1's alignment, then Algorithm 2 up to the mask: EvalMult, Relinearize, Rescale and
-    the product with the one-hot mask at min_pos (one level below the top, before the second rescale)."""
+    the product with the one-hot mask at min_pos (one level below the top, before the second rescale).
+    With hoisting on (spmspm(..., hoist=True)) the alignment rotations use rotate_hoisted."""
     ca, cb, ra, rb, mn = alignment(params, a_pos, b_pos)
     vA, vB = A.chunks[ca], B.chunks[cb]
+    rot = ckks.rotate_hoisted if _HOIST["on"] else ckks.rotate
     if rb:
-        vB = ckks.rotate(params, keys, vB, rb)
+        vB = rot(params, keys, vB, rb)
     if ra:
-        vA = ckks.rotate(params, keys, vA, ra)
+        vA = rot(params, keys, vA, ra)
     d = ckks.mult_relin(params, keys, vA, vB)
     d = ckks.rescale(params, d)
     return ckks.mul_plain(params, d, ckks.mask(params, mn), params.delta_mask)
@@ -272,7 +277,18 @@ def rotation_elements(params: Params, A: EncSparse, B: EncSparse, pairs: list) -
 
 
 def spmspm(params: Params, keys: Keys, A: EncSparse, B: EncSparse, workers: int = 1, pairs: list | None = None,
-           grouped: bool = False, tree: bool = False) -> list:
+           grouped: bool = False, tree: bool = False, hoist: bool = False) -> list:
+    """See _spmspm; hoist: every alignment rotation step is hoisted (ckks.rotate_single_hoisted: the
+    automorphism applied to the ModUp digits of the step's input), in any plan mode."""
+    _HOIST["on"] = hoist
+    try:
+        return _spmspm(params, keys, A, B, workers, pairs, grouped, tree)
+    finally:
+        _HOIST["on"] = False
+
+
+def _spmspm(params: Params, keys: Keys, A: EncSparse, B: EncSparse, workers: int = 1, pairs: list | None = None,
+            grouped: bool = False, tree: bool = False) -> list:
     """Encrypted C = A B as a list of result-chunk ciphertexts (row-major slots).
 
     ``pairs`` restricts the sum to a subset of matched pairs (default: all).
