@@ -346,7 +346,7 @@ def run_graph(ctx, A, B, steps: int) -> dict:
             "steps": steps, "ms_per_step": round(1000 * dt / steps, 3), "record_and_first_ms": round(1000 * rec, 1)}
 
 
-def run_grouped(ctx, sk, A, B, st, ref, steps: int, tree: bool = False) -> dict:
+def run_grouped(ctx, sk, A, B, st, ref, steps: int, tree: bool = False, hoist: bool = False) -> dict:
     """The grouped plan on the same operands: masked products sharing (result chunk, target rotation)
     summed, then one rescale and one rotation per group. Different ciphertext bits from the per-pair
     plan (its own oracle mode), same decryption up to noise."""
@@ -354,7 +354,7 @@ def run_grouped(ctx, sk, A, B, st, ref, steps: int, tree: bool = False) -> dict:
     groups, gks, tks = ctx.plan_groups(A, B)
     if tree:
         gks = tks
-    C = ctx.spmspm(A, B, grouped=True, tree=tree)  # warm-up (allocates the resident products)
+    C = ctx.spmspm(A, B, grouped=True, tree=tree, hoist=hoist)  # warm-up (allocates the resident products)
     C.close()
     torch.cuda.synchronize()
     log(f"grouped warm-up done: {groups} groups, {gks} target key switches")
@@ -365,7 +365,7 @@ def run_grouped(ctx, sk, A, B, st, ref, steps: int, tree: bool = False) -> dict:
     for _ in range(steps):
         if C is not None:
             C.close()
-        C = ctx.spmspm(A, B, grouped=True, tree=tree)
+        C = ctx.spmspm(A, B, grouped=True, tree=tree, hoist=hoist)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     fhe.profile_enable(False)
@@ -375,8 +375,9 @@ def run_grouped(ctx, sk, A, B, st, ref, steps: int, tree: bool = False) -> dict:
     dec = ctx.decrypt_decode(sk, C)
     C.close()
     v = steps / dt
-    log(f"{'tree' if tree else 'grouped'}: {1000 * dt / steps:.1f} ms/step")
-    return {"plan": "grouped target rotations" + (", shared digit by digit" if tree else ""), "value": round(v, 6), "unit": "SpMSpM/s", "steps": steps,
+    log(f"{'tree' if tree else 'grouped'}{' hoisted' if hoist else ''}: {1000 * dt / steps:.1f} ms/step")
+    return {"plan": "grouped target rotations" + (", shared digit by digit" if tree else "") +
+            (", hoisted alignment rotations" if hoist else ""), "value": round(v, 6), "unit": "SpMSpM/s", "steps": steps,
             "ms_per_step": round(1000 * dt / steps, 2), "groups": groups, "target_keyswitches": gks,
             "keyswitches_executed": ks, "matched_pairs_per_s": round(st.matched_pairs * v, 1),
             "keyswitch_per_s": round(ks * v, 1), "max_abs_err": float(np.abs(dec - ref).max()),
@@ -524,6 +525,7 @@ def main():
         line["grouped"], gkernels = run_grouped(ctx, sk, A, B, st, ref, args.grouped_steps)
     if args.tree_steps > 0:
         line["tree"], _ = run_grouped(ctx, sk, A, B, st, ref, args.tree_steps, tree=True)
+        line["tree_hoisted"], _ = run_grouped(ctx, sk, A, B, st, ref, args.tree_steps, tree=True, hoist=True)
     if args.kernels_out:
         with open(args.kernels_out, "w") as f:
             json.dump({"kernels": kernels, "grouped_kernels": gkernels, "plan": st.__dict__}, f, indent=1)

@@ -148,6 +148,7 @@ int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, co
 #define FHE_PLAN_GROUPED 1  /* grouped target rotations, see fhe_spmspm_plan */
 #define FHE_PLAN_TREE 2     /* grouped, with the target rotations shared digit by digit */
 #define FHE_PLAN_GRAPH 256  /* flag: record the launch stream as a HIP graph and replay it, see below */
+#define FHE_PLAN_HOIST 512  /* flag: hoisted alignment rotations, see below */
 
 /* General form of the matmul calls: C_out[i] = A[i] B[i] for i < cnt as one merged launch stream,
  * each restricted to the matched pairs with traversal index in [pair_begin[i], pair_end[i]) (both
@@ -176,7 +177,12 @@ int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, co
  * and NTT split replay it with a single launch on `stream`. Results are bit-identical to the eager
  * form. A context keeps at most two graphs (the oldest is dropped) and drops them all when its
  * scratch has to grow. Graph calls are not timed per kernel by fhe_profile_* (one "graph_replay"
- * record per call). */
+ * record per call).
+ * With FHE_PLAN_HOIST or-ed into mode, every alignment rotation step (Algorithm 1) is hoisted: the
+ * key switch uses the automorphism of the ModUp digits of its input, tau(ModUp(c1)), rather than
+ * ModUp(tau(c1)); both are congruent modulo every digit modulus, so the rotation decrypts the same up
+ * to noise, while one ModUp (and one transform of its digits) serves every rotation of the same
+ * ciphertext in a batch. The limbs are those of that sequence (any plan mode). */
 int fhe_spmspm_plan(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B,
                     const int64_t* pair_begin, const int64_t* pair_end, int32_t mode, void* stream, fhe_mat** C_out);
 

@@ -182,7 +182,7 @@ int fhe_spmspm_plan(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe
       need(B, "B");
     }
     for (size_t i = 0; i < cnt; ++i) C_out[i] = nullptr;
-    const int32_t plan_mode = mode & ~FHE_PLAN_GRAPH;
+    const int32_t plan_mode = mode & ~(FHE_PLAN_GRAPH | FHE_PLAN_HOIST);
     if (plan_mode != FHE_PLAN_PER_PAIR && plan_mode != FHE_PLAN_GROUPED && plan_mode != FHE_PLAN_TREE)
       fail(FHE_EINVAL, "unknown plan mode");
     if ((pair_begin == nullptr) != (pair_end == nullptr)) fail(FHE_EINVAL, "pair_begin and pair_end go together");
@@ -199,7 +199,7 @@ int fhe_spmspm_plan(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe
       jobs[i] = Job{A[i], B[i], build_plan(ctx->p, A[i], B[i], lo, hi), Cs[i].get(), lo, hi};
     }
     execute_jobs(ctx, jobs, as_stream(stream), plan_mode == FHE_PLAN_GROUPED, (mode & FHE_PLAN_GRAPH) != 0,
-                 plan_mode == FHE_PLAN_TREE);
+                 plan_mode == FHE_PLAN_TREE, (mode & FHE_PLAN_HOIST) != 0);
     for (size_t i = 0; i < cnt; ++i) C_out[i] = Cs[i].release();
   });
 }

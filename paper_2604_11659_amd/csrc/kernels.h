@@ -61,6 +61,17 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
                const uint64_t* const* keys, const uint64_t* const* add, uint64_t* const* out, uint64_t* ws,
                hipStream_t st, const uint32_t* galois = nullptr, const uint64_t* const* in_ptrs = nullptr);
 
+// Hoisted key switches of B rotations of S polynomials (S <= B): state_c1[s] ([nl][N], NTT domain;
+// `ident`: S Galois elements equal to 1) gets ModUp and the forward transform of its digits once;
+// item b then switches tau_(galois[b])(state_c1[state_of[b]]) with keys[b], reading those digits through
+// the automorphism (in_ptrs[b] = state_c1[state_of[b]]). add/out as in keyswitch (with galois). ws:
+// keyswitch_ws_elems(ctx, B, nl). The digits of tau(x) are tau(ModUp(x)) here, not ModUp(tau(x)): the
+// same rotation up to noise, other limbs.
+void keyswitch_hoisted(const fhe_ctx* ctx, uint32_t S, uint32_t B, uint32_t nl, const uint64_t* const* state_c1,
+                       const uint32_t* ident, const uint32_t* state_of, const uint64_t* const* in_ptrs,
+                       const uint32_t* galois, const uint64_t* const* keys, const uint64_t* const* add,
+                       uint64_t* const* out, uint64_t* ws, hipStream_t st);
+
 // Rescale of B ciphertexts [ncomp][nl][N] -> [ncomp][nl-1][N] (nearest rounding of the dropped limb).
 // With mask_galois (device array of B Galois elements, needs rescale_fuses_mask and nl <= nq - 1),
 // every input is first multiplied by its one-hot mask tau_(galois[b])(base mask), on the fly: the

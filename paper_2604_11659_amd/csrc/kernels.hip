@@ -496,6 +496,114 @@ __global__ __launch_bounds__(kInnerThreads) void k_ntt_p2_inner(
                                 ext, keys, u);
 }
 
+// Hoisted rotations. The ModUp digits of S polynomials, column phase already applied
+// (ext [beta][S][R][N], raw form), get their forward row phase in place, so that every rotation of a
+// polynomial can read them through its automorphism afterwards. Workgroup (digit j, poly s, compact
+// row r, tile); rows of Q primes (q_rows = true) and of special primes are separate launches. The
+// compact row r of digit j is limb e = r (r < lo_j) or r + cnt_j, as the key-switch kernels map it.
+template <class A, bool kQRows>
+__global__ __launch_bounds__(kInnerThreads) void k_ext_rows(uint32_t S, uint32_t nl, uint32_t K, uint32_t nq,
+                                                           uint32_t alpha, uint32_t R, uint32_t rows, uint32_t logN,
+                                                           uint32_t k1, const ModInfo* __restrict__ mods,
+                                                           const typename A::W* __restrict__ tw,
+                                                           uint64_t* __restrict__ ext) {
+  extern __shared__ uint64_t lds[];
+  constexpr uint32_t kPer = kNttE / kInnerThreads;
+  const uint32_t N = 1u << logN, tiles = N >> kNttLogE;
+  const uint32_t tile = blockIdx.x % tiles, rest = blockIdx.x / tiles;
+  const uint32_t rr = rest % rows, js = rest / rows, s = js % S, j = js / S;
+  const uint32_t lo = j * alpha, cnt = min(alpha, nl - lo);
+  const uint32_t nq_rows = nl - cnt;  // Q rows of this digit
+  if (kQRows && rr >= nq_rows) return;  // the last digit may have fewer rows (whole workgroup exits)
+  const uint32_t r = kQRows ? rr : nq_rows + rr;
+  const uint32_t e = r < lo ? r : r + cnt;
+  const uint32_t mi = e < nl ? e : nq + (e - nl);
+  A ar;
+  ar.init(mods[mi]);
+  const uint32_t j0 = tile * kNttE, k = logN - k1, logC = kNttLogE - k;
+  uint64_t* row = ext + (((uint64_t)j * S + s) * R + r) * N + j0;
+  const uint32_t wb = (threadIdx.x >> 6) * (kNttE / (kInnerThreads / 64)), lane = threadIdx.x & 63;
+#pragma unroll
+  for (uint32_t r_ = 0; r_ < kPer; ++r_) {
+    const uint32_t idx = wb + lane + r_ * 64;
+    lds[pad_idx(idx)] = row[idx];  // raw form, as the column phase left it
+  }
+  wave_sync();
+  ntt_rounds<false, 2, A, kPer, kInnerThreads, true>(lds, ar, tw + (uint64_t)mi * 4 * N, k, logC, k1, j0);
+  const uint32_t ln = opaque(lane);
+#pragma unroll
+  for (uint32_t r_ = 0; r_ < kPer; ++r_) {
+    const uint32_t idx = wb + ln + r_ * 64;
+    row[idx] = ar.raw(lds[pad_idx(idx)]);
+  }
+}
+
+// Key inner product of hoisted rotations: item b rotates polynomial state[b] by tau_(gal[b]). Per
+// (item, extended limb e, tile): u_c = sum_j tau(ext_j)[e] * key_(j,c)[e], reading the transformed
+// digits of the item's polynomial through the automorphism (a wavefront's 64 indices fall in one
+// aligned 64-word block) and, for the digit that contains e, the NTT-domain input itself. No transform.
+template <class A>
+__global__ __launch_bounds__(kThreads) void k_hoisted_inner(
+    uint32_t B, uint32_t S, uint32_t nl, uint32_t K, uint32_t nq, uint32_t alpha, uint32_t R, uint32_t e0,
+    uint32_t ne, uint32_t logN, const ModInfo* __restrict__ mods, const uint32_t* __restrict__ state,
+    const uint32_t* __restrict__ gal, const uint64_t* const* __restrict__ in_ptr, const uint64_t* __restrict__ ext,
+    const uint64_t* const* __restrict__ keys, uint64_t* __restrict__ u) {
+  constexpr uint32_t kPer = 8, kTile = kThreads * kPer;  // 2048 coefficients per workgroup
+  const uint32_t N = 1u << logN, tiles = N / kTile;
+  const uint32_t tile = blockIdx.x % tiles, be = blockIdx.x / tiles;
+  const uint32_t e = e0 + be % ne, b = be / ne;
+  const uint32_t next = nl + K, beta = (nl + alpha - 1) / alpha, nall = nq + K;
+  const uint32_t mi = e < nl ? e : nq + (e - nl);
+  A ar;
+  ar.init(mods[mi]);
+  const uint32_t j0 = tile * kTile, g = gal[b], sb = state[b];
+  const uint64_t* key = keys[b];
+  const uint32_t wb = (threadIdx.x >> 6) * (kTile / (kThreads / 64)), lane = threadIdx.x & 63;
+  uint32_t src[kPer];
+#pragma unroll
+  for (uint32_t r = 0; r < kPer; ++r) src[r] = automorph_src(j0 + wb + lane + r * 64, g, logN);
+  typename A::Acc acc0[kPer], acc1[kPer];
+#pragma unroll
+  for (uint32_t r = 0; r < kPer; ++r) acc0[r] = acc1[r] = 0;
+  for (uint32_t j = 0; j < beta; ++j) {
+    const uint32_t lo = j * alpha, cnt = min(alpha, nl - lo);
+    const uint64_t* kb = key + ((uint64_t)(j * 2 + 0) * nall + mi) * N + j0 + wb;
+    const uint64_t* ka = key + ((uint64_t)(j * 2 + 1) * nall + mi) * N + j0 + wb;
+    if (e >= lo && e < lo + cnt) {  // the digit's own limbs (Q limbs only): the input itself
+      const uint64_t* x = in_ptr[b] + (uint64_t)e * N;
+#pragma unroll
+      for (uint32_t r = 0; r < kPer; ++r) {
+        const typename A::T xv = ar.from_u64(x[src[r]]);
+        acc0[r] = ar.kacc(acc0[r], xv, kb[lane + r * 64]);
+        acc1[r] = ar.kacc(acc1[r], xv, ka[lane + r * 64]);
+      }
+    } else {
+      const uint32_t row = e < lo ? e : e - cnt;
+      const uint64_t* x = ext + (((uint64_t)j * S + sb) * R + row) * N;
+#pragma unroll
+      for (uint32_t r = 0; r < kPer; ++r) {
+        const typename A::T xv = ar.ld(x[src[r]]);
+        acc0[r] = ar.kacc(acc0[r], xv, kb[lane + r * 64]);
+        acc1[r] = ar.kacc(acc1[r], xv, ka[lane + r * 64]);
+      }
+    }
+    if ((j & 3) == 3) {
+#pragma unroll
+      for (uint32_t r = 0; r < kPer; ++r) {
+        ar.kred(acc0[r]);
+        ar.kred(acc1[r]);
+      }
+    }
+  }
+  uint64_t* u0 = u + ((uint64_t)(b * 2 + 0) * next + e) * N + j0 + wb;
+  uint64_t* u1 = u + ((uint64_t)(b * 2 + 1) * next + e) * N + j0 + wb;
+#pragma unroll
+  for (uint32_t r = 0; r < kPer; ++r) {
+    u0[lane + r * 64] = ar.kfinal(acc0[r]);
+    u1[lane + r * 64] = ar.kfinal(acc1[r]);
+  }
+}
+
 // Row phase of the forward NTT of the ModDown conversion fused with the final combine:
 // out[b][c][i] = add[2b+c][i] + (u[b][c][i] - NTT(conv)[b][c][i]) P^-1 (NTT domain).
 // Workgroup (poly bc = 2b + c, limb i, tile); conv has had its column phase.
@@ -1505,29 +1613,21 @@ static bool cols_fusable(const fhe_ctx* ctx, uint32_t regs_needed) {
   return cols_lds_bytes(cols_log_e(p)) <= max_lds_per_block(ctx->device);
 }
 
-size_t keyswitch_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t nl) {
-  const Params& p = ctx->p;
-  const size_t N = p.N, next = nl + p.np, beta = p.beta(nl), R = modup_rows(p, nl);
-  return (size_t)B * N * (nl + beta * R + 2 * next + 2 * nl);
-}
+static void keyswitch_moddown(const fhe_ctx* ctx, uint32_t B, uint32_t nl, uint64_t* u, uint64_t* conv,
+                              const uint64_t* const* add, const uint32_t* galois, uint64_t* const* out,
+                              hipStream_t st);
 
-void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, uint64_t in_stride,
-               const uint64_t* const* keys, const uint64_t* const* add, uint64_t* const* out, uint64_t* ws,
-               hipStream_t st, const uint32_t* galois, const uint64_t* const* in_ptrs) {
-  if (!B) return;
-  if (in_ptrs && !galois) fail(FHE_EINVAL, "key switch input pointers need their Galois elements");
+// Steps 1-3 of the key switch for B inputs (contiguous `in` with in_stride, or in_ptrs read through
+// galois): INTT into dcoef, ModUp of every digit, column phase of the extended rows into ext
+// ([beta][B][R][N], raw form).
+static void keyswitch_modup(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, uint64_t in_stride,
+                            const uint64_t* const* in_ptrs, const uint32_t* galois, uint64_t* dcoef, uint64_t* ext,
+                            hipStream_t st) {
   const Params& p = ctx->p;
-  if (p.alpha > kMaxAlpha || p.np > kMaxK) fail(FHE_EINVAL, "alpha or n_p above kernel limits");
-  if (nl < 1 || nl > (uint32_t)p.nq) fail(FHE_ESHAPE, "key switch level out of range");
-  prof_count("keyswitch", B);
   const uint32_t N = p.N, K = p.np, next = nl + K, beta = p.beta(nl), alpha = p.alpha;
   const uint32_t R = modup_rows(p, nl), cnt_last = nl - (beta - 1) * alpha;
   const uint32_t beta_full = cnt_last == alpha ? beta : beta - 1;
   const double e8 = 8.0 * N * B;
-  uint64_t* dcoef = ws;                                 // [B][nl][N]
-  uint64_t* ext = dcoef + (size_t)B * nl * N;           // [beta][B][R][N]
-  uint64_t* u = ext + (size_t)beta * B * R * N;         // [B][2][next][N]
-  uint64_t* conv = u + (size_t)B * 2 * next * N;        // [B][2][nl][N]
   // 1. INTT of the input into dcoef (the NTT-domain input is kept for the digits' own limbs).
   LimbBatch lb_in{dcoef, nl, B, (uint64_t)nl * N, nl, 0};
   lb_in.src = in;
@@ -1592,6 +1692,30 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
       ntt_forward_cols(ctx, lb, st);
     }
   }
+}
+
+size_t keyswitch_ws_elems(const fhe_ctx* ctx, uint32_t B, uint32_t nl) {
+  const Params& p = ctx->p;
+  const size_t N = p.N, next = nl + p.np, beta = p.beta(nl), R = modup_rows(p, nl);
+  return (size_t)B * N * (nl + beta * R + 2 * next + 2 * nl);
+}
+
+void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, uint64_t in_stride,
+               const uint64_t* const* keys, const uint64_t* const* add, uint64_t* const* out, uint64_t* ws,
+               hipStream_t st, const uint32_t* galois, const uint64_t* const* in_ptrs) {
+  if (!B) return;
+  if (in_ptrs && !galois) fail(FHE_EINVAL, "key switch input pointers need their Galois elements");
+  const Params& p = ctx->p;
+  if (p.alpha > kMaxAlpha || p.np > kMaxK) fail(FHE_EINVAL, "alpha or n_p above kernel limits");
+  if (nl < 1 || nl > (uint32_t)p.nq) fail(FHE_ESHAPE, "key switch level out of range");
+  prof_count("keyswitch", B);
+  const uint32_t N = p.N, K = p.np, next = nl + K, beta = p.beta(nl), alpha = p.alpha;
+  const uint32_t R = modup_rows(p, nl);
+  uint64_t* dcoef = ws;                                 // [B][nl][N]
+  uint64_t* ext = dcoef + (size_t)B * nl * N;           // [beta][B][R][N]
+  uint64_t* u = ext + (size_t)beta * B * R * N;         // [B][2][next][N]
+  uint64_t* conv = u + (size_t)B * 2 * next * N;        // [B][2][nl][N]
+  keyswitch_modup(ctx, B, nl, in, in_stride, in_ptrs, galois, dcoef, ext, st);
   // 4. Row phase fused with the key inner product (Q limbs on the FP64 path, P limbs on the integer path).
   const size_t lds = kNttLdsElems * sizeof(uint64_t);
   const uint32_t tiles = N >> kNttLogE;
@@ -1611,6 +1735,58 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
   FHE_LAUNCH_T("ntt_p2_inner_p", ib * K, (k_ntt_p2_inner<IntArith, false>), (uint64_t)B * K * tiles, kInnerThreads, lds,
                st, B, nl, K, (uint32_t)p.nq, alpha, R, nl, K, p.logN, p.k1, mods_of(ctx), ctx->t.tw.u64(), in,
                in_stride, nullptr, nullptr, ext, keys, u);
+  keyswitch_moddown(ctx, B, nl, u, conv, add, galois, out, st);
+}
+
+void keyswitch_hoisted(const fhe_ctx* ctx, uint32_t S, uint32_t B, uint32_t nl, const uint64_t* const* state_c1,
+                       const uint32_t* ident, const uint32_t* state_of, const uint64_t* const* in_ptrs,
+                       const uint32_t* galois, const uint64_t* const* keys, const uint64_t* const* add,
+                       uint64_t* const* out, uint64_t* ws, hipStream_t st) {
+  if (!B) return;
+  const Params& p = ctx->p;
+  if (S < 1 || S > B) fail(FHE_EINVAL, "hoisted key switch needs 1 <= S <= B polynomials");
+  if (p.alpha > kMaxAlpha || p.np > kMaxK) fail(FHE_EINVAL, "alpha or n_p above kernel limits");
+  if (nl < 1 || nl > (uint32_t)p.nq) fail(FHE_ESHAPE, "key switch level out of range");
+  prof_count("keyswitch", B);
+  const uint32_t N = p.N, K = p.np, next = nl + K, beta = p.beta(nl), alpha = p.alpha;
+  const uint32_t R = modup_rows(p, nl), cnt_last = nl - (beta - 1) * alpha;
+  uint64_t* dcoef = ws;                                 // [S][nl][N] within the B-item layout
+  uint64_t* ext = dcoef + (size_t)B * nl * N;           // [beta][S][R][N]
+  uint64_t* u = ext + (size_t)beta * B * R * N;         // [B][2][next][N]
+  uint64_t* conv = u + (size_t)B * 2 * next * N;        // [B][2][nl][N]
+  // ModUp of every polynomial once (no automorphism), then the row phase of its digits in place
+  keyswitch_modup(ctx, S, nl, nullptr, 0, state_c1, ident, dcoef, ext, st);
+  const size_t lds = kNttLdsElems * sizeof(uint64_t);
+  const uint32_t tiles = N >> kNttLogE, qrows = nl - cnt_last;
+  const double* twf = (const double*)ctx->t.twf.get();
+  const double e8s = 8.0 * N * S;
+  if (qrows)
+    FHE_LAUNCH_T("ext_rows_q", 16.0 * N * S * beta * qrows, (k_ext_rows<FpArith, true>),
+                 (uint64_t)beta * S * qrows * tiles, kInnerThreads, lds, st, S, nl, K, (uint32_t)p.nq, alpha, R, qrows,
+                 p.logN, p.k1, mods_of(ctx), twf, ext);
+  FHE_LAUNCH_T("ext_rows_p", 2.0 * e8s * beta * K, (k_ext_rows<IntArith, false>), (uint64_t)beta * S * K * tiles,
+               kInnerThreads, lds, st, S, nl, K, (uint32_t)p.nq, alpha, R, K, p.logN, p.k1, mods_of(ctx),
+               ctx->t.tw.u64(), ext);
+  // every rotation: the inner product through its automorphism, then ModDown as usual
+  const uint32_t htiles = N / (kThreads * 8);
+  const double ib = 8.0 * N * (double)B * (3.0 * beta + 2.0);
+  FHE_LAUNCH("hoisted_inner_q", ib * nl, k_hoisted_inner<FpArith>, (uint64_t)B * nl * htiles, 0, st, B, S, nl, K,
+             (uint32_t)p.nq, alpha, R, 0u, nl, p.logN, mods_of(ctx), state_of, galois, in_ptrs, ext, keys, u);
+  FHE_LAUNCH("hoisted_inner_p", ib * K, k_hoisted_inner<IntArith>, (uint64_t)B * K * htiles, 0, st, B, S, nl, K,
+             (uint32_t)p.nq, alpha, R, nl, K, p.logN, mods_of(ctx), state_of, galois, in_ptrs, ext, keys, u);
+  keyswitch_moddown(ctx, B, nl, u, conv, add, galois, out, st);
+}
+
+// ModDown of the inner products u ([B][2][next][N]) into out, plus the addends (see keyswitch).
+static void keyswitch_moddown(const fhe_ctx* ctx, uint32_t B, uint32_t nl, uint64_t* u, uint64_t* conv,
+                              const uint64_t* const* add, const uint32_t* galois, uint64_t* const* out,
+                              hipStream_t st) {
+  const Params& p = ctx->p;
+  const uint32_t N = p.N, K = p.np, next = nl + K;
+  const double e8 = 8.0 * N * B;
+  const size_t lds = kNttLdsElems * sizeof(uint64_t);
+  const uint32_t tiles = N >> kNttLogE;
+  const double* twf = (const double*)ctx->t.twf.get();
   // 5. ModDown: INTT of the P limbs, conversion to Q_l, column phase, row phase fused with the combine.
   const LimbBatch lb_up{u + (size_t)nl * N, K, 2 * B, (uint64_t)next * N, 0, (uint32_t)p.nq};
   if (cols_fusable(ctx, K)) {

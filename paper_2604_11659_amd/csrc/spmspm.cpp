@@ -216,6 +216,51 @@ void enqueue_rotation(fhe_ctx* ctx, ArgPack& ap, std::vector<std::function<void(
   });
 }
 
+// Hoisted rotation step: src[b] -> out[b] rotated left by steps[b]; the items that rotate the same
+// src share its ModUp (one per distinct src) and read its transformed digits through their
+// automorphisms (keyswitch_hoisted). out[b] must be disjoint from every src.
+void enqueue_rotation_hoisted(fhe_ctx* ctx, ArgPack& ap, std::vector<std::function<void()>>& ops, uint32_t nl,
+                              const std::vector<const uint64_t*>& src_in, const std::vector<uint32_t>& steps_in,
+                              const std::vector<uint64_t*>& out_in, const Workspace& ws, hipStream_t st) {
+  const Params& p = ctx->p;
+  const uint32_t N = p.N, B = (uint32_t)src_in.size();
+  if (!B) return;
+  std::vector<uint32_t> ord(B);
+  for (uint32_t b = 0; b < B; ++b) ord[b] = b;
+  std::stable_sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) { return steps_in[x] < steps_in[y]; });
+  std::unordered_map<const uint64_t*, uint32_t> sid;
+  std::vector<const uint64_t*> state_c1, in_ptrs(B), keys(B), add(2 * B);
+  std::vector<uint32_t> state_of(B), gal(B);
+  std::vector<uint64_t*> out(B);
+  for (uint32_t b = 0; b < B; ++b) {
+    const uint32_t o = ord[b];
+    const uint64_t* src = src_in[o];
+    auto it = sid.find(src);
+    if (it == sid.end()) {
+      it = sid.emplace(src, (uint32_t)state_c1.size()).first;
+      state_c1.push_back(src + (size_t)nl * N);
+    }
+    state_of[b] = it->second;
+    in_ptrs[b] = state_c1[it->second];
+    gal[b] = galois_of_step(p, steps_in[o]);
+    keys[b] = rotation_key(ctx, steps_in[o])->buf.u64();
+    add[2 * b] = src;  // component 0, read through the automorphism by the final combine
+    add[2 * b + 1] = nullptr;
+    out[b] = out_in[o];
+  }
+  for (uint64_t* q : out)
+    if (sid.count(q)) fail(FHE_EINVAL, "hoisted rotation output overlaps an input");
+  const uint32_t S = (uint32_t)state_c1.size();
+  const std::vector<uint32_t> ident(S, 1u);
+  const size_t o_c1 = ap.push(state_c1), o_id = ap.push(ident), o_so = ap.push(state_of), o_in = ap.push(in_ptrs),
+               o_g = ap.push(gal), o_k = ap.push(keys), o_a = ap.push(add), o_o = ap.push(out);
+  ops.push_back([=, &ap] {
+    keyswitch_hoisted(ctx, S, B, nl, ap.at<const uint64_t*>(o_c1), ap.at<uint32_t>(o_id), ap.at<uint32_t>(o_so),
+                      ap.at<const uint64_t*>(o_in), ap.at<uint32_t>(o_g), ap.at<const uint64_t*>(o_k),
+                      ap.at<const uint64_t*>(o_a), ap.at<uint64_t*>(o_o), ws.ksws, st);
+  });
+}
+
 }  // namespace
 
 void index_plan(Plan& plan) {
@@ -251,13 +296,14 @@ void prepare_result(fhe_ctx* ctx, Job& J, hipStream_t st) {
   HIPCHECK(hipMemsetAsync(C->data.get(), 0, (size_t)J.plan.nres * chunk_elems * 8, st));
 }
 
-void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool grouped, bool graph, bool tree) {
+void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool grouped, bool graph, bool tree,
+                  bool hoist) {
   std::vector<Slice> slices;
   for (auto& J : jobs) {
     prepare_result(ctx, J, st);
     slices.push_back(Slice{&J, 0, (int32_t)J.plan.prods.size()});
   }
-  execute_slices(ctx, slices, st, grouped, graph, tree);
+  execute_slices(ctx, slices, st, grouped, graph, tree, hoist);
 }
 
 GraphEntry::~GraphEntry() {
@@ -301,7 +347,7 @@ struct Runner {
 // EvalMult -> Relinearize -> Rescale of the products ids[k] (after their alignment rotations) into
 // ws.prod slot k, [2][nq - 1][N] each.
 void enqueue_products(fhe_ctx* ctx, ArgPack& ap, Ops& ops, const Plan& plan, const std::vector<const Job*>& job_of,
-                      const int32_t* ids, size_t npb, const Workspace& ws, hipStream_t st,
+                      const int32_t* ids, size_t npb, const Workspace& ws, hipStream_t st, bool hoist,
                       uint64_t* const* dest = nullptr) {
   const Params& p = ctx->p;
   const uint32_t N = p.N, nq = p.nq, nl1 = nq - 1;
@@ -354,7 +400,10 @@ void enqueue_products(fhe_ctx* ctx, ArgPack& ap, Ops& ops, const Plan& plan, con
       }
       new_slot[k] = it->second;
     }
-    enqueue_rotation(ctx, ap, ops, nq, src, st_amt, out, ws, st, true);
+    if (hoist)
+      enqueue_rotation_hoisted(ctx, ap, ops, nq, src, st_amt, out, ws, st);
+    else
+      enqueue_rotation(ctx, ap, ops, nq, src, st_amt, out, ws, st, true);
     for (size_t k = 0; k < npb; ++k) {
       if (new_slot[k] == -2) continue;
       if (slot_of[k] >= 0) --refs[slot_of[k]];
@@ -476,7 +525,7 @@ size_t group_budget_bytes() {
 // launch straight into the tail's input buffer. When all products do not fit the group budget, the
 // groups run in passes, each recomputing the products its pairs use.
 void execute_grouped(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job*>& job_of, const Workspace& ws,
-                     size_t PB, size_t BB, uint64_t* const* res, Runner& run, DevBuf& gbuf, bool tree) {
+                     size_t PB, size_t BB, uint64_t* const* res, Runner& run, DevBuf& gbuf, bool tree, bool hoist) {
   const hipStream_t st = run.ls;
   const Params& p = ctx->p;
   const uint32_t N = p.N, nl1 = p.nq - 1;
@@ -597,7 +646,7 @@ void execute_grouped(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job
       for (size_t k = 0; k < npb; ++k) dest[k] = store + (size_t)slot[order[b0 + k]] * pe;
       ArgPack& ap = run.pack();
       Ops ops;
-      enqueue_products(ctx, ap, ops, plan, job_of, order.data() + b0, npb, ws, st, dest.data());
+      enqueue_products(ctx, ap, ops, plan, job_of, order.data() + b0, npb, ws, st, hoist, dest.data());
       run.submit(ap, ops);
     }
     // groups of the pass in tail batches: masked sums into the mask buffer, then the tail
@@ -693,11 +742,12 @@ void execute_grouped(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job
 }
 
 void run_per_pair(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job*>& job_of, const Workspace& ws,
-                  size_t PB, size_t BB, uint64_t* const* res, Runner& run);
+                  size_t PB, size_t BB, uint64_t* const* res, Runner& run, bool hoist);
 
 }  // namespace
 
-void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bool grouped, bool graph, bool tree) {
+void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bool grouped, bool graph, bool tree,
+                    bool hoist) {
   grouped = grouped || tree;
   const Params& p = ctx->p;
   const uint32_t N = p.N, nq = p.nq, nl1 = nq - 1, nl2 = nq - 2;
@@ -729,7 +779,7 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bo
     return;
   }
   // A captured launch stream for these operands, ranges, plan mode and NTT split, on this scratch.
-  std::vector<uint64_t> key{tree ? 2u : grouped ? 1u : 0u, p.k1, slices.size()};
+  std::vector<uint64_t> key{(tree ? 2u : grouped ? 1u : 0u) | (hoist ? 4u : 0u), p.k1, slices.size()};
   for (auto& sl : slices)
     for (uint64_t v : {sl.job->A->id, sl.job->B->id, (uint64_t)sl.job->pair_lo, (uint64_t)sl.job->pair_hi,
                        (uint64_t)sl.lo, (uint64_t)sl.hi})
@@ -800,9 +850,9 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bo
   Runner run{ls, graph, graph ? entry->packs : local_packs, {}};
   DevBuf& gbuf = graph ? entry->gbuf : local_gbuf;
   if (grouped) {
-    execute_grouped(ctx, plan, job_of, ws, PB, BB, res, run, gbuf, tree);
+    execute_grouped(ctx, plan, job_of, ws, PB, BB, res, run, gbuf, tree, hoist);
   } else {
-    run_per_pair(ctx, plan, job_of, ws, PB, BB, res, run);
+    run_per_pair(ctx, plan, job_of, ws, PB, BB, res, run, hoist);
   }
   if (!graph) {
     HIPCHECK(hipStreamSynchronize(st));
@@ -852,7 +902,7 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bo
 namespace {
 
 void run_per_pair(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job*>& job_of, const Workspace& ws,
-                  size_t PB, size_t BB, uint64_t* const* res, Runner& run) {
+                  size_t PB, size_t BB, uint64_t* const* res, Runner& run, bool hoist) {
   const Params& p = ctx->p;
   const uint32_t N = p.N, nl1 = p.nq - 1;
   const hipStream_t st = run.ls;
@@ -865,7 +915,7 @@ void run_per_pair(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job*>&
     const size_t p1 = std::min(nprod, p0 + PB), npb = p1 - p0;
     ArgPack& ap = run.pack();
     Ops ops;
-    enqueue_products(ctx, ap, ops, plan, job_of, ids.data() + p0, npb, ws, st);
+    enqueue_products(ctx, ap, ops, plan, job_of, ids.data() + p0, npb, ws, st, hoist);
     // (3) Pairs of these products: mask, rescale, target rotation, accumulate.
     std::vector<uint32_t> pairs(by_prod.begin() + first[p0], by_prod.begin() + first[p1]);
     std::stable_sort(pairs.begin(), pairs.end(), [&](uint32_t x, uint32_t y) {

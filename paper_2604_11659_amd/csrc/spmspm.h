@@ -60,8 +60,9 @@ struct Job {
 // between replays (rewritten before each launch, outside the graph).
 // tree (implies grouped): the groups' target rotations are shared digit by digit (level t rotates
 // the partial sums of equal (chunk, digits above t) once by digit t).
+// hoist: the alignment rotation steps share the ModUp of their input (keyswitch_hoisted).
 void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool grouped = false, bool graph = false,
-                  bool tree = false);
+                  bool tree = false, bool hoist = false);
 
 // A captured matmul launch stream and everything its kernels read that is not an operand or key.
 struct GraphEntry {
@@ -86,7 +87,7 @@ struct Slice {
 };
 void prepare_result(fhe_ctx* ctx, Job& J, hipStream_t st);
 void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bool grouped = false,
-                    bool graph = false, bool tree = false);
+                    bool graph = false, bool tree = false, bool hoist = false);
 
 // Counts of key-switch work in the plan: [F, products, align KS, relin KS, target KS, result chunks].
 void plan_counts(const Params& p, const Plan& plan, int64_t out[6]);

@@ -290,18 +290,19 @@ class Context(_Handle):
         return self._encrypt(_lib.fhe_encrypt_csc, sk, rows, cols, indptr, indices, values, seed, stream)
 
     def spmspm(self, A: Matrix, B: Matrix, stream=None, grouped: bool = False, graph: bool = False,
-               tree: bool = False) -> Matrix:
+               tree: bool = False, hoist: bool = False) -> Matrix:
         """C = A B. grouped: pairs sharing (result chunk, target rotation) share one second rescale
         and one target rotation (FHE_PLAN_GROUPED); tree: grouped, with the target rotations shared
-        digit by digit (FHE_PLAN_TREE). graph: record / replay the call as a HIP graph."""
-        if grouped or graph or tree:
-            return self.spmspm_batch([A], [B], stream, grouped=grouped, graph=graph, tree=tree)[0]
+        digit by digit (FHE_PLAN_TREE). graph: record / replay the call as a HIP graph. hoist: hoisted
+        alignment rotations (FHE_PLAN_HOIST)."""
+        if grouped or graph or tree or hoist:
+            return self.spmspm_batch([A], [B], stream, grouped=grouped, graph=graph, tree=tree, hoist=hoist)[0]
         out = c_vp()
         _check(_lib.fhe_spmspm(self._ptr, A._ptr, B._ptr, _stream(stream), ctypes.byref(out)))
         return Matrix(out.value, self)
 
     def spmspm_batch(self, As, Bs, stream=None, pair_ranges=None, grouped: bool = False,
-                     graph: bool = False, tree: bool = False) -> list:
+                     graph: bool = False, tree: bool = False, hoist: bool = False) -> list:
         """[A_i B_i] in one merged launch stream (bit-identical to one-at-a-time spmspm).
 
         pair_ranges: optional [(begin, end)] per matmul, restricting each to those matched pairs.
@@ -320,14 +321,16 @@ class Context(_Handle):
             hi = np.asarray([r[1] for r in pair_ranges] or [0], np.int64)
         _check(_lib.fhe_spmspm_plan(self._ptr, n, ctypes.cast(pa, PP), ctypes.cast(pb, PP),
                                     None if lo is None else _ptr(lo, c_i64), None if hi is None else _ptr(hi, c_i64),
-                                    (2 if tree else 1 if grouped else 0) | (256 if graph else 0), _stream(stream),
+                                    (2 if tree else 1 if grouped else 0) | (256 if graph else 0) | (512 if hoist else 0),
+                                    _stream(stream),
                                     ctypes.cast(out, PP)))
         return [Matrix(out[i], self) for i in range(n)]
 
     def spmspm_pairs(self, A: Matrix, B: Matrix, begin: int, end: int, stream=None, grouped: bool = False,
-                     tree: bool = False) -> Matrix:
-        if grouped or tree:
-            return self.spmspm_batch([A], [B], stream, pair_ranges=[(begin, end)], grouped=grouped, tree=tree)[0]
+                     tree: bool = False, hoist: bool = False) -> Matrix:
+        if grouped or tree or hoist:
+            return self.spmspm_batch([A], [B], stream, pair_ranges=[(begin, end)], grouped=grouped, tree=tree,
+                                     hoist=hoist)[0]
         out = c_vp()
         _check(_lib.fhe_spmspm_pairs(self._ptr, A._ptr, B._ptr, begin, end, _stream(stream), ctypes.byref(out)))
         return Matrix(out.value, self)

@@ -198,3 +198,28 @@ def test_large_workload_sampled_pairs_bit_exact():
             assert (ctx.export(Cs, c) == r.data).all(), (lo, hi, c)
         Cs.close()
     ctx.close()
+
+
+@pytest.mark.timeout(1200)
+def test_dnn_layer_hoisted_window_bit_exact():
+    """Hoisted alignment rotations at the DNN layer's size: a traversal window (its products rotate
+    operand chunks by several amounts) bit-exact against the oracle's hoisted plan, per pair and with
+    the digit tree; the full layer decrypts within 1e-5 with both."""
+    w = synth.WORKLOADS["dnn"]
+    _say("[full] dnn hoisted setup")
+    a, b, ctx, sk, A, B, op, keys, OA, OB = _prepare(w)
+    pairs = spmspm.matched_pairs(w.m, w.n, OA.indptr, OA.indices, OB.indptr, OB.indices)
+    lo, hi = _merged_window(op, pairs, w.n, 24)
+    for tree in (False, True):
+        _say(f"[full] dnn hoisted tree={tree} pairs [{lo}, {hi}) gpu")
+        Cs = ctx.spmspm_pairs(A, B, lo, hi, tree=tree, hoist=True)
+        _say(f"[full] dnn hoisted tree={tree} oracle")
+        ref = spmspm.spmspm(op, keys, OA, OB, workers=WORKERS, pairs=pairs[lo:hi], tree=tree, hoist=True)
+        assert (ctx.export(Cs, 0) == ref[0].data).all(), (tree, lo, hi)
+        Cs.close()
+        _say(f"[full] dnn hoisted tree={tree} full layer")
+        C = ctx.spmspm(A, B, tree=tree, hoist=True)
+        err = np.abs(ctx.decrypt_decode(sk, C) - a @ b).max()
+        _say(f"[full] dnn hoisted tree={tree} max-abs error {err:.3e}")
+        assert err < 1e-5
+        C.close()
