@@ -409,6 +409,8 @@ def main():
     ap.add_argument("--plan", default="per_pair", choices=["per_pair", "grouped", "tree"],
                     help="plan of the timed steps: Algorithm 2 per matched pair, grouped target rotations, or "
                          "grouped with digit-shared rotations (then the other legs are skipped)")
+    ap.add_argument("--hoist", action="store_true",
+                    help="hoisted alignment rotations in the timed steps (changes the limbs: its own oracle mode)")
     ap.add_argument("--graph-steps", type=int, default=2,
                     help="also time this many replays of the per-pair plan recorded as one HIP graph (0 = skip)")
     ap.add_argument("--tree-steps", type=int, default=2,
@@ -471,11 +473,11 @@ def main():
     log(f"setup {setup_s:.1f} s; plan {st}")
 
     grouped, tree = args.plan in ("grouped", "tree"), args.plan == "tree"
-    if grouped:
+    if grouped or args.hoist:
         args.graph_steps = args.grouped_steps = args.tree_steps = 0
     C = None
     for _ in range(args.warmup):
-        C = ctx.spmspm(A, B, grouped=grouped, tree=tree)
+        C = ctx.spmspm(A, B, grouped=grouped, tree=tree, hoist=args.hoist)
         C.close()
         log("warmup step done")
     torch.cuda.synchronize()
@@ -484,7 +486,7 @@ def main():
     for _ in range(args.steps):
         if C is not None:
             C.close()
-        C = ctx.spmspm(A, B, grouped=grouped, tree=tree)
+        C = ctx.spmspm(A, B, grouped=grouped, tree=tree, hoist=args.hoist)
         log(f"timed step done at {time.perf_counter() - t0:.2f} s")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -507,7 +509,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": describe(w),
                    "plan": ("grouped target rotations, shared digit by digit" if tree else
-                            "grouped target rotations" if grouped else "per matched pair"),
+                            "grouped target rotations" if grouped else "per matched pair") +
+                           (", hoisted alignment rotations" if args.hoist else ""),
                    "matched_pairs": st.matched_pairs, "products": st.products,
                    "keyswitches": st.keyswitches, "parallelism": "single GPU, batched launches",
                    "ntt_split_autotuned": tuned},
