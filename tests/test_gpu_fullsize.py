@@ -56,6 +56,7 @@ def test_plain_16x16_full_bit_exact():
     err = np.abs(ctx.decrypt_decode(sk, C) - a @ b).max()
     assert err < 1e-5
     _say(f"[full] plain ok, max-abs error {err:.3e}")
+    ctx.close()
 
 
 @pytest.mark.timeout(1200)
@@ -78,6 +79,7 @@ def test_dnn_layer_full_fp64_and_sampled_bit_exact():
         _say(f"[full] dnn pairs [{lo}, {hi}) oracle")
         ref = spmspm.spmspm(op, keys, OA, OB, workers=WORKERS, pairs=pairs[lo:hi])
         assert (ctx.export(Cs, 0) == ref[0].data).all(), (lo, hi)
+    ctx.close()
 
 
 def _merged_window(op, pairs, n, width):
@@ -113,6 +115,7 @@ def test_dnn_layer_grouped_full_fp64_and_sampled_bit_exact():
     _say(f"[full] dnn grouped pairs [{lo}, {hi}) oracle")
     ref = spmspm.spmspm(op, keys, OA, OB, workers=WORKERS, pairs=pairs[lo:hi], grouped=True)
     assert (ctx.export(Cs, 0) == ref[0].data).all(), (lo, hi)
+    ctx.close()
 
 
 @pytest.mark.timeout(1200)
@@ -139,6 +142,8 @@ def test_dnn_layer_tree_full_fp64_and_sampled_bit_exact():
 
 
 # ---- the larger parameter sets (N = 2^16 with 24 Q + 3 P primes, N = 2^17 with 35 Q + 3 P) ----
+    ctx.close()
+
 
 def _ctx_pair(prm):
     from paper_2604_11659_amd import fhe
@@ -223,3 +228,4 @@ def test_dnn_layer_hoisted_window_bit_exact():
         _say(f"[full] dnn hoisted tree={tree} max-abs error {err:.3e}")
         assert err < 1e-5
         C.close()
+    ctx.close()
