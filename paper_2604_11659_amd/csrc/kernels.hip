@@ -772,11 +772,7 @@ __global__ __launch_bounds__(kThreads) void k_moddown_conv(uint32_t B, uint32_t 
 }
 
 // Column-phase tiles of 2^LOG_E elements: 2^k1 rows (stride 2^(logN - k1)) by C = 2^(LOG_E - k1)
-// adjacent columns; `col_index` maps a tile slot to its coefficient index.
-__device__ __forceinline__ uint32_t col_index(uint32_t idx, uint32_t logC, uint32_t k2, uint32_t tile) {
-  return ((idx >> logC) << k2) + (tile << logC) + (idx & ((1u << logC) - 1));
-}
-
+// adjacent columns.
 // Column-phase slots owned by one wavefront in the fused column kernels: wavefront w owns columns
 // [w Cw, (w + 1) Cw) of the tile (Cw = C / waves) in every row; lane l handles slots l + 64 r.
 // Returns the LDS index of slot s; *g receives its coefficient index.
@@ -1597,12 +1593,6 @@ static size_t max_lds_per_block(int device) {
     cached[device] = (size_t)v;
   }
   return cached[device];
-}
-
-// Opts a kernel into more than 64 KiB of dynamic LDS (once per kernel and size class).
-static void allow_lds(const void* kern, size_t bytes) {
-  if (bytes <= 65536) return;
-  HIPCHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
 
 // The fused column kernels keep at most 4 digit limbs / special primes in registers and are
