@@ -258,14 +258,15 @@ def run_serve(args) -> dict:
         B = ctxs[ci].encrypt_csc(sks[ci], n, n, *synth.to_csc(b), seed=40_000 + i)
         return ci, A, B, a @ b
 
+    tree = args.serve_plan == "tree_hoist"
     # capacity: a few requests of each parameter set alone
     svc = []
     for i in range(2 * len(ctxs)):
         ci, A, B, _ = make(i)
-        ctxs[ci].spmspm(A, B).close()  # first call per context allocates its workspace
+        ctxs[ci].spmspm(A, B, tree=tree, hoist=tree).close()  # first call per context allocates its workspace
         torch.cuda.synchronize()
         t = time.perf_counter()
-        ctxs[ci].spmspm(A, B).close()
+        ctxs[ci].spmspm(A, B, tree=tree, hoist=tree).close()
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - t)
     t_req = float(np.mean(svc))
@@ -276,7 +277,7 @@ def run_serve(args) -> dict:
         arrivals = synth.poisson_arrivals(rate, window_s, seed)
         reqs = [make(1000 * seed + i) for i in range(len(arrivals))]
         srvs = [fhe.Server(c, hbm_budget=args.serve_budget_gb << 30, max_inflight=8, slice_products=32,
-                           max_queue=4096) for c in ctxs]
+                           max_queue=4096, tree=tree, hoist=tree) for c in ctxs]
         tickets = []
         torch.cuda.synchronize()
         start = time.perf_counter()
@@ -320,6 +321,8 @@ def run_serve(args) -> dict:
         "config": {"workload": (f"serve: Poisson arrivals, square sizes {sizes}, per-operand sparsity U[0.70, 0.95], "
                                 f"values U[-1,1], parameter sets (log_n, n_q, n_p, alpha, digits) {params} "
                                 f"alternating; keys and operands resident"),
+                   "plan": ("grouped target rotations shared digit by digit, hoisted alignment rotations "
+                            "(each request whole in a step)" if tree else "per matched pair"),
                    "capacity_req_per_s_alone": round(1.0 / t_req, 4)},
         "steady": steady, "overload": over,
     }
@@ -407,6 +410,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=20.0, help="overload phase arrival rate (req/s)")
     ap.add_argument("--serve-overload-s", type=float, default=3.0)
     ap.add_argument("--serve-budget-gb", type=int, default=16)
+    ap.add_argument("--serve-plan", default="per_pair", choices=["per_pair", "tree_hoist"],
+                    help="plan of the served requests")
     ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle pairs to time (0 = skip, -1 = one per core)")
     ap.add_argument("--kernels-out", default=None, help="write per-kernel timings (JSON) here")
     ap.add_argument("--plan", default="per_pair", choices=["per_pair", "grouped", "tree"],

@@ -268,12 +268,19 @@ typedef struct fhe_server fhe_server;
 int fhe_server_create(fhe_ctx* ctx, size_t hbm_budget, int32_t max_inflight, int32_t slice_products,
                       int32_t max_queue, fhe_server** out);
 
+/* Plan mode of the server's requests (FHE_PLAN_PER_PAIR, FHE_PLAN_GROUPED or FHE_PLAN_TREE, optionally
+ * or-ed with FHE_PLAN_HOIST; not FHE_PLAN_GRAPH). Grouped and tree plans run every request as one
+ * slice (all of its products in one step, merged with the other requests of that step); each result
+ * is bit-identical to fhe_spmspm_plan in the same mode. Only before the first submission: FHE_EAGAIN
+ * afterwards; FHE_EINVAL for an unknown mode. */
+int fhe_server_set_plan(fhe_server* s, int32_t mode);
+
 /* Queues C = A B (A: CSR handle, B: CSC handle; both must stay alive until the request is polled).
  * Returns a ticket. Errors: FHE_EAGAIN (queue full), FHE_EINVAL, FHE_ESHAPE. */
 int fhe_server_submit(fhe_server* s, const fhe_mat* A, const fhe_mat* B, uint64_t* ticket);
 
 /* Waits up to wait_ms for the ticket. FHE_OK: *C_out receives the result (bit-identical to
- * fhe_spmspm on the same operands) and *latency_s the submit-to-completion time; the ticket is
+ * fhe_spmspm, or fhe_spmspm_plan in the server's plan mode, on the same operands) and *latency_s the submit-to-completion time; the ticket is
  * retired. FHE_EAGAIN: not finished yet. Other codes: the request failed (FHE_ENOMEM if its result
  * exceeds the whole budget, FHE_EKEY for a missing rotation key) and the ticket is retired. */
 int fhe_server_poll(fhe_server* s, uint64_t ticket, int32_t wait_ms, fhe_mat** C_out, double* latency_s);

@@ -6,7 +6,9 @@
 // scheduling step takes the next slice of products (with all their matched pairs) from every
 // request in flight and runs them as ONE merged launch stream, so requests that arrive while others
 // are running join the very next step and their work shares launches with the older ones. A request
-// completes when its last slice has been accumulated; its latency is submit -> completion.
+// completes when its last slice has been accumulated; its latency is submit -> completion. With a
+// grouped plan (fhe_server_set_plan) a request's slice is the whole request, since its groups span
+// all of its products; requests still join the next step and share its launches.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -41,6 +43,8 @@ struct fhe_server {
   size_t budget = 0;
   int max_inflight = 1;
   int slice_products = 64;
+  int plan_mode = FHE_PLAN_PER_PAIR;  // FHE_PLAN_* (grouped and tree plans run each request whole)
+  bool hoist = false;
   size_t max_queue = 1024;
   std::mutex mu;
   std::condition_variable cv, done_cv;
@@ -118,7 +122,8 @@ struct fhe_server {
         for (uint64_t t : active) {
           Req* r = reqs[t].get();
           const int32_t np = (int32_t)r->job.plan.prods.size();
-          const int32_t hi = std::min(np, r->next_prod + slice_products);
+          // grouped plans sum over all the pairs of a request at once: one slice per request
+          const int32_t hi = plan_mode == FHE_PLAN_PER_PAIR ? std::min(np, r->next_prod + slice_products) : np;
           slices.push_back(Slice{&r->job, r->next_prod, hi});
           in_step.push_back(r);
         }
@@ -127,7 +132,7 @@ struct fhe_server {
       int err = 0;
       std::string msg;
       try {
-        execute_slices(ctx, slices, stream);
+        execute_slices(ctx, slices, stream, plan_mode == FHE_PLAN_GROUPED, false, plan_mode == FHE_PLAN_TREE, hoist);
       } catch (const Error& e) {
         err = e.code;
         msg = e.msg;
@@ -164,6 +169,17 @@ int fhe_server_create(fhe_ctx* ctx, size_t hbm_budget, int32_t max_inflight, int
   fhe_server* raw = s.get();
   s->worker = std::thread([raw] { raw->run(); });
   *out = s.release();
+  return FHE_OK;
+}
+
+int fhe_server_set_plan(fhe_server* s, int32_t mode) {
+  if (!s) return FHE_EINVAL;
+  const int32_t plan = mode & ~FHE_PLAN_HOIST;
+  if (plan != FHE_PLAN_PER_PAIR && plan != FHE_PLAN_GROUPED && plan != FHE_PLAN_TREE) return FHE_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->next_ticket != 1) return FHE_EAGAIN;  // only before the first request
+  s->plan_mode = plan;
+  s->hoist = (mode & FHE_PLAN_HOIST) != 0;
   return FHE_OK;
 }
 

@@ -84,6 +84,7 @@ _SIGS = {
     "fhe_ct_free": ([c_vp], None),
     "fhe_server_create": ([c_vp, c_sz, c_i32, c_i32, c_i32, PP], c_i32),
     "fhe_server_submit": ([c_vp, c_vp, c_vp, ctypes.POINTER(c_u64)], c_i32),
+    "fhe_server_set_plan": ([c_vp, c_i32], c_i32),
     "fhe_server_poll": ([c_vp, c_u64, c_i32, PP, P_dbl], c_i32),
     "fhe_server_stats": ([c_vp, P_dbl, P_dbl, P_i64, P_i64, P_i64], c_i32),
     "fhe_server_free": ([c_vp], None),
@@ -431,12 +432,14 @@ class Server(_Handle):
     _free_fn = staticmethod(_lib.fhe_server_free)
 
     def __init__(self, ctx: Context, hbm_budget: int, max_inflight: int = 8, slice_products: int = 64,
-                 max_queue: int = 1024):
+                 max_queue: int = 1024, grouped: bool = False, tree: bool = False, hoist: bool = False):
         out = c_vp()
         _check(_lib.fhe_server_create(ctx._ptr, hbm_budget, max_inflight, slice_products, max_queue,
                                       ctypes.byref(out)))
         super().__init__(out.value, ctx)
         self._keep = {}
+        if grouped or tree or hoist:
+            _check(_lib.fhe_server_set_plan(self._ptr, (2 if tree else 1 if grouped else 0) | (512 if hoist else 0)))
 
     def submit(self, A: Matrix, B: Matrix) -> int:
         t = c_u64()

@@ -77,3 +77,27 @@ def test_budget_admission_and_rejection(env):
         srv.poll(t, wait_ms=60000)
     assert ei.value.code == -5
     srv.close()
+
+
+def test_mixed_arrivals_tree_hoisted_bit_identical(env):
+    """The request loop in the digit-tree plan with hoisted alignment rotations: every request runs
+    whole in a step shared with the others, and its result equals the standalone call in that mode."""
+    fhe, ctx, sk, reqs, alone = env
+    srv = fhe.Server(ctx, hbm_budget=1 << 34, max_inflight=4, tree=True, hoist=True)
+    _say("[serve] tree + hoisted, staggered submissions")
+    tickets = []
+    for i, (a, b, A, B) in enumerate(reqs):
+        tickets.append(srv.submit(A, B))
+        time.sleep(0.002 * i)
+    with pytest.raises(fhe.FheError):  # the plan is fixed once requests have been submitted
+        _lib_set = fhe._lib.fhe_server_set_plan
+        fhe._check(_lib_set(srv._ptr, 0))
+    for i, t in enumerate(tickets):
+        res = srv.poll(t, wait_ms=60000)
+        assert res is not None
+        C, _ = res
+        A, B = reqs[i][2], reqs[i][3]
+        ref = ctx.spmspm(A, B, tree=True, hoist=True)
+        assert all((ctx.export(C, c) == ctx.export(ref, c)).all() for c in range(C.info()["chunks"])), i
+        assert np.abs(ctx.decrypt_decode(sk, C) - reqs[i][0] @ reqs[i][1]).max() < 1e-5
+    srv.close()
