@@ -113,12 +113,16 @@ def run_batch(args) -> dict:
         As.append(ctx.encrypt_csr(sk, n, n, *synth.to_csr(a), seed=10_000 + i))
         Bs.append(ctx.encrypt_csc(sk, n, n, *synth.to_csc(b), seed=20_000 + i))
         F.append(ctx.plan_stats(As[-1], Bs[-1]).matched_pairs)
+        if w.rot_digits == 1:  # per-amount rotation keys for the amounts this plan uses
+            ctx.keygen_rotations(sk, ctx.plan_rotations(As[-1], Bs[-1]))
     setup_s = time.perf_counter() - t0
     ranges = [(0, min(f, args.batch_cap)) for f in F]
     pairs = sum(hi for _, hi in ranges)
     log(f"setup {setup_s:.1f} s; {len(specs)} matmuls, F total {sum(F)}, prefix pairs {pairs}")
-    # warm-up on a small prefix (workspace allocation, code objects)
-    for C in ctx.spmspm_batch(As[:2], Bs[:2], pair_ranges=[(0, min(8, f)) for f in F[:2]]):
+    # warm-up (workspace allocation, code objects): the whole batched call when it is small, else a
+    # small prefix of two matmuls
+    warm = ranges if pairs <= 50_000 else [(0, min(8, f)) for f in F[:2]]
+    for C in ctx.spmspm_batch(As[: len(warm)], Bs[: len(warm)], pair_ranges=warm):
         C.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -131,6 +135,19 @@ def run_batch(args) -> dict:
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     log(f"plain: {t_plain:.2f} s")
+    # the batched call recorded once as a HIP graph and replayed
+    t_graph = None
+    if args.batch_graph > 0 or (args.batch_graph < 0 and pairs <= 50_000):
+        for C in ctx.spmspm_batch(As, Bs, pair_ranges=ranges, graph=True):
+            C.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Cg = ctx.spmspm_batch(As, Bs, pair_ranges=ranges, graph=True)
+        torch.cuda.synchronize()
+        t_graph = time.perf_counter() - t0
+        log(f"batched, graph replay: {t_graph:.3f} s")
+        for C in Cg:
+            C.close()
     same = all((ctx.export(x, c) == ctx.export(y, c)).all()
                for x, y in list(zip(Cb, Cp))[:: max(1, len(Cb) // 8)] for c in range(x.info()["chunks"]))
     for C in Cb + Cp:
@@ -166,10 +183,12 @@ def run_batch(args) -> dict:
                                 f"digits={w.rot_digits}"),
                    "prefix_pairs_per_matmul": args.batch_cap, "pairs_run": pairs, "full_pairs": sum(F),
                    "parallelism": "single GPU"},
-        "projected": True,
+        "projected": pairs < sum(F),  # SpMSpM/s from a prefix of every plan
         "batched": {"pairs_per_s": round(pb, 1), "spmspm_per_s_projected": pb / mean_f, "s": round(t_batch, 3)},
         "plain": {"pairs_per_s": round(pp, 1), "spmspm_per_s_projected": pp / mean_f, "s": round(t_plain, 3)},
         "batched_over_plain": round(t_plain / t_batch, 3),
+        "batched_graph": None if t_graph is None else {"pairs_per_s": round(pairs / t_graph, 1), "s": round(t_graph, 4),
+                                                       "over_plain": round(t_plain / t_graph, 3)},
         "results_bit_identical": bool(same), "setup_s": round(setup_s, 1),
         "tree": tree,
     }
@@ -396,6 +415,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dnn", choices=sorted(synth.WORKLOADS) + sorted(synth.BATCH_WORKLOADS))
     ap.add_argument("--batch-cap", type=int, default=256, help="batching workload: matched pairs run per matmul")
+    ap.add_argument("--batch-graph", type=int, default=-1,
+                    help="batching workload: also time the batched call replayed as a HIP graph "
+                         "(-1: when the batch is small)")
     ap.add_argument("--batch-tree", type=int, default=1,
                     help="batching workload: also time the digit-tree plan with hoisted alignment rotations")
     ap.add_argument("--autotune", type=int, default=1, help="1: pick the NTT split by timing (untimed set-up)")

@@ -129,6 +129,10 @@ BATCH_WORKLOADS = {
     # 64 matmuls, square sizes from {32, 64, 128, 256}, per-operand sparsity U[0.5, 0.95], values
     # U[-1, 1]; N = 2^16, 24 x 50-bit Q primes, 3 x 60-bit P primes, alpha = 3, 3 rotation digits
     "batch": BatchWorkload("batch", 16, 24, 3, 3, 3, 64, (32, 64, 128, 256), (0.5, 0.95), 1),
+    # the same batch shape at the 16x16 workload's parameters: 64 matmuls of square size 8 or 16 at
+    # N = 2^13, 4 Q + 1 P primes, alpha = 1, per-amount rotation keys (small plans, where launches
+    # of one matmul do not fill the GPU)
+    "batch_small": BatchWorkload("batch_small", 13, 4, 1, 1, 1, 64, (8, 16), (0.5, 0.95), 1),
 }
 
 
