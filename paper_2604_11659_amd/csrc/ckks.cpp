@@ -163,7 +163,7 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
   ctx->t.modup = upload(mu, st);
 
   // ModDown constants.
-  std::vector<uint64_t> md(2 * K + 2 * (size_t)K * p.nq + 3 * (size_t)p.nq, 0);
+  std::vector<uint64_t> md(4 * K + 2 * (size_t)K * p.nq + 3 * (size_t)p.nq, 0);
   for (int kk = 0; kk < K; ++kk) {
     const uint64_t pk = p.moduli[p.nq + kk];
     uint64_t ph = 1;
@@ -172,6 +172,11 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
     const uint64_t inv = invmod_host(ph, pk);
     md[2 * kk] = inv;
     md[2 * kk + 1] = shoup_prep(inv, pk);
+    // the same factor times N^-1 (the fused kernel applies both after the inverse column phase)
+    const uint64_t inv_n = mulmod_host(inv, invmod_host((uint64_t)p.N % pk, pk), pk);
+    const size_t tail = 2 * K + 2 * (size_t)K * p.nq + 3 * (size_t)p.nq;
+    md[tail + 2 * kk] = inv_n;
+    md[tail + 2 * kk + 1] = shoup_prep(inv_n, pk);
     for (int i = 0; i < p.nq; ++i) {
       const uint64_t qi = p.moduli[i];
       uint64_t v = 1;

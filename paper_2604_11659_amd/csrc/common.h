@@ -94,7 +94,7 @@ struct Tables {
   DevBuf tw;       // per modulus: fwd[N][2] (w, shoup), inv[N][2] (w, shoup)
   DevBuf twf;      // per modulus (as double): fwd[N][2] (w, w / q), inv[N][2] (w, w / q)
   DevBuf modup;    // per (nl, digit): see modup_offset
-  DevBuf moddown;  // phat_inv[K][2], phat_mod_q[K][nq][2], pinv_mod_q[nq][2], p_mod_q[nq]
+  DevBuf moddown;  // phat_inv[K][2], phat_mod_q[K][nq][2], pinv_mod_q[nq][2], p_mod_q[nq], N^-1 phat_inv[K][2]
   DevBuf moddown_f;  // doubles [K][nq][4]: c0 = phat mod q_i, c0 / q_i, c1 = c0 2^30 mod q_i, c1 / q_i
   DevBuf rescale;  // ql_inv[l][i][2] = (q_l^-1 mod q_i, shoup), l < nq, i < l
   DevBuf mask;     // NTT of the base mask on limbs 0..nq-2, Montgomery form: [nq-1][N]

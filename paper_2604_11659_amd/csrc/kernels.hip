@@ -92,6 +92,16 @@ __device__ __forceinline__ double opaque(double x) {
   return x;
 }
 
+// Exact conversions between uint64 and double for integers in [0, 2^52): the double 2^52 + x has the
+// bits of x as its mantissa, so each direction is one FP64 add and one bit operation (the generic
+// 64-bit conversions take four to six instructions).
+__device__ __forceinline__ double u52_to_f64(uint64_t x) {
+  return __longlong_as_double((long long)(x | 0x4330000000000000ull)) - 0x1p52;
+}
+__device__ __forceinline__ uint64_t f64_to_u52(double x) {
+  return (uint64_t)__double_as_longlong(x + 0x1p52) & 0x000FFFFFFFFFFFFFull;
+}
+
 // Integer arithmetic for the special primes (p < 2^61, so 4p < 2^63), with lazy reduction in the
 // style of Harvey's NTT butterflies: forward butterflies keep values in [0, 4p) (the sum branch is
 // brought below 2p before use, the twiddle product is left in [0, 2p)), inverse butterflies keep
@@ -158,15 +168,15 @@ struct FpArith {
     q = (double)m.q;
     qinv = 1.0 / q;
   }
-  __device__ __forceinline__ uint64_t lds_in(uint64_t x) const { return __double_as_longlong((double)x); }
+  __device__ __forceinline__ uint64_t lds_in(uint64_t x) const { return __double_as_longlong(u52_to_f64(x)); }
   __device__ __forceinline__ uint64_t lds_out(uint64_t bits) const {
     const double x = __longlong_as_double((long long)bits);
-    return (uint64_t)(x < 0.0 ? x + q : x);
+    return f64_to_u52(x < 0.0 ? x + q : x);
   }
   __device__ __forceinline__ uint64_t raw(uint64_t bits) const { return bits; }  // internal form as is
   __device__ __forceinline__ T ld(uint64_t bits) const { return __longlong_as_double((long long)bits); }
   __device__ __forceinline__ uint64_t st(T x) const { return (uint64_t)__double_as_longlong(x); }
-  __device__ __forceinline__ T from_u64(uint64_t x) const { return (double)x; }
+  __device__ __forceinline__ T from_u64(uint64_t x) const { return u52_to_f64(x); }
   __device__ __forceinline__ T red(T x) const { return __fma_rn(-rint(x * qinv), q, x); }
   __device__ __forceinline__ T mulc(T a, W w, W wq) const {
     const double c = rint(a * wq);
@@ -198,7 +208,7 @@ struct FpArith {
   __device__ __forceinline__ void kred(Acc& acc) const { acc = red(acc); }
   __device__ __forceinline__ uint64_t kfinal(Acc acc) const {
     const double x = red(acc);
-    return (uint64_t)(x < 0.0 ? x + q : x);
+    return f64_to_u52(x < 0.0 ? x + q : x);
   }
 };
 
@@ -650,10 +660,10 @@ __global__ __launch_bounds__(NT) void k_ntt_p2_combine(uint32_t nl, uint32_t K, 
 #pragma unroll
   for (uint32_t r_ = 0; r_ < kPer; ++r_) {
     const uint32_t idx = wb + ln + r_ * 64;
-    double v = ar.mulc((double)uu[idx] - ar.ld(lds[pad_idx(idx)]), pv, pvq);
-    if (ad) v += (double)(galois ? ad[automorph_src(j0 + idx, gal, logN)] : ad[idx]);
+    double v = ar.mulc(u52_to_f64(uu[idx]) - ar.ld(lds[pad_idx(idx)]), pv, pvq);
+    if (ad) v += u52_to_f64(galois ? ad[automorph_src(j0 + idx, gal, logN)] : ad[idx]);
     v = ar.red(v);
-    o[idx] = (uint64_t)(v < 0.0 ? v + ar.q : v);
+    o[idx] = f64_to_u52(v < 0.0 ? v + ar.q : v);
   }
 }
 
@@ -811,7 +821,11 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
   double y[ALPHA][EPT];
 #pragma unroll
   for (uint32_t i = 0; i < ALPHA; ++i) {
-    if (i >= cnt) break;
+    if (i >= cnt) {  // a short last digit: zero terms (their constants are zero too)
+#pragma unroll
+      for (uint32_t r = 0; r < EPT; ++r) y[i][r] = 0.0;
+      continue;
+    }
     const ModInfo m = mods[lo + i];
     FpArith ar;
     ar.init(m);
@@ -874,14 +888,22 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
     } else {
       IntArith ar;
       ar.init(m);
+      // constants of the digit's limbs (zero beyond cnt, so those terms vanish without a branch)
+      uint64_t cw[ALPHA], cws[ALPHA];
+#pragma unroll
+      for (uint32_t i = 0; i < ALPHA; ++i) {
+        cw[i] = i < cnt ? mrow[(uint64_t)i * 2 * next] : 0;
+        cws[i] = i < cnt ? mrow[(uint64_t)i * 2 * next + 1] : 0;
+      }
 #pragma unroll
       for (uint32_t r = 0; r < EPT; ++r) {
-        uint64_t v = 0;
+        // lazy Shoup terms in [0, 2p) summed two at a time into [0, 4p), the forward butterflies'
+        // input range (p < 2^61, so no sum wraps)
+        uint64_t v = shoup_mul_lazy(f64_to_u52(opaque(y[0][r])), cw[0], cws[0], m.q);
 #pragma unroll
-        for (uint32_t i = 0; i < ALPHA; ++i) {
-          if (i >= cnt) break;
-          const uint64_t* cc = mrow + (uint64_t)i * 2 * next;
-          v = add_mod(v, shoup_mul((uint64_t)opaque(y[i][r]), cc[0], cc[1], m.q), m.q);
+        for (uint32_t i = 1; i < ALPHA; ++i) {
+          const uint64_t t = shoup_mul_lazy(f64_to_u52(opaque(y[i][r])), cw[i], cws[i], m.q);
+          v = (i == 1 ? v : (v >= ar.q2 ? v - ar.q2 : v)) + t;
         }
         uint32_t g;
         const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
@@ -903,8 +925,8 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
 // ModDown conversion fused with the column phases around it, per wavefront. Workgroup (item b,
 // component c, tile): the K special-prime limbs of u (row phase of the inverse NTT already applied)
 // go through the inverse column phase in LDS and are scaled to z_k = [u_(p_k) (P/p_k)^-1]_(p_k)
-// (N^-1 applied first) and centred (z_k - p_k when z_k > (p_k - 1)/2), which accounts for the
-// P mod q_i subtractions of k_moddown_conv. The centred z_k is kept in registers as two exact 30-bit
+// (one Shoup product by N^-1 (P/p_k)^-1) and centred (z_k - p_k when z_k > (p_k - 1)/2), which
+// accounts for the P mod q_i subtractions of k_moddown_conv. The centred z_k is kept in registers as two exact 30-bit
 // halves (high part signed), so every Q limb's conversion sum_k zc_k (P/p_k mod q_i) is formed in
 // exact FP64 from the constants c0 = (P/p_k) mod q_i and c1 = c0 2^30 mod q_i, goes through the
 // forward column phase and is written to conv [B][2][nl][N] in the FP64 kernels' internal form.
@@ -923,6 +945,7 @@ __global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, ui
   const uint32_t tile = blockIdx.x % tiles, bc = blockIdx.x / tiles;
   const uint32_t next = nl + K, k2 = logN - k1, logC = LOG_E - k1, logCw = logC - WaveSplit<NT>::kLogWaves;
   const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t* tinv = tab + 2 * K + 2 * (uint64_t)K * nq + 3 * (uint64_t)nq;  // N^-1 (P/p_k)^-1 mod p_k
   int32_t zh[KP][EPT], zl[KP][EPT];
 #pragma unroll
   for (uint32_t kk = 0; kk < KP; ++kk) {
@@ -944,8 +967,7 @@ __global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, ui
     for (uint32_t r = 0; r < EPT; ++r) {
       uint32_t g;
       const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      const uint64_t x = shoup_mul(work[Lay::idx(li)], m.n_inv, m.n_inv_shoup, m.q);
-      const uint64_t z = shoup_mul(x, tab[2 * kk], tab[2 * kk + 1], m.q);
+      const uint64_t z = shoup_mul(work[Lay::idx(li)], tinv[2 * kk], tinv[2 * kk + 1], m.q);
       const int64_t zc = z > half ? (int64_t)z - (int64_t)m.q : (int64_t)z;
       zh[kk][r] = (int32_t)(zc >> 30);
       zl[kk][r] = (int32_t)(zc & 0x3FFFFFFF);
@@ -1158,8 +1180,8 @@ __global__ __launch_bounds__(NT) void k_rescale_rows(uint32_t ncomp, uint32_t nl
     uint64_t xv = x[idx];
     if (galois)  // one-hot mask multiply fused in (mask in Montgomery form)
       xv = mont_mul(xv, maskm[((uint64_t)i << logN) + automorph_src(j0 + idx, galois[b], logN)], m.q, m.qinv);
-    const double v = ar.red(ar.mulc((double)xv - ar.ld(lds[pad_idx(idx)]), iv, ivq));
-    o[idx] = (uint64_t)(v < 0.0 ? v + ar.q : v);
+    const double v = ar.red(ar.mulc(u52_to_f64(xv) - ar.ld(lds[pad_idx(idx)]), iv, ivq));
+    o[idx] = f64_to_u52(v < 0.0 ? v + ar.q : v);
   }
 }
 
@@ -1212,8 +1234,8 @@ __global__ __launch_bounds__(kThreads) void k_mask_sum(uint32_t nseg, uint32_t n
     uint64_t* a = acc + (uint64_t)seg[4 * s] * 2 * per + off;
     double v0 = 0.0, v1 = 0.0;
     if (!seg[4 * s + 3]) {
-      v0 = (double)a[0];
-      v1 = (double)a[per];
+      v0 = u52_to_f64(a[0]);
+      v1 = u52_to_f64(a[per]);
     }
     const uint64_t* mrow = maskf + ((uint64_t)i << logN);
     uint32_t e = e0;
@@ -1229,8 +1251,8 @@ __global__ __launch_bounds__(kThreads) void k_mask_sum(uint32_t nseg, uint32_t n
       }
 #pragma unroll
       for (uint32_t j = 0; j < 4; ++j) {
-        v0 = ar.kacc(v0, (double)x0[j], mk[j]);
-        v1 = ar.kacc(v1, (double)x1[j], mk[j]);
+        v0 = ar.kacc(v0, u52_to_f64(x0[j]), mk[j]);
+        v1 = ar.kacc(v1, u52_to_f64(x1[j]), mk[j]);
       }
       ar.kred(v0);
       ar.kred(v1);
@@ -1238,8 +1260,8 @@ __global__ __launch_bounds__(kThreads) void k_mask_sum(uint32_t nseg, uint32_t n
     for (; e < e1; ++e) {
       const uint64_t mk = mrow[automorph_src(k, galois[e], logN)];
       const uint64_t* x = in[e] + off;
-      v0 = ar.kacc(v0, (double)x[0], mk);
-      v1 = ar.kacc(v1, (double)x[per], mk);
+      v0 = ar.kacc(v0, u52_to_f64(x[0]), mk);
+      v1 = ar.kacc(v1, u52_to_f64(x[per]), mk);
     }
     a[0] = ar.kfinal(v0);
     a[per] = ar.kfinal(v1);
