@@ -783,15 +783,49 @@ __global__ __launch_bounds__(kThreads) void k_moddown_conv(uint32_t B, uint32_t 
 
 // Column-phase tiles of 2^LOG_E elements: 2^k1 rows (stride 2^(logN - k1)) by C = 2^(LOG_E - k1)
 // adjacent columns.
-// Column-phase slots owned by one wavefront in the fused column kernels: wavefront w owns columns
-// [w Cw, (w + 1) Cw) of the tile (Cw = C / waves) in every row; lane l handles slots l + 64 r.
-// Returns the LDS index of slot s; *g receives its coefficient index.
-__device__ __forceinline__ uint32_t wave_col_slot(uint32_t s, uint32_t wv, uint32_t logCw, uint32_t logC, uint32_t k2,
-                                                  uint32_t tile, uint32_t* g) {
-  const uint32_t row = s >> logCw, col = (wv << logCw) + (s & ((1u << logCw) - 1));
-  *g = (row << k2) + (tile << logC) + col;
-  return (row << logC) + col;
-}
+// Column-phase slots owned by one wavefront in the fused column kernels (2048-element tiles, four
+// wavefronts, ColSwz<K1> layout): wavefront w owns columns [w Cw, (w + 1) Cw) of the tile
+// (Cw = C / 4) in every row; lane l handles slots l + 64 r (r < 8), i.e. row l / Cw + r 64 / Cw and
+// column w Cw + l mod Cw. Consecutive r are 256 LDS words apart, and the swizzle depends on r only
+// through r mod 2 (the row bits it reads above l / Cw are bit 0 of r, or none for K1 = 8), so two
+// base indices kept in registers give every slot's LDS word with a constant offset that folds into
+// the LDS instruction. The coefficient index advances by (64 / Cw) 2^k2 per r.
+template <int K1>
+struct ColSlots {
+  static constexpr uint32_t kLogC = 11 - K1, kLogCw = kLogC - 2, kLogRows = 6 - kLogCw, kStep = 256, kEPT = 8;
+  uint32_t lds_even, lds_odd, g0, gshift;
+  __device__ __forceinline__ ColSlots(uint32_t lane, uint32_t wv, uint32_t k2, uint32_t tile) {
+    const uint32_t row0 = lane >> kLogCw, col = (wv << kLogCw) + (lane & ((1u << kLogCw) - 1));
+    const uint32_t li0 = (row0 << kLogC) + col;
+    lds_even = ColSwz<K1>::idx(li0);
+    lds_odd = ColSwz<K1>::idx(li0 + kStep) - kStep;
+    g0 = (row0 << k2) + (tile << kLogC) + col;
+    gshift = k2 + kLogRows;
+  }
+  // opaque bases: the per-slot sums are formed at each use instead of being kept live in registers
+  __device__ __forceinline__ uint32_t lds(uint32_t r) const {
+    return opaque((r & 1) ? lds_odd : lds_even) + r * kStep;
+  }
+  __device__ __forceinline__ uint32_t g(uint32_t r) const { return opaque(g0) + (r << gshift); }
+  // work <- src over the lane's kEPT slots: every load is issued before the first LDS write, so the
+  // wavefront waits for one memory latency instead of kEPT of them
+  __device__ __forceinline__ void load(uint64_t* work, const uint64_t* src) const {
+    uint64_t v[kEPT];
+#pragma unroll
+    for (uint32_t r = 0; r < kEPT; ++r) v[r] = src[g(r)];
+#pragma unroll
+    for (uint32_t r = 0; r < kEPT; ++r) work[lds(r)] = v[r];
+  }
+  // dst <- f(work) over the lane's kEPT slots, all LDS reads first
+  template <class F>
+  __device__ __forceinline__ void store(uint64_t* dst, const uint64_t* work, F f) const {
+    uint64_t v[kEPT];
+#pragma unroll
+    for (uint32_t r = 0; r < kEPT; ++r) v[r] = f(work[lds(r)]);
+#pragma unroll
+    for (uint32_t r = 0; r < kEPT; ++r) dst[g(r)] = v[r];
+  }
+};
 
 // ModUp fused with the column phases around it, per wavefront. Workgroup (digit j, item b, tile);
 // every wavefront owns a group of the tile's columns: the digit's limbs (row phase of the inverse
@@ -815,8 +849,9 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
   const uint32_t tile = blockIdx.x % tiles, rest = blockIdx.x / tiles;
   const uint32_t b = rest % B, j = rest / B;
   const uint32_t next = nl + K, lo = j * alpha, cnt = min(alpha, nl - lo);
-  const uint32_t k2 = logN - k1, logC = LOG_E - k1, logCw = logC - WaveSplit<NT>::kLogWaves;
+  const uint32_t k2 = logN - k1, logC = LOG_E - k1;
   const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const ColSlots<K1> cs(lane, wv, k2, tile);
   const uint64_t* blk = tab + (uint64_t)j * (2 * alpha + 2 * alpha * next);
   double y[ALPHA][EPT];
 #pragma unroll
@@ -830,12 +865,7 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
     FpArith ar;
     ar.init(m);
     const uint64_t* src = dc2 + ((uint64_t)b * nl + lo + i) * N;
-#pragma unroll
-    for (uint32_t r = 0; r < EPT; ++r) {
-      uint32_t g;
-      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      work[Lay::idx(li)] = src[g];  // row-phase output in internal FP64 form
-    }
+    cs.load(work, src);  // row-phase output in internal FP64 form
     wave_sync();
     ntt_rounds<true, 1, FpArith, EPT, NT, true, Lay>(work, ar, twf + (uint64_t)(lo + i) * 4 * N + 2 * (uint64_t)N, k1,
                                                 logC, 0, 0);
@@ -843,9 +873,7 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
     const double cq = c / ar.q;
 #pragma unroll
     for (uint32_t r = 0; r < EPT; ++r) {
-      uint32_t g;
-      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      const double v = ar.mulc(ar.ld(work[Lay::idx(li)]), c, cq);
+      const double v = ar.mulc(ar.ld(work[cs.lds(r)]), c, cq);
       y[i][r] = v < 0.0 ? v + ar.q : v;  // [0, q_i)
     }
     wave_sync();
@@ -873,18 +901,11 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
 #pragma unroll
         for (uint32_t i = 0; i < ALPHA; ++i)
           if (i < cnt) v += ar.mulc(opaque(y[i][r]), cw[i], cwq[i]);
-        uint32_t g;
-        const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-        work[Lay::idx(li)] = ar.st(ar.red(v));
+        work[cs.lds(r)] = ar.st(ar.red(v));
       }
       wave_sync();
       ntt_rounds<false, 1, FpArith, EPT, NT, true, Lay>(work, ar, twf + (uint64_t)mi * 4 * N, k1, logC, 0, 0);
-#pragma unroll
-      for (uint32_t r = 0; r < EPT; ++r) {
-        uint32_t g;
-        const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-        o[g] = work[Lay::idx(li)];  // internal FP64 form, read by the row-phase inner product
-      }
+      cs.store(o, work, [](uint64_t x) { return x; });  // internal FP64 form, read by the inner product
     } else {
       IntArith ar;
       ar.init(m);
@@ -905,18 +926,11 @@ __global__ __launch_bounds__(NT) void k_modup_cols(uint32_t B, uint32_t nl, uint
           const uint64_t t = shoup_mul_lazy(f64_to_u52(opaque(y[i][r])), cw[i], cws[i], m.q);
           v = (i == 1 ? v : (v >= ar.q2 ? v - ar.q2 : v)) + t;
         }
-        uint32_t g;
-        const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-        work[Lay::idx(li)] = v;
+        work[cs.lds(r)] = v;
       }
       wave_sync();
       ntt_rounds<false, 1, IntArith, EPT, NT, true, Lay>(work, ar, twi + (uint64_t)mi * 4 * N, k1, logC, 0, 0);
-#pragma unroll
-      for (uint32_t r = 0; r < EPT; ++r) {
-        uint32_t g;
-        const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-        o[g] = ar.lds_out(work[Lay::idx(li)]);
-      }
+      cs.store(o, work, [&ar](uint64_t x) { return ar.lds_out(x); });
     }
     wave_sync();
   }
@@ -943,8 +957,9 @@ __global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, ui
   extern __shared__ uint64_t work[];
   const uint32_t N = 1u << logN, tiles = N >> LOG_E;
   const uint32_t tile = blockIdx.x % tiles, bc = blockIdx.x / tiles;
-  const uint32_t next = nl + K, k2 = logN - k1, logC = LOG_E - k1, logCw = logC - WaveSplit<NT>::kLogWaves;
+  const uint32_t next = nl + K, k2 = logN - k1, logC = LOG_E - k1;
   const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const ColSlots<K1> cs(lane, wv, k2, tile);
   const uint64_t* tinv = tab + 2 * K + 2 * (uint64_t)K * nq + 3 * (uint64_t)nq;  // N^-1 (P/p_k)^-1 mod p_k
   int32_t zh[KP][EPT], zl[KP][EPT];
 #pragma unroll
@@ -954,20 +969,13 @@ __global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, ui
     IntArith ar;
     ar.init(m);
     const uint64_t* src = u + ((uint64_t)bc * next + nl + kk) * N;
-#pragma unroll
-    for (uint32_t r = 0; r < EPT; ++r) {
-      uint32_t g;
-      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      work[Lay::idx(li)] = src[g];
-    }
+    cs.load(work, src);
     wave_sync();
     ntt_rounds<true, 1, IntArith, EPT, NT, true, Lay>(work, ar, twi + (uint64_t)(nq + kk) * 4 * N + 2 * (uint64_t)N, k1,
                                                  logC, 0, 0);
 #pragma unroll
     for (uint32_t r = 0; r < EPT; ++r) {
-      uint32_t g;
-      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      const uint64_t z = shoup_mul(work[Lay::idx(li)], tinv[2 * kk], tinv[2 * kk + 1], m.q);
+      const uint64_t z = shoup_mul(work[cs.lds(r)], tinv[2 * kk], tinv[2 * kk + 1], m.q);
       const int64_t zc = z > half ? (int64_t)z - (int64_t)m.q : (int64_t)z;
       zh[kk][r] = (int32_t)(zc >> 30);
       zl[kk][r] = (int32_t)(zc & 0x3FFFFFFF);
@@ -997,19 +1005,12 @@ __global__ __launch_bounds__(NT) void k_moddown_cols(uint32_t nl, uint32_t K, ui
       for (uint32_t kk = 0; kk < KP; ++kk)
         acc += ar.mulc((double)(int32_t)opaque((uint32_t)zh[kk][r]), c1[kk], c1q[kk]) +
                ar.mulc((double)(int32_t)opaque((uint32_t)zl[kk][r]), c0[kk], c0q[kk]);
-      uint32_t g;
-      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      work[Lay::idx(li)] = ar.st(ar.red(acc));
+      work[cs.lds(r)] = ar.st(ar.red(acc));
     }
     wave_sync();
     ntt_rounds<false, 1, FpArith, EPT, NT, true, Lay>(work, ar, twf + (uint64_t)i * 4 * N, k1, logC, 0, 0);
     uint64_t* o = conv + ((uint64_t)bc * nl + i) * N;
-#pragma unroll
-    for (uint32_t r = 0; r < EPT; ++r) {
-      uint32_t g;
-      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      o[g] = work[Lay::idx(li)];  // internal FP64 form, read by the combine
-    }
+    cs.store(o, work, [](uint64_t x) { return x; });  // internal FP64 form, read by the combine
     wave_sync();
   }
 }
@@ -1088,29 +1089,23 @@ __global__ __launch_bounds__(NT) void k_rescale_cols(uint32_t nl, uint32_t logN,
   extern __shared__ uint64_t work[];
   const uint32_t N = 1u << logN, tiles = N >> LOG_E;
   const uint32_t tile = blockIdx.x % tiles, bc = blockIdx.x / tiles;
-  const uint32_t no = nl - 1, k2 = logN - k1, logC = LOG_E - k1, logCw = logC - WaveSplit<NT>::kLogWaves;
+  const uint32_t no = nl - 1, k2 = logN - k1, logC = LOG_E - k1;
   const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const ColSlots<K1> cs(lane, wv, k2, tile);
   double vs[EPT];
   {
     const ModInfo m = mods[no];
     FpArith ar;
     ar.init(m);
     const uint64_t* src = tmp + ((uint64_t)bc << logN);
-#pragma unroll
-    for (uint32_t r = 0; r < EPT; ++r) {
-      uint32_t g;
-      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      work[Lay::idx(li)] = src[g];  // row-phase output in internal FP64 form
-    }
+    cs.load(work, src);  // row-phase output in internal FP64 form
     wave_sync();
     ntt_rounds<true, 1, FpArith, EPT, NT, true, Lay>(work, ar, twf + (uint64_t)no * 4 * N + 2 * (uint64_t)N, k1, logC, 0,
                                                 0);
     const double c = (double)m.n_inv, cq = c / ar.q;
 #pragma unroll
     for (uint32_t r = 0; r < EPT; ++r) {
-      uint32_t g;
-      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      double v = ar.mulc(ar.ld(work[Lay::idx(li)]), c, cq);  // |v| <= 0.7 q_l
+      double v = ar.mulc(ar.ld(work[cs.lds(r)]), c, cq);  // |v| <= 0.7 q_l
       v = v < 0.0 ? v + ar.q : v;                             // [0, q_l)
       vs[r] = v > 0.5 * (ar.q - 1.0) ? v - ar.q : v;          // centred
     }
@@ -1122,19 +1117,12 @@ __global__ __launch_bounds__(NT) void k_rescale_cols(uint32_t nl, uint32_t logN,
     ar.init(m);
 #pragma unroll
     for (uint32_t r = 0; r < EPT; ++r) {
-      uint32_t g;
-      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      work[Lay::idx(li)] = ar.st(vs[r]);
+      work[cs.lds(r)] = ar.st(vs[r]);
     }
     wave_sync();
     ntt_rounds<false, 1, FpArith, EPT, NT, true, Lay>(work, ar, twf + (uint64_t)i * 4 * N, k1, logC, 0, 0);
     uint64_t* o = w + ((uint64_t)bc * no + i) * N;
-#pragma unroll
-    for (uint32_t r = 0; r < EPT; ++r) {
-      uint32_t g;
-      const uint32_t li = wave_col_slot(opaque(lane) + 64 * r, wv, logCw, logC, k2, tile, &g);
-      o[g] = work[Lay::idx(li)];  // internal FP64 form, read by k_rescale_rows
-    }
+    cs.store(o, work, [](uint64_t x) { return x; });  // internal FP64 form, read by k_rescale_rows
     wave_sync();
   }
 }
