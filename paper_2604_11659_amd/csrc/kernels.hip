@@ -329,7 +329,9 @@ __device__ __forceinline__ void ntt_rounds(uint64_t* lds, const A& ar, const typ
 }
 
 // kSrcPtr: the first phase reads its input through lb.src_ptr / lb.src_gal (automorphism gather).
-template <bool kInv, int kPhase, class A, int NT, bool kSrcPtr = false>
+// KR: the row phase's stage count as a compile-time constant (0: logN - k1 at run time), so its
+// rounds unroll and their index arithmetic folds.
+template <bool kInv, int kPhase, class A, int NT, bool kSrcPtr = false, int KR = 0>
 __global__ __launch_bounds__(NT) void k_ntt(LimbBatch lb, const ModInfo* __restrict__ mods,
                                                  const typename A::W* __restrict__ tw, uint32_t logN, uint32_t k1,
                                                  bool from_src) {
@@ -344,7 +346,7 @@ __global__ __launch_bounds__(NT) void k_ntt(LimbBatch lb, const ModInfo* __restr
   const ModInfo m = mods[mi];
   A ar;
   ar.init(m);
-  const uint32_t k = kPhase == 1 ? k1 : logN - k1, k2 = logN - k1;
+  const uint32_t k2 = KR ? KR : logN - k1, k = kPhase == 1 ? k1 : k2;
   const uint32_t logC = kNttLogE - k, C = 1u << logC;
   const uint32_t j0 = tile * kNttE;
   const uint64_t toff = (uint64_t)mi * 4 * N + (kInv ? 2 * (uint64_t)N : 0);
@@ -617,7 +619,7 @@ __global__ __launch_bounds__(kThreads) void k_hoisted_inner(
 // Row phase of the forward NTT of the ModDown conversion fused with the final combine:
 // out[b][c][i] = add[2b+c][i] + (u[b][c][i] - NTT(conv)[b][c][i]) P^-1 (NTT domain).
 // Workgroup (poly bc = 2b + c, limb i, tile); conv has had its column phase.
-template <class A, int NT>
+template <class A, int NT, int KR = 0>  // KR as in k_ntt
 __global__ __launch_bounds__(NT) void k_ntt_p2_combine(uint32_t nl, uint32_t K, uint32_t nq, uint32_t logN,
                                                             uint32_t k1, const ModInfo* __restrict__ mods,
                                                             const typename A::W* __restrict__ tw,
@@ -635,7 +637,7 @@ __global__ __launch_bounds__(NT) void k_ntt_p2_combine(uint32_t nl, uint32_t K, 
   A ar;
   ar.init(m);
   const uint64_t j0 = (uint64_t)tile * kNttE;
-  const uint32_t k = logN - k1, logC = kNttLogE - k;
+  const uint32_t k = KR ? KR : logN - k1, logC = kNttLogE - k;
   const uint64_t* src = conv + ((uint64_t)bc * nl + i) * N + j0;
   constexpr uint32_t kPer = kNttE / NT;
   const uint32_t wb = (threadIdx.x >> 6) * (kNttE / (NT / 64)), lane = threadIdx.x & 63;
@@ -1129,7 +1131,7 @@ __global__ __launch_bounds__(NT) void k_rescale_cols(uint32_t nl, uint32_t logN,
 
 // Rescale, row part: per (polynomial bc = b * ncomp + c, remaining limb i, tile), the forward row
 // phase of w in LDS fused with out = (in - w) q_l^-1 mod q_i (NTT domain), per wavefront.
-template <int NT>
+template <int NT, int KR = 0>  // KR as in k_ntt
 __global__ __launch_bounds__(NT) void k_rescale_rows(uint32_t ncomp, uint32_t nl, uint32_t nq, uint32_t logN,
                                                           uint32_t k1, const ModInfo* __restrict__ mods,
                                                           const double* __restrict__ twf,
@@ -1147,7 +1149,7 @@ __global__ __launch_bounds__(NT) void k_rescale_rows(uint32_t ncomp, uint32_t nl
   const ModInfo m = mods[i];
   FpArith ar;
   ar.init(m);
-  const uint32_t j0 = tile * kNttE, k = logN - k1, logC = kNttLogE - k;
+  const uint32_t j0 = tile * kNttE, k = KR ? KR : logN - k1, logC = kNttLogE - k;
   const uint32_t wb = (threadIdx.x >> 6) * (kNttE / (NT / 64)), lane = threadIdx.x & 63;
   const uint64_t* src = w + ((uint64_t)bc * no + i) * N + j0;
 #pragma unroll
@@ -1497,17 +1499,29 @@ static void ntt_phase(const fhe_ctx* ctx, const LimbBatch& lb, const char* name_
     const uint32_t blocks = ntt_blocks(ctx, sub);
     const double bytes = 16.0 * p.N * sub.limbs * sub.npoly;
     // row phase: the 512-thread variant (see rows_nt); column phase: 256 threads x 16 elements
+    // the usual row length (2^9): compile-time rounds (fewer VGPRs, a fourth workgroup per CU; the
+    // forward gather instance is left out, it would need more)
+    const bool r9 = p.logN - p.k1 == 9;
     if (kPhase == 2 && from_src && sub.src_ptr) {
-      if (r.q)
+      if (r.q && r9 && kInv)
+        FHE_LAUNCH_T(name_q, bytes, (k_ntt<kInv, kPhase, FpArith, 512, true, 9>), blocks, 512, lds, st, sub,
+                     mods_of(ctx), twf, p.logN, p.k1, from_src);
+      else if (r.q)
         FHE_LAUNCH_T(name_q, bytes, (k_ntt<kInv, kPhase, FpArith, 512, true>), blocks, 512, lds, st, sub, mods_of(ctx),
                      twf, p.logN, p.k1, from_src);
       else
         FHE_LAUNCH_T(name_p, bytes, (k_ntt<kInv, kPhase, IntArith, 512, true>), blocks, 512, lds, st, sub,
                      mods_of(ctx), ctx->t.tw.u64(), p.logN, p.k1, from_src);
     } else if (kPhase == 2 && rows_nt() == 512) {
-      if (r.q)
+      if (r.q && r9)
+        FHE_LAUNCH_T(name_q, bytes, (k_ntt<kInv, kPhase, FpArith, 512, false, 9>), blocks, 512, lds, st, sub,
+                     mods_of(ctx), twf, p.logN, p.k1, from_src);
+      else if (r.q)
         FHE_LAUNCH_T(name_q, bytes, (k_ntt<kInv, kPhase, FpArith, 512>), blocks, 512, lds, st, sub, mods_of(ctx), twf,
                      p.logN, p.k1, from_src);
+      else if (r9)
+        FHE_LAUNCH_T(name_p, bytes, (k_ntt<kInv, kPhase, IntArith, 512, false, 9>), blocks, 512, lds, st, sub,
+                     mods_of(ctx), ctx->t.tw.u64(), p.logN, p.k1, from_src);
       else
         FHE_LAUNCH_T(name_p, bytes, (k_ntt<kInv, kPhase, IntArith, 512>), blocks, 512, lds, st, sub, mods_of(ctx),
                      ctx->t.tw.u64(), p.logN, p.k1, from_src);
@@ -1822,7 +1836,11 @@ static void keyswitch_moddown(const fhe_ctx* ctx, uint32_t B, uint32_t nl, uint6
     lb_conv.raw_out = 1;
     ntt_forward_cols(ctx, lb_conv, st);
   }
-  if (rows_nt() == 512)
+  if (rows_nt() == 512 && p.logN - p.k1 == 9)
+    FHE_LAUNCH_T("ntt_p2_combine", e8 * 2 * nl * 3.5, (k_ntt_p2_combine<FpArith, 512, 9>),
+                 (uint64_t)2 * B * nl * tiles, 512, lds, st, nl, K, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf,
+                 ctx->t.moddown.u64(), u, conv, add, galois, out);
+  else if (rows_nt() == 512)
     FHE_LAUNCH_T("ntt_p2_combine", e8 * 2 * nl * 3.5, (k_ntt_p2_combine<FpArith, 512>), (uint64_t)2 * B * nl * tiles,
                  512, lds, st, nl, K, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.moddown.u64(), u, conv,
                  add, galois, out);
@@ -1878,7 +1896,11 @@ void rescale(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const 
         break;
     }
     const size_t lds = kNttLdsElems * sizeof(uint64_t);
-    if (rows_nt() == 512)
+    if (rows_nt() == 512 && p.logN - p.k1 == 9)
+      FHE_LAUNCH_T("rescale_rows", e8 * 3 * (nl - 1), (k_rescale_rows<512, 9>),
+                   (uint64_t)BC * (nl - 1) * (N >> kNttLogE), 512, lds, st, ncomp, nl, (uint32_t)p.nq, p.logN, p.k1,
+                   mods_of(ctx), twf, ctx->t.rescale.u64(), ctx->t.mask.u64(), mask_galois, in, w, out);
+    else if (rows_nt() == 512)
       FHE_LAUNCH_T("rescale_rows", e8 * 3 * (nl - 1), k_rescale_rows<512>, (uint64_t)BC * (nl - 1) * (N >> kNttLogE),
                    512, lds, st, ncomp, nl, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.rescale.u64(),
                    ctx->t.mask.u64(), mask_galois, in, w, out);
