@@ -659,11 +659,26 @@ __global__ __launch_bounds__(NT) void k_ntt_p2_combine(uint32_t nl, uint32_t K, 
   // exact FP64: |u - conv| < 1.5q + 2, so the product with P^-1 is below 0.9q and adding the
   // [0, q) addend keeps the sum below 2q before the final reduction
   const double pv = (double)pinv[0], pvq = pv * ar.qinv;
+  // all loads first: `o` may alias the addend as far as the compiler knows, so a load placed after
+  // a store would wait for it
+  uint64_t uv[kPer], av[kPer];
+#pragma unroll
+  for (uint32_t r_ = 0; r_ < kPer; ++r_) uv[r_] = uu[wb + ln + r_ * 64];
+  if (ad && galois) {  // uniform branches outside the unrolled loops
+#pragma unroll
+    for (uint32_t r_ = 0; r_ < kPer; ++r_) av[r_] = ad[automorph_src(j0 + wb + ln + r_ * 64, gal, logN)];
+  } else if (ad) {
+#pragma unroll
+    for (uint32_t r_ = 0; r_ < kPer; ++r_) av[r_] = ad[wb + ln + r_ * 64];
+  } else {
+#pragma unroll
+    for (uint32_t r_ = 0; r_ < kPer; ++r_) av[r_] = 0;
+  }
 #pragma unroll
   for (uint32_t r_ = 0; r_ < kPer; ++r_) {
     const uint32_t idx = wb + ln + r_ * 64;
-    double v = ar.mulc(u52_to_f64(uu[idx]) - ar.ld(lds[pad_idx(idx)]), pv, pvq);
-    if (ad) v += u52_to_f64(galois ? ad[automorph_src(j0 + idx, gal, logN)] : ad[idx]);
+    double v = ar.mulc(u52_to_f64(uv[r_]) - ar.ld(lds[pad_idx(idx)]), pv, pvq);
+    v += u52_to_f64(av[r_]);  // zero without an addend
     v = ar.red(v);
     o[idx] = f64_to_u52(v < 0.0 ? v + ar.q : v);
   }
@@ -1164,13 +1179,20 @@ __global__ __launch_bounds__(NT) void k_rescale_rows(uint32_t ncomp, uint32_t nl
   uint64_t* o = out[b] + ((uint64_t)c * no + i) * N + j0;
   const uint32_t ln = opaque(lane);
   const double iv = (double)inv[0], ivq = iv * ar.qinv;  // exact FP64 as in k_ntt_p2_combine
+  // all loads first (as in k_ntt_p2_combine: `o` may alias the input as far as the compiler knows)
+  uint64_t xv[kPer], mk[kPer];
 #pragma unroll
   for (uint32_t r_ = 0; r_ < kPer; ++r_) {
     const uint32_t idx = wb + ln + r_ * 64;
-    uint64_t xv = x[idx];
-    if (galois)  // one-hot mask multiply fused in (mask in Montgomery form)
-      xv = mont_mul(xv, maskm[((uint64_t)i << logN) + automorph_src(j0 + idx, galois[b], logN)], m.q, m.qinv);
-    const double v = ar.red(ar.mulc(u52_to_f64(xv) - ar.ld(lds[pad_idx(idx)]), iv, ivq));
+    xv[r_] = x[idx];
+    mk[r_] = galois ? maskm[((uint64_t)i << logN) + automorph_src(j0 + idx, galois[b], logN)] : 0;
+  }
+#pragma unroll
+  for (uint32_t r_ = 0; r_ < kPer; ++r_) {
+    const uint32_t idx = wb + ln + r_ * 64;
+    // one-hot mask multiply fused in (mask in Montgomery form)
+    const uint64_t xm = galois ? mont_mul(xv[r_], mk[r_], m.q, m.qinv) : xv[r_];
+    const double v = ar.red(ar.mulc(u52_to_f64(xm) - ar.ld(lds[pad_idx(idx)]), iv, ivq));
     o[idx] = f64_to_u52(v < 0.0 ? v + ar.q : v);
   }
 }
