@@ -1,17 +1,25 @@
 """Benchmark: encrypted sparse x sparse matmul throughput on one MI355X.
 
-A step is one full CSR x CSC ciphertext matmul (Algorithms 1 and 2: every matched pair's alignment
-rotation, EvalMult + relinearisation + rescale, one-hot mask + rescale, target rotation and
-accumulation) over the synthetic DNN-layer operands, with ciphertexts and evaluation keys already
-resident in HBM. Prints one JSON line.
+Default (the headline): the batching workload at N = 2^16 (24 x 50-bit Q primes, 3 x 60-bit special
+primes, alpha = 3, three rotation digits): 64 square matmuls of size 32..256 with per-operand
+sparsity U[0.5, 0.95]. The full batch is 2.04e7 matched pairs (hours), so every matmul runs a seeded
+prefix of its plan: its first --batch-cap matched pairs in Algorithm 1's order, each with its full
+Algorithm 2 sequence. A step is ONE batched call (fhe_spmspm_batch_pairs) over the 64 prefixes, with
+ciphertexts and evaluation keys resident in HBM; the plain form runs the same prefixes as 64 single
+calls on the same kernels. `value` is the batched form's SpMSpM/s, projected from measured pairs/s
+over the mean matched pairs of a full matmul (`projected: true`). Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload dnn] [--cpu-sample 0]
+  python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--batch-cap 32] [--cpu-sample -1] [--dnn 1]
+  python bench.py --workload dnn|plain|large      one full matmul per step (its own metric line)
+  python bench.py --workload batch_small          the batching shape at N = 2^13
+  python bench.py --serve | --sweep               request loop / sparsity sweep (own lines)
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -22,12 +30,40 @@ sys.path.insert(0, ROOT)
 
 from paper_2604_11659_amd import synth  # noqa: E402
 
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 METRIC = "encrypted SpMSpM/s at N=2^16 (batched vs plain) + key-switch HBM GB/s"
 HBM_PEAK_GBPS = 8000.0
+# ALU peak of the FP64 modular product, from the chip's figures: 78.6 TFLOP/s FP64 vector = 39.3e12
+# FP64 lane operations per second (256 CUs x 64 lanes x 2.4 GHz; an FMA counts as one operation),
+# and one product of the Q primes is 6 of them (two multiplies, two FMAs, a rounding, an add).
+FP64_LANE_OPS = 78.6e12 / 2
+ALU_PEAK_TMULMOD = FP64_LANE_OPS / 6 / 1e12
+# every kernel of the key switch (ModUp, inner product, ModDown and the transforms around them)
+KS_KERNELS = ("ntt_inv_p2_", "ntt_inv_p1_", "ntt_fwd_p1_", "ntt_fwd_p2_", "modup", "ntt_p2_inner", "moddown",
+              "ntt_p2_combine", "ext_rows", "hoisted_inner")
+
+
+def host_info() -> dict:
+    """Host CPU as the oracle sees it: logical CPUs, the process's CPU affinity and the model name."""
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None and os.path.exists("/proc/cpuinfo"):
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"nproc": os.cpu_count(), "affinity_cpus": aff, "model": model}
 
 
 def describe(w) -> str:
@@ -37,168 +73,452 @@ def describe(w) -> str:
             f"scale 2^40, output scale 2^50")
 
 
-def cpu_baseline(w, a, b, sample: int, workers: int) -> dict:
-    """The oracle (plain C + Python, untuned) on a seeded sample of the workload's matched pairs."""
+def describe_batch(w) -> str:
+    return (f"{w.name}: {w.count} square matmuls, n from {list(w.sizes)}, per-operand sparsity "
+            f"U[{w.sparsity[0]}, {w.sparsity[1]}], values U[-1,1] (seed {w.seed}); CKKS N=2^{w.log_n}, {w.n_q} x "
+            f"50-bit Q + {w.n_p} x 60-bit P primes, alpha={w.alpha}, rotation digits={w.rot_digits}, scale 2^40, "
+            f"output scale 2^50")
+
+
+def matched_pairs_count(a: np.ndarray, b: np.ndarray) -> int:
+    """F = sum over k of (nonzeros in column k of A) x (nonzeros in row k of B)."""
+    return int((a != 0).sum(axis=0).astype(np.int64) @ (b != 0).sum(axis=1).astype(np.int64))
+
+
+def prefix_reference(a: np.ndarray, b: np.ndarray, cap: int) -> np.ndarray:
+    """The FP64 sum over the first `cap` matched pairs in Algorithm 1's order (i, then j, then k)."""
+    m, n = a.shape[0], b.shape[1]
+    out = np.zeros((m, n))
+    left = cap
+    for i in range(m):
+        ka = np.nonzero(a[i])[0]
+        for j in range(n):
+            ks = ka[b[ka, j] != 0]
+            if left <= 0:
+                return out
+            ks = ks[:left]
+            out[i, j] = float(np.sum(a[i, ks] * b[ks, j]))
+            left -= len(ks)
+    return out
+
+
+def sample_cells(a: np.ndarray, b: np.ndarray, count: int, rng) -> list:
+    """`count` matched pairs (i, j, a_pos, b_pos) from random cells (i, j) of C that have at least one
+    (Algorithm 1's merge of row i of A and column j of B; one random match per cell). Positions index
+    the CSR value order of A and the CSC value order of B."""
+    nz_a, nz_b = a != 0, b != 0
+    row_start = np.concatenate([[0], np.cumsum(nz_a.sum(axis=1))])
+    col_start = np.concatenate([[0], np.cumsum(nz_b.sum(axis=0))])
+    out = []
+    while len(out) < count:
+        i, j = int(rng.integers(a.shape[0])), int(rng.integers(b.shape[1]))
+        ks = np.nonzero(nz_a[i] & nz_b[:, j])[0]
+        if not len(ks):
+            continue
+        k = int(ks[rng.integers(len(ks))])
+        a_pos = int(row_start[i] + np.count_nonzero(nz_a[i, :k]))
+        b_pos = int(col_start[j] + np.count_nonzero(nz_b[:k, j]))
+        out.append((i, j, a_pos, b_pos))
+    return out
+
+
+def cpu_baseline_batch(w, specs, mats, mean_f: float, workers: int, seed: int = 7) -> dict:
+    """The oracle (plain C + Python, untuned) on a seeded sample of the batching workload's matched
+    pairs: one pair on one thread, then `workers` pairs on `workers` processes. Each pair runs its full
+    sequence (alignment rotation, EvalMult + relinearisation + rescale, mask, rescale, target rotation,
+    accumulation); rotation keys are generated before the clock starts (key generation is not timed)."""
+    import multiprocessing as mp
+
     from oracle import ckks, spmspm
     pr = ckks.Params(log_n=w.log_n, n_q=w.n_q, n_p=w.n_p, alpha=w.alpha, rot_digits=w.rot_digits)
+    t0 = time.perf_counter()
     keys = ckks.Keys(pr, 42)
-    ipa, ixa, va = synth.to_csr(a)
-    ipb, ixb, vb = synth.to_csc(b)
-    A = spmspm.encrypt_csr(pr, keys, w.m, w.k, ipa, ixa, va, 43)
-    B = spmspm.encrypt_csc(pr, keys, w.k, w.n, ipb, ixb, vb, 44)
-    pairs = spmspm.matched_pairs(w.m, w.n, ipa, ixa, ipb, ixb)
-    rng = np.random.default_rng(7)
-    pick = sorted(rng.choice(len(pairs), size=min(sample, len(pairs)), replace=False).tolist())
-    sub = [pairs[i] for i in pick]
-    # keys for the sample are generated outside the timed region (key generation is not timed)
-    import multiprocessing as mp
-    gs = sorted(spmspm.rotation_elements(pr, A, B, sub))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pick = sorted(int(x) for x in rng.choice(len(specs), size=2, replace=False))
+    jobs = []  # (matmul index, oracle A, oracle B, pairs)
+    for t, i in enumerate(pick):
+        a, b = mats[i]
+        n = specs[i][0]
+        OA = spmspm.encrypt_csr(pr, keys, n, n, *synth.to_csr(a), seed=10_000 + i)
+        OB = spmspm.encrypt_csc(pr, keys, n, n, *synth.to_csc(b), seed=20_000 + i)
+        cnt = workers // 2 + (workers % 2 if t == 0 else 0)
+        jobs.append((i, OA, OB, sample_cells(a, b, cnt, rng)))
+    gs = set()
+    for (_, OA, OB, prs) in jobs:
+        gs |= spmspm.rotation_elements(pr, OA, OB, prs)
     spmspm._G.update(keys=keys)
     with mp.get_context("fork").Pool(workers) as pool:
-        for g, key in pool.imap_unordered(spmspm._keygen_worker, gs):
+        for g, key in pool.imap_unordered(spmspm._keygen_worker, sorted(gs)):
             keys._rot[g] = key
     spmspm._G.clear()
+    setup = time.perf_counter() - t0
+    log(f"cpu baseline: keys and operands in {setup:.1f} s")
+    # one pair, one thread
+    i0, OA, OB, prs = jobs[0]
     t0 = time.perf_counter()
-    spmspm.spmspm(pr, keys, A, B, workers=workers, pairs=sub)
-    dt = time.perf_counter() - t0
-    pairs_per_s = len(sub) / dt
-    return {"value": pairs_per_s / len(pairs), "unit": "SpMSpM/s", "cores": workers, "kind": "oracle",
-            "sample": f"{len(sub)} of {len(pairs)} matched pairs (seeded), full per-pair sequence, "
-                      f"{dt:.1f} s wall on {workers} processes; scaled by 1/F",
-            "pairs_per_s": pairs_per_s}
+    spmspm.spmspm(pr, keys, OA, OB, workers=1, pairs=prs[:1])
+    t1 = time.perf_counter() - t0
+    log(f"cpu baseline: one pair on one thread in {t1:.1f} s")
+    # `workers` pairs on `workers` processes (each matmul's pairs split across the processes)
+    t0 = time.perf_counter()
+    n_pairs = 0
+    for (_, OA, OB, prs) in jobs:
+        spmspm.spmspm(pr, keys, OA, OB, workers=min(workers, len(prs)), pairs=prs)
+        n_pairs += len(prs)
+    tw = time.perf_counter() - t0
+    log(f"cpu baseline: {n_pairs} pairs on {workers} processes in {tw:.1f} s")
+    pps = n_pairs / tw
+    return {"value": pps / mean_f, "unit": "SpMSpM/s", "cores": workers, "kind": "oracle",
+            "sample": (f"{n_pairs} matched pairs of matmuls {pick} of the batching workload (random cells of C with "
+                       f"a match, seeded), full per-pair sequence at N=2^16, {tw:.1f} s wall on {workers} processes; "
+                       f"scaled by 1 / mean F of a full matmul ({mean_f:.0f})"),
+            "pairs_per_s": pps,
+            "single_thread": {"pairs_per_s": 1.0 / t1, "value": 1.0 / t1 / mean_f, "pair_s": round(t1, 2)},
+            "host": host_info()}
 
 
-def roofline(prof: dict) -> tuple[dict, dict]:
+def ks_bytes(log_n: int, nl: int, n_p: int, alpha: int) -> float:
+    """Algorithmic HBM bytes of one key switch at nl active Q limbs: the input and output ciphertext
+    words (4 nl N) and both key components of every digit on the nl + K limbs (2 beta (nl + K) N)."""
+    beta = -(-nl // alpha)
+    return (4 * nl + 2 * beta * (nl + n_p)) * (1 << log_n) * 8.0
+
+
+def roofline(prof: dict, steps: int, log_n: int, n_p: int, alpha: int, step_s: float, probe: dict | None) -> tuple:
+    """Dominant kernel (largest summed event time) against its HBM and ALU bounds, and the key switch
+    as a unit (all of its kernels together)."""
     kernels = {}
     for name, r in prof.items():
-        if r["total_ms"] <= 0:
+        if name.startswith("count:") or r["total_ms"] <= 0:
             continue
+        t = r["total_ms"] * 1e-3
         kernels[name] = {"launches": r["launches"], "total_ms": round(r["total_ms"], 3),
                          "avg_us": round(1000 * r["total_ms"] / r["launches"], 2),
-                         "algo_GBps": round(r["bytes"] / (r["total_ms"] * 1e6), 1)}
+                         "algo_GBps": round(r["bytes"] / t / 1e9, 1),
+                         "Tmulmod_per_s": round(r.get("mulmods", 0.0) / t / 1e12, 3)}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     r = prof[dom]
-    achieved = r["bytes"] / (r["total_ms"] * 1e6)
-    # HBM bytes per launch from the committed counter runs, only if taken on the current kernel source
+    t = r["total_ms"] * 1e-3
+    hbm = r["bytes"] / t / 1e9
+    alu = r.get("mulmods", 0.0) / t / 1e12
+    hfrac, afrac = hbm / HBM_PEAK_GBPS, alu / ALU_PEAK_TMULMOD
     from paper_2604_11659_amd import profiling
-    t = profiling.load_traffic(os.path.join(ROOT, "profiles"), dom)
-    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": round(t["bytes_per_launch"]) if t else None,
-            "traffic_source": t["file"] if t else None,
-            "avg_launch_us": kernels[dom]["avg_us"],
-            "algo_bytes_per_launch": r["bytes"] / r["launches"]}
+    tr = profiling.load_traffic(os.path.join(ROOT, "profiles"), dom)
+    fp = probe.get("fp64_Tmulmod_per_s") if probe else None
+    roof = {"kernel": dom, "bound": "alu" if afrac > hfrac else "hbm"}
+    if roof["bound"] == "alu":
+        roof.update({"achieved": round(alu, 3), "peak": round(ALU_PEAK_TMULMOD, 3), "unit": "Tmulmod/s",
+                     "frac": round(afrac, 4)})
+    else:
+        roof.update({"achieved": round(hbm, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(hfrac, 4)})
+    roof.update({
+        "traffic": round(tr["bytes_per_launch"]) if tr else None,
+        "traffic_source": tr["file"] if tr else None,
+        "avg_launch_us": kernels[dom]["avg_us"], "launches": r["launches"],
+        "algo_bytes_per_launch": r["bytes"] / r["launches"], "mulmods_per_launch": r.get("mulmods", 0.0) / r["launches"],
+        "hbm": {"achieved": round(hbm, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(hfrac, 4)},
+        "alu": {"achieved": round(alu, 3), "peak": round(ALU_PEAK_TMULMOD, 3), "unit": "Tmulmod/s",
+                "frac": round(afrac, 4), "measured_peak_fp64": fp,
+                "frac_of_measured": round(alu / fp, 4) if fp else None},
+    })
+    # the key switch as a unit
+    ks = {n: prof[n] for n in kernels if n.startswith(KS_KERNELS)}
+    ks_t = sum(x["total_ms"] for x in ks.values()) * 1e-3
+    ks_mm = sum(x.get("mulmods", 0.0) for x in ks.values())
+    levels = {int(n[len("count:keyswitch_nl"):]): x["launches"] for n, x in prof.items()
+              if n.startswith("count:keyswitch_nl")}
+    n_ks = sum(levels.values())
+    algo = sum(c * ks_bytes(log_n, nl, n_p, alpha) for nl, c in levels.items())
+    if n_ks and ks_t > 0:
+        kh = algo / ks_t / 1e9
+        ka = ks_mm / ks_t / 1e12
+        roof["keyswitch"] = {
+            "kernels": sorted(ks), "keyswitches_per_step": n_ks / steps,
+            "per_level": {str(k): v / steps for k, v in sorted(levels.items())},
+            "algo_bytes_per_keyswitch": algo / n_ks, "mulmods_per_keyswitch": ks_mm / n_ks,
+            "time_ms_per_step": round(1000 * ks_t / steps, 2), "share_of_step": round(ks_t / steps / step_s, 4),
+            "us_per_keyswitch": round(1e6 * ks_t / n_ks, 2),
+            "hbm": {"achieved": round(kh, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(kh / HBM_PEAK_GBPS, 4)},
+            "alu": {"achieved": round(ka, 3), "peak": round(ALU_PEAK_TMULMOD, 3), "unit": "Tmulmod/s",
+                    "frac": round(ka / ALU_PEAK_TMULMOD, 4), "frac_of_measured": round(ka / fp, 4) if fp else None},
+        }
     return roof, kernels
 
 
-def run_batch(args) -> dict:
-    """Batched vs plain form of the batching workload on a bounded prefix of every matmul's plan.
+def mulmod_probe() -> dict:
+    from paper_2604_11659_amd import fhe
+    out = {}
+    for kind, name in ((0, "fp64"), (1, "shoup"), (2, "montgomery")):
+        out[f"{name}_Tmulmod_per_s"] = round(fhe.bench_mulmod(kind, 4096) / 1e12, 3)
+    out["derived_fp64_peak_Tmulmod_per_s"] = round(ALU_PEAK_TMULMOD, 3)
+    return out
 
-    The full workload (64 matmuls, about 2e7 matched pairs at N = 2^16) takes hours; here every matmul
-    runs its first `--batch-cap` matched pairs (all of them when it has fewer), once as one
-    fhe_spmspm_batch_pairs call and once as one fhe_spmspm_pairs call per matmul, on the same
-    ciphertexts and keys. SpMSpM/s is projected as measured pairs/s divided by the mean F of the full
-    matmuls."""
+
+def _close(ms):
+    for m in ms:
+        m.close()
+
+
+def run_headline(args) -> dict:
+    """Batched vs plain on the N = 2^16 batching workload, over seeded plan prefixes."""
+    w = synth.BATCH_WORKLOADS["batch"]
+    specs = w.specs()
+    mats = [w.operands(i, sp) for i, sp in enumerate(specs)]
+    F = [matched_pairs_count(a, b) for a, b in mats]
+    mean_f = sum(F) / len(F)
+    cores = min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count() or 1)
+    sample = cores if args.cpu_sample < 0 else args.cpu_sample
+    cpu = cpu_baseline_batch(w, specs, mats, mean_f, sample) if sample > 0 else None
+
+    import torch
+    from paper_2604_11659_amd import fhe
+    t0 = time.perf_counter()
+    ctx = fhe.Context(w.log_n, w.n_q, w.n_p, w.alpha, w.rot_digits)
+    sk = ctx.keygen(42)
+    As, Bs = [], []
+    for i, ((a, b), sp) in enumerate(zip(mats, specs)):
+        n = sp[0]
+        As.append(ctx.encrypt_csr(sk, n, n, *synth.to_csr(a), seed=10_000 + i))
+        Bs.append(ctx.encrypt_csc(sk, n, n, *synth.to_csc(b), seed=20_000 + i))
+    ranges = [(0, min(f, args.batch_cap)) for f in F]
+    pairs = sum(hi for _, hi in ranges)
+    tuned = ctx.autotune(As[0], Bs[0], pairs=args.autotune_pairs) if args.autotune else None
+    setup_s = time.perf_counter() - t0
+    log(f"setup {setup_s:.1f} s; {len(specs)} matmuls, F total {sum(F)}, pairs per step {pairs}; autotune {tuned}")
+
+    for _ in range(args.warmup):
+        _close(ctx.spmspm_batch(As, Bs, pair_ranges=ranges))
+        log("warmup step done")
+    torch.cuda.synchronize()
+    fhe.profile_enable(True)
+    t0 = time.perf_counter()
+    Cb = None
+    for _ in range(args.steps):
+        if Cb is not None:
+            _close(Cb)
+        Cb = ctx.spmspm_batch(As, Bs, pair_ranges=ranges)
+        log(f"timed step done at {time.perf_counter() - t0:.2f} s")
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    fhe.profile_enable(False)
+    prof = fhe.profile_read()
+    ks_step = prof.get("count:keyswitch", {}).get("launches", 0) / args.steps
+
+    # plain: the same prefixes as 64 single calls
+    psteps = args.plain_steps if args.plain_steps > 0 else max(2, args.steps // 4)
+    _close(ctx.spmspm_pairs(A, B, lo, hi) for A, B, (lo, hi) in zip(As, Bs, ranges))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Cp = None
+    for _ in range(psteps):
+        if Cp is not None:
+            _close(Cp)
+        Cp = [ctx.spmspm_pairs(A, B, lo, hi) for A, B, (lo, hi) in zip(As, Bs, ranges)]
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / psteps
+    log(f"batched {1000 * t_batch:.1f} ms/step, plain {1000 * t_plain:.1f} ms/step")
+    same = all((ctx.export(x, c) == ctx.export(y, c)).all() for x, y in zip(Cb, Cp) for c in range(x.info()["chunks"]))
+    err = 0.0
+    for i, C in enumerate(Cb):
+        a, b = mats[i]
+        err = max(err, float(np.abs(ctx.decrypt_decode(sk, C) - prefix_reference(a, b, ranges[i][1])).max()))
+    _close(Cb)
+    _close(Cp)
+    log(f"results bit-identical {same}; max-abs error vs FP64 over the prefixes {err:.3e}")
+
+    tree = None
+    if args.tree_steps > 0:  # digit-tree plan with hoisted alignment rotations (groups within each prefix)
+        _close(ctx.spmspm_batch(As, Bs, pair_ranges=ranges, tree=True, hoist=True))
+        t0 = time.perf_counter()
+        for _ in range(args.tree_steps):
+            Tb = ctx.spmspm_batch(As, Bs, pair_ranges=ranges, tree=True, hoist=True)
+            _close(Tb)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / args.tree_steps
+        t0 = time.perf_counter()
+        for _ in range(args.tree_steps):
+            _close([ctx.spmspm_pairs(A, B, lo, hi, tree=True, hoist=True) for A, B, (lo, hi) in zip(As, Bs, ranges)])
+        torch.cuda.synchronize()
+        tp = (time.perf_counter() - t0) / args.tree_steps
+        log(f"tree + hoisted: batched {1000 * tb:.1f} ms, plain {1000 * tp:.1f} ms")
+        tree = {"plan": "grouped target rotations shared digit by digit, hoisted alignment rotations (groups within "
+                        "each prefix; its own oracle mode)",
+                "value": round(pairs / tb / mean_f, 8), "batched_pairs_per_s": round(pairs / tb, 1),
+                "plain_pairs_per_s": round(pairs / tp, 1), "batched_ms_per_step": round(1000 * tb, 2),
+                "plain_ms_per_step": round(1000 * tp, 2), "batched_over_plain": round(tp / tb, 3),
+                "steps": args.tree_steps}
+    probe = mulmod_probe()
+    log(f"mulmod probe {probe}")
+    roof, kernels = roofline(prof, args.steps, w.log_n, w.n_p, w.alpha, t_batch, probe)
+    ctx.close()
+    del As, Bs
+    dnn = run_dnn_leg(args) if args.dnn else None
+    pb, pp = pairs / t_batch, pairs / t_plain
+    line = {
+        "metric": METRIC, "value": round(pb / mean_f, 8), "unit": "SpMSpM/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1000 * t_batch, 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic", "projected": True,
+        "config": {"workload": describe_batch(w), "plan": "per matched pair (Algorithm 2)",
+                   "prefix_pairs_per_matmul": args.batch_cap, "pairs_per_step": pairs, "full_pairs": sum(F),
+                   "mean_full_pairs_per_matmul": round(mean_f, 1), "parallelism": "single GPU, one batched call per step",
+                   "ntt_split_autotuned": tuned},
+        "batched": {"pairs_per_s": round(pb, 1), "spmspm_per_s_projected": pb / mean_f, "ms_per_step": round(1000 * t_batch, 2),
+                    "steps": args.steps},
+        "plain": {"pairs_per_s": round(pp, 1), "spmspm_per_s_projected": pp / mean_f, "ms_per_step": round(1000 * t_plain, 2),
+                  "steps": psteps},
+        "batched_over_plain": round(t_plain / t_batch, 3), "results_bit_identical": bool(same),
+        "max_abs_err_vs_fp64_prefix": err, "matched_pairs_per_s": round(pb, 1),
+        "keyswitches_per_step": ks_step, "keyswitch_per_s": round(ks_step / t_batch, 1),
+        "ntt_keyswitch_algo_GBps": roof.get("keyswitch", {}).get("hbm", {}).get("achieved"),
+        "setup_s": round(setup_s, 1),
+        "roofline": roof, "cpu_baseline": cpu, "mulmod_probe": probe, "tree_hoisted": tree, "dnn": dnn,
+    }
+    if args.kernels_out:
+        with open(args.kernels_out, "w") as f:
+            json.dump({"kernels": kernels}, f, indent=1)
+    return line
+
+
+def run_dnn_leg(args) -> dict:
+    """The DNN-layer workload (N = 2^15): one full matmul per step, per-pair plan and the digit-tree plan
+    with hoisted alignment rotations; reported beside the headline."""
+    import torch
+    from paper_2604_11659_amd import fhe
+    w = synth.WORKLOADS["dnn"]
+    a, b = w.operands()
+    ref = a @ b
+    ctx = fhe.Context(w.log_n, w.n_q, w.n_p, w.alpha, w.rot_digits)
+    sk = ctx.keygen(42)
+    A = ctx.encrypt_csr(sk, w.m, w.k, *synth.to_csr(a), seed=43)
+    B = ctx.encrypt_csc(sk, w.k, w.n, *synth.to_csc(b), seed=44)
+    st = ctx.plan_stats(A, B)
+    out = {"workload": describe(w), "matched_pairs": st.matched_pairs, "products": st.products,
+           "keyswitches_in_plan": st.keyswitches}
+    for key, kw in (("per_pair", {}), ("tree_hoisted", {"tree": True, "hoist": True})):
+        ctx.spmspm(A, B, **kw).close()  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.dnn_steps):
+            C = ctx.spmspm(A, B, **kw)
+            if _ < args.dnn_steps - 1:
+                C.close()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.dnn_steps
+        dec = ctx.decrypt_decode(sk, C)
+        C.close()
+        out[key] = {"value": round(1.0 / dt, 6), "unit": "SpMSpM/s", "ms_per_step": round(1000 * dt, 2),
+                    "steps": args.dnn_steps, "matched_pairs_per_s": round(st.matched_pairs / dt, 1),
+                    "max_abs_err": float(np.abs(dec - ref).max()),
+                    "frobenius_err": float(np.sqrt(((dec - ref) ** 2).sum()))}
+        log(f"dnn {key}: {1000 * dt:.1f} ms/step")
+    ctx.close()
+    return out
+
+
+def run_batch(args) -> dict:
+    """Batched vs plain on another batch workload (batch_small: the same shape at N = 2^13, full plans
+    by default), one timed call of each form."""
     import torch
     from paper_2604_11659_amd import fhe
     w = synth.BATCH_WORKLOADS[args.workload]
     specs = w.specs()
-    t0 = time.perf_counter()
     ctx = fhe.Context(w.log_n, w.n_q, w.n_p, w.alpha, w.rot_digits)
     sk = ctx.keygen(42)
-    As, Bs, F = [], [], []
+    As, Bs, F, mats = [], [], [], []
     for i, sp in enumerate(specs):
         a, b = w.operands(i, sp)
         n = sp[0]
+        mats.append((a, b))
         As.append(ctx.encrypt_csr(sk, n, n, *synth.to_csr(a), seed=10_000 + i))
         Bs.append(ctx.encrypt_csc(sk, n, n, *synth.to_csc(b), seed=20_000 + i))
         F.append(ctx.plan_stats(As[-1], Bs[-1]).matched_pairs)
-        if w.rot_digits == 1:  # per-amount rotation keys for the amounts this plan uses
+        if w.rot_digits == 1:
             ctx.keygen_rotations(sk, ctx.plan_rotations(As[-1], Bs[-1]))
-    setup_s = time.perf_counter() - t0
     ranges = [(0, min(f, args.batch_cap)) for f in F]
     pairs = sum(hi for _, hi in ranges)
-    log(f"setup {setup_s:.1f} s; {len(specs)} matmuls, F total {sum(F)}, prefix pairs {pairs}")
-    # warm-up (workspace allocation, code objects): the whole batched call when it is small, else a
-    # small prefix of two matmuls
-    warm = ranges if pairs <= 50_000 else [(0, min(8, f)) for f in F[:2]]
-    for C in ctx.spmspm_batch(As[: len(warm)], Bs[: len(warm)], pair_ranges=warm):
-        C.close()
+    _close(ctx.spmspm_batch(As, Bs, pair_ranges=ranges))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     Cb = ctx.spmspm_batch(As, Bs, pair_ranges=ranges)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
-    log(f"batched: {t_batch:.2f} s")
     t0 = time.perf_counter()
     Cp = [ctx.spmspm_pairs(A, B, lo, hi) for A, B, (lo, hi) in zip(As, Bs, ranges)]
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    log(f"plain: {t_plain:.2f} s")
-    # the batched call recorded once as a HIP graph and replayed
-    t_graph = None
-    if args.batch_graph > 0 or (args.batch_graph < 0 and pairs <= 50_000):
-        for C in ctx.spmspm_batch(As, Bs, pair_ranges=ranges, graph=True):
-            C.close()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        Cg = ctx.spmspm_batch(As, Bs, pair_ranges=ranges, graph=True)
-        torch.cuda.synchronize()
-        t_graph = time.perf_counter() - t0
-        log(f"batched, graph replay: {t_graph:.3f} s")
-        for C in Cg:
-            C.close()
-    same = all((ctx.export(x, c) == ctx.export(y, c)).all()
-               for x, y in list(zip(Cb, Cp))[:: max(1, len(Cb) // 8)] for c in range(x.info()["chunks"]))
-    for C in Cb + Cp:
-        C.close()
-    # the same prefixes with the digit-tree plan and hoisted alignment rotations (groups formed within
-    # each matmul's prefix)
-    tree = None
-    if args.batch_tree:
-        t0 = time.perf_counter()
-        Tb = ctx.spmspm_batch(As, Bs, pair_ranges=ranges, tree=True, hoist=True)
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        Tp = [ctx.spmspm_pairs(A, B, lo, hi, tree=True, hoist=True) for A, B, (lo, hi) in zip(As, Bs, ranges)]
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - t0
-        tsame = all((ctx.export(x, c) == ctx.export(y, c)).all()
-                    for x, y in list(zip(Tb, Tp))[:: max(1, len(Tb) // 8)] for c in range(x.info()["chunks"]))
-        log(f"tree: batched {tb:.2f} s, plain {tp:.2f} s")
-        tree = {"plan": "grouped target rotations shared digit by digit, hoisted alignment rotations",
-                "batched_pairs_per_s": round(pairs / tb, 1), "plain_pairs_per_s": round(pairs / tp, 1),
-                "batched_s": round(tb, 3), "plain_s": round(tp, 3), "batched_over_plain": round(tp / tb, 3),
-                "results_bit_identical": bool(tsame)}
+    _close(ctx.spmspm_batch(As, Bs, pair_ranges=ranges, graph=True))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Cg = ctx.spmspm_batch(As, Bs, pair_ranges=ranges, graph=True)
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    same = all((ctx.export(x, c) == ctx.export(y, c)).all() and (ctx.export(x, c) == ctx.export(z, c)).all()
+               for x, y, z in zip(Cb, Cp, Cg) for c in range(x.info()["chunks"]))
+    _close(Cb + Cp + Cg)
     mean_f = sum(F) / len(F)
-    pb, pp = pairs / t_batch, pairs / t_plain
-    return {
-        "metric": METRIC, "value": round(pb / mean_f, 8), "unit": "SpMSpM/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": round(1000 * t_batch, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u64", "data": "synthetic",
-        "config": {"workload": (f"{w.name}: {w.count} square matmuls, n from {list(w.sizes)}, per-operand sparsity "
-                                f"U[{w.sparsity[0]}, {w.sparsity[1]}], values U[-1,1]; CKKS N=2^{w.log_n}, "
-                                f"{w.n_q} x 50-bit Q + {w.n_p} x 60-bit P primes, alpha={w.alpha}, rotation "
-                                f"digits={w.rot_digits}"),
-                   "prefix_pairs_per_matmul": args.batch_cap, "pairs_run": pairs, "full_pairs": sum(F),
-                   "parallelism": "single GPU"},
-        "projected": pairs < sum(F),  # SpMSpM/s from a prefix of every plan
-        "batched": {"pairs_per_s": round(pb, 1), "spmspm_per_s_projected": pb / mean_f, "s": round(t_batch, 3)},
-        "plain": {"pairs_per_s": round(pp, 1), "spmspm_per_s_projected": pp / mean_f, "s": round(t_plain, 3)},
-        "batched_over_plain": round(t_plain / t_batch, 3),
-        "batched_graph": None if t_graph is None else {"pairs_per_s": round(pairs / t_graph, 1), "s": round(t_graph, 4),
-                                                       "over_plain": round(t_plain / t_graph, 3)},
-        "results_bit_identical": bool(same), "setup_s": round(setup_s, 1),
-        "tree": tree,
-    }
+    return {"metric": f"encrypted SpMSpM/s, {w.name} (batched vs plain)", "value": round(pairs / t_batch / mean_f, 6),
+            "unit": "SpMSpM/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+            "projected": pairs < sum(F),
+            "config": {"workload": describe_batch(w), "prefix_pairs_per_matmul": args.batch_cap, "pairs_run": pairs,
+                       "full_pairs": sum(F)},
+            "batched_ms": round(1000 * t_batch, 2), "plain_ms": round(1000 * t_plain, 2),
+            "graph_ms": round(1000 * t_graph, 2), "batched_over_plain": round(t_plain / t_batch, 3),
+            "graph_over_plain": round(t_plain / t_graph, 3), "results_bit_identical": bool(same)}
+
+
+def run_single(args) -> dict:
+    """One full matmul of a single workload per step (dnn, plain, large), with its roofline."""
+    import torch
+    from paper_2604_11659_amd import fhe
+    w = synth.WORKLOADS[args.workload]
+    a, b = w.operands()
+    ref = a @ b
+    ctx = fhe.Context(w.log_n, w.n_q, w.n_p, w.alpha, w.rot_digits)
+    sk = ctx.keygen(42)
+    A = ctx.encrypt_csr(sk, w.m, w.k, *synth.to_csr(a), seed=43)
+    B = ctx.encrypt_csc(sk, w.k, w.n, *synth.to_csc(b), seed=44)
+    if w.rot_digits == 1:
+        ctx.keygen_rotations(sk, ctx.plan_rotations(A, B))
+    st = ctx.plan_stats(A, B)
+    kw = {"grouped": args.plan == "grouped", "tree": args.plan == "tree", "hoist": args.hoist}
+    for _ in range(args.warmup):
+        ctx.spmspm(A, B, **kw).close()
+    torch.cuda.synchronize()
+    fhe.profile_enable(True)
+    t0 = time.perf_counter()
+    C = None
+    for _ in range(args.steps):
+        if C is not None:
+            C.close()
+        C = ctx.spmspm(A, B, **kw)
+        log(f"timed step done at {time.perf_counter() - t0:.2f} s")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    fhe.profile_enable(False)
+    prof = fhe.profile_read()
+    dec = ctx.decrypt_decode(sk, C)
+    C.close()
+    roof, kernels = roofline(prof, args.steps, w.log_n, w.n_p, w.alpha, dt, None)
+    if args.kernels_out:
+        with open(args.kernels_out, "w") as f:
+            json.dump({"kernels": kernels}, f, indent=1)
+    ks = prof.get("count:keyswitch", {}).get("launches", 0) / args.steps
+    return {"metric": f"encrypted SpMSpM/s, {w.name} workload (one full matmul per step)", "value": round(1 / dt, 6),
+            "unit": "SpMSpM/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1000 * dt, 2),
+            "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": describe(w), "plan": args.plan + (" + hoisted" if args.hoist else ""),
+                       "matched_pairs": st.matched_pairs, "products": st.products, "keyswitches": st.keyswitches},
+            "matched_pairs_per_s": round(st.matched_pairs / dt, 1), "keyswitches_executed": ks,
+            "keyswitch_per_s": round(ks / dt, 1), "max_abs_err": float(np.abs(dec - ref).max()),
+            "frobenius_err": float(np.sqrt(((dec - ref) ** 2).sum())), "roofline": roof}
 
 
 def run_sweep(args) -> dict:
     """Runtime against sparsity on the 16x16 workload (the shape of the paper's Table 1 / Fig. 4a):
-    for sparsity 0 %, 10 %, ..., 100 % in both operands, the CSR x CSC plan (per pair, and replayed
-    as a HIP graph) and the naive dense plan (every entry stored, zeros included, so all m k n
-    products run) on the same values; time per matmul, matched pairs and max-abs error."""
+    for sparsity 0 %, 10 %, ..., 100 % in both operands, the CSR x CSC plan (per pair, and replayed as a
+    HIP graph), the naive sparse plan (every entry stored; a product is skipped only where both entries
+    are zero) and the naive dense plan (every product) on the same values; time per matmul, matched
+    pairs and max-abs error."""
     import torch
     from paper_2604_11659_amd import fhe
     w = synth.WORKLOADS["plain"]
@@ -226,20 +546,28 @@ def run_sweep(args) -> dict:
         B = ctx.encrypt_csc(sk, w.k, w.n, *synth.to_csc(b), seed=44)
         Ad = ctx.encrypt_csr(sk, w.m, w.k, *synth.full_csr(a), seed=45)
         Bd = ctx.encrypt_csc(sk, w.k, w.n, *synth.full_csc(b), seed=46)
+        za, zb = synth.stored_nonzero_csr(a), synth.stored_nonzero_csc(b)
         ctx.keygen_rotations(sk, sorted(set(ctx.plan_rotations(A, B)) | set(ctx.plan_rotations(Ad, Bd))))
         F, Fd = ctx.plan_stats(A, B).matched_pairs, ctx.plan_stats(Ad, Bd).matched_pairs
+        Fs = ctx.plan_stats(Ad, Bd, nonzero_a=za, nonzero_b=zb).matched_pairs
         t_s, C = timed(lambda: ctx.spmspm(A, B))
         e_s = float(np.abs(ctx.decrypt_decode(sk, C) - a @ b).max())
         t_g, C = timed(lambda: ctx.spmspm(A, B, graph=True))
+        t_n, Cn = timed(lambda: ctx.spmspm_naive_sparse(Ad, Bd, za, zb))
+        e_n = float(np.abs(ctx.decrypt_decode(sk, Cn) - a @ b).max())
         t_d, Cd = timed(lambda: ctx.spmspm(Ad, Bd))
         e_d = float(np.abs(ctx.decrypt_decode(sk, Cd) - a @ b).max())
         C.close()
+        Cn.close()
         Cd.close()
-        rows.append({"sparsity": s, "matched_pairs": F, "dense_pairs": Fd, "csr_ms": round(1000 * t_s, 3),
-                     "csr_graph_ms": round(1000 * t_g, 3), "dense_ms": round(1000 * t_d, 3),
-                     "speedup_vs_dense": round(t_d / t_s, 2), "csr_max_abs_err": e_s, "dense_max_abs_err": e_d})
-        log(f"sparsity {pct}%: F={F} csr {1000 * t_s:.2f} ms (graph {1000 * t_g:.2f}), dense {1000 * t_d:.2f} ms")
-    return {"metric": "encrypted 16x16 SpMSpM time vs sparsity (CSR x CSC plan vs naive dense plan)",
+        rows.append({"sparsity": s, "matched_pairs": F, "naive_sparse_pairs": Fs, "dense_pairs": Fd,
+                     "csr_ms": round(1000 * t_s, 3), "csr_graph_ms": round(1000 * t_g, 3),
+                     "naive_sparse_ms": round(1000 * t_n, 3), "dense_ms": round(1000 * t_d, 3),
+                     "speedup_vs_dense": round(t_d / t_s, 2), "csr_max_abs_err": e_s,
+                     "naive_sparse_max_abs_err": e_n, "dense_max_abs_err": e_d})
+        log(f"sparsity {pct}%: F={F} csr {1000 * t_s:.2f} ms (graph {1000 * t_g:.2f}), naive sparse "
+            f"{1000 * t_n:.2f} ms ({Fs} pairs), dense {1000 * t_d:.2f} ms")
+    return {"metric": "encrypted 16x16 SpMSpM time vs sparsity (CSR x CSC vs naive sparse vs naive dense)",
             "unit": "ms per matmul", "n_gpus": 1, "higher_is_better": False, "dtype": "u64", "data": "synthetic",
             "config": {"workload": describe(w) + "; both operands at the same sparsity, seeds 0-3",
                        "repetitions": reps}, "rows": rows}
@@ -249,25 +577,28 @@ SERVE_PARAMS = [(16, 24, 3, 3, 3), (17, 35, 3, 3, 4)]  # (log_n, n_q, n_p, alpha
 
 
 def run_serve(args) -> dict:
-    """Request loop under Poisson arrivals: one server (worker thread + stream) per parameter set.
+    """Request loop under Poisson arrivals: ONE server over both parameter sets (N = 2^16 and 2^17,
+    keys resident, one shared HBM budget), requests alternating between them.
 
-    Requests alternate between the parameter sets (a 50/50 mix), have square sizes from
-    `--serve-sizes` and per-operand sparsity U[0.70, 0.95], values U[-1, 1]; operands are encrypted
-    and keys generated before the clock starts (resident). Phase 1 offers load at `--serve-load` of the
-    capacity measured from requests run alone and reports p50/p99 latency and throughput; phase 2
-    offers `--serve-rate` requests/s for `--serve-overload-s` seconds and reports how many were
-    admitted, completed and left queued when the window closed."""
+    Phase 1, the stated load: sizes from {64, 128, 256, 512}, per-operand sparsity U[0.70, 0.95],
+    Poisson arrivals at --serve-rate (20/s) for --serve-overload-s; reports arrivals and the admitted,
+    queued and completed counts when the window closes, then cancels what is left. Phase 2, latency:
+    the capacity of the server is measured on --serve-sizes requests run back to back (saturated), and
+    Poisson arrivals at --serve-load of it are served until at least --serve-min-complete requests have
+    completed; reports p50/p99 latency and throughput = completions / (last completion - first arrival)
+    beside the offered rate."""
     import torch
     from paper_2604_11659_amd import fhe
-    sizes = [int(x) for x in args.serve_sizes.split(",")]
     params = SERVE_PARAMS[: 2 if args.serve_mix else 1]
     t0 = time.perf_counter()
     ctxs = [fhe.Context(*p) for p in params]
     sks = [c.keygen(42) for c in ctxs]
     log(f"keys for {len(ctxs)} parameter sets in {time.perf_counter() - t0:.1f} s")
+    budget = args.serve_budget_gb << 30
+    tree = args.serve_plan == "tree_hoist"
     rng = np.random.Generator(np.random.PCG64(5))
 
-    def make(i):
+    def make(i, sizes):
         ci = i % len(ctxs)
         n = int(rng.choice(sizes))
         sa, sb = (float(x) for x in rng.uniform(0.70, 0.95, size=2))
@@ -275,293 +606,165 @@ def run_serve(args) -> dict:
         b = synth.sparse_dense(n, n, sb, "uniform", 7001 + 4 * i, 7003 + 4 * i)
         A = ctxs[ci].encrypt_csr(sks[ci], n, n, *synth.to_csr(a), seed=30_000 + i)
         B = ctxs[ci].encrypt_csc(sks[ci], n, n, *synth.to_csc(b), seed=40_000 + i)
-        return ci, A, B, a @ b
+        return ci, A, B, a, b
 
-    tree = args.serve_plan == "tree_hoist"
-    # capacity: a few requests of each parameter set alone
-    svc = []
-    for i in range(2 * len(ctxs)):
-        ci, A, B, _ = make(i)
-        ctxs[ci].spmspm(A, B, tree=tree, hoist=tree).close()  # first call per context allocates its workspace
-        torch.cuda.synchronize()
-        t = time.perf_counter()
+    def server():
+        return fhe.Server(ctxs, hbm_budget=budget, max_inflight=args.serve_inflight, slice_products=args.serve_slice,
+                          max_queue=1 << 16, tree=tree, hoist=tree)
+
+    # phase 1: the stated arrival process and sizes
+    stated = [int(x) for x in args.serve_stated_sizes.split(",")]
+    arr = synth.poisson_arrivals(args.serve_rate, args.serve_overload_s, 7)
+    reqs = [make(100_000 + i, stated) for i in range(len(arr))]
+    fpairs = [matched_pairs_count(a, b) for (_, _, _, a, b) in reqs]
+    srv = server()
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    tickets = []
+    for t_arr, (ci, A, B, _, _) in zip(arr, reqs):
+        dt = start + t_arr - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(A, B, ctx_id=ci))
+    dt = start + args.serve_overload_s - time.perf_counter()
+    if dt > 0:
+        time.sleep(dt)
+    at_close = srv.stats()
+    for t in tickets:
+        srv.cancel(t)
+    srv.close()
+    over = {"offered_req_per_s": args.serve_rate, "window_s": args.serve_overload_s, "sizes": stated,
+            "arrived": len(arr), "admitted": at_close["inflight"] + at_close["completed"] + at_close["failed"],
+            "completed": at_close["completed"], "in_flight_at_close": at_close["inflight"],
+            "queued_at_close": at_close["queued"], "mean_matched_pairs_per_request": float(np.mean(fpairs)),
+            "offered_matched_pairs_per_s": float(np.mean(fpairs)) * args.serve_rate,
+            "budget_bytes": at_close["budget_bytes"], "fixed_bytes": at_close["fixed_bytes"],
+            "inflight_bytes_at_close": at_close["inflight_bytes"]}
+    log(f"stated load: {over}")
+    del reqs
+
+    # phase 2: capacity (saturated) and latency at a fraction of it
+    sizes = [int(x) for x in args.serve_sizes.split(",")]
+    warm = [make(i, sizes) for i in range(len(ctxs))]
+    for (ci, A, B, _, _) in warm:  # first call per context sizes its workspace
         ctxs[ci].spmspm(A, B, tree=tree, hoist=tree).close()
-        torch.cuda.synchronize()
-        svc.append(time.perf_counter() - t)
-    t_req = float(np.mean(svc))
-    lam = args.serve_load / t_req
-    log(f"mean service time alone {t_req:.3f} s -> offered rate {lam:.3f} req/s")
-
-    def run_window(rate, window_s, seed, drain):
-        arrivals = synth.poisson_arrivals(rate, window_s, seed)
-        reqs = [make(1000 * seed + i) for i in range(len(arrivals))]
-        srvs = [fhe.Server(c, hbm_budget=args.serve_budget_gb << 30, max_inflight=8, slice_products=32,
-                           max_queue=4096, tree=tree, hoist=tree) for c in ctxs]
-        tickets = []
-        torch.cuda.synchronize()
-        start = time.perf_counter()
-        for t_arr, (ci, A, B, ref) in zip(arrivals, reqs):
-            dt = start + t_arr - time.perf_counter()
-            if dt > 0:
-                time.sleep(dt)
-            tickets.append((ci, srvs[ci].submit(A, B), ref))
-        at_close = [s.stats() for s in srvs]
-        lat, errs = [], []
-        if drain:
-            for ci, tk, ref in tickets:
-                C, l = srvs[ci].poll(tk, wait_ms=600_000)
-                lat.append(l)
-                if len(errs) < 4:
-                    errs.append(float(np.abs(ctxs[ci].decrypt_decode(sks[ci], C) - ref).max()))
-                C.close()
-        elapsed = time.perf_counter() - start
-        st = [s.stats() for s in srvs]
-        for s in srvs:
-            s.close()
-        return arrivals, lat, errs, elapsed, at_close, st
-
-    arr, lat, errs, el, _, st = run_window(lam, args.serve_window_s, 6, True)
-    steady = {"offered_req_per_s": round(lam, 4), "requests": len(arr), "completed": len(lat),
-              "throughput_req_per_s": round(len(lat) / el, 4),
-              "p50_s": round(float(np.percentile(lat, 50)), 4) if lat else None,
-              "p99_s": round(float(np.percentile(lat, 99)), 4) if lat else None,
-              "server_p50_p99_s": [(round(x["p50_s"], 4), round(x["p99_s"], 4)) for x in st],
+    sat = [make(200_000 + i, sizes) for i in range(args.serve_capacity_requests)]
+    srv = server()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tk = [srv.submit(A, B, ctx_id=ci) for (ci, A, B, _, _) in sat]
+    for t in tk:
+        srv.poll(t, wait_ms=600_000)[0].close()
+    cap = len(sat) / (time.perf_counter() - t0)
+    srv.close()
+    lam = args.serve_load * cap
+    log(f"capacity {cap:.3f} req/s (saturated, {len(sat)} requests); offered {lam:.3f} req/s")
+    n_req = args.serve_min_complete
+    arr = synth.poisson_arrivals(lam, 10 * n_req / lam, 6)[:n_req]
+    reqs = [make(300_000 + i, sizes) for i in range(len(arr))]
+    srv = server()
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    tickets = []
+    for t_arr, (ci, A, B, _, _) in zip(arr, reqs):
+        dt = start + t_arr - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(A, B, ctx_id=ci))
+    lat, errs, done_at = [], [], []
+    for (ci, _, _, a, b), t in zip(reqs, tickets):
+        C, l = srv.poll(t, wait_ms=600_000)
+        lat.append(l)
+        done_at.append(time.perf_counter())
+        if len(errs) < 8:
+            errs.append(float(np.abs(ctxs[ci].decrypt_decode(sks[ci], C) - a @ b).max()))
+        C.close()
+    st = srv.stats()
+    srv.close()
+    # completions over (last completion - first arrival); poll order is arrival order, so done_at is an
+    # upper bound of each completion time; the server's own latencies give the exact span
+    first_arrival = start + float(arr[0])
+    last_done = max(start + float(t_a) + l for t_a, l in zip(arr, lat))
+    steady = {"offered_req_per_s": round(lam, 4), "capacity_req_per_s": round(cap, 4), "sizes": sizes,
+              "requests": len(arr), "completed": len(lat),
+              "throughput_req_per_s": round(len(lat) / (last_done - first_arrival), 4),
+              "p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4),
+              "server_p50_p99_s": (round(st["p50_s"], 4), round(st["p99_s"], 4)),
+              "max_merged_requests": st["max_merged"], "max_step_requests": st["max_step_requests"],
               "max_abs_err_sampled": max(errs) if errs else None}
-    log(f"steady: {steady}")
-    arr2, _, _, el2, at_close, _ = run_window(args.serve_rate, args.serve_overload_s, 7, False)
-    over = {"offered_req_per_s": args.serve_rate, "window_s": args.serve_overload_s, "arrived": len(arr2),
-            "completed_in_window": sum(x["completed"] for x in at_close),
-            "in_flight_at_close": sum(x["inflight"] for x in at_close),
-            "queued_at_close": sum(x["queued"] for x in at_close), "wall_incl_inflight_drain_s": round(el2, 2)}
-    log(f"overload: {over}")
+    log(f"latency window: {steady}")
     return {
         "metric": "encrypted SpMSpM serving latency p50/p99 (s) under Poisson arrivals", "value": steady["p99_s"],
         "unit": "s (p99)", "n_gpus": 1, "higher_is_better": False, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": (f"serve: Poisson arrivals, square sizes {sizes}, per-operand sparsity U[0.70, 0.95], "
-                                f"values U[-1,1], parameter sets (log_n, n_q, n_p, alpha, digits) {params} "
-                                f"alternating; keys and operands resident"),
-                   "plan": ("grouped target rotations shared digit by digit, hoisted alignment rotations "
-                            "(each request whole in a step)" if tree else "per matched pair"),
-                   "capacity_req_per_s_alone": round(1.0 / t_req, 4)},
-        "steady": steady, "overload": over,
+        "config": {"workload": (f"serve: one server over parameter sets (log_n, n_q, n_p, alpha, digits) {params}, "
+                                f"requests alternating, per-operand sparsity U[0.70, 0.95], values U[-1,1], keys and "
+                                f"operands resident, one HBM budget of {args.serve_budget_gb} GiB"),
+                   "plan": ("digit tree + hoisted alignment rotations (each request whole in a step)" if tree
+                            else "per matched pair"),
+                   "max_inflight": args.serve_inflight, "slice_products": args.serve_slice},
+        "stated_load": over, "latency": steady,
     }
-
-
-def run_graph(ctx, A, B, steps: int) -> dict:
-    """The per-pair plan recorded once as a HIP graph (FHE_PLAN_GRAPH) and replayed: one launch per
-    matmul instead of one per kernel; the limbs are those of the eager form."""
-    import torch
-    t0 = time.perf_counter()
-    C = ctx.spmspm(A, B, graph=True)  # records the graph, then launches it
-    torch.cuda.synchronize()
-    rec = time.perf_counter() - t0
-    C.close()
-    t0 = time.perf_counter()
-    C = None
-    for _ in range(steps):
-        if C is not None:
-            C.close()
-        C = ctx.spmspm(A, B, graph=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    C.close()
-    log(f"graph: record + first launch {1000 * rec:.1f} ms, replay {1000 * dt / steps:.2f} ms/step")
-    return {"plan": "per-pair, HIP graph replay", "value": round(steps / dt, 6), "unit": "SpMSpM/s",
-            "steps": steps, "ms_per_step": round(1000 * dt / steps, 3), "record_and_first_ms": round(1000 * rec, 1)}
-
-
-def run_grouped(ctx, sk, A, B, st, ref, steps: int, tree: bool = False, hoist: bool = False) -> dict:
-    """The grouped plan on the same operands: masked products sharing (result chunk, target rotation)
-    summed, then one rescale and one rotation per group. Different ciphertext bits from the per-pair
-    plan (its own oracle mode), same decryption up to noise."""
-    import torch
-    groups, gks, tks = ctx.plan_groups(A, B)
-    if tree:
-        gks = tks
-    C = ctx.spmspm(A, B, grouped=True, tree=tree, hoist=hoist)  # warm-up (allocates the resident products)
-    C.close()
-    torch.cuda.synchronize()
-    log(f"grouped warm-up done: {groups} groups, {gks} target key switches")
-    from paper_2604_11659_amd import fhe
-    fhe.profile_enable(True)
-    t0 = time.perf_counter()
-    C = None
-    for _ in range(steps):
-        if C is not None:
-            C.close()
-        C = ctx.spmspm(A, B, grouped=True, tree=tree, hoist=hoist)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    fhe.profile_enable(False)
-    prof = fhe.profile_read()
-    ks = prof.get("count:keyswitch", {}).get("launches", 0) / steps
-    _, kernels = roofline(prof)
-    dec = ctx.decrypt_decode(sk, C)
-    C.close()
-    v = steps / dt
-    log(f"{'tree' if tree else 'grouped'}{' hoisted' if hoist else ''}: {1000 * dt / steps:.1f} ms/step")
-    return {"plan": "grouped target rotations" + (", shared digit by digit" if tree else "") +
-            (", hoisted alignment rotations" if hoist else ""), "value": round(v, 6), "unit": "SpMSpM/s", "steps": steps,
-            "ms_per_step": round(1000 * dt / steps, 2), "groups": groups, "target_keyswitches": gks,
-            "keyswitches_executed": ks, "matched_pairs_per_s": round(st.matched_pairs * v, 1),
-            "keyswitch_per_s": round(ks * v, 1), "max_abs_err": float(np.abs(dec - ref).max()),
-            "frobenius_err": float(np.sqrt(((dec - ref) ** 2).sum()))}, kernels
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dnn", choices=sorted(synth.WORKLOADS) + sorted(synth.BATCH_WORKLOADS))
-    ap.add_argument("--batch-cap", type=int, default=256, help="batching workload: matched pairs run per matmul")
-    ap.add_argument("--batch-graph", type=int, default=-1,
-                    help="batching workload: also time the batched call replayed as a HIP graph "
-                         "(-1: when the batch is small)")
-    ap.add_argument("--batch-tree", type=int, default=1,
-                    help="batching workload: also time the digit-tree plan with hoisted alignment rotations")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="batch", choices=sorted(synth.WORKLOADS) + sorted(synth.BATCH_WORKLOADS))
+    ap.add_argument("--batch-cap", type=int, default=32, help="batching workloads: matched pairs run per matmul")
+    ap.add_argument("--plain-steps", type=int, default=0, help="headline: timed plain steps (0: max(2, steps / 4))")
+    ap.add_argument("--tree-steps", type=int, default=2, help="headline: timed steps of the tree + hoisted plan")
+    ap.add_argument("--dnn", type=int, default=1, help="headline: also run the DNN-layer workload (N = 2^15)")
+    ap.add_argument("--dnn-steps", type=int, default=1)
     ap.add_argument("--autotune", type=int, default=1, help="1: pick the NTT split by timing (untimed set-up)")
-    ap.add_argument("--autotune-pairs", type=int, default=4000, help="matched pairs timed per candidate split")
-    ap.add_argument("--serve", action="store_true", help="run the request-loop benchmark instead")
-    ap.add_argument("--sweep", action="store_true",
-                    help="run the 16x16 sparsity sweep (CSR x CSC plan vs naive dense plan) instead")
-    ap.add_argument("--serve-mix", type=int, default=1, help="1: N=2^16 and N=2^17 parameter sets, 0: N=2^16 only")
-    ap.add_argument("--serve-sizes", default="16,32")
-    ap.add_argument("--serve-load", type=float, default=0.7, help="offered load as a fraction of capacity")
-    ap.add_argument("--serve-window-s", type=float, default=40.0)
-    ap.add_argument("--serve-rate", type=float, default=20.0, help="overload phase arrival rate (req/s)")
-    ap.add_argument("--serve-overload-s", type=float, default=3.0)
-    ap.add_argument("--serve-budget-gb", type=int, default=16)
-    ap.add_argument("--serve-plan", default="per_pair", choices=["per_pair", "tree_hoist"],
-                    help="plan of the served requests")
-    ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle pairs to time (0 = skip, -1 = one per core)")
+    ap.add_argument("--autotune-pairs", type=int, default=64, help="matched pairs timed per candidate split")
+    ap.add_argument("--cpu-sample", type=int, default=-1,
+                    help="oracle pairs on as many processes (0 = skip, -1 = one per core up to 16)")
     ap.add_argument("--kernels-out", default=None, help="write per-kernel timings (JSON) here")
     ap.add_argument("--plan", default="per_pair", choices=["per_pair", "grouped", "tree"],
-                    help="plan of the timed steps: Algorithm 2 per matched pair, grouped target rotations, or "
-                         "grouped with digit-shared rotations (then the other legs are skipped)")
-    ap.add_argument("--hoist", action="store_true",
-                    help="hoisted alignment rotations in the timed steps (changes the limbs: its own oracle mode)")
-    ap.add_argument("--graph-steps", type=int, default=2,
-                    help="also time this many replays of the per-pair plan recorded as one HIP graph (0 = skip)")
-    ap.add_argument("--tree-steps", type=int, default=2,
-                    help="also time this many steps of the grouped plan with its target rotations shared digit "
-                         "by digit (0 = skip)")
-    ap.add_argument("--grouped-steps", type=int, default=2,
-                    help="also time this many steps of the grouped plan (one rescale and rotation per result "
-                         "chunk and target rotation; 0 = skip), after one warm-up step")
+                    help="single workloads: plan of the timed steps")
+    ap.add_argument("--hoist", action="store_true", help="single workloads: hoisted alignment rotations")
     ap.add_argument("--copy-calibrate", action="store_true",
-                    help="run one 1 GiB device-to-device tensor copy first (reference kernel for HBM counters)")
+                    help="run one 1 GiB copy-like kernel first (reference kernel for HBM counters)")
+    ap.add_argument("--serve", action="store_true", help="run the request-loop benchmark instead")
+    ap.add_argument("--sweep", action="store_true", help="run the 16x16 sparsity sweep instead")
+    ap.add_argument("--serve-mix", type=int, default=1, help="1: N=2^16 and N=2^17 parameter sets, 0: N=2^16 only")
+    ap.add_argument("--serve-stated-sizes", default="64,128,256,512")
+    ap.add_argument("--serve-sizes", default="8,16", help="latency window request sizes")
+    ap.add_argument("--serve-load", type=float, default=0.7, help="latency window load as a fraction of capacity")
+    ap.add_argument("--serve-min-complete", type=int, default=60)
+    ap.add_argument("--serve-capacity-requests", type=int, default=24)
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="stated arrival rate (req/s)")
+    ap.add_argument("--serve-overload-s", type=float, default=10.0)
+    ap.add_argument("--serve-budget-gb", type=int, default=200)
+    ap.add_argument("--serve-inflight", type=int, default=8)
+    ap.add_argument("--serve-slice", type=int, default=32)
+    ap.add_argument("--serve-plan", default="per_pair", choices=["per_pair", "tree_hoist"])
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of the "
-              "matched pairs is a design note, not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the matched pairs over "
+              "several GPUs is a design note, not built.", file=sys.stderr)
         sys.exit(2)
-
-    if args.serve:
-        print(json.dumps(run_serve(args)), flush=True)
-        return
-    if args.sweep:
-        print(json.dumps(run_sweep(args)), flush=True)
-        return
-    if args.workload in synth.BATCH_WORKLOADS:
-        print(json.dumps(run_batch(args)), flush=True)
-        return
-    w = synth.WORKLOADS[args.workload]
-    a, b = w.operands()
-    ref = a @ b
-    cores = min(16, os.cpu_count() or 1)
-    sample = cores if args.cpu_sample < 0 else args.cpu_sample
-    cpu = cpu_baseline(w, a, b, sample, cores) if sample > 0 else None
-    log(f"cpu baseline done: {cpu}")
-
-    import torch
-    from paper_2604_11659_amd import fhe
     if args.copy_calibrate:
-        # Plain copy-like kernels of known size: 2^27 int64 words (1 GiB) read and 1 GiB written, once
-        # as a device-to-device copy and once as an elementwise kernel (bitwise not).
+        import torch
+        # a plain copy-like kernel of known size: 2^27 int64 words (1 GiB) read and 1 GiB written
         src = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
         torch.bitwise_not(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-        log("copy calibration done (1 GiB read + 1 GiB written, twice)")
-    ipa, ixa, va = synth.to_csr(a)
-    ipb, ixb, vb = synth.to_csc(b)
-    t0 = time.perf_counter()
-    ctx = fhe.Context(w.log_n, w.n_q, w.n_p, w.alpha, w.rot_digits)
-    sk = ctx.keygen(42)
-    A = ctx.encrypt_csr(sk, w.m, w.k, ipa, ixa, va, seed=43)
-    B = ctx.encrypt_csc(sk, w.k, w.n, ipb, ixb, vb, seed=44)
-    if w.rot_digits == 1:
-        ctx.keygen_rotations(sk, ctx.plan_rotations(A, B))
-    # schedule choice only (results are unchanged): time a prefix of this matmul's own plan per split
-    tuned = ctx.autotune(A, B, pairs=args.autotune_pairs) if args.autotune else None
-    log(f"autotune: {tuned}")
-    setup_s = time.perf_counter() - t0
-    st = ctx.plan_stats(A, B)
-    log(f"setup {setup_s:.1f} s; plan {st}")
-
-    grouped, tree = args.plan in ("grouped", "tree"), args.plan == "tree"
-    if grouped or args.hoist:
-        args.graph_steps = args.grouped_steps = args.tree_steps = 0
-    C = None
-    for _ in range(args.warmup):
-        C = ctx.spmspm(A, B, grouped=grouped, tree=tree, hoist=args.hoist)
-        C.close()
-        log("warmup step done")
-    torch.cuda.synchronize()
-    fhe.profile_enable(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        if C is not None:
-            C.close()
-        C = ctx.spmspm(A, B, grouped=grouped, tree=tree, hoist=args.hoist)
-        log(f"timed step done at {time.perf_counter() - t0:.2f} s")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    fhe.profile_enable(False)
-    prof = fhe.profile_read()
-    dec = ctx.decrypt_decode(sk, C)
-    err = float(np.abs(dec - ref).max())
-    frob = float(np.sqrt(((dec - ref) ** 2).sum()))
-
-    value = args.steps / dt
-    roof, kernels = roofline(prof)
-    # NTT and key-switch kernels together (every transform phase, ModUp, ModDown and the fused inner
-    # product / combine): algorithmic bytes over their summed launch time
-    executed_ks = prof.get("count:keyswitch", {}).get("launches", 0) / args.steps
-    ks = [r for n, r in prof.items() if n.startswith(("ntt_", "modup", "moddown"))]
-    ks_bytes, ks_ms = sum(r["bytes"] for r in ks), sum(r["total_ms"] for r in ks)
-    line = {
-        "metric": METRIC, "value": round(value, 6), "unit": "SpMSpM/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(1000 * dt / args.steps, 2), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": describe(w),
-                   "plan": ("grouped target rotations, shared digit by digit" if tree else
-                            "grouped target rotations" if grouped else "per matched pair") +
-                           (", hoisted alignment rotations" if args.hoist else ""),
-                   "matched_pairs": st.matched_pairs, "products": st.products,
-                   "keyswitches": st.keyswitches, "parallelism": "single GPU, batched launches",
-                   "ntt_split_autotuned": tuned},
-        "matched_pairs_per_s": round(st.matched_pairs * value, 1),
-        "keyswitch_per_s": round(executed_ks * value, 1), "keyswitches_executed": executed_ks,
-        "ntt_keyswitch_algo_GBps": round(ks_bytes / (ks_ms * 1e6), 1) if ks_ms > 0 else None,
-        "ntt_keyswitch_time_frac": round(ks_ms / (1000 * dt), 4),
-        "max_abs_err": err, "frobenius_err": frob, "setup_s": round(setup_s, 2),
-        "roofline": roof, "cpu_baseline": cpu,
-    }
-    gkernels = None
-    if args.graph_steps > 0:
-        line["graph"] = run_graph(ctx, A, B, args.graph_steps)
-    if args.grouped_steps > 0:
-        line["grouped"], gkernels = run_grouped(ctx, sk, A, B, st, ref, args.grouped_steps)
-    if args.tree_steps > 0:
-        line["tree"], _ = run_grouped(ctx, sk, A, B, st, ref, args.tree_steps, tree=True)
-        line["tree_hoisted"], _ = run_grouped(ctx, sk, A, B, st, ref, args.tree_steps, tree=True, hoist=True)
-    if args.kernels_out:
-        with open(args.kernels_out, "w") as f:
-            json.dump({"kernels": kernels, "grouped_kernels": gkernels, "plan": st.__dict__}, f, indent=1)
+        log("copy calibration done (1 GiB read + 1 GiB written)")
+    if args.serve:
+        line = run_serve(args)
+    elif args.sweep:
+        line = run_sweep(args)
+    elif args.workload == "batch":
+        line = run_headline(args)
+    elif args.workload in synth.BATCH_WORKLOADS:
+        line = run_batch(args)
+    else:
+        line = run_single(args)
     print(json.dumps(line), flush=True)
 
 

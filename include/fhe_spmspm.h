@@ -48,6 +48,7 @@ extern "C" {
 #define FHE_ENOMEM (-5)  /* device allocation failed */
 #define FHE_EAGAIN (-6)  /* resource temporarily unavailable */
 #define FHE_EDEVICE (-7) /* HIP runtime error */
+#define FHE_ECANCELED (-8) /* the request was cancelled (server closed before admitting it) */
 
 typedef struct fhe_ctx fhe_ctx; /* parameters, device tables and evaluation keys (server side) */
 typedef struct fhe_sk fhe_sk;   /* secret key (client side) */
@@ -186,6 +187,22 @@ int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, co
 int fhe_spmspm_plan(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fhe_mat* const* B,
                     const int64_t* pair_begin, const int64_t* pair_end, int32_t mode, void* stream, fhe_mat** C_out);
 
+/* The naive sparse method of the paper's evaluation (Section 4, method (ii)), on the same executor: the
+ * multiplication stays element-wise, and a product is skipped only where both of its entries are
+ * zero. A and B store every entry they may multiply (typically all m k and k n entries, zeros
+ * included, as CSR / CSC patterns); nonzero_a[A.nnz] and nonzero_b[B.nnz] (host arrays, one byte per
+ * stored entry in packing order: 1 = nonzero, 0 = zero) give the public zero pattern. Every matched
+ * pair of Algorithm 1's traversal whose two entries are not both zero runs Algorithm 2 exactly as in
+ * fhe_spmspm, so C's limbs are those of that per-pair sequence over the kept pairs (with every flag 1
+ * this is fhe_spmspm, the naive dense method when every entry is stored). Errors as fhe_spmspm,
+ * FHE_EINVAL for a NULL flag array of a non-empty operand. */
+int fhe_spmspm_naive_sparse(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, const uint8_t* nonzero_a,
+                            const uint8_t* nonzero_b, void* stream, fhe_mat** C_out);
+
+/* Plan statistics of fhe_spmspm_naive_sparse (as fhe_plan_stats, over the kept pairs). */
+int fhe_plan_stats_naive_sparse(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, const uint8_t* nonzero_a,
+                                const uint8_t* nonzero_b, int64_t counts[6]);
+
 /* Autotuner (batch scheduler): picks the NTT split 2^k1 x 2^(log_n - k1) for ctx by timing every
  * admissible one (k1 in [max(1, log_n - 9), min(9, log_n - 1)]); keeps the current split unless
  * another is at least 2% faster. Every split computes the same transform, so results are unchanged;
@@ -255,42 +272,75 @@ int fhe_ct_mask(fhe_ctx* ctx, const fhe_ct* ct, int32_t slot, void* stream, fhe_
 int fhe_ct_add(fhe_ctx* ctx, const fhe_ct* a, const fhe_ct* b, void* stream, fhe_ct** out);
 void fhe_ct_free(fhe_ct* ct);
 
-/* ---- Request loop with continuous batching. ---- */
+
+/* ---- Request loop with continuous batching (Section 3: ciphertexts and keys stay on the GPU). ---- */
 
 typedef struct fhe_server fhe_server;
 
-/* Starts a serving loop on ctx (a worker thread with its own HIP stream). Requests are admitted while
- * fewer than max_inflight are running and the sum of their result buffers stays within hbm_budget
- * bytes (operands and keys are already resident). Each scheduling step runs the next
- * slice_products products (with all their matched pairs) of every admitted request as one merged
- * launch stream, so a request that arrives while others run joins the next step. At most max_queue
- * requests wait for admission. Errors: FHE_EINVAL, FHE_EDEVICE. */
-int fhe_server_create(fhe_ctx* ctx, size_t hbm_budget, int32_t max_inflight, int32_t slice_products,
-                      int32_t max_queue, fhe_server** out);
+/* Starts a serving loop over nctx contexts (parameter sets with their evaluation keys resident, all on
+ * one GPU): a worker thread with its own HIP stream serves the requests of every context. Requests
+ * wait in one arrival-order queue (at most max_queue) and are admitted while fewer than max_inflight
+ * run and the server's memory stays within hbm_budget bytes, one budget shared by all contexts:
+ *   - charged once, at creation: each context's constant tables and evaluation keys, and each
+ *     context's executor scratch, capped at workspace_bytes per context (0: automatic, a quarter of
+ *     what the budget leaves after the keys divided among the contexts, at most FHE_WORKSPACE_MB);
+ *     the requests of one context share that scratch within a step. A larger scratch left on a
+ *     context by earlier calls is released. Grouped plans (fhe_server_set_plan) add the tail's
+ *     second ping-pong buffers to this part;
+ *   - charged per request from admission to completion: its result chunks (2 (n_q - 2) N words each)
+ *     and, for grouped plans, its products kept resident (2 (n_q - 1) N words each) and, for the
+ *     digit tree, its partial sums.
+ * Each scheduling step runs, per context, the next slice_products products (with all their matched
+ * pairs) of every admitted request of that context as one merged launch stream, so a request that
+ * arrives while others run joins the next step. Errors: FHE_EINVAL (NULL or out-of-range arguments,
+ * contexts on different devices), FHE_ENOMEM (the fixed part exceeds hbm_budget), FHE_EDEVICE. */
+int fhe_server_create(fhe_ctx* const* ctxs, size_t nctx, size_t hbm_budget, size_t workspace_bytes,
+                      int32_t max_inflight, int32_t slice_products, int32_t max_queue, fhe_server** out);
 
 /* Plan mode of the server's requests (FHE_PLAN_PER_PAIR, FHE_PLAN_GROUPED or FHE_PLAN_TREE, optionally
  * or-ed with FHE_PLAN_HOIST; not FHE_PLAN_GRAPH). Grouped and tree plans run every request as one
- * slice (all of its products in one step, merged with the other requests of that step); each result
- * is bit-identical to fhe_spmspm_plan in the same mode. Only before the first submission: FHE_EAGAIN
- * afterwards; FHE_EINVAL for an unknown mode. */
+ * slice (all of its products in one step, merged with the other requests of that context in that step);
+ * each result is bit-identical to fhe_spmspm_plan in the same mode. Only before the first submission:
+ * FHE_EAGAIN afterwards; FHE_EINVAL for an unknown mode; FHE_ENOMEM if the grouped tail buffers do
+ * not fit the budget. */
 int fhe_server_set_plan(fhe_server* s, int32_t mode);
 
-/* Queues C = A B (A: CSR handle, B: CSC handle; both must stay alive until the request is polled).
- * Returns a ticket. Errors: FHE_EAGAIN (queue full), FHE_EINVAL, FHE_ESHAPE. */
-int fhe_server_submit(fhe_server* s, const fhe_mat* A, const fhe_mat* B, uint64_t* ticket);
+/* Queues C = A B on context ctxs[ctx_id] (A: CSR handle, B: CSC handle of that context; both must stay
+ * alive until the request is polled). Returns a ticket. In the per-pair plan the request's plan
+ * (Algorithm 1's merge) is built by the worker at admission, so submission costs O(1); grouped plans
+ * build it here, since their charge depends on it. Errors: FHE_EAGAIN (queue full), FHE_ENOMEM
+ * (the request's own charge does not fit the budget even with nothing else in flight), FHE_EINVAL
+ * (bad handle kinds or ctx_id), FHE_ESHAPE (A.cols != B.rows). */
+int fhe_server_submit(fhe_server* s, int32_t ctx_id, const fhe_mat* A, const fhe_mat* B, uint64_t* ticket);
 
 /* Waits up to wait_ms for the ticket. FHE_OK: *C_out receives the result (bit-identical to
- * fhe_spmspm, or fhe_spmspm_plan in the server's plan mode, on the same operands) and *latency_s the submit-to-completion time; the ticket is
- * retired. FHE_EAGAIN: not finished yet. Other codes: the request failed (FHE_ENOMEM if its result
- * exceeds the whole budget, FHE_EKEY for a missing rotation key) and the ticket is retired. */
+ * fhe_spmspm, or to fhe_spmspm_plan in the server's plan mode, on the same operands) and *latency_s
+ * the submit-to-completion time; the ticket is retired. FHE_EAGAIN: not finished yet. FHE_ECANCELED:
+ * the server was closed before the request was admitted; the ticket is retired. Other codes: the
+ * request failed (for instance FHE_EKEY for a missing rotation key) and the ticket is retired. */
 int fhe_server_poll(fhe_server* s, uint64_t ticket, int32_t wait_ms, fhe_mat** C_out, double* latency_s);
 
-/* Latency percentiles (seconds) over completed requests, and the completed / in-flight / queued counts. */
-int fhe_server_stats(fhe_server* s, double* p50_s, double* p99_s, int64_t* completed, int64_t* inflight,
-                     int64_t* queued);
+/* Cancels a request: one still waiting for admission at once, one in flight at the next step
+ * boundary (its partial result is dropped and its memory released); its poll then returns
+ * FHE_ECANCELED. A request already finished keeps its outcome. Errors: FHE_EINVAL (unknown ticket). */
+int fhe_server_cancel(fhe_server* s, uint64_t ticket);
 
-/* Cancels the requests still waiting for admission, lets the admitted ones run to the end, stops the
- * worker and frees the server (result handles not yet polled are released with it). */
+typedef struct fhe_server_info {
+  double p50_s, p99_s;        /* latency percentiles over completed requests (0 if none) */
+  int64_t completed, failed, cancelled, inflight, queued;
+  int64_t steps;              /* scheduling steps that ran work */
+  int64_t max_merged;         /* most requests of one context merged into one launch stream */
+  int64_t max_step_requests;  /* most requests (all contexts) served by one step */
+  size_t budget_bytes, fixed_bytes, inflight_bytes; /* the budget, its fixed part, the admitted requests' charges */
+} fhe_server_info;
+
+/* Snapshot of the server's counters. Errors: FHE_EINVAL. */
+int fhe_server_stats(fhe_server* s, fhe_server_info* out);
+
+/* Cancels the requests still waiting for admission (their polls return FHE_ECANCELED), lets the
+ * admitted ones run to the end, stops the worker, wakes the threads waiting in fhe_server_poll and
+ * waits for them to return, then frees the server (result handles not yet polled are released with
+ * it). No call on s may start once fhe_server_free has been called. */
 void fhe_server_free(fhe_server* s);
 
 /* ---- Measurement hooks (not part of the method). ---- */
@@ -305,11 +355,22 @@ typedef struct fhe_kernel_stat {
   int64_t launches;     /* recorded launches */
   double total_ms;      /* sum of event-measured durations */
   double bytes;         /* sum of the launches' algorithmic HBM bytes (reads + writes the kernel must do) */
+  double mulmods;       /* sum of the launches' modular products (NTT butterflies, pointwise and
+                           base-conversion products; 0 for kernels that are not counted) */
 } fhe_kernel_stat;
 
 /* Aggregates the records per kernel name into out[cap] (synchronises on the recorded events);
  * returns the number of distinct kernels (entries beyond cap are not written). */
 int fhe_profile_read(fhe_kernel_stat* out, size_t cap);
+
+/* Throughput probe of the modular products the kernels use, for stating ALU bounds: runs 8
+ * independent chains of `iters` dependent products per thread over a full grid on `device` and
+ * writes the products per second of the second of two launches into *per_s. kind 0: the FP64 product
+ * of the Q primes (q < 2^50: quotient estimate from a precomputed w/q, remainder recovered exactly by
+ * two FMAs), 1: the lazy Shoup product of the special primes (p < 2^61), 2: the Montgomery product
+ * (R = 2^64) of the special primes' key words. Allocates device memory. Errors: FHE_EINVAL,
+ * FHE_EDEVICE. */
+int fhe_bench_mulmod(int32_t device, int32_t kind, int32_t iters, void* stream, double* per_s);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* fhe_last_error(void);

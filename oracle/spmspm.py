@@ -90,6 +90,17 @@ def matched_pairs(m: int, n: int, indptr_a, indices_a, indptr_b, indices_b) -> l
     return pairs
 
 
+def naive_sparse_pairs(m: int, n: int, indptr_a, indices_a, indptr_b, indices_b, nonzero_a, nonzero_b) -> list:
+    """The naive sparse method of the paper's evaluation (Section 4, method (ii)): the multiplication
+    stays element-wise over the stored entries, and a product is skipped only when BOTH of its values
+    are zero. The operands store every entry they may multiply (for the method as evaluated, all m k
+    and k n entries, zeros included); nonzero_a / nonzero_b flag the stored entries (packing order)
+    whose value is nonzero, which is public. Returns the matched pairs of Algorithm 1's traversal over
+    the stored patterns, less those whose two entries are both flagged zero, in traversal order."""
+    return [pr for pr in matched_pairs(m, n, indptr_a, indices_a, indptr_b, indices_b)
+            if nonzero_a[pr[2]] or nonzero_b[pr[3]]]
+
+
 def alignment(params: Params, a_pos: int, b_pos: int):
     """(chunk of A, chunk of B, rotation of A, rotation of B, min local position).
     Only the operand whose value sits at the larger local slot is rotated, by the

@@ -254,6 +254,41 @@ int fhe_plan_stats(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t cou
   });
 }
 
+int fhe_spmspm_naive_sparse(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, const uint8_t* nonzero_a,
+                            const uint8_t* nonzero_b, void* stream, fhe_mat** C_out) {
+  return guarded([&] {
+    need(ctx, "ctx");
+    need(C_out, "C_out");
+    *C_out = nullptr;
+    check_operands(A, B);
+    if (A->nnz) need(nonzero_a, "nonzero_a");
+    if (B->nnz) need(nonzero_b, "nonzero_b");
+    set_dev(ctx);
+    std::unique_ptr<fhe_mat> C(new fhe_mat());
+    std::vector<Job> jobs(1);
+    static const uint8_t none = 0;
+    jobs[0] = Job{A, B, build_plan(ctx->p, A, B, 0, INT64_MAX, nonzero_a ? nonzero_a : &none,
+                                   nonzero_b ? nonzero_b : &none),
+                  C.get()};
+    execute_jobs(ctx, jobs, as_stream(stream));
+    *C_out = C.release();
+  });
+}
+
+int fhe_plan_stats_naive_sparse(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, const uint8_t* nonzero_a,
+                                const uint8_t* nonzero_b, int64_t counts[6]) {
+  return guarded([&] {
+    need(ctx, "ctx");
+    need(counts, "counts");
+    check_operands(A, B);
+    if (A->nnz) need(nonzero_a, "nonzero_a");
+    if (B->nnz) need(nonzero_b, "nonzero_b");
+    static const uint8_t none = 0;
+    Plan plan = build_plan(ctx->p, A, B, 0, INT64_MAX, nonzero_a ? nonzero_a : &none, nonzero_b ? nonzero_b : &none);
+    plan_counts(ctx->p, plan, counts);
+  });
+}
+
 int fhe_plan_groups(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int64_t counts[3]) {
   return guarded([&] {
     need(ctx, "ctx");
@@ -525,13 +560,23 @@ int fhe_profile_read(fhe_kernel_stat* out, size_t cap) {
     n = (int)rows.size();
     for (size_t i = 0; i < rows.size() && out && i < cap; ++i) {
       memset(&out[i], 0, sizeof(out[i]));
-      strncpy(out[i].name, std::get<0>(rows[i]).c_str(), sizeof(out[i].name) - 1);
-      out[i].launches = std::get<1>(rows[i]);
-      out[i].total_ms = std::get<2>(rows[i]);
-      out[i].bytes = std::get<3>(rows[i]);
+      strncpy(out[i].name, rows[i].name.c_str(), sizeof(out[i].name) - 1);
+      out[i].launches = rows[i].launches;
+      out[i].total_ms = rows[i].ms;
+      out[i].bytes = rows[i].bytes;
+      out[i].mulmods = rows[i].mulmods;
     }
   });
   return rc ? rc : n;
+}
+
+int fhe_bench_mulmod(int32_t device, int32_t kind, int32_t iters, void* stream, double* per_s) {
+  return guarded([&] {
+    need(per_s, "per_s");
+    if (iters < 1) fail(FHE_EINVAL, "iters must be positive");
+    HIPCHECK(hipSetDevice(device));
+    *per_s = bench_mulmod(kind, (uint32_t)iters, as_stream(stream));
+  });
 }
 
 const char* fhe_last_error(void) { return g_err.c_str(); }

@@ -239,6 +239,18 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
   sync(st);
 }
 
+size_t ctx_key_bytes(const fhe_ctx* ctx) {
+  size_t b = ctx->relin ? ctx->relin->buf.bytes() : 0;
+  for (const auto& kv : ctx->rot) b += kv.second->buf.bytes();
+  return b;
+}
+
+size_t ctx_resident_bytes(const fhe_ctx* ctx) {
+  const Tables& t = ctx->t;
+  return ctx_key_bytes(ctx) + t.mods.bytes() + t.tw.bytes() + t.twf.bytes() + t.modup.bytes() + t.moddown.bytes() +
+         t.moddown_f.bytes() + t.rescale.bytes() + t.mask.bytes() + t.mask_f.bytes();
+}
+
 std::vector<uint32_t> rotation_steps(const Params& p, int64_t r) {
   std::vector<uint32_t> out;
   int64_t rr = r % (int64_t)p.S;

@@ -44,6 +44,9 @@ void autotune_split(fhe_ctx* ctx, hipStream_t st, uint32_t B, std::vector<std::p
 // As autotune_split, timing the first `pairs` matched pairs of A B (the real per-pair sequence).
 void autotune_plan(fhe_ctx* ctx, hipStream_t st, const fhe_mat* A, const fhe_mat* B, int64_t pairs,
                    std::vector<std::pair<int, double>>& tried, int& best_k1, double& best_ms);
+// Device bytes a context holds for good: constant tables and every evaluation key.
+size_t ctx_resident_bytes(const fhe_ctx* ctx);
+size_t ctx_key_bytes(const fhe_ctx* ctx);
 void keygen(fhe_ctx* ctx, uint64_t seed, hipStream_t st, fhe_sk* sk);
 void keygen_rotation_steps(fhe_ctx* ctx, const fhe_sk* sk, const std::vector<uint32_t>& steps, hipStream_t st);
 
@@ -67,5 +70,6 @@ void ct_mult_relin(fhe_ctx* ctx, const uint64_t* a, const uint64_t* b, int nl, u
 void ct_rescale(fhe_ctx* ctx, const uint64_t* src, int ncomp, int nl, uint64_t* dst, hipStream_t st);
 void ct_mask(fhe_ctx* ctx, const uint64_t* src, int nl, int slot, uint64_t* dst, hipStream_t st);
 uint32_t mask_galois(const Params& p, int slot);
+
 
 }  // namespace fhe

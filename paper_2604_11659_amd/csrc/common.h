@@ -33,7 +33,9 @@ Allocator current_allocator();
 
 // Per-kernel device timing (HIP events around tracked launches); see runtime.cpp.
 int prof_begin(const char* name, hipStream_t st);
-void prof_end(int tok, hipStream_t st, double algorithmic_bytes);
+// algorithmic_bytes: the HBM reads + writes the launch must do; mulmods: the modular products it
+// performs (an NTT butterfly, a pointwise or a base-conversion product count one each).
+void prof_end(int tok, hipStream_t st, double algorithmic_bytes, double mulmods = 0.0);
 void prof_enable(bool on);
 // Adds n to the work counter `name` while timing is on (reported as "count:<name>" with n launches).
 void prof_count(const char* name, int64_t n);
@@ -44,7 +46,12 @@ struct CaptureScope {
   ~CaptureScope();
   int64_t count(const char* name) const;
 };
-std::vector<std::tuple<std::string, int64_t, double, double>> prof_summary();
+struct ProfRow {
+  std::string name;
+  int64_t launches = 0;
+  double ms = 0.0, bytes = 0.0, mulmods = 0.0;
+};
+std::vector<ProfRow> prof_summary();
 
 // Owning device buffer, allocated and released through the registered allocator.
 class DevBuf {

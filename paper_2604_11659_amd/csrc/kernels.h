@@ -138,4 +138,9 @@ void decrypt_combine(const fhe_ctx* ctx, uint32_t nl, uint32_t nlim, const uint6
 void add_ct(const fhe_ctx* ctx, uint32_t ncomp, uint32_t nl, const uint64_t* a, const uint64_t* b, uint64_t* out,
             hipStream_t st);
 
+// Measurement hook: modular products per second of one form (0: FP64 product for q < 2^50, 1: lazy
+// Shoup product, 2: Montgomery product, both for p < 2^61) over 8 independent chains of `iters`
+// dependent products per thread on a full grid (second of two timed launches).
+double bench_mulmod(int kind, uint32_t iters, hipStream_t st);
+
 }  // namespace fhe

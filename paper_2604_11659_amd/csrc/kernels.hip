@@ -1433,6 +1433,44 @@ __global__ __launch_bounds__(kThreads) void k_add(uint32_t ncomp, uint32_t nl, u
   }
 }
 
+// Throughput probe of the modular-product forms (a measurement hook, not a step of the method): every
+// thread runs 8 independent chains of `iters` dependent products x <- x w mod q. kKind 0: the FP64
+// product of the Q primes (FpArith::mulc), 1: the lazy Shoup product of the special primes, 2: the
+// Montgomery product of the special primes' key words. The chains' ends are stored so that no
+// product is dead code.
+template <int kKind>
+__global__ __launch_bounds__(kThreads) void k_bench_mulmod(uint32_t iters, uint64_t q, uint64_t qinv, uint64_t w,
+                                                         uint64_t wx, uint64_t* __restrict__ out) {
+  const uint64_t gid = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (kKind == 0) {
+    FpArith ar;
+    ar.q = (double)q;
+    ar.qinv = 1.0 / ar.q;
+    const double wd = (double)w, wq = wd / ar.q;
+    double x[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) x[c] = (double)((gid * 8 + c) % q);
+    for (uint32_t i = 0; i < iters; ++i)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) x[c] = ar.mulc(x[c], wd, wq);
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc += x[c];
+    out[gid] = (uint64_t)__double_as_longlong(acc);
+  } else {
+    uint64_t x[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) x[c] = (gid * 8 + c) % q;
+    for (uint32_t i = 0; i < iters; ++i)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) x[c] = kKind == 1 ? shoup_mul_lazy(x[c], w, wx, q) : mont_mul(x[c], w, q, qinv);
+    uint64_t acc = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc ^= x[c];
+    out[gid] = acc;
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------------
@@ -1447,13 +1485,16 @@ static void check_launch(const char* what) {
 }
 
 // Launch with optional event timing; `bytes` is the kernel's algorithmic HBM traffic for this launch.
-#define FHE_LAUNCH_T(name, bytes, kern, grid, threads, lds, st, ...)            \
+// `ops` is the launch's count of modular products (see prof_end), 0 where it is not counted.
+#define FHE_LAUNCH_TO(name, bytes, ops, kern, grid, threads, lds, st, ...)      \
   do {                                                                           \
     const int tok_ = prof_begin(name, st);                                       \
     hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, __VA_ARGS__);  \
-    prof_end(tok_, st, (double)(bytes));                                         \
+    prof_end(tok_, st, (double)(bytes), (double)(ops));                          \
     check_launch(name);                                                          \
   } while (0)
+#define FHE_LAUNCH_T(name, bytes, kern, grid, threads, lds, st, ...) \
+  FHE_LAUNCH_TO(name, bytes, 0.0, kern, grid, threads, lds, st, __VA_ARGS__)
 #define FHE_LAUNCH(name, bytes, kern, grid, lds, st, ...) \
   FHE_LAUNCH_T(name, bytes, kern, grid, kThreads, lds, st, __VA_ARGS__)
 
@@ -1520,39 +1561,44 @@ static void ntt_phase(const fhe_ctx* ctx, const LimbBatch& lb, const char* name_
     }
     const uint32_t blocks = ntt_blocks(ctx, sub);
     const double bytes = 16.0 * p.N * sub.limbs * sub.npoly;
+    // butterflies of the phase's stages (plus the N^-1 scaling of the inverse column phase)
+    const double ops = (double)sub.limbs * sub.npoly * p.N *
+                       (0.5 * (kPhase == 1 ? p.k1 : p.logN - p.k1) + (kInv && kPhase == 1 ? 1.0 : 0.0));
     // row phase: the 512-thread variant (see rows_nt); column phase: 256 threads x 16 elements
     // the usual row length (2^9): compile-time rounds (fewer VGPRs, a fourth workgroup per CU; the
     // forward gather instance is left out, it would need more)
     const bool r9 = p.logN - p.k1 == 9;
     if (kPhase == 2 && from_src && sub.src_ptr) {
       if (r.q && r9 && kInv)
-        FHE_LAUNCH_T(name_q, bytes, (k_ntt<kInv, kPhase, FpArith, 512, true, 9>), blocks, 512, lds, st, sub,
+        FHE_LAUNCH_TO(name_q, bytes, ops, (k_ntt<kInv, kPhase, FpArith, 512, true, 9>), blocks, 512, lds, st, sub,
                      mods_of(ctx), twf, p.logN, p.k1, from_src);
       else if (r.q)
-        FHE_LAUNCH_T(name_q, bytes, (k_ntt<kInv, kPhase, FpArith, 512, true>), blocks, 512, lds, st, sub, mods_of(ctx),
+        FHE_LAUNCH_TO(name_q, bytes, ops, (k_ntt<kInv, kPhase, FpArith, 512, true>), blocks, 512, lds, st, sub, mods_of(ctx),
                      twf, p.logN, p.k1, from_src);
       else
-        FHE_LAUNCH_T(name_p, bytes, (k_ntt<kInv, kPhase, IntArith, 512, true>), blocks, 512, lds, st, sub,
+        FHE_LAUNCH_TO(name_p, bytes, ops, (k_ntt<kInv, kPhase, IntArith, 512, true>), blocks, 512, lds, st, sub,
                      mods_of(ctx), ctx->t.tw.u64(), p.logN, p.k1, from_src);
     } else if (kPhase == 2 && rows_nt() == 512) {
       if (r.q && r9)
-        FHE_LAUNCH_T(name_q, bytes, (k_ntt<kInv, kPhase, FpArith, 512, false, 9>), blocks, 512, lds, st, sub,
+        FHE_LAUNCH_TO(name_q, bytes, ops, (k_ntt<kInv, kPhase, FpArith, 512, false, 9>), blocks, 512, lds, st, sub,
                      mods_of(ctx), twf, p.logN, p.k1, from_src);
       else if (r.q)
-        FHE_LAUNCH_T(name_q, bytes, (k_ntt<kInv, kPhase, FpArith, 512>), blocks, 512, lds, st, sub, mods_of(ctx), twf,
+        FHE_LAUNCH_TO(name_q, bytes, ops, (k_ntt<kInv, kPhase, FpArith, 512>), blocks, 512, lds, st, sub, mods_of(ctx), twf,
                      p.logN, p.k1, from_src);
       else if (r9)
-        FHE_LAUNCH_T(name_p, bytes, (k_ntt<kInv, kPhase, IntArith, 512, false, 9>), blocks, 512, lds, st, sub,
+        FHE_LAUNCH_TO(name_p, bytes, ops, (k_ntt<kInv, kPhase, IntArith, 512, false, 9>), blocks, 512, lds, st, sub,
                      mods_of(ctx), ctx->t.tw.u64(), p.logN, p.k1, from_src);
       else
-        FHE_LAUNCH_T(name_p, bytes, (k_ntt<kInv, kPhase, IntArith, 512>), blocks, 512, lds, st, sub, mods_of(ctx),
+        FHE_LAUNCH_TO(name_p, bytes, ops, (k_ntt<kInv, kPhase, IntArith, 512>), blocks, 512, lds, st, sub, mods_of(ctx),
                      ctx->t.tw.u64(), p.logN, p.k1, from_src);
     } else {
       if (r.q)
-        FHE_LAUNCH(name_q, bytes, (k_ntt<kInv, kPhase, FpArith, kThreads>), blocks, lds, st, sub, mods_of(ctx), twf,
+        FHE_LAUNCH_TO(name_q, bytes, ops, (k_ntt<kInv, kPhase, FpArith, kThreads>), blocks, kThreads, lds, st, sub,
+                      mods_of(ctx), twf,
                    p.logN, p.k1, from_src);
       else
-        FHE_LAUNCH(name_p, bytes, (k_ntt<kInv, kPhase, IntArith, kThreads>), blocks, lds, st, sub, mods_of(ctx),
+        FHE_LAUNCH_TO(name_p, bytes, ops, (k_ntt<kInv, kPhase, IntArith, kThreads>), blocks, kThreads, lds, st, sub,
+                      mods_of(ctx),
                    ctx->t.tw.u64(), p.logN, p.k1, from_src);
     }
   }
@@ -1580,12 +1626,14 @@ void ntt_forward(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st) {
   ntt_phase<false, 2>(ctx, lb, "ntt_fwd_p2_q", "ntt_fwd_p2_p", false, st);
 }
 
-// Row phase of the inverse transform only (the column phase is fused into a consumer).
-static void ntt_inverse_rows(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st) {
+// Row phase of the inverse transform only (the column phase is fused into a consumer). The timer
+// names default to the key switch's; the rescale passes its own.
+static void ntt_inverse_rows(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st, const char* name_q = "ntt_inv_p2_q",
+                             const char* name_p = "ntt_inv_p2_p") {
   if (lb.limbs == 0 || lb.npoly == 0) return;
   check_batch(ctx, lb);
   check_holes(ctx, lb);
-  ntt_phase<true, 2>(ctx, lb, "ntt_inv_p2_q", "ntt_inv_p2_p", lb.src != nullptr || lb.src_ptr != nullptr, st);
+  ntt_phase<true, 2>(ctx, lb, name_q, name_p, lb.src != nullptr || lb.src_ptr != nullptr, st);
 }
 
 void ntt_inverse(const fhe_ctx* ctx, const LimbBatch& lb, hipStream_t st) {
@@ -1682,10 +1730,18 @@ static void keyswitch_modup(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const u
     const uint64_t grid = (uint64_t)B * beta * (N >> le);
     if (grid >= (1ull << 31)) fail(FHE_EINVAL, "key-switch batch too large");
     const double bytes = e8 * beta * (double)next;  // nl digit rows read, beta * next - nl rows written
+    // per digit: inverse column phase and scaling of its limbs, conversion to and forward column
+    // phase of every other limb
+    double ops = 0.0;
+    for (uint32_t j = 0; j < beta; ++j) {
+      const double cnt = (double)std::min(alpha, nl - j * alpha), h = 0.5 * N * p.k1;
+      ops += cnt * (h + N) + ((double)next - cnt) * (cnt * N + h);
+    }
+    ops *= B;
     const uint64_t* mtab = ctx->t.modup.u64() + ctx->t.modup_offset[nl];
     const double* twf0 = (const double*)ctx->t.twf.get();
 #define FHE_MODUP_COLS(AL, K1)                                                                                  \
-  FHE_LAUNCH_T("modup_cols", bytes, (k_modup_cols<11, 256, AL, K1>), grid, 256, lds_mu, st, B, nl, K,             \
+  FHE_LAUNCH_TO("modup_cols", bytes, ops, (k_modup_cols<11, 256, AL, K1>), grid, 256, lds_mu, st, B, nl, K,      \
                (uint32_t)p.nq, alpha, R, p.logN, mods_of(ctx), twf0, ctx->t.tw.u64(), mtab, dcoef, ext)
 #define FHE_MODUP_COLS_K(AL)          \
   switch (p.k1) {                     \
@@ -1745,6 +1801,7 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
   if (p.alpha > kMaxAlpha || p.np > kMaxK) fail(FHE_EINVAL, "alpha or n_p above kernel limits");
   if (nl < 1 || nl > (uint32_t)p.nq) fail(FHE_ESHAPE, "key switch level out of range");
   prof_count("keyswitch", B);
+  prof_count(("keyswitch_nl" + std::to_string(nl)).c_str(), B);
   const uint32_t N = p.N, K = p.np, next = nl + K, beta = p.beta(nl), alpha = p.alpha;
   const uint32_t R = modup_rows(p, nl);
   uint64_t* dcoef = ws;                                 // [B][nl][N]
@@ -1760,15 +1817,23 @@ void keyswitch(const fhe_ctx* ctx, uint32_t B, uint32_t nl, const uint64_t* in, 
   // per extended limb: beta digit words (input or ModUp row), 2 beta key words, 2 output words
   const double ib = 8.0 * N * (double)B * (3.0 * beta + 2.0);
   const uint32_t* in_gal = in_ptrs ? galois : nullptr;
+  // per Q limb: two key products per digit and the row phase of every digit's row but its own; per
+  // special-prime limb: both for every digit
+  const double hrow = 0.5 * N * (p.logN - p.k1);
+  const double ops_q = (double)B * nl * (2.0 * N * beta + hrow * (beta - 1));
+  const double ops_p = (double)B * K * beta * (2.0 * N + hrow);
   if (in_ptrs)
-    FHE_LAUNCH_T("ntt_p2_inner_q", ib * nl, (k_ntt_p2_inner<FpArith, true>), (uint64_t)B * nl * tiles, kInnerThreads,
+    FHE_LAUNCH_TO("ntt_p2_inner_q", ib * nl, ops_q, (k_ntt_p2_inner<FpArith, true>), (uint64_t)B * nl * tiles,
+                  kInnerThreads,
                  lds, st, B, nl, K, (uint32_t)p.nq, alpha, R, 0u, nl, p.logN, p.k1, mods_of(ctx), twf, in, in_stride,
                  in_ptrs, in_gal, ext, keys, u);
   else
-    FHE_LAUNCH_T("ntt_p2_inner_q", ib * nl, (k_ntt_p2_inner<FpArith, false>), (uint64_t)B * nl * tiles, kInnerThreads,
+    FHE_LAUNCH_TO("ntt_p2_inner_q", ib * nl, ops_q, (k_ntt_p2_inner<FpArith, false>), (uint64_t)B * nl * tiles,
+                  kInnerThreads,
                  lds, st, B, nl, K, (uint32_t)p.nq, alpha, R, 0u, nl, p.logN, p.k1, mods_of(ctx), twf, in, in_stride,
                  in_ptrs, in_gal, ext, keys, u);
-  FHE_LAUNCH_T("ntt_p2_inner_p", ib * K, (k_ntt_p2_inner<IntArith, false>), (uint64_t)B * K * tiles, kInnerThreads, lds,
+  FHE_LAUNCH_TO("ntt_p2_inner_p", ib * K, ops_p, (k_ntt_p2_inner<IntArith, false>), (uint64_t)B * K * tiles,
+                kInnerThreads, lds,
                st, B, nl, K, (uint32_t)p.nq, alpha, R, nl, K, p.logN, p.k1, mods_of(ctx), ctx->t.tw.u64(), in,
                in_stride, nullptr, nullptr, ext, keys, u);
   keyswitch_moddown(ctx, B, nl, u, conv, add, galois, out, st);
@@ -1784,6 +1849,7 @@ void keyswitch_hoisted(const fhe_ctx* ctx, uint32_t S, uint32_t B, uint32_t nl, 
   if (p.alpha > kMaxAlpha || p.np > kMaxK) fail(FHE_EINVAL, "alpha or n_p above kernel limits");
   if (nl < 1 || nl > (uint32_t)p.nq) fail(FHE_ESHAPE, "key switch level out of range");
   prof_count("keyswitch", B);
+  prof_count(("keyswitch_nl" + std::to_string(nl)).c_str(), B);
   const uint32_t N = p.N, K = p.np, next = nl + K, beta = p.beta(nl), alpha = p.alpha;
   const uint32_t R = modup_rows(p, nl), cnt_last = nl - (beta - 1) * alpha;
   uint64_t* dcoef = ws;                                 // [S][nl][N] within the B-item layout
@@ -1831,9 +1897,13 @@ static void keyswitch_moddown(const fhe_ctx* ctx, uint32_t B, uint32_t nl, uint6
     const size_t lds_md = cols_lds_bytes(le);
     const uint64_t grid = (uint64_t)2 * B * (N >> le);
     const double bytes = e8 * 2 * (K + nl);
+    // per component: inverse column phase and scaling of the K special-prime limbs, the two-part
+    // conversion into and the forward column phase of every Q limb
+    const double h1 = 0.5 * N * p.k1;
+    const double ops = 2.0 * B * (K * (h1 + N) + (double)nl * (2.0 * K * N + h1));
     const double* twf0 = (const double*)ctx->t.twf.get();
 #define FHE_MODDOWN_COLS(KP, K1)                                                                            \
-  FHE_LAUNCH_T("moddown_cols", bytes, (k_moddown_cols<11, 256, KP, K1>), grid, 256, lds_md, st, nl, K,        \
+  FHE_LAUNCH_TO("moddown_cols", bytes, ops, (k_moddown_cols<11, 256, KP, K1>), grid, 256, lds_md, st, nl, K, \
                (uint32_t)p.nq, p.logN, mods_of(ctx), twf0, ctx->t.tw.u64(), ctx->t.moddown.u64(),                 \
                (const double*)ctx->t.moddown_f.get(), u, conv)
 #define FHE_MODDOWN_COLS_K(KP)             \
@@ -1858,16 +1928,20 @@ static void keyswitch_moddown(const fhe_ctx* ctx, uint32_t B, uint32_t nl, uint6
     lb_conv.raw_out = 1;
     ntt_forward_cols(ctx, lb_conv, st);
   }
+  // row phase of every converted Q limb and its product by P^-1
+  const double ops_c = 2.0 * B * nl * (0.5 * N * (p.logN - p.k1) + N);
   if (rows_nt() == 512 && p.logN - p.k1 == 9)
-    FHE_LAUNCH_T("ntt_p2_combine", e8 * 2 * nl * 3.5, (k_ntt_p2_combine<FpArith, 512, 9>),
+    FHE_LAUNCH_TO("ntt_p2_combine", e8 * 2 * nl * 3.5, ops_c, (k_ntt_p2_combine<FpArith, 512, 9>),
                  (uint64_t)2 * B * nl * tiles, 512, lds, st, nl, K, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf,
                  ctx->t.moddown.u64(), u, conv, add, galois, out);
   else if (rows_nt() == 512)
-    FHE_LAUNCH_T("ntt_p2_combine", e8 * 2 * nl * 3.5, (k_ntt_p2_combine<FpArith, 512>), (uint64_t)2 * B * nl * tiles,
+    FHE_LAUNCH_TO("ntt_p2_combine", e8 * 2 * nl * 3.5, ops_c, (k_ntt_p2_combine<FpArith, 512>),
+                  (uint64_t)2 * B * nl * tiles,
                  512, lds, st, nl, K, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.moddown.u64(), u, conv,
                  add, galois, out);
   else
-    FHE_LAUNCH_T("ntt_p2_combine", e8 * 2 * nl * 3.5, (k_ntt_p2_combine<FpArith, 256>), (uint64_t)2 * B * nl * tiles,
+    FHE_LAUNCH_TO("ntt_p2_combine", e8 * 2 * nl * 3.5, ops_c, (k_ntt_p2_combine<FpArith, 256>),
+                  (uint64_t)2 * B * nl * tiles,
                  256, lds, st, nl, K, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.moddown.u64(), u, conv,
                  add, galois, out);
 }
@@ -1897,37 +1971,42 @@ void rescale(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const 
     // phase of the broadcast fused with the combine
     LimbBatch lb_last{tmp, 1, BC, N, 0, nl - 1};
     lb_last.raw_out = 1;
-    ntt_inverse_rows(ctx, lb_last, st);
+    ntt_inverse_rows(ctx, lb_last, st, "rescale_inv_p2");
     const uint32_t le = cols_log_e(p);
     const size_t lds_rs = cols_lds_bytes(le);
     const uint64_t grid = (uint64_t)BC * (N >> le);
     const double* twf = (const double*)ctx->t.twf.get();
     if (grid >= (1ull << 31)) fail(FHE_EINVAL, "rescale batch too large");
+    // column phases: inverse of the dropped limb, forward of its broadcast into every other limb;
+    // rows: forward row phase of the broadcast and the (x - w) q_l^-1 product (and the mask product)
+    const double h1 = 0.5 * N * p.k1, h2 = 0.5 * N * (p.logN - p.k1);
+    const double ops_cols = (double)BC * (h1 + N + (nl - 1) * h1);
+    const double ops_rows = (double)BC * (nl - 1) * (h2 + (mask_galois ? 2.0 : 1.0) * N);
     switch (p.k1) {
       case 6:
-        FHE_LAUNCH_T("rescale_cols", e8 * nl, (k_rescale_cols<11, 256, 6>), grid, 256, lds_rs, st, nl, p.logN,
+        FHE_LAUNCH_TO("rescale_cols", e8 * nl, ops_cols, (k_rescale_cols<11, 256, 6>), grid, 256, lds_rs, st, nl, p.logN,
                      mods_of(ctx), twf, tmp, w);
         break;
       case 7:
-        FHE_LAUNCH_T("rescale_cols", e8 * nl, (k_rescale_cols<11, 256, 7>), grid, 256, lds_rs, st, nl, p.logN,
+        FHE_LAUNCH_TO("rescale_cols", e8 * nl, ops_cols, (k_rescale_cols<11, 256, 7>), grid, 256, lds_rs, st, nl, p.logN,
                      mods_of(ctx), twf, tmp, w);
         break;
       default:
-        FHE_LAUNCH_T("rescale_cols", e8 * nl, (k_rescale_cols<11, 256, 8>), grid, 256, lds_rs, st, nl, p.logN,
+        FHE_LAUNCH_TO("rescale_cols", e8 * nl, ops_cols, (k_rescale_cols<11, 256, 8>), grid, 256, lds_rs, st, nl, p.logN,
                      mods_of(ctx), twf, tmp, w);
         break;
     }
     const size_t lds = kNttLdsElems * sizeof(uint64_t);
     if (rows_nt() == 512 && p.logN - p.k1 == 9)
-      FHE_LAUNCH_T("rescale_rows", e8 * 3 * (nl - 1), (k_rescale_rows<512, 9>),
+      FHE_LAUNCH_TO("rescale_rows", e8 * 3 * (nl - 1), ops_rows, (k_rescale_rows<512, 9>),
                    (uint64_t)BC * (nl - 1) * (N >> kNttLogE), 512, lds, st, ncomp, nl, (uint32_t)p.nq, p.logN, p.k1,
                    mods_of(ctx), twf, ctx->t.rescale.u64(), ctx->t.mask.u64(), mask_galois, in, w, out);
     else if (rows_nt() == 512)
-      FHE_LAUNCH_T("rescale_rows", e8 * 3 * (nl - 1), k_rescale_rows<512>, (uint64_t)BC * (nl - 1) * (N >> kNttLogE),
+      FHE_LAUNCH_TO("rescale_rows", e8 * 3 * (nl - 1), ops_rows, k_rescale_rows<512>, (uint64_t)BC * (nl - 1) * (N >> kNttLogE),
                    512, lds, st, ncomp, nl, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.rescale.u64(),
                    ctx->t.mask.u64(), mask_galois, in, w, out);
     else
-      FHE_LAUNCH_T("rescale_rows", e8 * 3 * (nl - 1), k_rescale_rows<256>, (uint64_t)BC * (nl - 1) * (N >> kNttLogE),
+      FHE_LAUNCH_TO("rescale_rows", e8 * 3 * (nl - 1), ops_rows, k_rescale_rows<256>, (uint64_t)BC * (nl - 1) * (N >> kNttLogE),
                    256, lds, st, ncomp, nl, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.rescale.u64(),
                    ctx->t.mask.u64(), mask_galois, in, w, out);
     return;
@@ -2026,6 +2105,36 @@ void add_ct(const fhe_ctx* ctx, uint32_t ncomp, uint32_t nl, const uint64_t* a, 
             hipStream_t st) {
   FHE_LAUNCH("add", 24.0 * ncomp * nl * ctx->p.N, k_add, grid_for((uint64_t)ncomp * nl << ctx->p.logN), 0, st, ncomp,
              nl, ctx->p.logN, mods_of(ctx), a, b, out);
+}
+
+double bench_mulmod(int kind, uint32_t iters, hipStream_t st) {
+  if (kind < 0 || kind > 2) fail(FHE_EINVAL, "kind must be 0 (FP64), 1 (Shoup) or 2 (Montgomery)");
+  if (iters < 1 || iters > (1u << 20)) fail(FHE_EINVAL, "iters must be in [1, 2^20]");
+  // any odd modulus of the right size times the same instruction sequence as a prime
+  const uint64_t q = kind == 0 ? (1ull << 49) + 12345 : (1ull << 59) + 54321;
+  const uint64_t w = q / 3 + 7, wx = shoup_prep(w, q), qinv = mont_qinv(q);
+  const uint32_t blocks = 256 * 16;
+  DevBuf out((size_t)blocks * kThreads * 8, st);
+  hipEvent_t a, b;
+  HIPCHECK(hipEventCreate(&a));
+  HIPCHECK(hipEventCreate(&b));
+  float ms = 0.f;
+  for (int rep = 0; rep < 2; ++rep) {  // the first launch loads the code object
+    HIPCHECK(hipEventRecord(a, st));
+    if (kind == 0)
+      hipLaunchKernelGGL(k_bench_mulmod<0>, dim3(blocks), dim3(kThreads), 0, st, iters, q, qinv, w, wx, out.u64());
+    else if (kind == 1)
+      hipLaunchKernelGGL(k_bench_mulmod<1>, dim3(blocks), dim3(kThreads), 0, st, iters, q, qinv, w, wx, out.u64());
+    else
+      hipLaunchKernelGGL(k_bench_mulmod<2>, dim3(blocks), dim3(kThreads), 0, st, iters, q, qinv, w, wx, out.u64());
+    check_launch("bench_mulmod");
+    HIPCHECK(hipEventRecord(b, st));
+    HIPCHECK(hipEventSynchronize(b));
+    HIPCHECK(hipEventElapsedTime(&ms, a, b));
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return (double)blocks * kThreads * 8.0 * iters / (ms * 1e-3);
 }
 
 }  // namespace fhe

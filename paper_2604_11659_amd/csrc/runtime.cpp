@@ -82,6 +82,7 @@ struct TimerRec {
   const char* name;
   hipEvent_t a, b;
   double bytes;
+  double mulmods;
 };
 struct KernelTimer {
   std::mutex mu;
@@ -141,18 +142,19 @@ int prof_begin(const char* name, hipStream_t st) {
   KernelTimer& t = timer();
   std::lock_guard<std::mutex> lk(t.mu);
   if (!t.on) return -1;
-  TimerRec r{name, take_event(t), take_event(t), 0.0};
+  TimerRec r{name, take_event(t), take_event(t), 0.0, 0.0};
   HIPCHECK(hipEventRecord(r.a, st));
   t.recs.push_back(r);
   return (int)t.recs.size() - 1;
 }
 
-void prof_end(int tok, hipStream_t st, double bytes) {
+void prof_end(int tok, hipStream_t st, double bytes, double mulmods) {
   if (tok < 0) return;
   KernelTimer& t = timer();
   std::lock_guard<std::mutex> lk(t.mu);
   if (tok >= (int)t.recs.size()) return;
   t.recs[tok].bytes = bytes;
+  t.recs[tok].mulmods = mulmods;
   HIPCHECK(hipEventRecord(t.recs[tok].b, st));
 }
 
@@ -181,23 +183,30 @@ void prof_enable(bool on) {
   t.on = on;
 }
 
-// Aggregates the records: name -> (launches, total ms, algorithmic bytes).
-std::vector<std::tuple<std::string, int64_t, double, double>> prof_summary() {
+// Aggregates the records per kernel name (launches, total ms, algorithmic bytes, modular products).
+std::vector<ProfRow> prof_summary() {
   KernelTimer& t = timer();
   std::lock_guard<std::mutex> lk(t.mu);
-  std::map<std::string, std::tuple<int64_t, double, double>> agg;
+  std::map<std::string, ProfRow> agg;
   for (auto& r : t.recs) {
     HIPCHECK(hipEventSynchronize(r.b));
     float ms = 0.f;
     HIPCHECK(hipEventElapsedTime(&ms, r.a, r.b));
-    auto& x = agg[r.name];
-    std::get<0>(x) += 1;
-    std::get<1>(x) += ms;
-    std::get<2>(x) += r.bytes;
+    ProfRow& x = agg[r.name];
+    x.name = r.name;
+    x.launches += 1;
+    x.ms += ms;
+    x.bytes += r.bytes;
+    x.mulmods += r.mulmods;
   }
-  std::vector<std::tuple<std::string, int64_t, double, double>> out;
-  for (auto& kv : agg) out.emplace_back(kv.first, std::get<0>(kv.second), std::get<1>(kv.second), std::get<2>(kv.second));
-  for (auto& kv : t.counts) out.emplace_back("count:" + kv.first, kv.second, 0.0, 0.0);
+  std::vector<ProfRow> out;
+  for (auto& kv : agg) out.push_back(kv.second);
+  for (auto& kv : t.counts) {
+    ProfRow x;
+    x.name = "count:" + kv.first;
+    x.launches = kv.second;
+    out.push_back(x);
+  }
   return out;
 }
 

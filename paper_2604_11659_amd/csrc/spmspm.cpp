@@ -33,7 +33,8 @@ void check_pattern(int32_t outer, int32_t inner, const int32_t* indptr, const in
   }
 }
 
-Plan build_plan(const Params& p, const fhe_mat* A, const fhe_mat* B, int64_t begin, int64_t end) {
+Plan build_plan(const Params& p, const fhe_mat* A, const fhe_mat* B, int64_t begin, int64_t end,
+                const uint8_t* nonzero_a, const uint8_t* nonzero_b) {
   Plan plan;
   const int64_t S = p.S;
   const int m = A->rows, n = B->cols;
@@ -48,6 +49,11 @@ Plan build_plan(const Params& p, const fhe_mat* A, const fhe_mat* B, int64_t beg
       while (a_pos < a_end && b_pos < b_end) {
         const int32_t a_col = A->indices[a_pos], b_row = B->indices[b_pos];
         if (a_col == b_row) {
+          if (nonzero_a && !nonzero_a[a_pos] && !nonzero_b[b_pos]) {  // both entries known zero: skipped
+            ++a_pos;
+            ++b_pos;
+            continue;
+          }
           if (idx >= begin && idx < end) {
             const int32_t ca = (int32_t)(a_pos / S), la = (int32_t)(a_pos % S);
             const int32_t cb = (int32_t)(b_pos / S), lb = (int32_t)(b_pos % S);
@@ -303,7 +309,55 @@ void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool gro
     prepare_result(ctx, J, st);
     slices.push_back(Slice{&J, 0, (int32_t)J.plan.prods.size()});
   }
-  execute_slices(ctx, slices, st, grouped, graph, tree, hoist);
+  ExecOpts o;
+  o.grouped = grouped;
+  o.graph = graph;
+  o.tree = tree;
+  o.hoist = hoist;
+  execute_slices(ctx, slices, st, o);
+}
+
+WsPlan ws_plan(const fhe_ctx* ctx, size_t budget, size_t nprod, size_t npairs) {
+  const Params& p = ctx->p;
+  const size_t N = p.N, nq = p.nq, nl1 = nq - 1, nl2 = nq - 2;
+  const size_t e = 8ull * N;
+  const size_t per_prod = e * (2 * nq + 3 * nq + 2 * nq + 2 * nl1 + 2 * nq) +
+                          8 * (keyswitch_ws_elems(ctx, 1, (uint32_t)nq) + rescale_ws_elems(ctx, 1, 2, (uint32_t)nq));
+  const size_t per_pair = e * (2 * nl1 + 2 * nl2 + 2 * nl2) +
+                          8 * (keyswitch_ws_elems(ctx, 1, (uint32_t)nl2) + rescale_ws_elems(ctx, 1, 2, (uint32_t)nl1));
+  WsPlan w;
+  w.PB = std::max<size_t>(1, std::min<size_t>(nprod, (budget / 3) / per_prod));
+  w.BB = std::max<size_t>(1, std::min<size_t>(npairs, (2 * budget / 3) / per_pair));
+  w.PB = std::min<size_t>(w.PB, 4096);
+  w.BB = std::min<size_t>(w.BB, 8192);
+  const size_t PB = w.PB, BB = w.BB;
+  const size_t rt = std::max<size_t>(PB * 2 * nq, BB * 2 * nl2) * N;
+  const size_t sz_ks = std::max(keyswitch_ws_elems(ctx, (uint32_t)PB, (uint32_t)nq),
+                                keyswitch_ws_elems(ctx, (uint32_t)BB, (uint32_t)nl2));
+  const size_t sz_rs = std::max(rescale_ws_elems(ctx, (uint32_t)PB, 2, (uint32_t)nq),
+                                rescale_ws_elems(ctx, (uint32_t)BB, 2, (uint32_t)nl1));
+  w.words = PB * 2 * nq * N + rt + PB * 3 * nq * N + PB * 2 * nq * N + PB * 2 * nl1 * N + BB * 2 * nl1 * N +
+            BB * 2 * nl2 * N + sz_ks + sz_rs;
+  return w;
+}
+
+size_t grouped_resident_words(const Params& p, const Plan& plan, bool tree) {
+  const size_t N = p.N, pe = 2 * (size_t)(p.nq - 1) * N, ce = 2 * (size_t)(p.nq - 2) * N;
+  size_t nlev = 0;
+  if (tree) {
+    std::vector<uint64_t> keys;
+    for (const auto& pa : plan.pairs) keys.push_back(((uint64_t)(uint32_t)pa.chunk << 32) | pa.rot);
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    const uint32_t rb = (uint32_t)p.rot_bits;
+    for (int t = 1; t < p.rot_digits; ++t) {
+      std::vector<uint64_t> lk;
+      for (uint64_t k : keys) lk.push_back((k & ~0xffffffffull) | ((k & 0xffffffffull) >> (rb * t)));
+      std::sort(lk.begin(), lk.end());
+      nlev += (size_t)(std::unique(lk.begin(), lk.end()) - lk.begin());
+    }
+  }
+  return plan.prods.size() * pe + nlev * ce;
 }
 
 GraphEntry::~GraphEntry() {
@@ -525,7 +579,8 @@ size_t group_budget_bytes() {
 // launch straight into the tail's input buffer. When all products do not fit the group budget, the
 // groups run in passes, each recomputing the products its pairs use.
 void execute_grouped(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job*>& job_of, const Workspace& ws,
-                     size_t PB, size_t BB, uint64_t* const* res, Runner& run, DevBuf& gbuf, bool tree, bool hoist) {
+                     size_t PB, size_t BB, uint64_t* const* res, Runner& run, DevBuf& gbuf, bool tree, bool hoist,
+                     size_t group_bytes) {
   const hipStream_t st = run.ls;
   const Params& p = ctx->p;
   const uint32_t N = p.N, nl1 = p.nq - 1;
@@ -550,7 +605,7 @@ void execute_grouped(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job
   }
   // resident products (at most PS) plus the tail's second ping-pong buffers
   const size_t pe = (size_t)2 * nl1 * N;
-  const size_t budget = group_budget_bytes() / 8;
+  const size_t budget = (group_bytes ? group_bytes : group_budget_bytes()) / 8;
   const size_t alt_elems = BB * pe;
   // store size: the budget, but never less than the largest group's distinct products
   size_t gmax = 1;
@@ -746,9 +801,8 @@ void run_per_pair(fhe_ctx* ctx, const Plan& plan, const std::vector<const Job*>&
 
 }  // namespace
 
-void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bool grouped, bool graph, bool tree,
-                    bool hoist) {
-  grouped = grouped || tree;
+void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, const ExecOpts& opts) {
+  const bool tree = opts.tree, grouped = opts.grouped || tree, graph = opts.graph, hoist = opts.hoist;
   const Params& p = ctx->p;
   const uint32_t N = p.N, nq = p.nq, nl1 = nq - 1, nl2 = nq - 2;
   std::lock_guard<std::recursive_mutex> exec_lock(ctx->exec_mu);
@@ -808,16 +862,8 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bo
   const size_t nprod = plan.prods.size();
 
   // Batch sizes from the workspace budget.
-  const size_t e = 8ull * N;
-  const size_t per_prod = e * (2 * nq + 3 * nq + 2 * nq + 2 * nl1 + 2 * nq) +
-                          8 * (keyswitch_ws_elems(ctx, 1, nq) + rescale_ws_elems(ctx, 1, 2, nq));
-  const size_t per_pair = e * (2 * nl1 + 2 * nl2 + 2 * nl2) +
-                          8 * (keyswitch_ws_elems(ctx, 1, nl2) + rescale_ws_elems(ctx, 1, 2, nl1));
-  const size_t budget = workspace_budget_bytes();
-  size_t PB = std::max<size_t>(1, std::min<size_t>(nprod, (budget / 3) / per_prod));
-  size_t BB = std::max<size_t>(1, std::min<size_t>(plan.pairs.size(), (2 * budget / 3) / per_pair));
-  PB = std::min<size_t>(PB, 4096);
-  BB = std::min<size_t>(BB, 8192);
+  const WsPlan wp = ws_plan(ctx, opts.ws_bytes ? opts.ws_bytes : workspace_budget_bytes(), nprod, plan.pairs.size());
+  const size_t PB = wp.PB, BB = wp.BB;
 
   Workspace ws;
   const size_t rt = std::max<size_t>(PB * 2 * nq, BB * 2 * nl2) * N;
@@ -827,6 +873,7 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bo
   const size_t sz_rs =
       std::max(rescale_ws_elems(ctx, (uint32_t)PB, 2, nq), rescale_ws_elems(ctx, (uint32_t)BB, 2, nl1));
   const size_t total = sz_align + rt + sz_tens + sz_pfull + sz_prod + sz_msk + sz_cur + sz_ks + sz_rs;
+  if (total != wp.words) fail(FHE_EINVAL, "internal: workspace layout differs from its plan");
   if (ctx->ws_cache.bytes() < total * 8) {  // grow-only scratch kept by the context between calls
     HIPCHECK(hipStreamSynchronize(st));      // earlier work on the old scratch has finished
     ctx->graphs.clear();                      // graphs captured on the old scratch are stale
@@ -850,7 +897,7 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bo
   Runner run{ls, graph, graph ? entry->packs : local_packs, {}};
   DevBuf& gbuf = graph ? entry->gbuf : local_gbuf;
   if (grouped) {
-    execute_grouped(ctx, plan, job_of, ws, PB, BB, res, run, gbuf, tree, hoist);
+    execute_grouped(ctx, plan, job_of, ws, PB, BB, res, run, gbuf, tree, hoist, opts.group_bytes);
   } else {
     run_per_pair(ctx, plan, job_of, ws, PB, BB, res, run, hoist);
   }

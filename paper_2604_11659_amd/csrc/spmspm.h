@@ -37,7 +37,11 @@ void index_plan(Plan& plan);
 void check_pattern(int32_t outer, int32_t inner, const int32_t* indptr, const int32_t* indices);
 
 // Algorithm 1 over A (CSR) and B (CSC), keeping the pairs with traversal index in [begin, end).
-Plan build_plan(const Params& p, const fhe_mat* A, const fhe_mat* B, int64_t begin, int64_t end);
+// With nonzero_a / nonzero_b (flags over the stored entries of A and B in packing order), a matched
+// pair whose two entries are both flagged zero is skipped and not counted in the traversal index (the
+// naive sparse method of the paper's evaluation, on operands that store every entry).
+Plan build_plan(const Params& p, const fhe_mat* A, const fhe_mat* B, int64_t begin, int64_t end,
+                const uint8_t* nonzero_a = nullptr, const uint8_t* nonzero_b = nullptr);
 
 // One matmul of a batch: operands, its plan, its result handle.
 struct Job {
@@ -64,6 +68,25 @@ struct Job {
 void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool grouped = false, bool graph = false,
                   bool tree = false, bool hoist = false);
 
+// Plan mode and memory limits of one execution.
+struct ExecOpts {
+  bool grouped = false, graph = false, tree = false, hoist = false;
+  size_t ws_bytes = 0;     // executor scratch budget (0: FHE_WORKSPACE_MB, default 24576 MiB)
+  size_t group_bytes = 0;  // grouped plans: budget of the resident products (0: FHE_GROUP_MB, default 49152 MiB)
+};
+
+// Executor scratch layout for a budget: batch sizes (products per launch PB, pairs per tail launch BB)
+// and the words the scratch takes, for a step with nprod products and npairs pairs.
+struct WsPlan {
+  size_t PB = 1, BB = 1, words = 0;
+};
+WsPlan ws_plan(const fhe_ctx* ctx, size_t budget_bytes, size_t nprod, size_t npairs);
+
+// Device words a grouped execution of `plan` keeps beyond the executor scratch and the tail's second
+// ping-pong buffers: every product resident (2 (nq - 1) N words each) plus, for the digit tree, one
+// partial sum (2 (nq - 2) N words) per distinct (result chunk, higher rotation digits) of each level.
+size_t grouped_resident_words(const Params& p, const Plan& plan, bool tree);
+
 // A captured matmul launch stream and everything its kernels read that is not an operand or key.
 struct GraphEntry {
   std::vector<uint64_t> key;
@@ -86,8 +109,7 @@ struct Slice {
   int32_t lo, hi;
 };
 void prepare_result(fhe_ctx* ctx, Job& J, hipStream_t st);
-void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, bool grouped = false,
-                    bool graph = false, bool tree = false, bool hoist = false);
+void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, const ExecOpts& opts);
 
 // Counts of key-switch work in the plan: [F, products, align KS, relin KS, target KS, result chunks].
 void plan_counts(const Params& p, const Plan& plan, int64_t out[6]);

@@ -31,8 +31,10 @@ c_i32, c_i64, c_u64, c_sz, c_dbl, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes
 P_i32, P_i64, P_u64, P_dbl = (ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
                               ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double))
 PP = ctypes.POINTER(ctypes.c_void_p)
+P_u8 = ctypes.POINTER(ctypes.c_uint8)
 
-FHE_ERRORS = {-1: "EINVAL", -2: "ESHAPE", -3: "ELEVEL", -4: "EKEY", -5: "ENOMEM", -6: "EAGAIN", -7: "EDEVICE"}
+FHE_ERRORS = {-1: "EINVAL", -2: "ESHAPE", -3: "ELEVEL", -4: "EKEY", -5: "ENOMEM", -6: "EAGAIN", -7: "EDEVICE",
+              -8: "ECANCELED"}
 
 
 class fhe_params_desc(ctypes.Structure):
@@ -42,7 +44,15 @@ class fhe_params_desc(ctypes.Structure):
 
 
 class fhe_kernel_stat(ctypes.Structure):
-    _fields_ = [("name", ctypes.c_char * 32), ("launches", c_i64), ("total_ms", c_dbl), ("bytes", c_dbl)]
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", c_i64), ("total_ms", c_dbl), ("bytes", c_dbl),
+                ("mulmods", c_dbl)]
+
+
+class fhe_server_info(ctypes.Structure):
+    _fields_ = [("p50_s", c_dbl), ("p99_s", c_dbl), ("completed", c_i64), ("failed", c_i64), ("cancelled", c_i64),
+                ("inflight", c_i64), ("queued", c_i64), ("steps", c_i64), ("max_merged", c_i64),
+                ("max_step_requests", c_i64), ("budget_bytes", c_sz), ("fixed_bytes", c_sz),
+                ("inflight_bytes", c_sz)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(c_vp, c_sz, c_vp, c_vp)
@@ -65,6 +75,8 @@ _SIGS = {
     "fhe_plan_stats": ([c_vp, c_vp, c_vp, P_i64], c_i32),
     "fhe_spmspm_plan": ([c_vp, c_sz, PP, PP, P_i64, P_i64, c_i32, c_vp, PP], c_i32),
     "fhe_plan_groups": ([c_vp, c_vp, c_vp, P_i64], c_i32),
+    "fhe_spmspm_naive_sparse": ([c_vp, c_vp, c_vp, P_u8, P_u8, c_vp, PP], c_i32),
+    "fhe_plan_stats_naive_sparse": ([c_vp, c_vp, c_vp, P_u8, P_u8, P_i64], c_i32),
     "fhe_autotune": ([c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_dbl),
                       ctypes.POINTER(c_i32), P_i32, P_dbl, c_i32], c_i32),
     "fhe_plan_pattern": ([c_i32, c_i32, c_i32, c_i32, c_i32, P_i32, P_i32, P_i32, P_i32, P_i64], c_i32),
@@ -82,14 +94,16 @@ _SIGS = {
     "fhe_ct_mask": ([c_vp, c_vp, c_i32, c_vp, PP], c_i32),
     "fhe_ct_add": ([c_vp, c_vp, c_vp, c_vp, PP], c_i32),
     "fhe_ct_free": ([c_vp], None),
-    "fhe_server_create": ([c_vp, c_sz, c_i32, c_i32, c_i32, PP], c_i32),
-    "fhe_server_submit": ([c_vp, c_vp, c_vp, ctypes.POINTER(c_u64)], c_i32),
+    "fhe_server_create": ([PP, c_sz, c_sz, c_sz, c_i32, c_i32, c_i32, PP], c_i32),
+    "fhe_server_submit": ([c_vp, c_i32, c_vp, c_vp, ctypes.POINTER(c_u64)], c_i32),
     "fhe_server_set_plan": ([c_vp, c_i32], c_i32),
     "fhe_server_poll": ([c_vp, c_u64, c_i32, PP, P_dbl], c_i32),
-    "fhe_server_stats": ([c_vp, P_dbl, P_dbl, P_i64, P_i64, P_i64], c_i32),
+    "fhe_server_stats": ([c_vp, ctypes.POINTER(fhe_server_info)], c_i32),
+    "fhe_server_cancel": ([c_vp, c_u64], c_i32),
     "fhe_server_free": ([c_vp], None),
     "fhe_profile_enable": ([ctypes.c_int], c_i32),
     "fhe_profile_read": ([ctypes.POINTER(fhe_kernel_stat), c_sz], c_i32),
+    "fhe_bench_mulmod": ([c_i32, c_i32, c_i32, c_vp, P_dbl], c_i32),
     "fhe_last_error": ([], ctypes.c_char_p),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -142,12 +156,21 @@ def profile_enable(on: bool = True):
 
 
 def profile_read() -> dict:
-    """{kernel: dict(launches, total_ms, bytes)} for the records since the last profile_enable(True)."""
+    """{kernel: dict(launches, total_ms, bytes, mulmods)} for the records since the last profile_enable(True)."""
     n = _check(_lib.fhe_profile_read(None, 0))
     arr = (fhe_kernel_stat * max(1, n))()
     _check(_lib.fhe_profile_read(arr, n))
-    return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms, bytes=arr[i].bytes)
+    return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms, bytes=arr[i].bytes,
+                                       mulmods=arr[i].mulmods)
             for i in range(n)}
+
+
+def bench_mulmod(kind: int, iters: int = 4096, device: int = 0, stream=None) -> float:
+    """Modular products per second of one form (0: FP64 for Q primes, 1: Shoup, 2: Montgomery for the
+    60-bit special primes), from the library's throughput probe."""
+    v = c_dbl()
+    _check(_lib.fhe_bench_mulmod(device, kind, iters, _stream(stream), ctypes.byref(v)))
+    return v.value
 
 
 _TORCH_HOOKS = None
@@ -354,10 +377,25 @@ class Context(_Handle):
                 "pairs" if A else "batch": pairs if A else batch,
                 "tried": {int(kt[i]): round(float(mt[i]), 3) for i in range(m)}}
 
-    def plan_stats(self, A: Matrix, B: Matrix) -> PlanStats:
+    def plan_stats(self, A: Matrix, B: Matrix, nonzero_a=None, nonzero_b=None) -> PlanStats:
+        """Plan counts of A B; with nonzero_a / nonzero_b, of the naive sparse plan (see spmspm_naive_sparse)."""
         c = np.zeros(6, np.int64)
-        _check(_lib.fhe_plan_stats(self._ptr, A._ptr, B._ptr, _ptr(c, c_i64)))
+        if nonzero_a is None and nonzero_b is None:
+            _check(_lib.fhe_plan_stats(self._ptr, A._ptr, B._ptr, _ptr(c, c_i64)))
+        else:
+            za, zb = _arr(nonzero_a, np.uint8), _arr(nonzero_b, np.uint8)
+            _check(_lib.fhe_plan_stats_naive_sparse(self._ptr, A._ptr, B._ptr, _ptr(za, ctypes.c_uint8),
+                                                    _ptr(zb, ctypes.c_uint8), _ptr(c, c_i64)))
         return PlanStats(*[int(x) for x in c])
+
+    def spmspm_naive_sparse(self, A: Matrix, B: Matrix, nonzero_a, nonzero_b, stream=None) -> Matrix:
+        """The naive sparse method on operands that store every entry: a product runs unless both of its
+        entries are zero. nonzero_a / nonzero_b: one flag per stored entry of A / B in packing order."""
+        za, zb = _arr(nonzero_a, np.uint8), _arr(nonzero_b, np.uint8)
+        out = c_vp()
+        _check(_lib.fhe_spmspm_naive_sparse(self._ptr, A._ptr, B._ptr, _ptr(za, ctypes.c_uint8),
+                                            _ptr(zb, ctypes.c_uint8), _stream(stream), ctypes.byref(out)))
+        return Matrix(out.value, self)
 
     def plan_groups(self, A: Matrix, B: Matrix) -> tuple:
         """(groups, target-rotation key switches grouped, same with the digit tree) of A B."""
@@ -428,40 +466,49 @@ class Context(_Handle):
 
 
 class Server(_Handle):
-    """Continuous-batching request loop on a Context (worker thread + own HIP stream)."""
+    """Continuous-batching request loop over one or more Contexts on one GPU (worker thread + own HIP
+    stream), with one HBM budget shared by all of them."""
     _free_fn = staticmethod(_lib.fhe_server_free)
 
-    def __init__(self, ctx: Context, hbm_budget: int, max_inflight: int = 8, slice_products: int = 64,
-                 max_queue: int = 1024, grouped: bool = False, tree: bool = False, hoist: bool = False):
+    def __init__(self, ctxs, hbm_budget: int, max_inflight: int = 8, slice_products: int = 64,
+                 max_queue: int = 1024, grouped: bool = False, tree: bool = False, hoist: bool = False,
+                 workspace_bytes: int = 0):
+        if isinstance(ctxs, Context):
+            ctxs = [ctxs]
+        self._ctxs = list(ctxs)
+        arr = (c_vp * len(self._ctxs))(*[c._ptr for c in self._ctxs])
         out = c_vp()
-        _check(_lib.fhe_server_create(ctx._ptr, hbm_budget, max_inflight, slice_products, max_queue,
-                                      ctypes.byref(out)))
-        super().__init__(out.value, ctx)
+        _check(_lib.fhe_server_create(ctypes.cast(arr, PP), len(self._ctxs), hbm_budget, workspace_bytes,
+                                      max_inflight, slice_products, max_queue, ctypes.byref(out)))
+        super().__init__(out.value, self._ctxs)
         self._keep = {}
         if grouped or tree or hoist:
             _check(_lib.fhe_server_set_plan(self._ptr, (2 if tree else 1 if grouped else 0) | (512 if hoist else 0)))
 
-    def submit(self, A: Matrix, B: Matrix) -> int:
+    def submit(self, A: Matrix, B: Matrix, ctx_id: int = 0) -> int:
         t = c_u64()
-        _check(_lib.fhe_server_submit(self._ptr, A._ptr, B._ptr, ctypes.byref(t)))
-        self._keep[t.value] = (A, B)  # operands must outlive the request
+        _check(_lib.fhe_server_submit(self._ptr, ctx_id, A._ptr, B._ptr, ctypes.byref(t)))
+        self._keep[t.value] = (ctx_id, A, B)  # operands must outlive the request
         return t.value
 
     def poll(self, ticket: int, wait_ms: int = 0):
-        """(Matrix, latency_s) when done, None while running; raises FheError if the request failed."""
+        """(Matrix, latency_s) when done, None while running; raises FheError if the request failed
+        or was cancelled (code -8)."""
         out = c_vp()
         lat = c_dbl()
         rc = _lib.fhe_server_poll(self._ptr, ticket, wait_ms, ctypes.byref(out), ctypes.byref(lat))
         if rc == -6:
             return None
-        self._keep.pop(ticket, None)
+        ctx_id = self._keep.pop(ticket, (0,))[0]
         if rc < 0:
-            raise FheError(rc, "request failed")
-        return Matrix(out.value, self._owner), lat.value
+            raise FheError(rc, "request cancelled" if rc == -8 else "request failed")
+        return Matrix(out.value, self._ctxs[ctx_id]), lat.value
+
+    def cancel(self, ticket: int):
+        """Cancel a queued request at once, an in-flight one at the next step boundary."""
+        _check(_lib.fhe_server_cancel(self._ptr, ticket))
 
     def stats(self) -> dict:
-        p50, p99 = c_dbl(), c_dbl()
-        done, infl, qd = c_i64(), c_i64(), c_i64()
-        _check(_lib.fhe_server_stats(self._ptr, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(done),
-                                     ctypes.byref(infl), ctypes.byref(qd)))
-        return dict(p50_s=p50.value, p99_s=p99.value, completed=done.value, inflight=infl.value, queued=qd.value)
+        info = fhe_server_info()
+        _check(_lib.fhe_server_stats(self._ptr, ctypes.byref(info)))
+        return {name: getattr(info, name) for name, _ in fhe_server_info._fields_}

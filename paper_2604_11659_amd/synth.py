@@ -61,6 +61,16 @@ def full_csc(d: np.ndarray):
     return full_csr(np.ascontiguousarray(d.T))
 
 
+def stored_nonzero_csr(d: np.ndarray) -> np.ndarray:
+    """One flag per entry of full_csr(d) in its packing order (row-major): 1 where the value is nonzero."""
+    return (np.ascontiguousarray(d) != 0).reshape(-1).astype(np.uint8)
+
+
+def stored_nonzero_csc(d: np.ndarray) -> np.ndarray:
+    """One flag per entry of full_csc(d) in its packing order (column-major)."""
+    return stored_nonzero_csr(np.ascontiguousarray(d.T))
+
+
 @dataclass(frozen=True)
 class Workload:
     name: str
