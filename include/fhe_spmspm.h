@@ -272,6 +272,22 @@ int fhe_ct_mask(fhe_ctx* ctx, const fhe_ct* ct, int32_t slot, void* stream, fhe_
 int fhe_ct_add(fhe_ctx* ctx, const fhe_ct* a, const fhe_ct* b, void* stream, fhe_ct** out);
 void fhe_ct_free(fhe_ct* ct);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops and
+ * harnesses that forbid hipMalloc): fhe_ct_rotate into an existing caller-owned ciphertext `out`
+ * (2 components, the limb count of `ct`; it may be `ct` itself), with the same result bit for bit.
+ * Nothing is allocated on the device: the automorphism's copy of the input, the key-switch workspace
+ * and the launch argument words live in one static device array of FHE_NOALLOC_SCRATCH_BYTES per
+ * GPU, which the library holds until the process ends. A rotation needing more (4 KiB + 8 bytes x
+ * (2 limbs N + the key-switch workspace words)) fails with FHE_ENOMEM before any work is enqueued;
+ * every level fits at N <= 2^15 and at N = 2^16 with up to 24 Q + 3 special primes (alpha = 3).
+ * All calls on one GPU share its array and nothing in it needs clearing: calls that overlap on one
+ * GPU (other host threads or streams) race and must be serialised by the caller. Returns once
+ * `stream` has finished the rotation; out's scale becomes ct's. Errors: FHE_EINVAL (NULL),
+ * FHE_ESHAPE (a 3-component ct or out, or out's limb count differs), FHE_ENOMEM (scratch too
+ * small), FHE_EKEY (a rotation key is missing), FHE_EDEVICE. */
+#define FHE_NOALLOC_SCRATCH_BYTES ((size_t)192 << 20)
+int fhe_ct_rotate_into(fhe_ctx* ctx, const fhe_ct* ct, int32_t r, fhe_ct* out, void* stream);
+
 
 /* ---- Request loop with continuous batching (Section 3: ciphertexts and keys stay on the GPU). ---- */
 

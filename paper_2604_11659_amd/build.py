@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfhe_spmspm.so")
-SOURCES = ["kernels.hip", "runtime.cpp", "host_math.cpp", "ckks.cpp", "spmspm.cpp", "server.cpp", "tune.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "host_math.cpp", "ckks.cpp", "spmspm.cpp", "server.cpp", "tune.cpp", "noalloc.hip", "capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("FHE_OFFLOAD_ARCH", "gfx950")
 FLAGS = [

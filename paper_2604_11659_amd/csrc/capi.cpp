@@ -482,6 +482,20 @@ int fhe_ct_rotate(fhe_ctx* ctx, const fhe_ct* ct, int32_t r, void* stream, fhe_c
   });
 }
 
+int fhe_ct_rotate_into(fhe_ctx* ctx, const fhe_ct* ct, int32_t r, fhe_ct* out, void* stream) {
+  return guarded([&] {
+    need(ctx, "ctx");
+    need(ct, "ct");
+    need(out, "out");
+    need2(ct);
+    need2(out);
+    if (out->nl != ct->nl) fail(FHE_ESHAPE, "out has another limb count than ct");
+    set_dev(ctx);
+    ct_rotate_noalloc(ctx, ct->data.u64(), (uint32_t)ct->nl, r, out->data.u64(), as_stream(stream));
+    out->scale = ct->scale;
+  });
+}
+
 int fhe_ct_mult_relin(fhe_ctx* ctx, const fhe_ct* a, const fhe_ct* b, void* stream, fhe_ct** out) {
   return guarded([&] {
     need(ctx, "ctx");

@@ -61,6 +61,7 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
   ctx->device = d->device;
   ctx->al = current_allocator();
   HIPCHECK(hipSetDevice(d->device));
+  noalloc_setup(d->device);
   p.logN = d->log_n;
   p.N = 1u << p.logN;
   p.S = p.N / 2;

@@ -66,6 +66,12 @@ void export_coeffs(fhe_ctx* ctx, const uint64_t* data, int ncomp, int nl, hipStr
 
 // Single-ciphertext operations (batch of one).
 void ct_rotate(fhe_ctx* ctx, const uint64_t* src, int nl, int64_t r, uint64_t* dst, hipStream_t st);
+// The no-alloc rotation (noalloc.hip): noalloc_setup resolves the static scratch array's device
+// address on `device` (current) once; ct_rotate_noalloc is ct_rotate with all of its scratch in that
+// array (dst may equal src), failing with FHE_ENOMEM when noalloc_rotate_bytes exceeds it.
+void noalloc_setup(int device);
+size_t noalloc_rotate_bytes(const fhe_ctx* ctx, uint32_t nl);
+void ct_rotate_noalloc(fhe_ctx* ctx, const uint64_t* src, uint32_t nl, int64_t r, uint64_t* dst, hipStream_t st);
 void ct_mult_relin(fhe_ctx* ctx, const uint64_t* a, const uint64_t* b, int nl, uint64_t* dst, hipStream_t st);
 void ct_rescale(fhe_ctx* ctx, const uint64_t* src, int ncomp, int nl, uint64_t* dst, hipStream_t st);
 void ct_mask(fhe_ctx* ctx, const uint64_t* src, int nl, int slot, uint64_t* dst, hipStream_t st);

@@ -89,6 +89,7 @@ _SIGS = {
     "fhe_ct_export": ([c_vp, c_vp, P_u64, c_sz, c_vp], c_i32),
     "fhe_ct_info": ([c_vp, P_i32, P_i32, P_dbl], c_i32),
     "fhe_ct_rotate": ([c_vp, c_vp, c_i32, c_vp, PP], c_i32),
+    "fhe_ct_rotate_into": ([c_vp, c_vp, c_i32, c_vp, c_vp], c_i32),
     "fhe_ct_mult_relin": ([c_vp, c_vp, c_vp, c_vp, PP], c_i32),
     "fhe_ct_rescale": ([c_vp, c_vp, c_vp, PP], c_i32),
     "fhe_ct_mask": ([c_vp, c_vp, c_i32, c_vp, PP], c_i32),
@@ -451,6 +452,11 @@ class Context(_Handle):
 
     def ct_rotate(self, ct: Ciphertext, r: int, stream=None) -> Ciphertext:
         return self._ct1(_lib.fhe_ct_rotate, ct._ptr, r, stream=stream)
+
+    def ct_rotate_into(self, ct: Ciphertext, r: int, out: Ciphertext, stream=None) -> Ciphertext:
+        """ct_rotate into the existing `out` (same limb count) with no device allocation."""
+        _check(_lib.fhe_ct_rotate_into(self._ptr, ct._ptr, r, out._ptr, _stream(stream)))
+        return out
 
     def ct_mult_relin(self, a: Ciphertext, b: Ciphertext, stream=None) -> Ciphertext:
         return self._ct1(_lib.fhe_ct_mult_relin, a._ptr, b._ptr, stream=stream)
