@@ -4,6 +4,10 @@ Builds ``oracle/libckks_oracle.so`` from ``ckks_oracle.c`` with gcc when it is
 missing (or when ``build_oracle(force=True)`` is called). Floating-point
 contraction is disabled so that encoding and sampling evaluate exactly the
 operation sequence written in the C source.
+
+``build_oracle(sanitize=True)`` builds ``libckks_oracle_san.so`` with gcc's
+AddressSanitizer and UndefinedBehaviorSanitizer; a process that sets
+``FHE_ORACLE_SANITIZED=1`` (and preloads gcc's libasan) loads that one instead.
 """
 from __future__ import annotations
 
@@ -16,17 +20,20 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ckks_oracle.c")
 _SO = os.path.join(_HERE, "libckks_oracle.so")
+_SO_SAN = os.path.join(_HERE, "libckks_oracle_san.so")
+_SAN = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
 
 _lib = None
 
 
-def build_oracle(force: bool = False) -> str:
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-               "-o", _SO + ".tmp", _SRC, "-lm"]
+def build_oracle(force: bool = False, sanitize: bool = False) -> str:
+    so = _SO_SAN if sanitize else _SO
+    if force or not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O1" if sanitize else "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+               *(_SAN if sanitize else []), "-o", so + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(_SO + ".tmp", _SO)
-    return _SO
+        os.replace(so + ".tmp", so)
+    return so
 
 
 u64 = ctypes.c_uint64
@@ -74,7 +81,7 @@ _SIGS = {
 def lib():
     global _lib
     if _lib is None:
-        path = build_oracle()
+        path = build_oracle(sanitize=os.environ.get("FHE_ORACLE_SANITIZED") == "1")
         handle = ctypes.CDLL(path)
         for name, (args, res) in _SIGS.items():
             fn = getattr(handle, name)

@@ -19,7 +19,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfhe_spmspm.so")
+# FHE_SPMSPM_LIB selects another build of the same library (the host-sanitizer build of the CPU tests)
+LIB_PATH = os.environ.get("FHE_SPMSPM_LIB") or os.path.join(_HERE, "libfhe_spmspm.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_11659_amd.build`")

@@ -8,9 +8,10 @@
 * N = 2^16 (24 Q + 3 P primes, three digits) and N = 2^17 (35 Q + 3 P, four digits): small matmuls
   bit-exact; the 512 x 512 workload bit-exact on pair ranges; and a merged batch of three uneven
   matmuls of the batching workload (seeded prefixes and a tail range) bit-exact in every chunk.
-The oracle runs in 8 forked CPU workers (they never touch the GPU). Contexts, keys and encrypted
+The oracle runs in up to 16 forked CPU workers (they never touch the GPU). Contexts, keys and encrypted
 operands of one parameter set are built once per module and shared by its tests.
 """
+import os
 import sys
 
 import numpy as np
@@ -20,7 +21,8 @@ from oracle import ckks, spmspm
 from paper_2604_11659_amd import synth
 
 pytestmark = pytest.mark.gpu
-WORKERS = 8
+# oracle worker processes: the CPUs this process may use, at most 16 (a GPU machine's CPU share)
+WORKERS = max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 def _say(msg):
