@@ -92,6 +92,15 @@ __device__ __forceinline__ double opaque(double x) {
   return x;
 }
 
+// Pointers read from per-item device tables are generic pointers to the compiler, so accesses through
+// them compile to flat instructions, which also count on the LDS counter: every wait for such a load
+// then waits for the wavefront's LDS operations too (and the other way round), and LDS accesses cannot
+// be moved past them. All of them point to global memory; this cast makes them global loads/stores.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // Exact conversions between uint64 and double for integers in [0, 2^52): the double 2^52 + x has the
 // bits of x as its mantissa, so each direction is one FP64 add and one bit operation (the generic
 // 64-bit conversions take four to six instructions).
@@ -355,7 +364,7 @@ __global__ __launch_bounds__(NT) void k_ntt(LimbBatch lb, const ModInfo* __restr
     const uint32_t wb = (threadIdx.x >> 6) * (kNttE / (NT / 64)), lane = threadIdx.x & 63;
     if (kSrcPtr) {
       // read through the automorphism: a wavefront's 64 indices map into one aligned 64-word block
-      const uint64_t* sp = lb.src_ptr[poly] + (uint64_t)(lb.src_ptr_limb0 + e) * N;
+      const auto sp = gmem(lb.src_ptr[poly] + (uint64_t)(lb.src_ptr_limb0 + e) * N);
       const uint32_t g = lb.src_gal[poly];
 #pragma unroll
       for (uint32_t r_ = 0; r_ < kPer; ++r_) {
@@ -422,7 +431,7 @@ __device__ __forceinline__ void ntt_p2_inner_body(
   const ModInfo m = mods[mi];
   const uint64_t j0 = (uint64_t)tile * kNttE;
   const uint32_t k = logN - k1, logC = kNttLogE - k;
-  const uint64_t* key = keys[b];
+  const auto key = gmem(keys[b]);
   A ar;
   ar.init(m);
   const typename A::W* w = tw + (uint64_t)mi * 4 * N;
@@ -434,11 +443,11 @@ __device__ __forceinline__ void ntt_p2_inner_body(
   for (uint32_t r = 0; r < kPer; ++r) acc0[r] = acc1[r] = 0;
   for (uint32_t j = 0; j < beta; ++j) {
     const uint32_t lo = j * alpha, cnt = min(alpha, nl - lo);
-    const uint64_t* kb = key + ((uint64_t)(j * 2 + 0) * nall + mi) * N + j0;
-    const uint64_t* ka = key + ((uint64_t)(j * 2 + 1) * nall + mi) * N + j0;
+    const auto kb = key + ((uint64_t)(j * 2 + 0) * nall + mi) * N + j0;
+    const auto ka = key + ((uint64_t)(j * 2 + 1) * nall + mi) * N + j0;
     if (e >= lo && e < lo + cnt) {  // the digit's own limbs (Q limbs only)
       if (kSrcPtr) {  // the input read through its automorphism (rotation without a separate pass)
-        const uint64_t* x = in_ptr[b] + (uint64_t)e * N;
+        const auto x = gmem(in_ptr[b] + (uint64_t)e * N);
         const uint32_t g = in_gal[b];
 #pragma unroll
         for (uint32_t r = 0; r < kPer; ++r) {
@@ -569,7 +578,7 @@ __global__ __launch_bounds__(kThreads) void k_hoisted_inner(
   A ar;
   ar.init(mods[mi]);
   const uint32_t j0 = tile * kTile, g = gal[b], sb = state[b];
-  const uint64_t* key = keys[b];
+  const auto key = gmem(keys[b]);
   const uint32_t wb = (threadIdx.x >> 6) * (kTile / (kThreads / 64)), lane = threadIdx.x & 63;
   uint32_t src[kPer];
 #pragma unroll
@@ -579,10 +588,10 @@ __global__ __launch_bounds__(kThreads) void k_hoisted_inner(
   for (uint32_t r = 0; r < kPer; ++r) acc0[r] = acc1[r] = 0;
   for (uint32_t j = 0; j < beta; ++j) {
     const uint32_t lo = j * alpha, cnt = min(alpha, nl - lo);
-    const uint64_t* kb = key + ((uint64_t)(j * 2 + 0) * nall + mi) * N + j0 + wb;
-    const uint64_t* ka = key + ((uint64_t)(j * 2 + 1) * nall + mi) * N + j0 + wb;
+    const auto kb = key + ((uint64_t)(j * 2 + 0) * nall + mi) * N + j0 + wb;
+    const auto ka = key + ((uint64_t)(j * 2 + 1) * nall + mi) * N + j0 + wb;
     if (e >= lo && e < lo + cnt) {  // the digit's own limbs (Q limbs only): the input itself
-      const uint64_t* x = in_ptr[b] + (uint64_t)e * N;
+      const auto x = gmem(in_ptr[b] + (uint64_t)e * N);
 #pragma unroll
       for (uint32_t r = 0; r < kPer; ++r) {
         const typename A::T xv = ar.from_u64(x[src[r]]);
@@ -651,10 +660,10 @@ __global__ __launch_bounds__(NT) void k_ntt_p2_combine(uint32_t nl, uint32_t K, 
   ntt_rounds<false, 2, A, kPer, NT, true>(lds, ar, w, k, logC, k1, j0);
   const uint64_t* pinv = tab + 2 * K + 2 * (uint64_t)K * nq + 2 * i;
   const uint64_t* uu = u + ((uint64_t)bc * next + i) * N + j0;
-  const uint64_t* ad = add[bc];
+  auto ad = gmem(add[bc]);
   const uint32_t gal = galois ? galois[b] : 0;  // rotation form: the addend goes through tau_gal
   if (ad) ad += (uint64_t)i * N + (galois ? 0 : j0);
-  uint64_t* o = out[b] + ((uint64_t)c * nl + i) * N + j0;
+  const auto o = gmem(out[b] + ((uint64_t)c * nl + i) * N + j0);
   const uint32_t ln = opaque(lane);
   // exact FP64: |u - conv| < 1.5q + 2, so the product with P^-1 is below 0.9q and adding the
   // [0, q) addend keeps the sum below 2q before the final reduction
@@ -697,7 +706,7 @@ __global__ __launch_bounds__(kThreads) void k_automorph(uint32_t B, uint32_t nco
   for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < total; t += (uint64_t)gridDim.x * kThreads) {
     const uint32_t b = (uint32_t)(t >> logN), k = (uint32_t)t & (N - 1);
     const uint32_t ks = automorph_src(k, galois[b], logN);
-    const uint64_t* s = src[b];
+    const auto s = gmem(src[b]);
     uint64_t* d = dst + (uint64_t)b * ncomp * nl * N;
     for (uint32_t r = 0; r < ncomp * nl; ++r) d[(uint64_t)r * N + k] = s[(uint64_t)r * N + ks];
   }
@@ -714,8 +723,8 @@ __global__ __launch_bounds__(kThreads) void k_tensor(uint32_t B, uint32_t nl, ui
     const uint64_t r = t >> logN;
     const uint32_t i = (uint32_t)(r % nl), b = (uint32_t)(r / nl);
     const ModInfo m = mods[i];
-    const uint64_t* a = A[b];
-    const uint64_t* bb = Bc[b];
+    const auto a = gmem(A[b]);
+    const auto bb = gmem(Bc[b]);
     const uint64_t a0 = a[(uint64_t)i * N + k], a1 = a[(uint64_t)(nl + i) * N + k];
     const uint64_t b0 = bb[(uint64_t)i * N + k], b1 = bb[(uint64_t)(nl + i) * N + k];
     uint64_t* o = out + (uint64_t)b * 3 * nl * N;
@@ -1045,7 +1054,7 @@ __global__ __launch_bounds__(kThreads) void k_copy_last(uint32_t B, uint32_t nco
   for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < total; t += (uint64_t)gridDim.x * kThreads) {
     const uint32_t k = (uint32_t)t & (N - 1);
     const uint32_t bc = (uint32_t)(t >> logN), b = bc / ncomp, c = bc - b * ncomp;
-    uint64_t v = in[b][((uint64_t)c * nl + nl - 1) * N + k];
+    uint64_t v = gmem(in[b])[((uint64_t)c * nl + nl - 1) * N + k];
     if (galois) {
       const ModInfo m = mods[nl - 1];
       v = mont_mul(v, maskm[((uint64_t)(nl - 1) << logN) + automorph_src(k, galois[b], logN)], m.q, m.qinv);
@@ -1086,8 +1095,8 @@ __global__ __launch_bounds__(kThreads) void k_rescale_combine(uint32_t B, uint32
     const uint32_t i = (uint32_t)(r % no);
     const uint32_t bc = (uint32_t)(r / no), b = bc / ncomp, c = bc - b * ncomp;
     const uint64_t q = mods[i].q;
-    const uint64_t x = sub_mod(in[b][((uint64_t)c * nl + i) * N + k], w[t], q);
-    out[b][((uint64_t)c * no + i) * N + k] = shoup_mul(x, inv[2 * i], inv[2 * i + 1], q);
+    const uint64_t x = sub_mod(gmem(in[b])[((uint64_t)c * nl + i) * N + k], w[t], q);
+    gmem(out[b])[((uint64_t)c * no + i) * N + k] = shoup_mul(x, inv[2 * i], inv[2 * i + 1], q);
   }
 }
 
@@ -1175,8 +1184,8 @@ __global__ __launch_bounds__(NT) void k_rescale_rows(uint32_t ncomp, uint32_t nl
   wave_sync();
   ntt_rounds<false, 2, FpArith, kPer, NT, true>(lds, ar, twf + (uint64_t)i * 4 * N, k, logC, k1, j0);
   const uint64_t* inv = tab + 2 * ((uint64_t)no * nq + i);
-  const uint64_t* x = in[b] + ((uint64_t)c * nl + i) * N + j0;
-  uint64_t* o = out[b] + ((uint64_t)c * no + i) * N + j0;
+  const auto x = gmem(in[b] + ((uint64_t)c * nl + i) * N + j0);
+  const auto o = gmem(out[b] + ((uint64_t)c * no + i) * N + j0);
   const uint32_t ln = opaque(lane);
   const double iv = (double)inv[0], ivq = iv * ar.qinv;  // exact FP64 as in k_ntt_p2_combine
   // all loads first (as in k_ntt_p2_combine: `o` may alias the input as far as the compiler knows)
@@ -1208,8 +1217,8 @@ __global__ __launch_bounds__(kThreads) void k_mask_mul(uint32_t B, uint32_t nl, 
   for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < total; t += (uint64_t)gridDim.x * kThreads) {
     const uint32_t b = (uint32_t)(t >> logN), k = (uint32_t)t & (N - 1);
     const uint32_t ks = automorph_src(k, galois[b], logN);
-    const uint64_t* s = in[b];
-    uint64_t* d = out[b];
+    const auto s = gmem(in[b]);
+    const auto d = gmem(out[b]);
     for (uint32_t i = 0; i < nl; ++i) {
       const ModInfo m = mods[i];
       const uint64_t mk = maskm[((uint64_t)i << logN) + ks];
@@ -1256,7 +1265,7 @@ __global__ __launch_bounds__(kThreads) void k_mask_sum(uint32_t nseg, uint32_t n
       uint64_t mk[4], x0[4], x1[4];
 #pragma unroll
       for (uint32_t j = 0; j < 4; ++j) {
-        const uint64_t* x = in[e + j] + off;
+        const auto x = gmem(in[e + j] + off);
         mk[j] = mrow[automorph_src(k, galois[e + j], logN)];
         x0[j] = x[0];
         x1[j] = x[per];
@@ -1271,7 +1280,7 @@ __global__ __launch_bounds__(kThreads) void k_mask_sum(uint32_t nseg, uint32_t n
     }
     for (; e < e1; ++e) {
       const uint64_t mk = mrow[automorph_src(k, galois[e], logN)];
-      const uint64_t* x = in[e] + off;
+      const auto x = gmem(in[e] + off);
       v0 = ar.kacc(v0, u52_to_f64(x[0]), mk);
       v1 = ar.kacc(v1, u52_to_f64(x[per]), mk);
     }
@@ -1294,9 +1303,9 @@ __global__ __launch_bounds__(kThreads) void k_accumulate_ptr(uint32_t nseg, uint
     const uint64_t off = t - (uint64_t)s * per;
     const uint64_t q = mods[(uint32_t)((off >> logN) % nl)].q;
     const uint32_t b0 = seg[3 * s + 1], b1 = seg[3 * s + 2];
-    uint64_t* res = results[seg[3 * s]];
+    const auto res = gmem(results[seg[3 * s]]);
     uint64_t acc = res[off];
-    for (uint32_t b = b0; b < b1; ++b) acc = add_mod(acc, contrib[b][off], q);
+    for (uint32_t b = b0; b < b1; ++b) acc = add_mod(acc, gmem(contrib[b])[off], q);
     res[off] = acc;
   }
 }
@@ -1326,7 +1335,7 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(uint32_t nseg, uint32_t
     const uint32_t i = (uint32_t)((off >> logN) % nl);
     const uint64_t q = mods[i].q;
     const uint32_t b0 = seg[3 * s + 1], b1 = seg[3 * s + 2];
-    uint64_t* res = results[seg[3 * s]];
+    const auto res = gmem(results[seg[3 * s]]);
     uint64_t acc = res[off];
     for (uint32_t b = b0; b < b1; ++b) acc = add_mod(acc, contrib[(uint64_t)b * per + off], q);
     res[off] = acc;

@@ -41,9 +41,11 @@ Plan build_plan(const Params& p, const fhe_mat* A, const fhe_mat* B, int64_t beg
   plan.nres = (int)std::max<int64_t>(1, ((int64_t)m * n + S - 1) / S);
   std::unordered_map<uint64_t, int32_t> prod_id;
   int64_t idx = 0;
-  for (int i = 0; i < m; ++i) {
+  // the traversal stops at the end of the range: pairs after it are not needed, and a prefix of a
+  // large matmul would otherwise pay for the merge over every cell of C
+  for (int i = 0; i < m && idx < end; ++i) {
     const int32_t a_end = A->indptr[i + 1];
-    for (int j = 0; j < n; ++j) {
+    for (int j = 0; j < n && idx < end; ++j) {
       int32_t a_pos = A->indptr[i], b_pos = B->indptr[j];
       const int32_t b_end = B->indptr[j + 1];
       while (a_pos < a_end && b_pos < b_end) {

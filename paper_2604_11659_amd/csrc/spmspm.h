@@ -24,7 +24,7 @@ struct Plan {
   std::vector<PlanProduct> prods;
   std::vector<PlanPair> pairs;
   int nres = 1;           // result chunks
-  int64_t matched = 0;    // matched pairs of the full traversal
+  int64_t matched = 0;    // matched pairs traversed (up to the end of the range; all for a full range)
   // pairs grouped by product: pairs[by_prod[first[i] .. first[i+1])] belong to product i
   std::vector<size_t> first;
   std::vector<uint32_t> by_prod;
