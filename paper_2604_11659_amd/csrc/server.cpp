@@ -230,7 +230,7 @@ int fhe_server_create(fhe_ctx* const* ctxs, size_t nctx, size_t hbm_budget, size
       const size_t left = hbm_budget > fixed ? hbm_budget - fixed : 0;
       cap = left / (4 * nctx);
       const char* e = getenv("FHE_WORKSPACE_MB");
-      cap = std::min(cap, (size_t)(e ? atoll(e) : 24576) << 20);
+      cap = std::min(cap, (size_t)(e ? atoll(e) : 131072) << 20);
     }
     cap = std::max(cap, one.words * 8);
     cap = std::min(cap, big.words * 8);

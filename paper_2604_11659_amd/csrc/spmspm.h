@@ -71,7 +71,7 @@ void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool gro
 // Plan mode and memory limits of one execution.
 struct ExecOpts {
   bool grouped = false, graph = false, tree = false, hoist = false;
-  size_t ws_bytes = 0;     // executor scratch budget (0: FHE_WORKSPACE_MB, default 24576 MiB)
+  size_t ws_bytes = 0;     // executor scratch budget (0: FHE_WORKSPACE_MB, default a third of free HBM, <= 128 GiB)
   size_t group_bytes = 0;  // grouped plans: budget of the resident products (0: FHE_GROUP_MB, default 49152 MiB)
 };
 

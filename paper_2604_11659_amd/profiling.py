@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 CSV output for the kernels of this library.
 
-Two summaries, both short markdown files:
+Three summaries, all short markdown files:
 
 * ``stats``: the ``*_kernel_stats.csv`` of a ``--kernel-trace --stats -f csv`` run, as a table of
   calls / total / average per kernel.
@@ -9,10 +9,13 @@ Two summaries, both short markdown files:
   copy-like kernel of known size run in the same process (1 GiB read and 1 GiB written). The result
   is embedded as a JSON block tagged with the SHA-256 of the kernel source it was measured on, so a
   reader can tell when the numbers have gone stale.
+* ``counters``: per-dispatch means of any ``--pmc`` counters (several CSVs, one per pass) for each
+  kernel, with the ratios that say where a kernel's waves spend their time.
 
   python -m paper_2604_11659_amd.profiling stats CSV --title T --command C --out FILE
   python -m paper_2604_11659_amd.profiling traffic FETCH_CSV WRITE_CSV --kernel REGEX --label NAME \
       --calib REGEX --calib-bytes 1073741824 --title T --command C --out FILE
+  python -m paper_2604_11659_amd.profiling counters CSV [CSV ...] --kernel REGEX --title T --command C --out FILE
 """
 from __future__ import annotations
 
@@ -108,6 +111,44 @@ def traffic_markdown(t: dict, label: str, title: str, command: str, note: str = 
     return "\n".join(out)
 
 
+def counters_markdown(csv_paths: list[str], kernel: str, title: str, command: str, note: str = "") -> str:
+    """Per-dispatch means of every counter in the CSVs for the kernels matching `kernel`."""
+    agg: dict[str, dict[str, list[float]]] = defaultdict(lambda: defaultdict(list))
+    for path in csv_paths:
+        for r in csv.DictReader(open(path)):
+            if re.search(kernel, r["Kernel_Name"]):
+                agg[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = sorted({c for cs in agg.values() for c in cs})
+    out = [f"# {title}", ""]
+    if note:
+        out += [note, ""]
+    out += ["Commands (from the repository root; one run per counter set):", "", "```", command, "```", "",
+            "Per-dispatch means (counters as the device reports them, summed over its units):", "",
+            "| kernel | dispatches | " + " | ".join(names) + " |", "|---" * (len(names) + 2) + "|"]
+    for k, cs in sorted(agg.items()):
+        n = max(len(v) for v in cs.values())
+        out.append(f"| `{k}` | {n} | " + " | ".join(
+            f"{sum(cs[c]) / len(cs[c]):.4g}" if cs.get(c) else "" for c in names) + " |")
+    ratios = [("SQ_INSTS_VALU", "SQ_WAVES", "VALU instructions per wave"),
+              ("SQ_INSTS_LDS", "SQ_WAVES", "LDS instructions per wave"),
+              ("SQ_INSTS_VMEM_RD", "SQ_WAVES", "vector memory reads per wave"),
+              ("SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES", "share of wave cycles waiting on a dependency (s_waitcnt)"),
+              ("SQ_WAIT_ANY", "SQ_WAVE_CYCLES", "share of wave cycles waiting on anything"),
+              ("SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES", "share of wave cycles issuing VALU"),
+              ("SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS", "LDS bank-conflict cycles per LDS-active cycle")]
+    rows = []
+    for k, cs in sorted(agg.items()):
+        vals = []
+        for a, b, _ in ratios:
+            if cs.get(a) and cs.get(b) and sum(cs[b]):
+                vals.append(f"{sum(cs[a]) / sum(cs[b]):.3g}")
+            else:
+                vals.append("")
+        rows.append(f"| `{k}` | " + " | ".join(vals) + " |")
+    out += ["", "| kernel | " + " | ".join(t for _, _, t in ratios) + " |", "|---" * (len(ratios) + 1) + "|", *rows]
+    return "\n".join(out) + "\n"
+
+
 def load_traffic(profiles_dir: str, label: str) -> dict | None:
     """The traffic block for `label` measured on the current kernel source, if any."""
     if not os.path.isdir(profiles_dir):
@@ -139,7 +180,10 @@ def main(argv=None) -> int:
     t.add_argument("--label", required=True)
     t.add_argument("--calib", required=True)
     t.add_argument("--calib-bytes", type=float, default=float(1 << 30))
-    for p in (s, t):
+    c = sub.add_parser("counters")
+    c.add_argument("csvs", nargs="+")
+    c.add_argument("--kernel", required=True)
+    for p in (s, t, c):
         p.add_argument("--title", required=True)
         p.add_argument("--command", required=True)
         p.add_argument("--note", default="")
@@ -147,6 +191,8 @@ def main(argv=None) -> int:
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         text = stats_markdown(a.csv, a.title, a.command, a.note)
+    elif a.cmd == "counters":
+        text = counters_markdown(a.csvs, a.kernel, a.title, a.command, a.note)
     else:
         text = traffic_markdown(traffic(a.fetch_csv, a.write_csv, a.kernel, a.calib, a.calib_bytes), a.label,
                                 a.title, a.command, a.note)
