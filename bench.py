@@ -304,20 +304,23 @@ def run_headline(args) -> dict:
     prof = fhe.profile_read()
     ks_step = prof.get("count:keyswitch", {}).get("launches", 0) / args.steps
 
-    # plain: the same prefixes as 64 single calls
+    # plain: the same prefixes as 64 single calls (left out only by counter runs of the batched form)
     psteps = args.plain_steps if args.plain_steps > 0 else max(2, args.steps // 4)
-    _close(ctx.spmspm_pairs(A, B, lo, hi) for A, B, (lo, hi) in zip(As, Bs, ranges))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    Cp = None
-    for _ in range(psteps):
-        if Cp is not None:
-            _close(Cp)
-        Cp = [ctx.spmspm_pairs(A, B, lo, hi) for A, B, (lo, hi) in zip(As, Bs, ranges)]
-    torch.cuda.synchronize()
-    t_plain = (time.perf_counter() - t0) / psteps
-    log(f"batched {1000 * t_batch:.1f} ms/step, plain {1000 * t_plain:.1f} ms/step")
-    same = all((ctx.export(x, c) == ctx.export(y, c)).all() for x, y in zip(Cb, Cp) for c in range(x.info()["chunks"]))
+    t_plain, same, Cp = None, None, []
+    if args.plain:
+        _close(ctx.spmspm_pairs(A, B, lo, hi) for A, B, (lo, hi) in zip(As, Bs, ranges))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Cp = None
+        for _ in range(psteps):
+            if Cp is not None:
+                _close(Cp)
+            Cp = [ctx.spmspm_pairs(A, B, lo, hi) for A, B, (lo, hi) in zip(As, Bs, ranges)]
+        torch.cuda.synchronize()
+        t_plain = (time.perf_counter() - t0) / psteps
+        log(f"batched {1000 * t_batch:.1f} ms/step, plain {1000 * t_plain:.1f} ms/step")
+        same = all((ctx.export(x, c) == ctx.export(y, c)).all() for x, y in zip(Cb, Cp)
+                   for c in range(x.info()["chunks"]))
     err = 0.0
     for i, C in enumerate(Cb):
         a, b = mats[i]
@@ -353,7 +356,8 @@ def run_headline(args) -> dict:
     ctx.close()
     del As, Bs
     dnn = run_dnn_leg(args) if args.dnn else None
-    pb, pp = pairs / t_batch, pairs / t_plain
+    pb = pairs / t_batch
+    pp = pairs / t_plain if t_plain else None
     line = {
         "metric": METRIC, "value": round(pb / mean_f, 8), "unit": "SpMSpM/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1000 * t_batch, 2), "higher_is_better": True, "scaling": "weak",
@@ -364,9 +368,10 @@ def run_headline(args) -> dict:
                    "ntt_split_autotuned": tuned},
         "batched": {"pairs_per_s": round(pb, 1), "spmspm_per_s_projected": pb / mean_f, "ms_per_step": round(1000 * t_batch, 2),
                     "steps": args.steps},
-        "plain": {"pairs_per_s": round(pp, 1), "spmspm_per_s_projected": pp / mean_f, "ms_per_step": round(1000 * t_plain, 2),
-                  "steps": psteps},
-        "batched_over_plain": round(t_plain / t_batch, 3), "results_bit_identical": bool(same),
+        "plain": ({"pairs_per_s": round(pp, 1), "spmspm_per_s_projected": pp / mean_f,
+                   "ms_per_step": round(1000 * t_plain, 2), "steps": psteps} if t_plain else None),
+        "batched_over_plain": round(t_plain / t_batch, 3) if t_plain else None,
+        "results_bit_identical": None if same is None else bool(same),
         "max_abs_err_vs_fp64_prefix": err, "matched_pairs_per_s": round(pb, 1),
         "keyswitches_per_step": ks_step, "keyswitch_per_s": round(ks_step / t_batch, 1),
         "ntt_keyswitch_algo_GBps": roof.get("keyswitch", {}).get("hbm", {}).get("achieved"),
@@ -581,8 +586,9 @@ def run_serve(args) -> dict:
     keys resident, one shared HBM budget), requests alternating between them.
 
     Phase 1, the stated load: sizes from {64, 128, 256, 512}, per-operand sparsity U[0.70, 0.95],
-    Poisson arrivals at --serve-rate (20/s) for --serve-overload-s; reports arrivals and the admitted,
-    queued and completed counts when the window closes, then cancels what is left. Phase 2, latency:
+    Poisson arrivals at --serve-rate (20/s) for --serve-overload-s, each arrival one of --serve-pool
+    distinct encrypted requests; reports arrivals and the admitted, queued and completed counts when
+    the window closes, then cancels what is left. Phase 2, latency:
     the capacity of the server is measured on --serve-sizes requests run back to back (saturated), and
     Poisson arrivals at --serve-load of it are served until at least --serve-min-complete requests have
     completed; reports p50/p99 latency and throughput = completions / (last completion - first arrival)
@@ -615,8 +621,11 @@ def run_serve(args) -> dict:
     # phase 1: the stated arrival process and sizes
     stated = [int(x) for x in args.serve_stated_sizes.split(",")]
     arr = synth.poisson_arrivals(args.serve_rate, args.serve_overload_s, 7)
-    reqs = [make(100_000 + i, stated) for i in range(len(arr))]
-    fpairs = [matched_pairs_count(a, b) for (_, _, _, a, b) in reqs]
+    # a pool of distinct encrypted requests (host encoding of 512 x 512 operands takes seconds each);
+    # arrival i submits pool entry i mod len(pool), alternating between the parameter sets as before
+    pool = [make(100_000 + i, stated) for i in range(min(len(arr), args.serve_pool))]
+    reqs = [pool[i % len(pool)] for i in range(len(arr))]
+    fpairs = [matched_pairs_count(a, b) for (_, _, _, a, b) in pool]
     srv = server()
     torch.cuda.synchronize()
     start = time.perf_counter()
@@ -634,14 +643,15 @@ def run_serve(args) -> dict:
         srv.cancel(t)
     srv.close()
     over = {"offered_req_per_s": args.serve_rate, "window_s": args.serve_overload_s, "sizes": stated,
-            "arrived": len(arr), "admitted": at_close["inflight"] + at_close["completed"] + at_close["failed"],
+            "arrived": len(arr), "distinct_requests": len(pool),
+            "admitted": at_close["inflight"] + at_close["completed"] + at_close["failed"],
             "completed": at_close["completed"], "in_flight_at_close": at_close["inflight"],
             "queued_at_close": at_close["queued"], "mean_matched_pairs_per_request": float(np.mean(fpairs)),
             "offered_matched_pairs_per_s": float(np.mean(fpairs)) * args.serve_rate,
             "budget_bytes": at_close["budget_bytes"], "fixed_bytes": at_close["fixed_bytes"],
             "inflight_bytes_at_close": at_close["inflight_bytes"]}
     log(f"stated load: {over}")
-    del reqs
+    del reqs, pool
 
     # phase 2: capacity (saturated) and latency at a fraction of it
     sizes = [int(x) for x in args.serve_sizes.split(",")]
@@ -714,6 +724,9 @@ def main():
     ap.add_argument("--workload", default="batch", choices=sorted(synth.WORKLOADS) + sorted(synth.BATCH_WORKLOADS))
     ap.add_argument("--batch-cap", type=int, default=32, help="batching workloads: matched pairs run per matmul")
     ap.add_argument("--plain-steps", type=int, default=0, help="headline: timed plain steps (0: max(2, steps / 4))")
+    ap.add_argument("--plain", type=int, default=1,
+                    help="headline: 1 runs the plain leg (one call per matmul) beside the batched one; 0 leaves it "
+                         "out (counter runs of the batched kernels)")
     ap.add_argument("--tree-steps", type=int, default=2, help="headline: timed steps of the tree + hoisted plan")
     ap.add_argument("--dnn", type=int, default=1, help="headline: also run the DNN-layer workload (N = 2^15)")
     ap.add_argument("--dnn-steps", type=int, default=1)
@@ -737,6 +750,7 @@ def main():
     ap.add_argument("--serve-capacity-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=20.0, help="stated arrival rate (req/s)")
     ap.add_argument("--serve-overload-s", type=float, default=10.0)
+    ap.add_argument("--serve-pool", type=int, default=32, help="distinct requests of the stated-load window")
     ap.add_argument("--serve-budget-gb", type=int, default=200)
     ap.add_argument("--serve-inflight", type=int, default=8)
     ap.add_argument("--serve-slice", type=int, default=32)

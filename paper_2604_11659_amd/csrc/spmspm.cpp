@@ -167,10 +167,10 @@ struct Workspace {
 };
 
 // Executor scratch budget: FHE_WORKSPACE_MB if set, else a third of the device memory free at the
-// call, between 1 and 128 GiB. Larger batches put more items that share a rotation key into one
-// launch (and fewer launches per matmul): at N = 2^16 a 128 GiB budget took 6 % off a step against
-// the former fixed 24 GiB.
-size_t workspace_budget_bytes() {
+// call plus the scratch the context already holds (which the call reuses), between 1 and 128 GiB.
+// Larger batches put more items that share a rotation key into one launch (and fewer launches per
+// matmul): at N = 2^16 a 128 GiB budget took 6 % off a step against the former fixed 24 GiB.
+size_t workspace_budget_bytes(const fhe_ctx* ctx) {
   if (const char* e = getenv("FHE_WORKSPACE_MB")) {
     size_t mb = (size_t)atoll(e);
     if (mb < 64) mb = 64;
@@ -178,7 +178,8 @@ size_t workspace_budget_bytes() {
   }
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)72 << 30;
-  return std::min<size_t>((size_t)128 << 30, std::max<size_t>((size_t)1 << 30, free_b / 3));
+  const size_t avail = free_b + ctx->ws_cache.bytes();
+  return std::min<size_t>((size_t)128 << 30, std::max<size_t>((size_t)1 << 30, avail / 3));
 }
 
 // One batched rotation step over `items`: src[b] -> out[b] rotated left by steps[b] (one key switch).
@@ -872,7 +873,7 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, co
   const size_t nprod = plan.prods.size();
 
   // Batch sizes from the workspace budget.
-  const WsPlan wp = ws_plan(ctx, opts.ws_bytes ? opts.ws_bytes : workspace_budget_bytes(), nprod, plan.pairs.size());
+  const WsPlan wp = ws_plan(ctx, opts.ws_bytes ? opts.ws_bytes : workspace_budget_bytes(ctx), nprod, plan.pairs.size());
   const size_t PB = wp.PB, BB = wp.BB;
 
   Workspace ws;
