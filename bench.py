@@ -629,12 +629,17 @@ def run_serve(args) -> dict:
     srv = server()
     torch.cuda.synchronize()
     start = time.perf_counter()
-    tickets = []
+    tickets, refused = [], 0
     for t_arr, (ci, A, B, _, _) in zip(arr, reqs):
         dt = start + t_arr - time.perf_counter()
         if dt > 0:
             time.sleep(dt)
-        tickets.append(srv.submit(A, B, ctx_id=ci))
+        try:
+            tickets.append(srv.submit(A, B, ctx_id=ci))
+        except fhe.FheError as e:  # a request that can never fit the budget (or a full queue) is refused
+            if e.code not in (-5, -6):
+                raise
+            refused += 1
     dt = start + args.serve_overload_s - time.perf_counter()
     if dt > 0:
         time.sleep(dt)
@@ -643,7 +648,7 @@ def run_serve(args) -> dict:
         srv.cancel(t)
     srv.close()
     over = {"offered_req_per_s": args.serve_rate, "window_s": args.serve_overload_s, "sizes": stated,
-            "arrived": len(arr), "distinct_requests": len(pool),
+            "arrived": len(arr), "distinct_requests": len(pool), "refused_at_submit": refused,
             "admitted": at_close["inflight"] + at_close["completed"] + at_close["failed"],
             "completed": at_close["completed"], "in_flight_at_close": at_close["inflight"],
             "queued_at_close": at_close["queued"], "mean_matched_pairs_per_request": float(np.mean(fpairs)),
@@ -663,8 +668,9 @@ def run_serve(args) -> dict:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tk = [srv.submit(A, B, ctx_id=ci) for (ci, A, B, _, _) in sat]
-    for t in tk:
+    for i, t in enumerate(tk):
         srv.poll(t, wait_ms=600_000)[0].close()
+        log(f"capacity run: request {i + 1}/{len(tk)} done at {time.perf_counter() - t0:.1f} s")
     cap = len(sat) / (time.perf_counter() - t0)
     srv.close()
     lam = args.serve_load * cap
@@ -685,6 +691,7 @@ def run_serve(args) -> dict:
     for (ci, _, _, a, b), t in zip(reqs, tickets):
         C, l = srv.poll(t, wait_ms=600_000)
         lat.append(l)
+        log(f"latency window: request {len(lat)}/{len(tickets)} done, latency {l:.3f} s")
         done_at.append(time.perf_counter())
         if len(errs) < 8:
             errs.append(float(np.abs(ctxs[ci].decrypt_decode(sks[ci], C) - a @ b).max()))

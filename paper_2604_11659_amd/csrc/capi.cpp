@@ -34,6 +34,17 @@ int guarded(F f) {
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
+}  // namespace
+
+namespace fhe {
+int set_error(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+}  // namespace fhe
+
+namespace {
+
 void need(const void* p, const char* what) {
   if (!p) fail(FHE_EINVAL, std::string(what) + " is NULL");
 }

@@ -21,6 +21,9 @@ struct Error {
   std::string msg;
 };
 [[noreturn]] void fail(int code, const std::string& msg);
+// Records msg as the calling thread's fhe_last_error() and returns code (entry points that return
+// codes directly instead of throwing).
+int set_error(int code, const char* msg);
 void hip_check(hipError_t e, const char* what, const char* file, int line);
 #define HIPCHECK(x) ::fhe::hip_check((x), #x, __FILE__, __LINE__)
 

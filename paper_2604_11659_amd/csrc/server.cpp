@@ -204,12 +204,14 @@ extern "C" {
 
 int fhe_server_create(fhe_ctx* const* ctxs, size_t nctx, size_t hbm_budget, size_t workspace_bytes,
                       int32_t max_inflight, int32_t slice_products, int32_t max_queue, fhe_server** out) {
-  if (!out) return FHE_EINVAL;
+  if (!out) return set_error(FHE_EINVAL, "out is NULL");
   *out = nullptr;
-  if (!ctxs || nctx < 1 || max_inflight < 1 || slice_products < 1 || max_queue < 1) return FHE_EINVAL;
+  if (!ctxs || nctx < 1 || max_inflight < 1 || slice_products < 1 || max_queue < 1)
+    return set_error(FHE_EINVAL, "contexts, max_inflight, slice_products and max_queue must be given and >= 1");
   for (size_t c = 0; c < nctx; ++c) {
-    if (!ctxs[c]) return FHE_EINVAL;
-    if (ctxs[c]->device != ctxs[0]->device) return FHE_EINVAL;  // one worker stream: one GPU
+    if (!ctxs[c]) return set_error(FHE_EINVAL, "a context is NULL");
+    if (ctxs[c]->device != ctxs[0]->device)  // one worker stream: one GPU
+      return set_error(FHE_EINVAL, "the contexts of one server must be on one device");
   }
   std::unique_ptr<fhe_server> s(new fhe_server());
   s->budget = hbm_budget;
@@ -241,7 +243,8 @@ int fhe_server_create(fhe_ctx* const* ctxs, size_t nctx, size_t hbm_budget, size
       // the server owns the context's scratch from now on: drop a larger one left by earlier calls
       std::lock_guard<std::recursive_mutex> lk(ctx->exec_mu);
       if (ctx->ws_cache.bytes() > w.words * 8) {
-        if (hipSetDevice(ctx->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return FHE_EDEVICE;
+        if (hipSetDevice(ctx->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+          return set_error(FHE_EDEVICE, "device synchronisation failed");
         ctx->graphs.clear();
         ctx->ws_cache.reset();
       }
@@ -250,9 +253,11 @@ int fhe_server_create(fhe_ctx* const* ctxs, size_t nctx, size_t hbm_budget, size
     s->ctxs.push_back(sc);
   }
   s->fixed = fixed;
-  if (fixed > hbm_budget) return FHE_ENOMEM;
-  if (hipSetDevice(ctxs[0]->device) != hipSuccess) return FHE_EDEVICE;
-  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) return FHE_EDEVICE;
+  if (fixed > hbm_budget)
+    return set_error(FHE_ENOMEM, "the budget is below the keys, tables and scratch the contexts hold");
+  if (hipSetDevice(ctxs[0]->device) != hipSuccess) return set_error(FHE_EDEVICE, "hipSetDevice failed");
+  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+    return set_error(FHE_EDEVICE, "stream creation failed");
   fhe_server* raw = s.get();
   s->worker = std::thread([raw] { raw->run(); });
   *out = s.release();
@@ -260,16 +265,18 @@ int fhe_server_create(fhe_ctx* const* ctxs, size_t nctx, size_t hbm_budget, size
 }
 
 int fhe_server_set_plan(fhe_server* s, int32_t mode) {
-  if (!s) return FHE_EINVAL;
+  if (!s) return set_error(FHE_EINVAL, "server is NULL");
   const int32_t plan = mode & ~FHE_PLAN_HOIST;
-  if (plan != FHE_PLAN_PER_PAIR && plan != FHE_PLAN_GROUPED && plan != FHE_PLAN_TREE) return FHE_EINVAL;
+  if (plan != FHE_PLAN_PER_PAIR && plan != FHE_PLAN_GROUPED && plan != FHE_PLAN_TREE)
+    return set_error(FHE_EINVAL, "unknown plan mode");
   std::lock_guard<std::mutex> lk(s->mu);
-  if (s->next_ticket != 1) return FHE_EAGAIN;  // only before the first request
+  if (s->next_ticket != 1)  // only before the first request
+    return set_error(FHE_EAGAIN, "the plan mode can only be set before the first request");
   if (plan != FHE_PLAN_PER_PAIR) {  // the tail's second ping-pong buffers join the fixed part
     for (auto& c : s->ctxs) s->fixed += c.tail_bytes;
     if (s->fixed > s->budget) {
       for (auto& c : s->ctxs) s->fixed -= c.tail_bytes;
-      return FHE_ENOMEM;
+      return set_error(FHE_ENOMEM, "the grouped plan's extra buffers exceed the budget");
     }
   }
   s->plan_mode = plan;
@@ -278,10 +285,10 @@ int fhe_server_set_plan(fhe_server* s, int32_t mode) {
 }
 
 int fhe_server_submit(fhe_server* s, int32_t ctx_id, const fhe_mat* A, const fhe_mat* B, uint64_t* ticket) {
-  if (!s || !A || !B || !ticket) return FHE_EINVAL;
-  if (ctx_id < 0 || (size_t)ctx_id >= s->ctxs.size()) return FHE_EINVAL;
-  if (A->kind != 0 || B->kind != 1) return FHE_EINVAL;
-  if (A->cols != B->rows) return FHE_ESHAPE;
+  if (!s || !A || !B || !ticket) return set_error(FHE_EINVAL, "server, operands and ticket must be given");
+  if (ctx_id < 0 || (size_t)ctx_id >= s->ctxs.size()) return set_error(FHE_EINVAL, "no such context id");
+  if (A->kind != 0 || B->kind != 1) return set_error(FHE_EINVAL, "A must be a CSR operand and B a CSC operand");
+  if (A->cols != B->rows) return set_error(FHE_ESHAPE, "A.cols != B.rows");
   const fhe_ctx* ctx = s->ctxs[ctx_id].ctx;
   std::unique_ptr<fhe_server::Req> r(new fhe_server::Req());
   r->ctx_id = ctx_id;
@@ -298,7 +305,7 @@ int fhe_server_submit(fhe_server* s, int32_t ctx_id, const fhe_mat* A, const fhe
     try {
       r->job.plan = build_plan(ctx->p, A, B, 0, INT64_MAX);
     } catch (const Error& e) {
-      return e.code;
+      return set_error(e.code, e.msg.c_str());
     }
     index_plan(r->job.plan);
     r->planned = true;
@@ -306,9 +313,10 @@ int fhe_server_submit(fhe_server* s, int32_t ctx_id, const fhe_mat* A, const fhe
     r->bytes += grouped_resident_words(ctx->p, r->job.plan, mode == FHE_PLAN_TREE) * 8;
   }
   std::lock_guard<std::mutex> lk(s->mu);
-  if (s->plan_mode != mode) return FHE_EAGAIN;  // the plan mode changed meanwhile
-  if (s->fixed + r->bytes > s->budget) return FHE_ENOMEM;  // would never fit, even alone
-  if (s->queue.size() >= s->max_queue) return FHE_EAGAIN;
+  if (s->plan_mode != mode) return set_error(FHE_EAGAIN, "the plan mode changed meanwhile");
+  if (s->fixed + r->bytes > s->budget)  // would never fit, even alone
+    return set_error(FHE_ENOMEM, "the request alone exceeds what the budget leaves after the fixed part");
+  if (s->queue.size() >= s->max_queue) return set_error(FHE_EAGAIN, "the queue is full");
   r->ticket = s->next_ticket++;
   r->t_submit = now_s();
   *ticket = r->ticket;
@@ -319,11 +327,11 @@ int fhe_server_submit(fhe_server* s, int32_t ctx_id, const fhe_mat* A, const fhe
 }
 
 int fhe_server_poll(fhe_server* s, uint64_t ticket, int32_t wait_ms, fhe_mat** C_out, double* latency_s) {
-  if (!s || !C_out) return FHE_EINVAL;
+  if (!s || !C_out) return set_error(FHE_EINVAL, "server and C_out must be given");
   *C_out = nullptr;
   std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->reqs.find(ticket);
-  if (it == s->reqs.end()) return FHE_EINVAL;
+  if (it == s->reqs.end()) return set_error(FHE_EINVAL, "unknown ticket");
   fhe_server::Req* r = it->second.get();
   if (r->state < 2 && wait_ms > 0 && !s->closing) {
     ++s->waiters;
@@ -331,23 +339,23 @@ int fhe_server_poll(fhe_server* s, uint64_t ticket, int32_t wait_ms, fhe_mat** C
     --s->waiters;
     s->gone_cv.notify_all();
   }
-  if (r->state < 2) return FHE_EAGAIN;
+  if (r->state < 2) return set_error(FHE_EAGAIN, "the request has not finished");
   int rc = FHE_OK;
   if (r->state == 2) {
     *C_out = r->C.release();
     if (latency_s) *latency_s = r->t_done - r->t_submit;
   } else {
-    rc = r->err ? r->err : FHE_EDEVICE;
+    rc = set_error(r->err ? r->err : FHE_EDEVICE, r->msg.c_str());
   }
   s->reqs.erase(it);
   return rc;
 }
 
 int fhe_server_cancel(fhe_server* s, uint64_t ticket) {
-  if (!s) return FHE_EINVAL;
+  if (!s) return set_error(FHE_EINVAL, "server is NULL");
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->reqs.find(ticket);
-  if (it == s->reqs.end()) return FHE_EINVAL;
+  if (it == s->reqs.end()) return set_error(FHE_EINVAL, "unknown ticket");
   fhe_server::Req* r = it->second.get();
   if (r->state >= 2) return FHE_OK;  // already finished: its outcome stands
   if (r->state == 0) {
@@ -366,7 +374,7 @@ int fhe_server_cancel(fhe_server* s, uint64_t ticket) {
 }
 
 int fhe_server_stats(fhe_server* s, fhe_server_info* out) {
-  if (!s || !out) return FHE_EINVAL;
+  if (!s || !out) return set_error(FHE_EINVAL, "server and out must be given");
   std::lock_guard<std::mutex> lk(s->mu);
   std::vector<double> v = s->latencies;
   std::sort(v.begin(), v.end());

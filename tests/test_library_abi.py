@@ -30,3 +30,14 @@ def test_error_path_without_device_work():
     rc = fhe._lib.fhe_params_create(ctypes.byref(d), ctypes.byref(out))
     assert rc == -1 and out.value is None
     assert b"log_n" in fhe._lib.fhe_last_error()
+
+
+def test_too_few_q_primes_is_a_level_error():
+    """FHE_ELEVEL: the method needs two rescales, so a parameter set with fewer than 3 Q primes is
+    refused before any device work."""
+    from paper_2604_11659_amd import fhe
+    d = fhe.fhe_params_desc(13, 2, 50, 1, 60, 1, 1, 40, 10, 0)
+    out = ctypes.c_void_p()
+    rc = fhe._lib.fhe_params_create(ctypes.byref(d), ctypes.byref(out))
+    assert rc == -3 and out.value is None
+    assert b"3 Q primes" in fhe._lib.fhe_last_error()
