@@ -140,6 +140,7 @@ struct fhe_ctx {
   std::recursive_mutex exec_mu;  // one matmul execution at a time per context (shared scratch); the
                                  // autotuner holds it across the matmuls it times
   fhe::DevBuf ws_cache;  // executor scratch, grown on demand
+  fhe::DevBuf group_cache;  // grouped plans' resident products between direct calls, grown on demand
   fhe::OwnedStream capture_stream;  // stream the executor captures HIP graphs on
   std::vector<std::shared_ptr<fhe::GraphEntry>> graphs;  // captured matmuls, most recent last
 };

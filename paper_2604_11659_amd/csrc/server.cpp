@@ -240,13 +240,18 @@ int fhe_server_create(fhe_ctx* const* ctxs, size_t nctx, size_t hbm_budget, size
     const WsPlan w = ws_plan(ctx, cap, SIZE_MAX / 4, SIZE_MAX / 4);
     sc.tail_bytes = w.BB * 2 * (size_t)(ctx->p.nq - 1) * ctx->p.N * 8;
     {
-      // the server owns the context's scratch from now on: drop a larger one left by earlier calls
+      // the server owns the context's scratch from now on: drop a larger one left by earlier calls,
+      // and the grouped products kept by direct calls (the server charges them per request)
       std::lock_guard<std::recursive_mutex> lk(ctx->exec_mu);
-      if (ctx->ws_cache.bytes() > w.words * 8) {
+      const bool drop_ws = ctx->ws_cache.bytes() > w.words * 8;
+      if (drop_ws || ctx->group_cache.bytes()) {
         if (hipSetDevice(ctx->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
           return set_error(FHE_EDEVICE, "device synchronisation failed");
-        ctx->graphs.clear();
-        ctx->ws_cache.reset();
+        if (drop_ws) {
+          ctx->graphs.clear();
+          ctx->ws_cache.reset();
+        }
+        ctx->group_cache.reset();
       }
     }
     fixed += w.words * 8;

@@ -904,9 +904,13 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, co
 
   uint64_t* const* res = (uint64_t* const*)result_local.get();
   std::vector<std::unique_ptr<ArgPack>> local_packs;
-  DevBuf local_gbuf;  // grouped form: resident products, released after the final synchronisation
+  // grouped form: resident products. A graph keeps its own; direct calls reuse the context's (a
+  // fresh allocation and release per call cost more than a small call's work); a call with an
+  // explicit group budget (the server's, which charges it per request) has its own, released after
+  // the final synchronisation.
+  DevBuf local_gbuf;
   Runner run{ls, graph, graph ? entry->packs : local_packs, {}};
-  DevBuf& gbuf = graph ? entry->gbuf : local_gbuf;
+  DevBuf& gbuf = graph ? entry->gbuf : opts.group_bytes ? local_gbuf : ctx->group_cache;
   if (grouped) {
     execute_grouped(ctx, plan, job_of, ws, PB, BB, res, run, gbuf, tree, hoist, opts.group_bytes);
   } else {
