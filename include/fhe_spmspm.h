@@ -163,7 +163,8 @@ int fhe_spmspm_batch_pairs(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, co
  * ones. The grouped form keeps the products (2 (n_q - 1) N words each) its groups use resident in
  * device memory, up to FHE_GROUP_MB (environment, default 49152 MiB, raised to the largest group's
  * products if needed); beyond that it runs the groups in passes and each pass recomputes the
- * products its pairs use. Errors as fhe_spmspm_batch_pairs, FHE_EINVAL for
+ * products its pairs use. The context keeps that store between calls and grows it on demand (like
+ * the executor scratch); fhe_server_create releases it. Errors as fhe_spmspm_batch_pairs, FHE_EINVAL for
  * an unknown mode; on error all C_out[i] are NULL.
  * FHE_PLAN_TREE is the grouped plan with its target rotations shared further: a rotation by
  * r = sum_t r_t 2^(b t) is the composition of its digit steps, so each group is rotated by its low
