@@ -177,3 +177,22 @@ def test_tree_two_result_chunks_passes_and_graph(fhe, monkeypatch):
     for rep in range(3):
         _say(f"[tree] graph call {rep}")
         assert _same(ctx, ctx.spmspm(A, B, tree=True, graph=True), ref)
+
+
+def test_tree_store_kept_between_calls(fhe):
+    """Direct grouped calls keep their resident product store on the context: a smaller digit-tree
+    call after a larger one reuses it (not shrunk, contents left over), and the larger call again
+    grows nothing; every result bit-exact against the oracle's tree mode on the same pair range."""
+    prm = PRM[0]
+    a = synth.sparse_dense(12, 9, 0.5, "uniform", 20, 22)
+    b = synth.sparse_dense(9, 10, 0.5, "uniform", 21, 23)
+    op, okeys, ctx, sk, A, B, OA, OB = _operands(fhe, prm, a, b, seeds=(63, 64))
+    pairs = spmspm.matched_pairs(a.shape[0], b.shape[1], OA.indptr, OA.indices, OB.indptr, OB.indices)
+    F = len(pairs)
+    assert F >= 8
+    _say(f"[tree store] {F} pairs, oracle")
+    refs = {F: spmspm.spmspm(op, okeys, OA, OB, tree=True, workers=8),
+            F // 4: spmspm.spmspm(op, okeys, OA, OB, tree=True, pairs=pairs[:F // 4], workers=4)}
+    for hi in (F, F // 4, F):
+        _say(f"[tree store] pairs [0, {hi}) gpu")
+        assert _same(ctx, ctx.spmspm_pairs(A, B, 0, hi, tree=True), refs[hi])
