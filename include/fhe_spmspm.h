@@ -250,6 +250,10 @@ int fhe_mat_info(const fhe_mat* M, int32_t* kind, int32_t* rows, int32_t* cols, 
 /* Exports ciphertext chunk `chunk` of M in the coefficient domain into out[cap] (uint64,
  * [2][limbs][N]). Errors: FHE_ESHAPE if cap is too small, FHE_EINVAL for a bad chunk index. */
 int fhe_mat_export(fhe_ctx* ctx, const fhe_mat* M, int32_t chunk, uint64_t* out, size_t cap, void* stream);
+/* Releases M. The device block of a matmul result goes back to its context (while the context
+ * lives), which hands it to its next result of the same size, up to FHE_RESULT_POOL_MB (environment,
+ * default 4096 MiB; 0 keeps none) of kept blocks per context; a context under fhe_server_create keeps
+ * none. Free a matrix only when no call that uses it is running. */
 void fhe_mat_free(fhe_mat* M);
 
 /* ---- Operation-level interface on single ciphertexts (the operations Algorithm 2 issues). ---- */

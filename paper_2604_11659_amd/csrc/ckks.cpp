@@ -1,4 +1,5 @@
 // Context tables, key generation, encryption/decryption and single-ciphertext operations.
+#include <algorithm>
 #include <cstdlib>
 
 #include "ckks.h"
@@ -60,6 +61,11 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
     fail(FHE_EINVAL, "log_delta / mask_bits out of range");
   ctx->device = d->device;
   ctx->al = current_allocator();
+  {  // released results kept for reuse: FHE_RESULT_POOL_MB (default 4096 MiB, 0 keeps none)
+    const char* e = std::getenv("FHE_RESULT_POOL_MB");
+    const long long mb = e ? std::max(0LL, std::atoll(e)) : 4096;
+    ctx->results->clear((size_t)mb << 20);
+  }
   HIPCHECK(hipSetDevice(d->device));
   noalloc_setup(d->device);
   p.logN = d->log_n;

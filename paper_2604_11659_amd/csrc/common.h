@@ -120,6 +120,17 @@ struct SwitchKey {
 }  // namespace fhe
 
 namespace fhe {
+// Device blocks of released matmul results, kept by size and handed to the next results of the same
+// size (a release and a fresh allocation per result cost more host time than a small call's
+// planning). At most `cap` bytes are kept; a context's pool dies with the context.
+struct ResultPool {
+  std::mutex mu;
+  std::map<size_t, std::vector<DevBuf>> blocks;
+  size_t bytes = 0, cap = 0;
+  DevBuf take(size_t size);  // a kept block of exactly `size` bytes, or an empty buffer
+  void put(DevBuf& b);       // keeps b (moved from) if it fits under the cap, else leaves it
+  void clear(size_t new_cap);
+};
 struct GraphEntry;  // a captured matmul launch stream (spmspm.cpp)
 uint64_t next_handle_id();
 // Stream created on first use (default priority), destroyed with its owner.
@@ -141,6 +152,7 @@ struct fhe_ctx {
                                  // autotuner holds it across the matmuls it times
   fhe::DevBuf ws_cache;  // executor scratch, grown on demand
   fhe::DevBuf group_cache;  // grouped plans' resident products between direct calls, grown on demand
+  std::shared_ptr<fhe::ResultPool> results = std::make_shared<fhe::ResultPool>();  // released result blocks
   fhe::OwnedStream capture_stream;  // stream the executor captures HIP graphs on
   std::vector<std::shared_ptr<fhe::GraphEntry>> graphs;  // captured matmuls, most recent last
 };
@@ -166,5 +178,9 @@ struct fhe_mat {
   int nl = 0, nchunks = 0;
   double scale = 1.0;
   fhe::DevBuf data;  // [nchunks][2][nl][N], NTT domain
+  std::weak_ptr<fhe::ResultPool> pool;  // results: where `data` goes back on release
   uint64_t* chunk(int c, uint32_t N) const { return data.u64() + (size_t)c * 2 * nl * N; }
+  ~fhe_mat() {
+    if (auto p = pool.lock()) p->put(data);
+  }
 };

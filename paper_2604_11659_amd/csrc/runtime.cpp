@@ -60,6 +60,34 @@ DevBuf& DevBuf::operator=(DevBuf&& o) noexcept {
   return *this;
 }
 
+DevBuf ResultPool::take(size_t size) {
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = blocks.find(size);
+  if (it == blocks.end() || it->second.empty()) return DevBuf();
+  DevBuf b = std::move(it->second.back());
+  it->second.pop_back();
+  bytes -= size;
+  return b;
+}
+
+void ResultPool::put(DevBuf& b) {
+  if (!b.get()) return;
+  std::lock_guard<std::mutex> lk(mu);
+  if (bytes + b.bytes() > cap) return;
+  bytes += b.bytes();
+  blocks[b.bytes()].push_back(std::move(b));
+}
+
+void ResultPool::clear(size_t new_cap) {
+  std::map<size_t, std::vector<DevBuf>> old;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    old.swap(blocks);
+    bytes = 0;
+    cap = new_cap;
+  }
+}  // the blocks are released here, outside the lock
+
 void DevBuf::reset() {
   if (ptr_) {
     if (al_.free_) al_.free_(ptr_, (void*)stream_, al_.user);

@@ -241,8 +241,10 @@ int fhe_server_create(fhe_ctx* const* ctxs, size_t nctx, size_t hbm_budget, size
     sc.tail_bytes = w.BB * 2 * (size_t)(ctx->p.nq - 1) * ctx->p.N * 8;
     {
       // the server owns the context's scratch from now on: drop a larger one left by earlier calls,
-      // and the grouped products kept by direct calls (the server charges them per request)
+      // the grouped products kept by direct calls and the kept result blocks (the server charges
+      // results and grouped products per request; blocks kept outside the budget would escape it)
       std::lock_guard<std::recursive_mutex> lk(ctx->exec_mu);
+      ctx->results->clear(0);
       const bool drop_ws = ctx->ws_cache.bytes() > w.words * 8;
       if (drop_ws || ctx->group_cache.bytes()) {
         if (hipSetDevice(ctx->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess)

@@ -309,8 +309,11 @@ void prepare_result(fhe_ctx* ctx, Job& J, hipStream_t st) {
   C->nl = nl2;
   C->nchunks = J.plan.nres;
   C->scale = std::ldexp(1.0, p.d.log_delta + p.d.mask_bits);
-  C->data = DevBuf((size_t)J.plan.nres * chunk_elems * 8, st);
-  HIPCHECK(hipMemsetAsync(C->data.get(), 0, (size_t)J.plan.nres * chunk_elems * 8, st));
+  const size_t bytes = (size_t)J.plan.nres * chunk_elems * 8;
+  C->data = ctx->results->take(bytes);  // a released result's block of the same size, if kept
+  if (!C->data.get()) C->data = DevBuf(bytes, st);
+  C->pool = ctx->results;
+  HIPCHECK(hipMemsetAsync(C->data.get(), 0, bytes, st));
 }
 
 void execute_jobs(fhe_ctx* ctx, std::vector<Job>& jobs, hipStream_t st, bool grouped, bool graph, bool tree,

@@ -169,6 +169,34 @@ def test_spmspm_parity_single_digit(fhe):
     _matmul_case(fhe, OP_PARAMS[1], 6, 5, 4, 0.4, 0.6, (4, 5, 6, 7))
 
 
+def test_released_result_block_reused(fhe):
+    """A released result's device block is kept by its context and handed to the next result of the
+    same size: a product of other values written into it equals the oracle's (the block is cleared
+    before accumulation), and so does the first product recomputed into a kept block."""
+    prm = OP_PARAMS[0]
+    op, okeys, ctx, sk = _setup(fhe, prm)
+    m, k, n = 5, 6, 7
+    cases = []
+    for t, seeds in enumerate(((30, 31, 32, 33), (34, 35, 36, 37))):
+        a = synth.sparse_dense(m, k, 0.5, "uniform", seeds[0], seeds[2])
+        b = synth.sparse_dense(k, n, 0.5, "uniform", seeds[1], seeds[3])
+        ipa, ixa, va = synth.to_csr(a)
+        ipb, ixb, vb = synth.to_csc(b)
+        A = ctx.encrypt_csr(sk, m, k, ipa, ixa, va, seed=43 + 2 * t)
+        B = ctx.encrypt_csc(sk, k, n, ipb, ixb, vb, seed=44 + 2 * t)
+        _say(f"[reuse] case {t} oracle")
+        ref = spmspm.spmspm(op, okeys, spmspm.encrypt_csr(op, okeys, m, k, ipa, ixa, va, seed=43 + 2 * t),
+                            spmspm.encrypt_csc(op, okeys, k, n, ipb, ixb, vb, seed=44 + 2 * t))
+        cases.append((A, B, ref))
+    for t in (0, 1, 0):
+        A, B, ref = cases[t]
+        _say(f"[reuse] case {t} gpu")
+        C = ctx.spmspm(A, B)
+        for c, rct in enumerate(ref):
+            assert (ctx.export(C, c) == rct.data).all(), f"case {t} chunk {c}"
+        C.close()  # its block goes back to the context for the next result of this size
+
+
 def test_unfused_split_fallback(fhe, monkeypatch):
     """An NTT split outside the fused column kernels' compiled ones (k1 = 5 at N = 2^12) runs the
     unfused ModUp / ModDown / rescale sequence and row-phase kernels with run-time stage counts;
