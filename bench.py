@@ -367,7 +367,7 @@ def run_headline(args) -> dict:
         "config": {"workload": describe_batch(w), "plan": "per matched pair (Algorithm 2)",
                    "prefix_pairs_per_matmul": args.batch_cap, "pairs_per_step": pairs, "full_pairs": sum(F),
                    "mean_full_pairs_per_matmul": round(mean_f, 1), "parallelism": "single GPU, one batched call per step",
-                   "ntt_split_autotuned": tuned},
+                   "schedule_autotuned": tuned},
         "batched": {"pairs_per_s": round(pb, 1), "spmspm_per_s_projected": pb / mean_f, "ms_per_step": round(1000 * t_batch, 2),
                     "steps": args.steps},
         "plain": ({"pairs_per_s": round(pp, 1), "spmspm_per_s_projected": pp / mean_f,
@@ -739,8 +739,8 @@ def main():
     ap.add_argument("--tree-steps", type=int, default=2, help="headline: timed steps of the tree + hoisted plan")
     ap.add_argument("--dnn", type=int, default=1, help="headline: also run the DNN-layer workload (N = 2^15)")
     ap.add_argument("--dnn-steps", type=int, default=1)
-    ap.add_argument("--autotune", type=int, default=1, help="1: pick the NTT split by timing (untimed set-up)")
-    ap.add_argument("--autotune-pairs", type=int, default=64, help="matched pairs timed per candidate split")
+    ap.add_argument("--autotune", type=int, default=1, help="1: pick the NTT split and row-phase shape by timing (untimed set-up)")
+    ap.add_argument("--autotune-pairs", type=int, default=64, help="matched pairs timed per candidate")
     ap.add_argument("--cpu-sample", type=int, default=-1,
                     help="oracle pairs on as many processes (0 = skip, -1 = one per core up to 16)")
     ap.add_argument("--kernels-out", default=None, help="write per-kernel timings (JSON) here")

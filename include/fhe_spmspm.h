@@ -204,18 +204,20 @@ int fhe_spmspm_naive_sparse(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, co
 int fhe_plan_stats_naive_sparse(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, const uint8_t* nonzero_a,
                                 const uint8_t* nonzero_b, int64_t counts[6]);
 
-/* Autotuner (batch scheduler): picks the NTT split 2^k1 x 2^(log_n - k1) for ctx by timing every
- * admissible one (k1 in [max(1, log_n - 9), min(9, log_n - 1)]); keeps the current split unless
- * another is at least 2% faster. Every split computes the same transform, so results are unchanged;
- * only the kernel schedule (LDS rounds, fused column kernels, row segment width) differs.
- * With A and B (a CSR and a CSC operand of ctx): times the first `pairs` matched pairs of A B, each
- * with its full sequence (median of 3). With A = B = NULL: times `batch` synthetic key switches at
- * the top level and two levels below (median of 5; needs fhe_keygen first, FHE_EKEY; batch in
- * [1, 4096], FHE_EINVAL). Reports the chosen k1 and its time (ms); if cap > 0, the first cap
- * candidates tried (k1_tried[i], ms_tried[i]) and their count (n_tried). Allocates device memory
- * for its runs. Must not overlap other calls on ctx. */
+/* Autotuner (batch scheduler): picks, for ctx, the NTT split 2^k1 x 2^(log_n - k1) (every k1 in
+ * [max(1, log_n - 9), min(9, log_n - 1)]) and the row-phase workgroup shape (512 threads x 8
+ * elements or 256 x 16) by timing every combination; keeps the current choice unless another is at
+ * least 2% faster. Every choice computes the same transform, so results are unchanged; only the
+ * kernel schedule (LDS rounds, fused column kernels, row segment width, registers per thread)
+ * differs. With A and B (a CSR and a CSC operand of ctx): times the first `pairs` matched pairs of
+ * A B, each with its full sequence (median of 3). With A = B = NULL: times `batch` synthetic key
+ * switches at the top level and two levels below (median of 5; needs fhe_keygen first, FHE_EKEY;
+ * batch in [1, 4096], FHE_EINVAL). Reports the chosen k1, row-phase threads and time (ms); if
+ * cap > 0, the first cap candidates tried (k1_tried[i], rows_tried[i], ms_tried[i]) and their
+ * count (n_tried). Allocates device memory for its runs. Must not overlap other calls on ctx. */
 int fhe_autotune(fhe_ctx* ctx, void* stream, const fhe_mat* A, const fhe_mat* B, int64_t pairs, int32_t batch,
-                 int32_t* k1_out, double* ms_out, int32_t* n_tried, int32_t* k1_tried, double* ms_tried, int32_t cap);
+                 int32_t* k1_out, int32_t* rows_out, double* ms_out, int32_t* n_tried, int32_t* k1_tried,
+                 int32_t* rows_tried, double* ms_tried, int32_t cap);
 
 /* Plan statistics of A B without running it: counts[0] = matched pairs F, [1] = distinct products,
  * [2] = alignment key switches, [3] = product relinearisations, [4] = target-rotation key switches,

@@ -226,27 +226,29 @@ int fhe_spmspm_batch(fhe_ctx* ctx, size_t cnt, const fhe_mat* const* A, const fh
 }
 
 int fhe_autotune(fhe_ctx* ctx, void* stream, const fhe_mat* A, const fhe_mat* B, int64_t pairs, int32_t batch,
-                 int32_t* k1_out, double* ms_out, int32_t* n_tried, int32_t* k1_tried, double* ms_tried, int32_t cap) {
+                 int32_t* k1_out, int32_t* rows_out, double* ms_out, int32_t* n_tried, int32_t* k1_tried,
+                 int32_t* rows_tried, double* ms_tried, int32_t cap) {
   return guarded([&] {
     need(ctx, "ctx");
-    if (cap < 0 || (cap > 0 && (!k1_tried || !ms_tried))) fail(FHE_EINVAL, "bad report arrays");
+    if (cap < 0 || (cap > 0 && (!k1_tried || !rows_tried || !ms_tried))) fail(FHE_EINVAL, "bad report arrays");
     if ((A == nullptr) != (B == nullptr)) fail(FHE_EINVAL, "A and B go together");
     set_dev(ctx);
-    std::vector<std::pair<int, double>> tried;
-    int best = 0;
-    double ms = 0;
+    std::vector<TuneTrial> tried;
+    TuneTrial best;
     if (A) {
       check_operands(A, B);
-      autotune_plan(ctx, as_stream(stream), A, B, pairs, tried, best, ms);
+      autotune_plan(ctx, as_stream(stream), A, B, pairs, tried, best);
     } else {
-      autotune_split(ctx, as_stream(stream), batch < 1 ? 0u : (uint32_t)batch, tried, best, ms);
+      autotune_split(ctx, as_stream(stream), batch < 1 ? 0u : (uint32_t)batch, tried, best);
     }
     for (size_t i = 0; i < tried.size() && (int32_t)i < cap; ++i) {
-      k1_tried[i] = tried[i].first;
-      ms_tried[i] = tried[i].second;
+      k1_tried[i] = tried[i].k1;
+      rows_tried[i] = tried[i].rows;
+      ms_tried[i] = tried[i].ms;
     }
-    if (k1_out) *k1_out = best;
-    if (ms_out) *ms_out = ms;
+    if (k1_out) *k1_out = best.k1;
+    if (rows_out) *rows_out = best.rows;
+    if (ms_out) *ms_out = best.ms;
     if (n_tried) *n_tried = (int32_t)tried.size();
   });
 }

@@ -84,6 +84,8 @@ void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d) {
     const int v = std::atoi(e);
     if (v >= (int)p.logN - 9 && v <= 9 && v >= 1 && v < (int)p.logN) p.k1 = (uint32_t)v;
   }
+  // row-phase workgroup shape (same results either way): FHE_ROWS_NT=256 or the autotuner
+  if (const char* e = std::getenv("FHE_ROWS_NT")) p.rows_nt = std::atoi(e) == 256 ? 256 : 512;
   const uint64_t m = 2ull * p.N;
   std::vector<uint64_t> qs = primes_below(d->q_bits, p.nq, m);
   if ((int)qs.size() != p.nq) fail(FHE_EINVAL, "not enough Q primes of the requested size");

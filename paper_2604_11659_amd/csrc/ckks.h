@@ -37,13 +37,17 @@ class ArgPack {
 };
 
 void ctx_init(fhe_ctx* ctx, const fhe_params_desc* d);
-// Times top-level key switches of B synthetic polynomials for every admissible NTT split, keeps
-// the fastest in ctx (results are identical for every split). tried: (k1, ms per batch).
-void autotune_split(fhe_ctx* ctx, hipStream_t st, uint32_t B, std::vector<std::pair<int, double>>& tried,
-                    int& best_k1, double& best_ms);
+// One autotuner candidate: NTT split k1, row-phase threads per workgroup, time (ms).
+struct TuneTrial {
+  int k1 = 0, rows = 0;
+  double ms = 0.0;
+};
+// Times top-level key switches of B synthetic polynomials for every admissible NTT split and
+// row-phase shape, keeps the fastest in ctx (results are identical for every choice).
+void autotune_split(fhe_ctx* ctx, hipStream_t st, uint32_t B, std::vector<TuneTrial>& tried, TuneTrial& best);
 // As autotune_split, timing the first `pairs` matched pairs of A B (the real per-pair sequence).
 void autotune_plan(fhe_ctx* ctx, hipStream_t st, const fhe_mat* A, const fhe_mat* B, int64_t pairs,
-                   std::vector<std::pair<int, double>>& tried, int& best_k1, double& best_ms);
+                   std::vector<TuneTrial>& tried, TuneTrial& best);
 // Device bytes a context holds for good: constant tables and every evaluation key.
 size_t ctx_resident_bytes(const fhe_ctx* ctx);
 size_t ctx_key_bytes(const fhe_ctx* ctx);

@@ -96,6 +96,7 @@ struct Params {
   int beta(int nl) const { return (nl + alpha - 1) / alpha; }
   // NTT split: phase 1 transforms columns of 2^k1 elements, phase 2 rows of 2^(logN-k1).
   uint32_t k1 = 0;
+  uint32_t rows_nt = 512;  // row-phase workgroups: 512 threads x 8 elements, or 256 x 16
 };
 
 // Constant tables for one context (all in device memory).

@@ -1557,16 +1557,6 @@ static void check_batch(const fhe_ctx* ctx, const LimbBatch& lb) {
   if (mi >= (uint32_t)p.nmod() || mi0 >= (uint32_t)p.nmod()) fail(FHE_EINVAL, "NTT batch modulus index out of range");
 }
 
-// Row-phase kernels: 512 threads x 8 elements (3-stage rounds; about 66 VGPRs, three workgroups
-// per CU), or 256 x 16 with FHE_ROWS_NT=256.
-static int rows_nt() {
-  static const int v = [] {
-    const char* e = std::getenv("FHE_ROWS_NT");
-    return e && std::atoi(e) == 256 ? 256 : 512;
-  }();
-  return v;
-}
-
 static uint32_t ntt_blocks(const fhe_ctx* ctx, const LimbBatch& lb) {
   const uint64_t blocks = (uint64_t)(ctx->p.N >> kNttLogE) * lb.limbs * lb.npoly;
   if (blocks >= (1ull << 31)) fail(FHE_EINVAL, "NTT batch too large");
@@ -1615,7 +1605,8 @@ static void ntt_phase(const fhe_ctx* ctx, const LimbBatch& lb, const char* name_
     // butterflies of the phase's stages (plus the N^-1 scaling of the inverse column phase)
     const double ops = (double)sub.limbs * sub.npoly * p.N *
                        (0.5 * (kPhase == 1 ? p.k1 : p.logN - p.k1) + (kInv && kPhase == 1 ? 1.0 : 0.0));
-    // row phase: the 512-thread variant (see rows_nt); column phase: 256 threads x 16 elements
+    // row phase: 512 threads x 8 elements (3-stage rounds; about 66 VGPRs, three workgroups per CU)
+    // or 256 x 16 (p.rows_nt); column phase: 256 threads x 16 elements
     // the usual row length (2^9): compile-time rounds (fewer VGPRs, a fourth workgroup per CU; the
     // forward gather instance is left out, it would need more)
     const bool r9 = p.logN - p.k1 == 9;
@@ -1629,7 +1620,7 @@ static void ntt_phase(const fhe_ctx* ctx, const LimbBatch& lb, const char* name_
       else
         FHE_LAUNCH_TO(name_p, bytes, ops, (k_ntt<kInv, kPhase, IntArith, 512, true>), blocks, 512, lds, st, sub,
                      mods_of(ctx), ctx->t.tw.u64(), p.logN, p.k1, from_src);
-    } else if (kPhase == 2 && rows_nt() == 512) {
+    } else if (kPhase == 2 && p.rows_nt == 512) {
       if (r.q && r9)
         FHE_LAUNCH_TO(name_q, bytes, ops, (k_ntt<kInv, kPhase, FpArith, 512, false, 9>), blocks, 512, lds, st, sub,
                      mods_of(ctx), twf, p.logN, p.k1, from_src);
@@ -1981,11 +1972,11 @@ static void keyswitch_moddown(const fhe_ctx* ctx, uint32_t B, uint32_t nl, uint6
   }
   // row phase of every converted Q limb and its product by P^-1
   const double ops_c = 2.0 * B * nl * (0.5 * N * (p.logN - p.k1) + N);
-  if (rows_nt() == 512 && p.logN - p.k1 == 9)
+  if (p.rows_nt == 512 && p.logN - p.k1 == 9)
     FHE_LAUNCH_TO("ntt_p2_combine", e8 * 2 * nl * 3.5, ops_c, (k_ntt_p2_combine<FpArith, 512, 9>),
                  (uint64_t)2 * B * nl * tiles, 512, lds, st, nl, K, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf,
                  ctx->t.moddown.u64(), u, conv, add, galois, out);
-  else if (rows_nt() == 512)
+  else if (p.rows_nt == 512)
     FHE_LAUNCH_TO("ntt_p2_combine", e8 * 2 * nl * 3.5, ops_c, (k_ntt_p2_combine<FpArith, 512>),
                   (uint64_t)2 * B * nl * tiles,
                  512, lds, st, nl, K, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.moddown.u64(), u, conv,
@@ -2048,11 +2039,11 @@ void rescale(const fhe_ctx* ctx, uint32_t B, uint32_t ncomp, uint32_t nl, const 
         break;
     }
     const size_t lds = kNttLdsElems * sizeof(uint64_t);
-    if (rows_nt() == 512 && p.logN - p.k1 == 9)
+    if (p.rows_nt == 512 && p.logN - p.k1 == 9)
       FHE_LAUNCH_TO("rescale_rows", e8 * 3 * (nl - 1), ops_rows, (k_rescale_rows<512, 9>),
                    (uint64_t)BC * (nl - 1) * (N >> kNttLogE), 512, lds, st, ncomp, nl, (uint32_t)p.nq, p.logN, p.k1,
                    mods_of(ctx), twf, ctx->t.rescale.u64(), ctx->t.mask.u64(), mask_galois, in, w, out);
-    else if (rows_nt() == 512)
+    else if (p.rows_nt == 512)
       FHE_LAUNCH_TO("rescale_rows", e8 * 3 * (nl - 1), ops_rows, k_rescale_rows<512>, (uint64_t)BC * (nl - 1) * (N >> kNttLogE),
                    512, lds, st, ncomp, nl, (uint32_t)p.nq, p.logN, p.k1, mods_of(ctx), twf, ctx->t.rescale.u64(),
                    ctx->t.mask.u64(), mask_galois, in, w, out);

@@ -1,11 +1,13 @@
 // Autotuner for the schedule choices that leave every result bit unchanged.
 //
-// The one knob with a real effect is the NTT split: a limb is transformed as 2^k1 columns by
-// 2^(logN - k1) rows, and k1 decides how the stages are grouped into LDS rounds, how wide the
-// column segments are and which kernels (fused column kernels for k1 in [6, 8]) run. The transform
-// itself is the same for every split, so the tuner may pick any of them. It times a batch of
-// synthetic key switches at the top level (the operation that dominates the matmul) for every
-// admissible split, keeps the fastest in the context and reports the timings.
+// Two knobs change the schedule without changing a bit of the results. The NTT split: a limb is
+// transformed as 2^k1 columns by 2^(logN - k1) rows, and k1 decides how the stages are grouped into
+// LDS rounds, how wide the column segments are and which kernels (fused column kernels for k1 in
+// [6, 8]) run. The row-phase workgroup shape: 512 threads with 8 elements each (3-stage rounds) or
+// 256 threads with 16 (4-stage rounds, more registers per thread). The transform is the same for
+// every choice, so the tuner may pick any of them. It times each candidate (a batch of synthetic
+// key switches, or a prefix of the caller's own plan), keeps the fastest in the context and
+// reports the timings.
 #include <algorithm>
 #include <random>
 
@@ -45,10 +47,41 @@ double time_keyswitch(fhe_ctx* ctx, uint32_t B, uint32_t nl, const DevBuf& in, c
   return t[t.size() / 2];
 }
 
+// Times every (k1 in [lo, hi], row shape) with `time_ms`, leaves the fastest in p and reports all.
+// The current choice stays unless another is at least 2 % faster (about the timing noise).
+template <class F>
+void search(Params& p, int lo, int hi, std::vector<TuneTrial>& tried, TuneTrial& best, F&& time_ms) {
+  const TuneTrial orig{(int)p.k1, (int)p.rows_nt, 0.0};
+  tried.clear();
+  best = orig;
+  double orig_ms = 0, best_ms = 0;
+  try {
+    for (int nt : {512, 256}) {
+      for (int k1 = lo; k1 <= hi; ++k1) {
+        p.k1 = (uint32_t)k1;
+        p.rows_nt = (uint32_t)nt;
+        const double ms = time_ms();
+        tried.push_back(TuneTrial{k1, nt, ms});
+        if (k1 == orig.k1 && nt == orig.rows) orig_ms = ms;
+        if (best_ms == 0 || ms < best_ms) {
+          best_ms = ms;
+          best = tried.back();
+        }
+      }
+    }
+  } catch (...) {
+    p.k1 = (uint32_t)orig.k1;
+    p.rows_nt = (uint32_t)orig.rows;
+    throw;
+  }
+  if (orig_ms > 0 && best_ms > 0.98 * orig_ms) best = TuneTrial{orig.k1, orig.rows, orig_ms};
+  p.k1 = (uint32_t)best.k1;
+  p.rows_nt = (uint32_t)best.rows;
+}
+
 }  // namespace
 
-void fhe::autotune_split(fhe_ctx* ctx, hipStream_t st, uint32_t B, std::vector<std::pair<int, double>>& tried,
-                         int& best_k1, double& best_ms) {
+void fhe::autotune_split(fhe_ctx* ctx, hipStream_t st, uint32_t B, std::vector<TuneTrial>& tried, TuneTrial& best) {
   if (B < 1 || B > 4096) fail(FHE_EINVAL, "autotune batch must be in [1, 4096]");
   if (!ctx->relin) fail(FHE_EKEY, "autotuning times key switches with the relinearisation key: run keygen first");
   std::lock_guard<std::recursive_mutex> lk(ctx->exec_mu);
@@ -72,46 +105,22 @@ void fhe::autotune_split(fhe_ctx* ctx, hipStream_t st, uint32_t B, std::vector<s
   const std::vector<const uint64_t*> adds(2 * (size_t)B, nullptr);  // no addend
   const size_t o_key = ap.push(keys), o_add = ap.push(adds), o_out = ap.push(outs);
   ap.upload(st);
-  const uint32_t k1_orig = p.k1;
   const int lo = std::max<int>(1, (int)p.logN - 9), hi = std::min<int>(9, (int)p.logN - 1);
   // the levels the matmul switches keys at: the top (alignment rotations, relinearisation) and two
   // below it (target rotations, the bulk); the same key serves both (lower levels index a prefix)
   const uint32_t nl_low = nl >= 3 ? nl - 2 : nl;
-  tried.clear();
-  best_k1 = (int)k1_orig;
-  best_ms = 0;
-  double orig_ms = 0;
-  try {
-    for (int k1 = lo; k1 <= hi; ++k1) {
-      p.k1 = (uint32_t)k1;
-      const double ms = time_keyswitch(ctx, B, nl, in, ap, o_key, o_add, o_out, ws, 5, st) +
-                        time_keyswitch(ctx, B, nl_low, in, ap, o_key, o_add, o_out, ws, 5, st);
-      tried.emplace_back(k1, ms);
-      if ((uint32_t)k1 == k1_orig) orig_ms = ms;
-      if (best_ms == 0 || ms < best_ms) {
-        best_ms = ms;
-        best_k1 = k1;
-      }
-    }
-  } catch (...) {
-    p.k1 = k1_orig;
-    throw;
-  }
-  // keep the current split unless another one is clearly faster (timing noise is about 2%)
-  if (orig_ms > 0 && best_ms > 0.98 * orig_ms) {
-    best_k1 = (int)k1_orig;
-    best_ms = orig_ms;
-  }
-  p.k1 = (uint32_t)best_k1;
+  search(p, lo, hi, tried, best, [&] {
+    return time_keyswitch(ctx, B, nl, in, ap, o_key, o_add, o_out, ws, 5, st) +
+           time_keyswitch(ctx, B, nl_low, in, ap, o_key, o_add, o_out, ws, 5, st);
+  });
   HIPCHECK(hipStreamSynchronize(st));
 }
 
 void fhe::autotune_plan(fhe_ctx* ctx, hipStream_t st, const fhe_mat* A, const fhe_mat* B, int64_t pairs,
-                        std::vector<std::pair<int, double>>& tried, int& best_k1, double& best_ms) {
+                        std::vector<TuneTrial>& tried, TuneTrial& best) {
   if (pairs < 1) fail(FHE_EINVAL, "autotune pair count must be positive");
   std::lock_guard<std::recursive_mutex> lk(ctx->exec_mu);
   Params& p = ctx->p;
-  const uint32_t k1_orig = p.k1;
   const int lo = std::max<int>(1, (int)p.logN - 9), hi = std::min<int>(9, (int)p.logN - 1);
   hipEvent_t a, b;
   HIPCHECK(hipEventCreate(&a));
@@ -130,35 +139,18 @@ void fhe::autotune_plan(fhe_ctx* ctx, hipStream_t st, const fhe_mat* A, const fh
     HIPCHECK(hipEventElapsedTime(&ms, a, b));
     return ms;
   };
-  tried.clear();
-  best_k1 = (int)k1_orig;
-  best_ms = 0;
-  double orig_ms = 0;
   try {
-    for (int k1 = lo; k1 <= hi; ++k1) {
-      p.k1 = (uint32_t)k1;
+    search(p, lo, hi, tried, best, [&] {
       run();  // warm-up
       std::vector<double> t{run(), run(), run()};
       std::sort(t.begin(), t.end());
-      const double ms = t[1];
-      tried.emplace_back(k1, ms);
-      if ((uint32_t)k1 == k1_orig) orig_ms = ms;
-      if (best_ms == 0 || ms < best_ms) {
-        best_ms = ms;
-        best_k1 = k1;
-      }
-    }
+      return t[1];
+    });
   } catch (...) {
-    p.k1 = k1_orig;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     throw;
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  if (orig_ms > 0 && best_ms > 0.98 * orig_ms) {
-    best_k1 = (int)k1_orig;
-    best_ms = orig_ms;
-  }
-  p.k1 = (uint32_t)best_k1;
 }

@@ -78,8 +78,8 @@ _SIGS = {
     "fhe_plan_groups": ([c_vp, c_vp, c_vp, P_i64], c_i32),
     "fhe_spmspm_naive_sparse": ([c_vp, c_vp, c_vp, P_u8, P_u8, c_vp, PP], c_i32),
     "fhe_plan_stats_naive_sparse": ([c_vp, c_vp, c_vp, P_u8, P_u8, P_i64], c_i32),
-    "fhe_autotune": ([c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_dbl),
-                      ctypes.POINTER(c_i32), P_i32, P_dbl, c_i32], c_i32),
+    "fhe_autotune": ([c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32),
+                      ctypes.POINTER(c_dbl), ctypes.POINTER(c_i32), P_i32, P_i32, P_dbl, c_i32], c_i32),
     "fhe_plan_pattern": ([c_i32, c_i32, c_i32, c_i32, c_i32, P_i32, P_i32, P_i32, P_i32, P_i64], c_i32),
     "fhe_plan_rotations": ([c_vp, c_vp, c_vp, P_i32, c_sz, ctypes.POINTER(c_sz)], c_i32),
     "fhe_decrypt_decode": ([c_vp, c_vp, c_vp, c_vp, P_dbl, c_sz], c_i32),
@@ -363,21 +363,24 @@ class Context(_Handle):
 
     def autotune(self, A: Matrix | None = None, B: Matrix | None = None, pairs: int = 2000,
                  batch: int | None = None, stream=None) -> dict:
-        """Pick the fastest NTT split for this context (results are unchanged); returns the timings.
+        """Pick the fastest NTT split and row-phase workgroup shape for this context (results are
+        unchanged); returns the timings, keyed "k1/row threads".
 
         With A and B: times the first `pairs` matched pairs of A B; else synthetic key switches."""
         if batch is None:
             batch = {12: 256, 13: 256, 14: 256, 15: 128, 16: 32}.get(self.N.bit_length() - 1, 12)
-        k1, ms, n = c_i32(), c_dbl(), c_i32()
-        kt = np.zeros(16, np.int32)
-        mt = np.zeros(16, np.float64)
+        k1, rows, ms, n = c_i32(), c_i32(), c_dbl(), c_i32()
+        cap = 32
+        kt = np.zeros(cap, np.int32)
+        rt = np.zeros(cap, np.int32)
+        mt = np.zeros(cap, np.float64)
         _check(_lib.fhe_autotune(self._ptr, _stream(stream), A._ptr if A else None, B._ptr if B else None, pairs,
-                                 batch, ctypes.byref(k1), ctypes.byref(ms), ctypes.byref(n), _ptr(kt, c_i32),
-                                 _ptr(mt, c_dbl), 16))
-        m = min(n.value, 16)
-        return {"k1": k1.value, "ms": ms.value, "mode": "plan" if A else "keyswitch",
+                                 batch, ctypes.byref(k1), ctypes.byref(rows), ctypes.byref(ms), ctypes.byref(n),
+                                 _ptr(kt, c_i32), _ptr(rt, c_i32), _ptr(mt, c_dbl), cap))
+        m = min(n.value, cap)
+        return {"k1": k1.value, "row_threads": rows.value, "ms": ms.value, "mode": "plan" if A else "keyswitch",
                 "pairs" if A else "batch": pairs if A else batch,
-                "tried": {int(kt[i]): round(float(mt[i]), 3) for i in range(m)}}
+                "tried": {f"{int(kt[i])}/{int(rt[i])}": round(float(mt[i]), 3) for i in range(m)}}
 
     def plan_stats(self, A: Matrix, B: Matrix, nonzero_a=None, nonzero_b=None) -> PlanStats:
         """Plan counts of A B; with nonzero_a / nonzero_b, of the naive sparse plan (see spmspm_naive_sparse)."""

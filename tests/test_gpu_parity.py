@@ -231,8 +231,9 @@ def test_autotune_keeps_results_bit_exact(fhe):
     _say("[autotune] synthetic key switches")
     rep = ctx.autotune(batch=4)
     log_n = prm[0]
-    assert sorted(rep["tried"]) == list(range(max(1, log_n - 9), min(9, log_n - 1) + 1))
-    assert rep["k1"] in rep["tried"] and rep["ms"] > 0
+    splits = range(max(1, log_n - 9), min(9, log_n - 1) + 1)
+    assert set(rep["tried"]) == {f"{k1}/{rows}" for k1 in splits for rows in (512, 256)}
+    assert f"{rep['k1']}/{rep['row_threads']}" in rep["tried"] and rep["ms"] > 0
     m, k, n = 3, 4, 5
     a = synth.sparse_dense(m, k, 0.3, "uniform", 31, 33)
     b = synth.sparse_dense(k, n, 0.3, "uniform", 32, 34)
@@ -242,13 +243,60 @@ def test_autotune_keeps_results_bit_exact(fhe):
     B = ctx.encrypt_csc(sk, k, n, ipb, ixb, vb, seed=44)
     _say("[autotune] plan prefix")
     rep2 = ctx.autotune(A, B, pairs=6)
-    assert rep2["mode"] == "plan" and rep2["k1"] in rep2["tried"] and rep2["ms"] > 0
-    _say(f"[autotune] k1={rep2['k1']} matmul")
+    assert rep2["mode"] == "plan" and f"{rep2['k1']}/{rep2['row_threads']}" in rep2["tried"] and rep2["ms"] > 0
+    _say(f"[autotune] k1={rep2['k1']} rows={rep2['row_threads']} matmul")
     C = ctx.spmspm(A, B)
     ref = spmspm.spmspm(op, okeys, spmspm.encrypt_csr(op, okeys, m, k, ipa, ixa, va, seed=43),
                         spmspm.encrypt_csc(op, okeys, k, n, ipb, ixb, vb, seed=44))
     for c, rct in enumerate(ref):
         assert (ctx.export(C, c) == rct.data).all(), f"chunk {c}"
+
+
+def test_row_shape_256_matmul_bit_exact(fhe, monkeypatch):
+    """Row-phase workgroups of 256 threads x 16 elements (FHE_ROWS_NT=256, one of the autotuner's
+    candidates: row transforms, the combine and the rescale rows in 4-stage rounds) give the same
+    matmul, bit-exact against the oracle."""
+    prm = OP_PARAMS[0]
+    op, okeys, _, _ = _setup(fhe, prm)
+    monkeypatch.setenv("FHE_ROWS_NT", "256")
+    ctx = fhe.Context(*prm)
+    monkeypatch.delenv("FHE_ROWS_NT")
+    sk = ctx.keygen(42)
+    m, k, n = 5, 4, 6
+    a = synth.sparse_dense(m, k, 0.3, "uniform", 41, 43)
+    b = synth.sparse_dense(k, n, 0.3, "uniform", 42, 44)
+    ipa, ixa, va = synth.to_csr(a)
+    ipb, ixb, vb = synth.to_csc(b)
+    _say("[rows 256] matmul gpu")
+    C = ctx.spmspm(ctx.encrypt_csr(sk, m, k, ipa, ixa, va, seed=43), ctx.encrypt_csc(sk, k, n, ipb, ixb, vb, seed=44))
+    _say("[rows 256] matmul oracle")
+    ref = spmspm.spmspm(op, okeys, spmspm.encrypt_csr(op, okeys, m, k, ipa, ixa, va, seed=43),
+                        spmspm.encrypt_csc(op, okeys, k, n, ipb, ixb, vb, seed=44))
+    for c, rct in enumerate(ref):
+        assert (ctx.export(C, c) == rct.data).all(), f"chunk {c}"
+
+
+@pytest.mark.parametrize("log_n", [15, 16])
+def test_row_shape_256_rows_of_512_bit_exact(fhe, monkeypatch, log_n):
+    """The 256-thread row shape on rows of 2^9 elements (N >= 2^15): mult + relinearise, a rotation
+    and a rescale bit-exact against the oracle."""
+    prm = (log_n, 3, 1, 1, 1)
+    op, okeys, _, _ = _setup(fhe, prm)
+    monkeypatch.setenv("FHE_ROWS_NT", "256")
+    ctx = fhe.Context(*prm)
+    monkeypatch.delenv("FHE_ROWS_NT")
+    sk = ctx.keygen(42)
+    _say(f"[rows 256] {prm}")
+    a, b = _rand_ct(op, 3, 80 + log_n), _rand_ct(op, 3, 90 + log_n)
+    ca, cb = ctx.ct_import(a, 1.0), ctx.ct_import(b, 1.0)
+    got = ctx.ct_export(ctx.ct_mult_relin(ca, cb))
+    assert (got == ckks.mult_relin(op, okeys, ckks.Ct(a, 1.0), ckks.Ct(b, 1.0)).data).all()
+    r = op.S // 5 + 3
+    ctx.keygen_rotations(sk, [r])
+    got = ctx.ct_export(ctx.ct_rotate(ca, r))
+    assert (got == ckks.rotate(op, okeys, ckks.Ct(a, 1.0), r).data).all()
+    got = ctx.ct_export(ctx.ct_rescale(ca))
+    assert (got == ckks.rescale(op, ckks.Ct(a, 1.0)).data).all()
 
 
 @pytest.mark.parametrize("log_n", [14, 15, 16, 17])
