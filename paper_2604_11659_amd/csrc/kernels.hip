@@ -610,8 +610,18 @@ __global__ __launch_bounds__(kThreads) void k_hoisted_inner(
     const uint64_t* const* __restrict__ keys, uint64_t* __restrict__ u) {
   constexpr uint32_t kPer = 8, kTile = kThreads * kPer;  // 2048 coefficients per workgroup
   const uint32_t N = 1u << logN, tiles = N / kTile;
-  const uint32_t tile = blockIdx.x % tiles, be = blockIdx.x / tiles;
-  const uint32_t e = e0 + be % ne, b = be / ne;
+  uint32_t tile, e, b;
+  if (std::is_same<A, FpArith>::value) {  // items innermost per XCD (key tiles of items sharing a key in L2)
+    uint32_t rest;
+    xcd_split(B, b, rest);
+    tile = rest % tiles;
+    e = e0 + rest / tiles;
+  } else {
+    tile = blockIdx.x % tiles;
+    const uint32_t be = blockIdx.x / tiles;
+    e = e0 + be % ne;
+    b = be / ne;
+  }
   const uint32_t next = nl + K, beta = (nl + alpha - 1) / alpha, nall = nq + K;
   const uint32_t mi = e < nl ? e : nq + (e - nl);
   A ar;
