@@ -82,8 +82,11 @@ typedef void (*fhe_free_fn)(void* ptr, void* stream, void* user);
 int fhe_set_allocator(fhe_alloc_fn alloc, fhe_free_fn free_, void* user);
 
 /* Creates a context: prime chain, NTT tables, base-conversion and rescale constants and the
- * transformed base mask, all resident on `desc->device`. Errors: FHE_EINVAL (desc out of range,
- * not enough primes), FHE_ELEVEL (n_q < 3), FHE_ENOMEM, FHE_EDEVICE. */
+ * transformed base mask, all resident on `desc->device`. Its schedule (same results either way)
+ * starts from the NTT split k1 = log_n - 9 for log_n >= 15, else log_n / 2 (environment
+ * FHE_NTT_K1 overrides it) and row-phase workgroups of 512 threads (FHE_ROWS_NT=256 for 256);
+ * fhe_autotune may change both. Errors: FHE_EINVAL (desc out of range, not enough primes),
+ * FHE_ELEVEL (n_q < 3), FHE_ENOMEM, FHE_EDEVICE. */
 int fhe_params_create(const fhe_params_desc* desc, fhe_ctx** out);
 void fhe_ctx_free(fhe_ctx* ctx);
 
