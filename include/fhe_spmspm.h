@@ -243,8 +243,10 @@ int fhe_plan_pattern(int32_t log_n, int32_t rot_digits, int32_t m, int32_t k, in
 int fhe_plan_rotations(fhe_ctx* ctx, const fhe_mat* A, const fhe_mat* B, int32_t* out, size_t cap, size_t* n_out);
 
 /* Decrypts and decodes a matrix handle into out[rows * cols] (row-major; for an encrypted CSR/CSC
- * operand, out receives its values array in packing order instead, length nnz). Decryption uses the
- * exact CRT of limbs q_0, q_1; decoding divides by the handle's scale. */
+ * operand, out receives its values array in packing order instead, length nnz): the client-side
+ * step after the server's result comes back (Figure 1). Decryption uses the exact CRT of limbs
+ * q_0, q_1; decoding divides by the handle's scale. Errors: FHE_ESHAPE if cap is too small,
+ * FHE_EINVAL for NULL arguments. */
 int fhe_decrypt_decode(fhe_ctx* ctx, const fhe_sk* sk, const fhe_mat* M, void* stream, double* out, size_t cap);
 
 /* Shape of a matrix handle: kind (0 = CSR operand, 1 = CSC operand, 2 = dense result), rows, cols,
