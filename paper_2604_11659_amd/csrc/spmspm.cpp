@@ -846,8 +846,8 @@ void execute_slices(fhe_ctx* ctx, std::vector<Slice>& slices, hipStream_t st, co
     HIPCHECK(hipStreamSynchronize(st));
     return;
   }
-  // A captured launch stream for these operands, ranges, plan mode and NTT split, on this scratch.
-  std::vector<uint64_t> key{(tree ? 2u : grouped ? 1u : 0u) | (hoist ? 4u : 0u), p.k1, slices.size()};
+  // A captured launch stream for these operands, ranges, plan mode and schedule, on this scratch.
+  std::vector<uint64_t> key{(tree ? 2u : grouped ? 1u : 0u) | (hoist ? 4u : 0u), p.k1, p.rows_nt, slices.size()};
   for (auto& sl : slices)
     for (uint64_t v : {sl.job->A->id, sl.job->B->id, (uint64_t)sl.job->pair_lo, (uint64_t)sl.job->pair_hi,
                        (uint64_t)sl.lo, (uint64_t)sl.hi})
