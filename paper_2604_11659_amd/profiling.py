@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 CSV output for the kernels of this library.
 
-Three summaries, all short markdown files:
+Four summaries, all short markdown files:
 
 * ``stats``: the ``*_kernel_stats.csv`` of a ``--kernel-trace --stats -f csv`` run, as a table of
   calls / total / average per kernel.
@@ -11,11 +11,15 @@ Three summaries, all short markdown files:
   reader can tell when the numbers have gone stale.
 * ``counters``: per-dispatch means of any ``--pmc`` counters (several CSVs, one per pass) for each
   kernel, with the ratios that say where a kernel's waves spend their time.
+* ``busy``: from the ``*_kernel_trace.csv`` of a ``--kernel-trace -f csv`` run, the share of each
+  time bin during which at least one kernel ran, and the idle gaps longer than a threshold (where
+  the device waited for the host).
 
   python -m paper_2604_11659_amd.profiling stats CSV --title T --command C --out FILE
   python -m paper_2604_11659_amd.profiling traffic FETCH_CSV WRITE_CSV --kernel REGEX --label NAME \
       --calib REGEX --calib-bytes 1073741824 --title T --command C --out FILE
   python -m paper_2604_11659_amd.profiling counters CSV [CSV ...] --kernel REGEX --title T --command C --out FILE
+  python -m paper_2604_11659_amd.profiling busy TRACE_CSV [--bin-ms 100] [--gap-ms 5] [--active 0.5] --title T --command C --out FILE
 """
 from __future__ import annotations
 
@@ -149,6 +153,66 @@ def counters_markdown(csv_paths: list[str], kernel: str, title: str, command: st
     return "\n".join(out) + "\n"
 
 
+def busy_intervals(csv_path: str) -> list[list[int]]:
+    """Union of the kernels' [start, end) intervals (ns), in time order."""
+    spans = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in csv.DictReader(open(csv_path)))
+    merged: list[list[int]] = []
+    for s, e in spans:
+        if merged and s <= merged[-1][1]:
+            merged[-1][1] = max(merged[-1][1], e)
+        else:
+            merged.append([s, e])
+    return merged
+
+
+def busy_bins(merged: list[list[int]], bin_ns: float) -> list[float]:
+    """Share of each bin of `bin_ns` (from the first kernel's start) covered by `merged`."""
+    t0 = merged[0][0]
+    nb = int((merged[-1][1] - t0) // bin_ns) + 1
+    cover = [0.0] * nb
+    for s, e in merged:
+        a, b = s - t0, e - t0
+        while a < b:
+            k = int(a // bin_ns)
+            edge = min(b, (k + 1) * bin_ns)
+            cover[k] += edge - a
+            a = edge
+    return [c / bin_ns for c in cover]
+
+
+def busy_markdown(csv_path: str, title: str, command: str, note: str = "", bin_ms: float = 100.0,
+                  gap_ms: float = 5.0, active: float = 0.5) -> str:
+    """Busy share per bin over the whole trace; the compute phase is the stretch from the first to the
+    last bin at least `active` busy, and its idle gaps longer than `gap_ms` are listed."""
+    merged = busy_intervals(csv_path)
+    bin_ns = bin_ms * 1e6
+    bins = busy_bins(merged, bin_ns)
+    t0, t1 = merged[0][0], merged[-1][1]
+    busy_ns = sum(e - s for s, e in merged)
+    hot = [i for i, b in enumerate(bins) if b >= active]
+    out = [f"# {title}", ""]
+    if note:
+        out += [note, ""]
+    out += ["Commands (from the repository root):", "", "```", command, "```", "",
+            f"Span from the first kernel's start to the last kernel's end: {(t1 - t0) / 1e9:.3f} s; at least one "
+            f"kernel running {busy_ns / 1e9:.3f} s of it ({busy_ns / (t1 - t0):.3f}).", "",
+            f"Share of each {bin_ms:g} ms bin with a kernel running:", "", "```"]
+    for i in range(0, len(bins), 20):
+        out.append(f"{i * bin_ms / 1e3:7.1f} s  " + " ".join(f"{b:.2f}" for b in bins[i:i + 20]))
+    out += ["```", ""]
+    if not hot:
+        return "\n".join(out + [f"No bin is {active:g} busy.", ""])
+    wa, wb = t0 + hot[0] * bin_ns, t0 + (hot[-1] + 1) * bin_ns
+    in_w = sum(max(0.0, min(e, wb) - max(s, wa)) for s, e in merged)
+    gaps = [(merged[i][1] - t0, merged[i + 1][0] - merged[i][1]) for i in range(len(merged) - 1)
+            if merged[i + 1][0] - merged[i][1] > gap_ms * 1e6 and wa <= merged[i][1] and merged[i + 1][0] <= wb]
+    out += [f"Compute phase (from the first to the last bin at least {active:g} busy): "
+            f"{(wa - t0) / 1e9:.1f}-{(wb - t0) / 1e9:.1f} s, a kernel running {in_w / (wb - wa):.4f} of it. "
+            f"Idle gaps longer than {gap_ms:g} ms inside it (start from the first kernel, length):", ""]
+    out += [f"* {g0 / 1e9:.3f} s: {g / 1e6:.1f} ms" for g0, g in gaps] or ["* none"]
+    return "\n".join(out) + "\n"
+
+
 def load_traffic(profiles_dir: str, label: str) -> dict | None:
     """The traffic block for `label` measured on the current kernel source, if any."""
     if not os.path.isdir(profiles_dir):
@@ -183,7 +247,12 @@ def main(argv=None) -> int:
     c = sub.add_parser("counters")
     c.add_argument("csvs", nargs="+")
     c.add_argument("--kernel", required=True)
-    for p in (s, t, c):
+    b = sub.add_parser("busy")
+    b.add_argument("csv")
+    b.add_argument("--bin-ms", type=float, default=100.0)
+    b.add_argument("--gap-ms", type=float, default=5.0)
+    b.add_argument("--active", type=float, default=0.5)
+    for p in (s, t, c, b):
         p.add_argument("--title", required=True)
         p.add_argument("--command", required=True)
         p.add_argument("--note", default="")
@@ -193,6 +262,8 @@ def main(argv=None) -> int:
         text = stats_markdown(a.csv, a.title, a.command, a.note)
     elif a.cmd == "counters":
         text = counters_markdown(a.csvs, a.kernel, a.title, a.command, a.note)
+    elif a.cmd == "busy":
+        text = busy_markdown(a.csv, a.title, a.command, a.note, a.bin_ms, a.gap_ms, a.active)
     else:
         text = traffic_markdown(traffic(a.fetch_csv, a.write_csv, a.kernel, a.calib, a.calib_bytes), a.label,
                                 a.title, a.command, a.note)
