@@ -43,3 +43,16 @@ def test_traffic_scaled_by_the_copy_kernel(tmp_path):
     assert abs(t["fetch_scale"] - 2.0) < 1e-12 and abs(t["write_scale"] - 1.0) < 1e-12
     assert abs(t["fetch_bytes_per_launch"] - 200.0 * 1024 * 2.0) < 1e-6
     assert abs(t["bytes_per_launch"] - (200.0 * 1024 * 2.0 + 50.0 * 1024)) < 1e-6
+
+
+def test_traffic_block_only_for_the_current_kernel_source(tmp_path):
+    """A traffic summary is used only while kernels.hip has the SHA-256 it was measured on."""
+    t = {"dispatches": 1, "fetch_bytes_per_launch": 1.0, "write_bytes_per_launch": 2.0, "bytes_per_launch": 3.0,
+         "fetch_scale": 2.0, "write_scale": 1.0, "raw_fetch_kib_per_launch": 0.5, "raw_write_kib_per_launch": 2.0}
+    (tmp_path / "a_traffic.md").write_text(pf.traffic_markdown(t, "inner", "T", "cmd"))
+    got = pf.load_traffic(str(tmp_path), "inner")
+    assert got is not None and got["bytes_per_launch"] == 3.0 and got["file"] == "a_traffic.md"
+    assert pf.load_traffic(str(tmp_path), "other") is None
+    stale = (tmp_path / "a_traffic.md").read_text().replace(pf.kernel_source_sha256(), "0" * 64)
+    (tmp_path / "a_traffic.md").write_text(stale)
+    assert pf.load_traffic(str(tmp_path), "inner") is None
